@@ -1,0 +1,246 @@
+"""Oracle: plain FP64 CPU reference of the consistent and conservative
+phase-field lattice Boltzmann method (Zhan, Chai & Shi, arXiv:2111.00847).
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and
+the ``cpu_baseline`` leg of ``bench.py`` may import this package.  It shares
+no code with the GPU library (``paper_2111_00847_amd``): it has its own C
+source (``lbm_oracle.c``), its own parameter struct and its own binding.
+
+The C library is built with ``gcc -O2 -ffp-contract=off -fopenmp`` (IEEE
+round-to-nearest, no fused multiply-add, no fast-math) by :func:`build`.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "lbm_oracle.c")
+_LIB = os.path.join(_HERE, "liblbm_oracle.so")
+
+
+def build(verbose: bool = False) -> str:
+    """Compile the oracle with gcc (always recompiles)."""
+    cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+           "-fPIC", "-shared", "-Wall", "-Wno-unused-function", _SRC, "-o", _LIB + ".tmp", "-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+class OrcParams(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int), ("ny", ctypes.c_int),
+        ("wall_x", ctypes.c_int), ("wall_y", ctypes.c_int),
+        ("visc_law", ctypes.c_int), ("model", ctypes.c_int),
+        ("phiA", ctypes.c_double), ("phiB", ctypes.c_double),
+        ("rhoA", ctypes.c_double), ("rhoB", ctypes.c_double),
+        ("nuA", ctypes.c_double), ("nuB", ctypes.c_double),
+        ("sigma", ctypes.c_double), ("W", ctypes.c_double),
+        ("M", ctypes.c_double), ("eta", ctypes.c_double),
+        ("sf", ctypes.c_double * 9), ("sg", ctypes.c_double * 9),
+        ("Gx", ctypes.c_double), ("Gy", ctypes.c_double),
+        ("gx", ctypes.c_double), ("gy", ctypes.c_double),
+        ("rho_ref", ctypes.c_double),
+        ("theta", ctypes.c_double * 4),
+        ("rho0", ctypes.c_double), ("eps", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = ctypes.CDLL(_LIB)
+        P = ctypes.POINTER
+        d = P(ctypes.c_double)
+        L.orc_create.restype = ctypes.c_void_p
+        L.orc_create.argtypes = [P(OrcParams)]
+        L.orc_destroy.argtypes = [ctypes.c_void_p]
+        L.orc_init.argtypes = [ctypes.c_void_p, d, d, d]
+        L.orc_step.argtypes = [ctypes.c_void_p, ctypes.c_long]
+        L.orc_moments.argtypes = [ctypes.c_void_p, d, d, d]
+        L.orc_diagnostics.argtypes = [ctypes.c_void_p, d]
+        L.orc_get_state.argtypes = [ctypes.c_void_p, d, d, d, d, P(ctypes.c_long)]
+        L.orc_set_state.argtypes = [ctypes.c_void_p, d, d, d, d, ctypes.c_long]
+        L.orc_rates.argtypes = [ctypes.c_void_p, d, d]
+        L.orc_stencils.argtypes = [ctypes.c_void_p, d, d, d, d]
+        L.orc_lattice.argtypes = [P(ctypes.c_int), P(ctypes.c_int), d, d, d]
+        L.orc_wetting.argtypes = [P(OrcParams), ctypes.c_double, ctypes.c_double,
+                                  ctypes.c_double, d, d]
+        L.orc_moments_f.argtypes = [P(OrcParams)] + [ctypes.c_double] * 7 + [d, d]
+        L.orc_moments_g.argtypes = [P(OrcParams)] + [ctypes.c_double] * 13 + [d, d]
+        L.orc_direct_g.argtypes = [P(OrcParams)] + [ctypes.c_double] * 13 + [d, d]
+        for name in ("orc_init", "orc_step", "orc_moments", "orc_diagnostics",
+                     "orc_get_state", "orc_set_state", "orc_rates"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def make_params(case) -> OrcParams:
+    """Translate a workload case (``workloads.Case``) into the oracle's own struct."""
+    p = OrcParams()
+    p.nx, p.ny = int(case.nx), int(case.ny)
+    p.wall_x, p.wall_y = int(bool(case.wall_x)), int(bool(case.wall_y))
+    p.visc_law = {"linear_mu": 0, "inverse_nu": 1}[case.visc_law]
+    p.model = {"present": 0, "original": 1, "corrected": 2}[case.model]
+    p.phiA, p.phiB = case.phiA, case.phiB
+    p.rhoA, p.rhoB = case.rhoA, case.rhoB
+    p.nuA, p.nuB = case.nuA, case.nuB
+    p.sigma, p.W, p.M, p.eta = case.sigma, case.W, case.M, case.eta
+    for i in range(9):
+        p.sf[i] = case.s_f[i]
+        p.sg[i] = case.s_g[i]
+    p.Gx, p.Gy = case.body_force
+    p.gx, p.gy = case.gravity
+    p.rho_ref = case.rho_ref
+    for i in range(4):
+        p.theta[i] = case.theta[i]
+    p.rho0 = case.rho0
+    p.eps = case.eps_n
+    return p
+
+
+class OracleSim:
+    """One lattice of the oracle (FP64)."""
+
+    def __init__(self, case):
+        self.case = case
+        self.p = make_params(case)
+        self.nx, self.ny = self.p.nx, self.p.ny
+        self.h = lib().orc_create(ctypes.byref(self.p))
+        if not self.h:
+            raise ValueError("oracle rejected the parameters")
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h:
+            lib().orc_destroy(h)
+            self.h = None
+
+    @property
+    def shape(self):
+        return (self.ny, self.nx)
+
+    def init(self, phi0, u0=None, p0=None):
+        phi0 = _f64(phi0).reshape(self.shape)
+        u0 = None if u0 is None else _f64(u0).reshape((2,) + self.shape)
+        p0 = None if p0 is None else _f64(p0).reshape(self.shape)
+        self._keep = (phi0, u0, p0)
+        rc = lib().orc_init(self.h, _dp(phi0), _dp(u0), _dp(p0))
+        assert rc == 0, rc
+        return self
+
+    def step(self, n=1):
+        rc = lib().orc_step(self.h, int(n))
+        assert rc == 0, rc
+        return self
+
+    def moments(self):
+        phi = np.empty(self.shape)
+        u = np.empty((2,) + self.shape)
+        p = np.empty(self.shape)
+        rc = lib().orc_moments(self.h, _dp(phi), _dp(u), _dp(p))
+        assert rc == 0
+        return phi, u, p
+
+    def diagnostics(self):
+        out = np.empty(6)
+        rc = lib().orc_diagnostics(self.h, _dp(out))
+        assert rc == 0
+        return dict(zip(["sum_phi", "max_div", "Du_rms", "Sm_rms", "umax", "nonfinite"], out))
+
+    def get_state(self):
+        f = np.empty((9,) + self.shape)
+        g = np.empty((9,) + self.shape)
+        H = np.empty((5,) + self.shape)
+        pp = np.empty(self.shape)
+        st = ctypes.c_long()
+        lib().orc_get_state(self.h, _dp(f), _dp(g), _dp(H), _dp(pp), ctypes.byref(st))
+        return dict(f=f, g=g, H=H, phi_prev=pp, step=st.value)
+
+    def set_state(self, f, g, step, phi_prev=None, u_prev=None):
+        f = _f64(f).reshape((9,) + self.shape)
+        g = _f64(g).reshape((9,) + self.shape)
+        pp = None if phi_prev is None else _f64(phi_prev).reshape(self.shape)
+        up = None if u_prev is None else _f64(u_prev).reshape((2,) + self.shape)
+        rc = lib().orc_set_state(self.h, _dp(f), _dp(g), _dp(pp), _dp(up), int(step))
+        assert rc == 0, rc
+        return self
+
+    def stencils(self, phi):
+        phi = _f64(phi).reshape(self.shape)
+        gx, gy, lap = (np.empty(self.shape) for _ in range(3))
+        rc = lib().orc_stencils(self.h, _dp(phi), _dp(gx), _dp(gy), _dp(lap))
+        assert rc == 0
+        return gx, gy, lap
+
+    def rates(self):
+        sf = np.empty(9)
+        sg = np.empty(9)
+        lib().orc_rates(self.h, _dp(sf), _dp(sg))
+        return sf, sg
+
+
+def lattice():
+    cx = (ctypes.c_int * 9)()
+    cy = (ctypes.c_int * 9)()
+    w = np.empty(9)
+    M = np.empty(81)
+    Minv = np.empty(81)
+    lib().orc_lattice(cx, cy, _dp(w), _dp(M), _dp(Minv))
+    return np.array(cx[:]), np.array(cy[:]), w, M.reshape(9, 9), Minv.reshape(9, 9)
+
+
+def wetting(case, theta, phi1, phi2):
+    p = make_params(case)
+    pw = ctypes.c_double()
+    pg = ctypes.c_double()
+    lib().orc_wetting(ctypes.byref(p), theta, phi1, phi2, ctypes.byref(pw), ctypes.byref(pg))
+    return pw.value, pg.value
+
+
+def moments_f(case, phi, u, v, lam_nx, lam_ny, dphiu, dphiv):
+    p = make_params(case)
+    meq = np.empty(9)
+    mR = np.empty(9)
+    lib().orc_moments_f(ctypes.byref(p), phi, u, v, lam_nx, lam_ny, dphiu, dphiv, _dp(meq), _dp(mR))
+    return meq, mR
+
+
+def moments_g(case, rho, pr, u, v, mx, my, Fx, Fy, drx, dry, d_umx, d_vmy, d_cross):
+    p = make_params(case)
+    meq = np.empty(9)
+    mF = np.empty(9)
+    lib().orc_moments_g(ctypes.byref(p), rho, pr, u, v, mx, my, Fx, Fy, drx, dry, d_umx, d_vmy,
+                        d_cross, _dp(meq), _dp(mF))
+    return meq, mF
+
+
+def direct_g(case, rho, pr, u, v, mx, my, Fx, Fy, drx, dry, d_umx, d_vmy, d_cross):
+    p = make_params(case)
+    geq = np.empty(9)
+    Fi = np.empty(9)
+    lib().orc_direct_g(ctypes.byref(p), rho, pr, u, v, mx, my, Fx, Fy, drx, dry, d_umx, d_vmy,
+                       d_cross, _dp(geq), _dp(Fi))
+    return geq, Fi

@@ -1,0 +1,32 @@
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (runs the HIP library)")
+    config.addinivalue_line("markers", "slow: long-running oracle physics pin")
+
+
+def pytest_collection_modifyitems(config, items):
+    gpu_ok = None
+    for item in items:
+        if "gpu" in item.keywords:
+            if gpu_ok is None:
+                import torch
+                gpu_ok = torch.cuda.is_available()
+            if not gpu_ok:
+                item.add_marker(pytest.mark.skip(reason="no GPU in this container"))
+
+
+@pytest.fixture(scope="session", autouse=True)
+def _oracle_built():
+    import oracle
+    if not os.path.exists(oracle._LIB):
+        oracle.build()
+    yield
