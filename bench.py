@@ -1,0 +1,169 @@
+#!/usr/bin/env python3
+"""Benchmark of the fused phase-field LBM step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Workload: the Rayleigh-Taylor set-up of Sec. 4.4 at 256 x 1024 nodes, FP32
+(synthetic initial interface, lattice parameters as in workloads.rti).  A step
+is one fused time step of the whole lattice (moments, stencils, closure, both
+MRT collisions, streaming with walls).  The timed region holds exactly K steps
+with the state resident in HBM; the value is lattice updates per second.
+
+The JSON line also carries:
+  roofline     -- the step kernel against the HBM peak: algorithmic bytes per
+                  launch (168 B per node in FP32) / average launch duration
+                  (HIP events over the timed region on the launch stream);
+                  `traffic` is the measured HBM bytes per launch from the
+                  committed rocprofv3 counter summary when it matches the
+                  current kernel source, else null;
+  large_grid   -- the same kernel at 4096 x 4096 (state 2.8 GB, far beyond the
+                  256 MB Infinity Cache), where HBM is the real bound;
+  cpu_baseline -- the FP64 oracle timed on the host on a bounded sample.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+ALG_BYTES = {"f32": 168, "f64": 336}   # per lattice update: f, g read+write, (phi, u, v) history read+write
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "k_step_rti_256x1024_traffic.json")
+KERNEL_SOURCES = ["paper_2111_00847_amd/csrc/lbm_step.hip", "paper_2111_00847_amd/csrc/lbm_tile.hpp",
+                  "paper_2111_00847_amd/csrc/lbm_device.hpp", "paper_2111_00847_amd/csrc/lbm_common.hpp"]
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def time_steps(sim, steps, torch):
+    """Run `steps` steps in one lbm_step call between two HIP events on the
+    launch stream; returns (total ms, ms per launch)."""
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    sim.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    return ms, ms / steps
+
+
+def measured_traffic(nodes):
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    on the current kernel source and this workload."""
+    try:
+        with open(PROFILE_TRAFFIC) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_hash") != kernel_source_hash() or rec.get("nodes") != nodes:
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(budget_s=15.0):
+    import oracle
+    import workloads as W
+    case, phi0 = W.rti()
+    s = oracle.OracleSim(case.replace(dtype="f64")).init(phi0, None, W.hydrostatic_pressure(case, phi0))
+    s.step(2)                       # first-touch of the oracle's fields
+    steps, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        s.step(5)
+        steps += 5
+    dt = time.perf_counter() - t0
+    mlups = case.nodes * steps / dt / 1e6
+    return {"value": round(mlups, 3), "unit": "MLUPS", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"FP64 oracle, rti 256x1024, {steps} steps after 2 untimed ({dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--large-steps", type=int, default=200)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-large", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
+              "a lattice is not sharded across GPUs here.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads as W
+    from paper_2111_00847_amd.sim import Sim
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+
+    case, phi0 = W.rti()
+    sim = Sim(case, "cuda:0").init(phi0, None, W.hydrostatic_pressure(case, phi0))
+    sim.step(args.warmup)
+    torch.cuda.synchronize()
+    ms, ms_launch = time_steps(sim, args.steps, torch)
+    nodes = case.nodes
+    mlups = nodes * args.steps / (ms * 1e-3) / 1e6
+    alg = ALG_BYTES[case.dtype] * nodes
+    achieved = alg / (ms_launch * 1e-3) / 1e9
+    traffic = measured_traffic(nodes)
+    d = sim.diagnostics()
+    assert d["nonfinite"] == 0, "non-finite state after the timed steps"
+
+    out = {
+        "metric": "MLUPS (fused FP32 phase-field LBM step, single launch per step)",
+        "value": round(mlups, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "rayleigh_taylor_256x1024", "nx": case.nx, "ny": case.ny,
+                   "lattice": "D2Q9 x2 (phase field + flow), MRT", "boundaries": "periodic x, walls y"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "kernel": "k_step<float>", "alg_bytes_per_launch": alg,
+                     "avg_launch_ms": round(ms_launch, 5)},
+    }
+    del sim
+    torch.cuda.empty_cache()
+
+    if not args.no_large:
+        caseL, phiL = W.rti(nx=4096, ny=4096)
+        simL = Sim(caseL, "cuda:0").init(phiL, None, W.hydrostatic_pressure(caseL, phiL))
+        simL.step(10)
+        msL, msLl = time_steps(simL, args.large_steps, torch)
+        algL = ALG_BYTES["f32"] * caseL.nodes
+        achL = algL / (msLl * 1e-3) / 1e9
+        out["large_grid"] = {"workload": "rayleigh_taylor_4096x4096", "steps": args.large_steps,
+                             "value": round(caseL.nodes * args.large_steps / (msL * 1e-3) / 1e6, 1),
+                             "unit": "MLUPS", "achieved_GBs": round(achL, 1),
+                             "frac": round(achL / HBM_PEAK_GBS, 4), "avg_launch_ms": round(msLl, 4)}
+        del simL
+        torch.cuda.empty_cache()
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

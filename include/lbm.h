@@ -1,0 +1,144 @@
+/*
+ * lbm.h -- C ABI of liblbm, an MI355X (gfx950) implementation of the
+ * consistent and conservative phase-field lattice Boltzmann method of
+ * Zhan, Chai & Shi, "Consistent and conservative phase-field based lattice
+ * Boltzmann method for incompressible two-phase flows" (arXiv:2111.00847).
+ *
+ * One time step advances two D2Q9 populations:
+ *   f -- conservative Allen-Cahn phase field, MRT collision in moment space
+ *        (Sec. 3, Eq. evoPF; App. C, Eq. MfMRAC1),
+ *   g -- incompressible flow with the consistent mass flux
+ *        m^CC = rho u + m^phiC, m^phiC = -(drho/dphi) M (grad phi - lambda n)
+ *        (Sec. 2; Sec. 3, Eq. evoNS, Remark 2; App. C, Eq. MgMF1),
+ * with isotropic gradient / Laplacian stencils (App. C, Eqs. central1,
+ * central2), explicit-Euler time derivatives (App. C), the pressure of
+ * Eq. computP in the second way of Remark 1, half-way bounce-back and the
+ * wetting boundary condition of Eq. Dwetting (Sec. 4.3).
+ *
+ * Conventions (all entry points):
+ *  - Lattice units: dx = dt = c = 1, cs^2 = 1/3.
+ *  - Fields are row-major [ny][nx], x fastest, y = 0 the bottom row; vector
+ *    fields are [2][ny][nx] (x component first); distributions are
+ *    [9][ny][nx] with c0..c8 = (0,0),(1,0),(0,1),(-1,0),(0,-1),(1,1),(-1,1),
+ *    (-1,-1),(1,-1) (the column order of M1 in App. C).
+ *  - Every array argument has the element type selected by lbm_params.dtype
+ *    (float or double) unless stated otherwise, and is DEVICE memory unless
+ *    stated otherwise.  The caller owns every buffer; the library never
+ *    allocates or frees caller memory and keeps no pointer after returning.
+ *    The only library-owned objects are lbm_batch plans.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Calls are
+ *    asynchronous on it unless documented as synchronising.
+ *  - Validation is synchronous and returns a negative lbm_status; a failing
+ *    HIP call returns LBM_E_HIP.  No C++ exception crosses the ABI.
+ *  - A state buffer is opaque: its size is given by lbm_state_size, it must
+ *    be 256-byte aligned, it is written only by lbm_init / lbm_import_state /
+ *    lbm_step, and it holds everything a step needs (both ping-pong copies of
+ *    the populations, the Euler history, the step counter).  A device-to-
+ *    device copy of it is a checkpoint; a state may only be used with the
+ *    lbm_params it was initialised with.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_E_NULL = -1,        /* a required pointer is NULL */
+    LBM_E_SIZE = -2,        /* grid or buffer size invalid (nx, ny < 1; < 2 across a wall axis) */
+    LBM_E_DTYPE = -3,       /* dtype not LBM_F32 / LBM_F64 */
+    LBM_E_PARAM = -4,       /* physical parameter invalid (rho, nu, W <= 0, phi_A <= phi_B, eta != 1, ...) */
+    LBM_E_UNSTABLE = -5,    /* a relaxation rate outside (0, 2): tau <= 1/2 */
+    LBM_E_HIP = -6,         /* a HIP runtime call failed */
+    LBM_E_NONFINITE = -7,   /* diagnostics found a NaN or Inf in the state */
+    LBM_E_UNSUPPORTED = -8  /* option not implemented (e.g. a model flag) */
+} lbm_status;
+
+typedef enum { LBM_F32 = 0, LBM_F64 = 1 } lbm_dtype;
+typedef enum { LBM_PERIODIC = 0, LBM_WALLS = 1 } lbm_bc;
+typedef enum {
+    LBM_VISC_LINEAR_MU = 0,   /* linear dynamic viscosity, Sec. 2, Eq. linearMu (the paper's default) */
+    LBM_VISC_INVERSE_NU = 1   /* inverse-linear kinematic viscosity, Sec. 2, Eq. inverseNu */
+} lbm_visc;
+typedef enum {
+    LBM_MODEL_PRESENT = 0,    /* consistent mass flux m^CC (the paper's model) */
+    LBM_MODEL_ORIGINAL = 1    /* mass flux rho u only (m^phiC = 0 in the flow model; Sec. 4 preamble) */
+} lbm_model;
+
+/* Problem statement in the paper's notation (Sec. 2; Sec. 4 preamble). */
+typedef struct lbm_params {
+    int32_t nx, ny;                 /* lattice nodes */
+    int32_t dtype;                  /* lbm_dtype: element type of state and fields */
+    int32_t bc_x, bc_y;             /* lbm_bc per axis; WALLS = half-way bounce-back on both faces */
+    int32_t visc_law;               /* lbm_visc */
+    int32_t model;                  /* lbm_model */
+    int32_t reserved;               /* must be 0 */
+    double phi_A, phi_B;            /* order parameter of the two bulk phases, phi_A > phi_B */
+    double rho_A, rho_B;            /* densities (Eq. rho-phi) */
+    double nu_A, nu_B;              /* kinematic viscosities; mu = rho nu */
+    double sigma, W, M_phi, eta;    /* surface tension, interface width, mobility; eta must be 1 */
+    double s_f[9], s_g[9];          /* MRT rates; an entry <= 0 selects the paper's default:
+                                       s_f^3 = s_f^5 = 1/(M_phi/(eta cs^2) + 1/2),
+                                       s_g^7 = s_g^8 = 1/(nu(phi)/cs^2 + 1/2) per node,
+                                       all others 1 (Sec. 4 preamble) */
+    double body_force[2];           /* uniform force density G (Sec. 4.2) */
+    double gravity[2];              /* adds (rho - rho_ref) * gravity to F (Secs. 4.4, 4.5) */
+    double rho_ref;
+    double theta[4];                /* contact angle [rad] at the x-, x+, y-, y+ walls (Sec. 4.3);
+                                       pi/2 is the neutral (no-flux) wall */
+    double rho0;                    /* constant density of g^eq (Eq. geq); a gauge, 0 is best for FP32 */
+    double eps_n;                   /* n = grad phi / sqrt(|grad phi|^2 + eps_n^2) */
+} lbm_params;
+
+/* Human-readable name of a status code (static storage). */
+const char *lbm_status_string(int status);
+
+/* Bytes of device memory the caller must provide for one lattice's state. */
+int lbm_state_size(const lbm_params *p, size_t *nbytes /* host */);
+
+/* Initial state f = f^eq(phi0, u0), g = g^eq(phi0, u0, p0) (equilibria of
+ * Eq. MfMRAC1 and Eq. MgMF1 at the given fields; the Euler time derivatives
+ * of the first step are zero).  phi0: [ny][nx]; u0: [2][ny][nx] or NULL
+ * (zero); p0: [ny][nx] or NULL (zero). */
+int lbm_init(const lbm_params *p, void *state, const void *phi0, const void *u0, const void *p0,
+             void *stream);
+
+/* Advance nsteps >= 0 time steps (Sec. 3): moments, closure, both MRT
+ * collisions and streaming with bounce-back, fused in one kernel per step. */
+int lbm_step(const lbm_params *p, void *state, int64_t nsteps, void *stream);
+
+/* Order parameter, velocity (Eq. comU) and pressure (Eq. computP) of the
+ * current time level.  phi, p: [ny][nx] or NULL; u: [2][ny][nx] or NULL. */
+int lbm_moments(const lbm_params *p, const void *state, void *phi, void *u, void *pr,
+                void *stream);
+
+/* Diagnostics of the current level (Sec. 4.1), FP64, written to HOST out[6]:
+ *   out[0] sum of phi, out[1] max |div u|, out[2] D_u^rms, out[3] S_m^rms,
+ *   out[4] max |u|, out[5] 1 if any population is NaN/Inf else 0,
+ * with div u = tr S of Eq. strainRate and S_m = d_t rho + div m^CC, where
+ * div m^phiC uses Eq. central1 (rms over nodes whose eight neighbours are
+ * fluid).  Synchronises the stream.  Returns LBM_E_NONFINITE when out[5] = 1. */
+int lbm_diagnostics(const lbm_params *p, const void *state, double *out /* host [6] */,
+                    void *stream);
+
+/* Post-streaming populations f^n, g^n ([9][ny][nx] each, either may be NULL),
+ * phi and u of level n-1 (hist: [3][ny][nx] = phi, u, v; NULL to skip), and the
+ * step index n (host int64, NULL to skip).  Synchronises the stream when step
+ * is requested. */
+int lbm_export_state(const lbm_params *p, const void *state, void *f, void *g, void *hist,
+                     int64_t *step, void *stream);
+
+/* Inverse of lbm_export_state: load post-streaming f^n, g^n and the level
+ * n-1 history (ignored when n == 0) as the state of step n. */
+int lbm_import_state(const lbm_params *p, void *state, const void *f, const void *g,
+                     const void *hist, int64_t step, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

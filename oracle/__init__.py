@@ -202,6 +202,10 @@ class OracleSim:
         return sf, sg
 
 
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
+
+
 def lattice():
     cx = (ctypes.c_int * 9)()
     cy = (ctypes.c_int * 9)()

@@ -26,6 +26,7 @@
 #include "lbm_oracle.h"
 
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -99,6 +100,8 @@ static int invert9(const double A[9][9], double R[9][9]) {
         for (int j = 0; j < 9; j++) R[i][j] = a[i][j + 9];
     return 0;
 }
+
+int orc_num_threads(void) { return omp_get_max_threads(); }
 
 void orc_lattice(int cx[9], int cy[9], double w[9], double M[81], double Minv[81]) {
     double R[9][9];

@@ -64,6 +64,9 @@ int orc_set_state(orc_sim *s, const double *f, const double *g, const double *ph
  * are -1 when they follow the local viscosity). */
 int orc_rates(const orc_sim *s, double sf[9], double sg[9]);
 
+/* OpenMP threads the oracle's loops use. */
+int orc_num_threads(void);
+
 /* ---- building blocks exposed for the pins ---- */
 /* grad phi and lap phi of an arbitrary field with this lattice's ghost rule. */
 int orc_stencils(const orc_sim *s, const double *phi, double *gx, double *gy, double *lap);

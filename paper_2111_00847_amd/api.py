@@ -1,0 +1,132 @@
+"""Python binding of the C ABI with the same entry-point names (include/lbm.h).
+
+Arguments are torch tensors on the GPU (device memory and streams come from
+PyTorch); each function checks shapes and dtypes, passes raw pointers to the
+library and raises :class:`LbmError` on a non-zero status.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+from typing import Optional
+
+import torch
+
+from ._lib import (LBM_F32, LBM_F64, LBM_PERIODIC, LBM_WALLS, LbmError, LbmParams, call, lib)
+
+_VISC = {"linear_mu": 0, "inverse_nu": 1}
+_MODEL = {"present": 0, "original": 1}
+
+
+def make_params(case) -> LbmParams:
+    """lbm_params from a workload case (plain field copy, no derived quantities)."""
+    p = LbmParams()
+    p.nx, p.ny = int(case.nx), int(case.ny)
+    p.dtype = LBM_F64 if case.dtype == "f64" else LBM_F32
+    p.bc_x = LBM_WALLS if case.wall_x else LBM_PERIODIC
+    p.bc_y = LBM_WALLS if case.wall_y else LBM_PERIODIC
+    p.visc_law = _VISC[case.visc_law]
+    p.model = _MODEL.get(case.model, 99)
+    p.reserved = 0
+    p.phi_A, p.phi_B = case.phiA, case.phiB
+    p.rho_A, p.rho_B = case.rhoA, case.rhoB
+    p.nu_A, p.nu_B = case.nuA, case.nuB
+    p.sigma, p.W, p.M_phi, p.eta = case.sigma, case.W, case.M, case.eta
+    for i in range(9):
+        p.s_f[i] = case.s_f[i]
+        p.s_g[i] = case.s_g[i]
+    p.body_force[0], p.body_force[1] = case.body_force
+    p.gravity[0], p.gravity[1] = case.gravity
+    p.rho_ref = case.rho_ref
+    for i in range(4):
+        p.theta[i] = case.theta[i]
+    p.rho0 = case.rho0
+    p.eps_n = case.eps_n
+    return p
+
+
+def torch_dtype(p: LbmParams):
+    return torch.float64 if p.dtype == LBM_F64 else torch.float32
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor], p: LbmParams, shape=None, name="array"):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if t.dtype != torch_dtype(p):
+        raise ValueError(f"{name} has dtype {t.dtype}, expected {torch_dtype(p)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def lbm_state_size(p: LbmParams) -> int:
+    n = ctypes.c_size_t()
+    call("lbm_state_size", ctypes.byref(p), ctypes.byref(n))
+    return n.value
+
+
+def new_state(p: LbmParams, device="cuda") -> torch.Tensor:
+    """A state buffer (uint8 tensor) of lbm_state_size bytes, 256-byte aligned."""
+    n = lbm_state_size(p)
+    buf = torch.empty(n + 256, dtype=torch.uint8, device=device)
+    off = (-buf.data_ptr()) % 256
+    return buf[off:off + n]
+
+
+def _state_ptr(state: torch.Tensor):
+    if not state.is_cuda or state.dtype != torch.uint8:
+        raise ValueError("state must be a uint8 GPU tensor from new_state()")
+    return ctypes.c_void_p(state.data_ptr())
+
+
+def lbm_init(p, state, phi0, u0=None, p0=None, stream=None):
+    shp = (p.ny, p.nx)
+    call("lbm_init", ctypes.byref(p), _state_ptr(state), _ptr(phi0, p, shp, "phi0"),
+         _ptr(u0, p, (2,) + shp, "u0"), _ptr(p0, p, shp, "p0"), _stream(stream))
+
+
+def lbm_step(p, state, nsteps=1, stream=None):
+    call("lbm_step", ctypes.byref(p), _state_ptr(state), int(nsteps), _stream(stream))
+
+
+def lbm_moments(p, state, phi=None, u=None, pr=None, stream=None):
+    shp = (p.ny, p.nx)
+    call("lbm_moments", ctypes.byref(p), _state_ptr(state), _ptr(phi, p, shp, "phi"),
+         _ptr(u, p, (2,) + shp, "u"), _ptr(pr, p, shp, "p"), _stream(stream))
+
+
+DIAG_NAMES = ("sum_phi", "max_div", "Du_rms", "Sm_rms", "umax", "nonfinite")
+
+
+def lbm_diagnostics(p, state, stream=None, raise_nonfinite=False):
+    out = (ctypes.c_double * 6)()
+    code = lib().lbm_diagnostics(ctypes.byref(p), _state_ptr(state), out, _stream(stream))
+    if code != 0 and not (code == -7 and not raise_nonfinite):
+        raise LbmError("lbm_diagnostics", code)
+    return dict(zip(DIAG_NAMES, list(out)))
+
+
+def lbm_export_state(p, state, f=None, g=None, hist=None, stream=None):
+    shp = (p.ny, p.nx)
+    st = ctypes.c_int64()
+    call("lbm_export_state", ctypes.byref(p), _state_ptr(state), _ptr(f, p, (9,) + shp, "f"),
+         _ptr(g, p, (9,) + shp, "g"), _ptr(hist, p, (3,) + shp, "hist"), ctypes.byref(st),
+         _stream(stream))
+    return st.value
+
+
+def lbm_import_state(p, state, f, g, hist, step, stream=None):
+    shp = (p.ny, p.nx)
+    call("lbm_import_state", ctypes.byref(p), _state_ptr(state), _ptr(f, p, (9,) + shp, "f"),
+         _ptr(g, p, (9,) + shp, "g"), _ptr(hist, p, (3,) + shp, "hist"), int(step),
+         _stream(stream))

@@ -1,0 +1,275 @@
+// lbm_api.hip -- extern "C" entry points of liblbm (declared in include/lbm.h):
+// parameter validation, resolution of the paper's parameters into kernel
+// constants, state layout and dispatch to the gfx950 kernels.
+#include <math.h>
+#include <string.h>
+
+#include "../../include/lbm.h"
+#include "lbm_kernels.hpp"
+
+namespace lbm {
+
+static size_t elem_size(int dtype) { return dtype == LBM_F64 ? 8 : 4; }
+
+// Workgroups of the diagnostics kernels (64 x 8 tiles), one partial record each.
+size_t diag_blocks(const lbm_params* p) { return (size_t)((p->nx + 63) / 64) * ((p->ny + 7) / 8); }
+
+Layout layout_of(const lbm_params* p) {
+    return make_layout(p->nx, p->ny, elem_size(p->dtype), diag_blocks(p));
+}
+
+int validate(const lbm_params* p) {
+    if (!p) return LBM_E_NULL;
+    if (p->dtype != LBM_F32 && p->dtype != LBM_F64) return LBM_E_DTYPE;
+    if (p->nx < 1 || p->ny < 1) return LBM_E_SIZE;
+    if ((long long)p->nx * p->ny > (1LL << 34)) return LBM_E_SIZE;
+    if (p->bc_x != LBM_PERIODIC && p->bc_x != LBM_WALLS) return LBM_E_PARAM;
+    if (p->bc_y != LBM_PERIODIC && p->bc_y != LBM_WALLS) return LBM_E_PARAM;
+    if (p->bc_x == LBM_WALLS && p->nx < 2) return LBM_E_SIZE;
+    if (p->bc_y == LBM_WALLS && p->ny < 2) return LBM_E_SIZE;
+    if (p->visc_law != LBM_VISC_LINEAR_MU && p->visc_law != LBM_VISC_INVERSE_NU) return LBM_E_PARAM;
+    if (p->model != LBM_MODEL_PRESENT && p->model != LBM_MODEL_ORIGINAL) return LBM_E_UNSUPPORTED;
+    if (p->reserved != 0) return LBM_E_PARAM;
+    const double vals[] = {p->phi_A, p->phi_B, p->rho_A, p->rho_B, p->nu_A, p->nu_B, p->sigma, p->W,
+                           p->M_phi, p->eta, p->body_force[0], p->body_force[1], p->gravity[0],
+                           p->gravity[1], p->rho_ref, p->rho0, p->eps_n};
+    for (double v : vals)
+        if (!isfinite(v)) return LBM_E_PARAM;
+    if (!(p->phi_A > p->phi_B)) return LBM_E_PARAM;
+    if (!(p->rho_A > 0 && p->rho_B > 0 && p->nu_A > 0 && p->nu_B > 0)) return LBM_E_PARAM;
+    if (!(p->W > 0 && p->sigma >= 0 && p->M_phi >= 0 && p->eps_n >= 0)) return LBM_E_PARAM;
+    if (p->eta != 1.0) return LBM_E_PARAM;
+    for (int i = 0; i < 9; i++) {
+        if (!isfinite(p->s_f[i]) || !isfinite(p->s_g[i])) return LBM_E_PARAM;
+        if (p->s_f[i] >= 2.0 || p->s_g[i] >= 2.0) return LBM_E_UNSTABLE;
+    }
+    for (int k = 0; k < 4; k++)
+        if (!(p->theta[k] > 0 && p->theta[k] < M_PI)) return LBM_E_PARAM;
+    // default rates must be stable: s = 1/(x/cs^2 + 1/2) lies in (0, 2) for x > 0
+    if (!(p->s_f[3] > 0 && p->s_f[5] > 0) && !(p->M_phi > 0)) return LBM_E_UNSTABLE;
+    return LBM_OK;
+}
+
+template <typename T>
+KParams<T> resolve(const lbm_params* p, const Layout& L) {
+    KParams<T> K;
+    memset(&K, 0, sizeof(K));
+    K.nx = p->nx;
+    K.ny = p->ny;
+    K.wall_x = p->bc_x == LBM_WALLS;
+    K.wall_y = p->bc_y == LBM_WALLS;
+    K.visc_law = p->visc_law;
+    K.model = p->model;
+    K.plane = L.plane;
+    const double dphi = p->phi_A - p->phi_B;
+    // Sec. 2: beta = 12 sigma / (W dphi^4), k = 3 sigma W / (2 dphi^2), sqrt(2 beta / k) = 4 / (W dphi)
+    const double beta = 12.0 * p->sigma / (p->W * dphi * dphi * dphi * dphi);
+    const double kap = 1.5 * p->sigma * p->W / (dphi * dphi);
+    K.phiA = (T)p->phi_A;
+    K.phiB = (T)p->phi_B;
+    K.phim = (T)(0.5 * (p->phi_A + p->phi_B));
+    K.beta4 = (T)(4.0 * beta);
+    K.kap = (T)kap;
+    K.lamc = (T)(4.0 / (p->W * dphi));
+    const double drho = (p->rho_A - p->rho_B) / dphi;
+    K.drho = (T)drho;
+    K.rhoB = (T)p->rho_B;
+    K.drhoM = (T)(drho * p->M_phi);
+    K.inv_dphi = (T)(1.0 / dphi);
+    K.muA = (T)(p->rho_A * p->nu_A);
+    K.muB = (T)(p->rho_B * p->nu_B);
+    K.inv_nuA = (T)(1.0 / p->nu_A);
+    K.inv_nuB = (T)(1.0 / p->nu_B);
+    // Sec. 4 preamble: rates of the mobility and the viscosity, the others 1.
+    const double cs2 = 1.0 / 3.0;
+    double sf[9], sg[9];
+    for (int i = 0; i < 9; i++) {
+        sf[i] = p->s_f[i] > 0 ? p->s_f[i] : 1.0;
+        sg[i] = p->s_g[i] > 0 ? p->s_g[i] : 1.0;
+    }
+    const double sM = 1.0 / (p->M_phi / (p->eta * cs2) + 0.5);
+    if (!(p->s_f[3] > 0)) sf[3] = sM;
+    if (!(p->s_f[5] > 0)) sf[5] = sM;
+    K.snu_local = !(p->s_g[7] > 0 && p->s_g[8] > 0);
+    for (int i = 0; i < 9; i++) {
+        K.sf[i] = (T)sf[i];
+        K.sg[i] = (T)sg[i];
+    }
+    K.Gx = (T)p->body_force[0];
+    K.Gy = (T)p->body_force[1];
+    K.gx = (T)p->gravity[0];
+    K.gy = (T)p->gravity[1];
+    K.rho_ref = (T)p->rho_ref;
+    // Eq. (Dwetting): a = 4 cos(theta) / (W dphi), b = 8/3 - a (phiA + phiB), c = a phiA phiB + ...
+    for (int k = 0; k < 4; k++) {
+        const double a = 4.0 * cos(p->theta[k]) / (p->W * dphi);
+        K.wa[k] = (T)a;
+        K.wb[k] = (T)(8.0 / 3.0 - a * (p->phi_A + p->phi_B));
+        K.wc0[k] = (T)(a * p->phi_A * p->phi_B);
+    }
+    K.rho0 = (T)p->rho0;
+    K.eps2 = (T)(p->eps_n * p->eps_n);
+    K.Hp = (T)((sg[2] - sg[0]) / (9.0 * sg[0] * sg[2]));
+    return K;
+}
+
+template KParams<float> resolve<float>(const lbm_params*, const Layout&);
+template KParams<double> resolve<double>(const lbm_params*, const Layout&);
+
+// Tile height of the step kernel: taller tiles amortise the halo ring, shorter
+// ones give small lattices enough workgroups to fill 256 CUs.
+int step_tile_rows(const lbm_params* p) {
+    long long tiles16 = (long long)((p->nx + 63) / 64) * ((p->ny + 15) / 16);
+    if (tiles16 >= 2048) return 16;
+    long long tiles8 = (long long)((p->nx + 63) / 64) * ((p->ny + 7) / 8);
+    if (tiles8 >= 1024) return 8;
+    return 4;
+}
+
+static thread_local char g_last_error[256];
+
+int hip_fail(hipError_t e) {
+    snprintf(g_last_error, sizeof g_last_error, "%s", hipGetErrorString(e));
+    return LBM_E_HIP;
+}
+
+}  // namespace lbm
+
+using namespace lbm;
+
+extern "C" {
+
+const char* lbm_status_string(int s) {
+    switch (s) {
+        case LBM_OK: return "ok";
+        case LBM_E_NULL: return "null pointer";
+        case LBM_E_SIZE: return "invalid size";
+        case LBM_E_DTYPE: return "invalid dtype";
+        case LBM_E_PARAM: return "invalid parameter";
+        case LBM_E_UNSTABLE: return "relaxation rate outside (0, 2)";
+        case LBM_E_HIP: return g_last_error[0] ? g_last_error : "HIP runtime error";
+        case LBM_E_NONFINITE: return "non-finite value in the state";
+        case LBM_E_UNSUPPORTED: return "unsupported option";
+        default: return "unknown status";
+    }
+}
+
+int lbm_state_size(const lbm_params* p, size_t* nbytes) {
+    int rc = validate(p);
+    if (rc) return rc;
+    if (!nbytes) return LBM_E_NULL;
+    *nbytes = layout_of(p).total;
+    return LBM_OK;
+}
+
+int lbm_init(const lbm_params* p, void* state, const void* phi0, const void* u0, const void* p0,
+             void* stream) {
+    int rc = validate(p);
+    if (rc) return rc;
+    if (!state || !phi0) return LBM_E_NULL;
+    if ((uintptr_t)state % 256) return LBM_E_SIZE;
+    Layout L = layout_of(p);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e;
+    if (p->dtype == LBM_F32)
+        e = launch_init<float>(resolve<float>(p, L), (char*)state, L, (const float*)phi0, (const float*)u0,
+                               (const float*)p0, p->dtype, s);
+    else
+        e = launch_init<double>(resolve<double>(p, L), (char*)state, L, (const double*)phi0,
+                                (const double*)u0, (const double*)p0, p->dtype, s);
+    return e == hipSuccess ? LBM_OK : hip_fail(e);
+}
+
+int lbm_step(const lbm_params* p, void* state, int64_t nsteps, void* stream) {
+    int rc = validate(p);
+    if (rc) return rc;
+    if (!state) return LBM_E_NULL;
+    if (nsteps < 0) return LBM_E_SIZE;
+    Layout L = layout_of(p);
+    hipStream_t s = (hipStream_t)stream;
+    int ty = step_tile_rows(p);
+    hipError_t e;
+    if (p->dtype == LBM_F32)
+        e = launch_step<float>(resolve<float>(p, L), (char*)state, L, nsteps, s, ty);
+    else
+        e = launch_step<double>(resolve<double>(p, L), (char*)state, L, nsteps, s, ty);
+    return e == hipSuccess ? LBM_OK : hip_fail(e);
+}
+
+int lbm_moments(const lbm_params* p, const void* state, void* phi, void* u, void* pr, void* stream) {
+    int rc = validate(p);
+    if (rc) return rc;
+    if (!state) return LBM_E_NULL;
+    Layout L = layout_of(p);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e;
+    if (p->dtype == LBM_F32)
+        e = launch_moments<float>(resolve<float>(p, L), (const char*)state, L, (float*)phi, (float*)u,
+                                  (float*)pr, s);
+    else
+        e = launch_moments<double>(resolve<double>(p, L), (const char*)state, L, (double*)phi, (double*)u,
+                                   (double*)pr, s);
+    return e == hipSuccess ? LBM_OK : hip_fail(e);
+}
+
+int lbm_diagnostics(const lbm_params* p, const void* state, double* out, void* stream) {
+    int rc = validate(p);
+    if (rc) return rc;
+    if (!state || !out) return LBM_E_NULL;
+    Layout L = layout_of(p);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e;
+    if (p->dtype == LBM_F32)
+        e = launch_diagnostics<float>(resolve<float>(p, L), (const char*)state, L, out, s);
+    else
+        e = launch_diagnostics<double>(resolve<double>(p, L), (const char*)state, L, out, s);
+    if (e != hipSuccess) return hip_fail(e);
+    return out[5] != 0.0 ? LBM_E_NONFINITE : LBM_OK;
+}
+
+int lbm_export_state(const lbm_params* p, const void* state, void* f, void* g, void* hist, int64_t* step,
+                     void* stream) {
+    int rc = validate(p);
+    if (rc) return rc;
+    if (!state) return LBM_E_NULL;
+    Layout L = layout_of(p);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipSuccess;
+    if (f || g || hist) {
+        if (p->dtype == LBM_F32)
+            e = launch_export<float>(resolve<float>(p, L), (const char*)state, L, (float*)f, (float*)g,
+                                     (float*)hist, s);
+        else
+            e = launch_export<double>(resolve<double>(p, L), (const char*)state, L, (double*)f, (double*)g,
+                                      (double*)hist, s);
+        if (e != hipSuccess) return hip_fail(e);
+    }
+    if (step) {
+        e = hipMemcpyAsync(step, state, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(e);
+    }
+    return LBM_OK;
+}
+
+int lbm_import_state(const lbm_params* p, void* state, const void* f, const void* g, const void* hist,
+                     int64_t step, void* stream) {
+    int rc = validate(p);
+    if (rc) return rc;
+    if (!state || !f || !g) return LBM_E_NULL;
+    if (step < 0) return LBM_E_SIZE;
+    if (step > 0 && !hist) return LBM_E_NULL;
+    if ((uintptr_t)state % 256) return LBM_E_SIZE;
+    Layout L = layout_of(p);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e;
+    if (p->dtype == LBM_F32)
+        e = launch_import<float>(resolve<float>(p, L), (char*)state, L, (const float*)f, (const float*)g,
+                                 (const float*)hist, step, p->dtype, s);
+    else
+        e = launch_import<double>(resolve<double>(p, L), (char*)state, L, (const double*)f,
+                                  (const double*)g, (const double*)hist, step, p->dtype, s);
+    return e == hipSuccess ? LBM_OK : hip_fail(e);
+}
+
+}  // extern "C"

@@ -1,0 +1,114 @@
+// lbm_common.hpp -- shared definitions of the gfx950 phase-field LBM kernels.
+//
+// Lattice units (dx = dt = c = 1, cs^2 = 1/3).  D2Q9 velocities in the column
+// order of M1 (App. C): c0..c8 = (0,0),(1,0),(0,1),(-1,0),(0,-1),(1,1),(-1,1),
+// (-1,-1),(1,-1).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+constexpr int Q = 9;
+constexpr int HDR_BYTES = 256;     // state header
+constexpr uint32_t STATE_MAGIC = 0x4C424D32u;  // "LBM2"
+
+__host__ __device__ constexpr int cx(int i) {
+    return i == 1 || i == 5 || i == 8 ? 1 : (i == 3 || i == 6 || i == 7 ? -1 : 0);
+}
+__host__ __device__ constexpr int cy(int i) {
+    return i == 2 || i == 5 || i == 6 ? 1 : (i == 4 || i == 7 || i == 8 ? -1 : 0);
+}
+__host__ __device__ constexpr int opp(int i) {
+    return i == 0 ? 0 : (i <= 4 ? ((i + 1) % 4) + 1 : ((i - 3) % 4) + 5);
+}
+static_assert(opp(1) == 3 && opp(2) == 4 && opp(3) == 1 && opp(4) == 2, "opp axis");
+static_assert(opp(5) == 7 && opp(6) == 8 && opp(7) == 5 && opp(8) == 6, "opp diag");
+
+// Device-side header at the start of every state buffer.  `step` is the index
+// n of the current time level; ping-pong buffer n & 1 holds the post-collision
+// populations of level n-1 (streamed by pulling) and the level n-1 history.
+struct StateHeader {
+    int64_t step;
+    uint32_t done;      // blocks of the running step kernel that have finished
+    uint32_t magic;
+    int32_t nx, ny, dtype, pad;
+};
+
+// Parameters resolved on the host and passed by value to every kernel.
+template <typename T>
+struct KParams {
+    int nx, ny;
+    int wall_x, wall_y;
+    int visc_law, model;
+    int snu_local;        // s_g^7 = s_g^8 follow nu(phi)
+    int pad0;
+    long long plane;      // elements between two population planes
+    T phiA, phiB, phim;   // phim = (phiA + phiB) / 2
+    T beta4, kap;         // 4 beta, k (Sec. 2)
+    T lamc;               // sqrt(2 beta / k) = 4 / (W dphi)
+    T drho, rhoB;         // drho/dphi, rho_B
+    T drhoM;              // drho/dphi * M_phi
+    T inv_dphi;
+    T muA, muB;           // linear-mu law
+    T inv_nuA, inv_nuB;   // inverse-nu law
+    T sf[9], sg[9];
+    T Gx, Gy, gx, gy, rho_ref;
+    T wa[4], wb[4], wc0[4];  // wetting quadratic per wall (x-, x+, y-, y+): a, b, a phiA phiB
+    T rho0, eps2;
+    T Hp;                 // H of App. C: (s_g^2 - s_g^0)/(9 s_g^0 s_g^2)
+};
+
+// One ping-pong copy of the state.  The rest population of f is kept in FP64
+// whatever the element type T: after each collision it is set to phi minus
+// the eight moving populations in double precision, so the total of phi is
+// conserved to double rounding even when the moving populations are FP32.
+// Planes: f0 (double) | f_1..f_8 | g_0..g_8 | hist phi, u, v (previous level).
+template <typename T>
+struct Copy {
+    double* f0;
+    T* f;   // f + i * plane is plane i, i = 1..8 (the pointer sits one plane before f_1)
+    T* g;   // g + i * plane, i = 0..8
+    T* h;   // h + j * plane, j = 0..2
+};
+
+template <typename T>
+__host__ __device__ inline Copy<T> copy_at(char* base, long long plane) {
+    Copy<T> c;
+    c.f0 = reinterpret_cast<double*>(base);
+    T* fm = reinterpret_cast<T*>(base + 8 * plane);
+    c.f = fm - plane;
+    c.g = fm + 8 * plane;
+    c.h = fm + 17 * plane;
+    return c;
+}
+
+// Byte layout of a state buffer.
+struct Layout {
+    long long n;          // nodes
+    long long plane;      // padded plane length (elements)
+    size_t esz;           // element size
+    size_t buf_bytes;     // one ping-pong copy: f0 (FP64), f[1..8], g[9], hist[3] planes
+    size_t off_buf[2];
+    size_t off_diag;      // diagnostics scratch: 3 planes (m^phiC, local S_m), partials, result
+    size_t diag_partials; // number of double slots for block partials
+    size_t total;
+};
+
+inline Layout make_layout(int nx, int ny, size_t esz, size_t diag_blocks) {
+    Layout L;
+    L.n = (long long)nx * ny;
+    L.plane = (L.n + 63) / 64 * 64;
+    L.esz = esz;
+    L.buf_bytes = (size_t)8 * L.plane + (size_t)20 * L.plane * esz;
+    L.off_buf[0] = HDR_BYTES;
+    L.off_buf[1] = L.off_buf[0] + L.buf_bytes;
+    L.off_diag = L.off_buf[1] + L.buf_bytes;
+    L.diag_partials = diag_blocks * 8;
+    size_t diag = (size_t)3 * L.plane * esz + L.diag_partials * sizeof(double) + 16 * sizeof(double);
+    L.total = L.off_diag + (diag + 255) / 256 * 256;
+    return L;
+}
+
+}  // namespace lbm

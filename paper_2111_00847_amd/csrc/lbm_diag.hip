@@ -1,0 +1,196 @@
+// lbm_diag.hip -- diagnostics of the current level (Sec. 4.1): sum of phi,
+// div u = tr S from the local strain rate (Eq. strainRate), the mass source
+// S_m = d_t rho + div m^CC with div m^phiC from the isotropic stencil
+// (Eq. central1), max |u| and a non-finite flag.
+//
+// Pass 1 (tile kernel): per-node quantities; m^phiC and the local part of S_m
+// go to scratch planes; per-workgroup partial sums/maxima in FP64.
+// Pass 2 (tile kernel): div m^phiC from the scratch planes, S_m^2 partials.
+// Pass 3 (one workgroup): fixed-order reduction of the partials.  Every
+// reduction has a fixed order, so results are bitwise reproducible.
+#include "lbm_kernels.hpp"
+#include "lbm_tile.hpp"
+
+namespace lbm {
+
+constexpr int DTY = 8;   // tile rows of the diagnostics kernels
+
+// Block-wide reduction of NV values (sum when is_max[j] == 0, else max) into
+// thread 0; fixed tree order.
+template <int NV>
+__device__ void block_reduce(double* v, const bool* is_max, double (*red)[NV]) {
+    const int tid = threadIdx.y * TX + threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < NV; j++)
+        for (int off = 32; off > 0; off >>= 1) {
+            double o = __shfl_xor(v[j], off, 64);
+            v[j] = is_max[j] ? fmax(v[j], o) : v[j] + o;
+        }
+    const int lane = tid & 63, wave = tid >> 6;
+    if (lane == 0)
+        for (int j = 0; j < NV; j++) red[wave][j] = v[j];
+    __syncthreads();
+    if (tid == 0) {
+        for (int j = 0; j < NV; j++) {
+            double a = red[0][j];
+            for (int w = 1; w < BY; w++) a = is_max[j] ? fmax(a, red[w][j]) : a + red[w][j];
+            v[j] = a;
+        }
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(TX* BY) void k_diag1(KParams<T> P, const char* state, size_t off0,
+                                                  size_t off1, T* scr, double* partials) {
+    __shared__ T sphi[DTY + 2][TX + 3];
+    __shared__ T sphp[DTY + 2][TX + 3];
+    __shared__ double red[BY][5];
+    const StateHeader* H = reinterpret_cast<const StateHeader*>(state);
+    const int64_t step = H->step;
+    const bool first = step == 0;
+    const int cur = (int)(step & 1);
+    const Copy<T> S = copy_at<T>(const_cast<char*>(state) + (cur ? off1 : off0), P.plane);
+    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * DTY;
+    fill_window<T, DTY>(P, S, true, x0, y0, sphi, sphp);
+
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // sum phi, max|div|, sum div^2, max|u|, nonfinite
+    for (int r = 0; r < DTY / BY; r++) {
+        const int lx = threadIdx.x, ly = threadIdx.y + r * BY;
+        const int x = x0 + lx, y = y0 + ly;
+        if (x >= P.nx || y >= P.ny) continue;
+        const long long k = (long long)y * P.nx + x;
+        T f[9], g[9];
+        const double phid = node_phi(P, S, x, y, f);
+        bool bad = !isfinite(phid);
+        for (int i = 0; i < Q; i++) {
+            g[i] = pull(S.g, P, i, x, y);
+            bad = bad || !isfinite(f[i]) || !isfinite(g[i]);
+        }
+        T gx, gy, lap, gxp = T(0), gyp = T(0), lp, php = sphp[ly + 1][lx + 1], up = T(0), vp = T(0);
+        win_stencil<T, DTY>(sphi, lx + 1, ly + 1, gx, gy, lap);
+        if (!first) {
+            win_stencil<T, DTY>(sphp, lx + 1, ly + 1, gxp, gyp, lp);
+            up = S.h[P.plane + k];
+            vp = S.h[2 * P.plane + k];
+        }
+        Macro<T> M = macro(P, g, sphi[ly + 1][lx + 1], gx, gy, lap, first, php, gxp, gyp, up, vp);
+        // g^eq of the current level (Eq. MgMF1 inverted through M1)
+        const T u = M.u, v = M.v, rho = M.rho;
+        T tr = T(3) * rho * (u * u + v * v) + T(3) * (u * M.mx + v * M.my);
+        T meq[9] = {P.rho0, T(-4) * P.rho0 + T(6) * M.p + tr, T(4) * P.rho0 - T(9) * M.p - tr,
+                    rho * u, -rho * u, rho * v, -rho * v,
+                    (u * M.mx - v * M.my) + rho * (u * u - v * v),
+                    T(0.5) * ((u * M.my + v * M.mx) + T(2) * rho * u * v)};
+        T geq[9];
+        from_moments(meq, geq);
+        T s = T(0);
+        for (int i = 1; i < Q; i++) s += T(cx(i) * cx(i) + cy(i) * cy(i)) * (g[i] - geq[i]);
+        T ugr = u * M.drx + v * M.dry;
+        T trM2F = T(2) * (u * M.Fx + v * M.Fy) + (M.d2 + M.d3) + (T(4) / T(3)) * ugr;
+        // tr S = -s_2 / (2 rho cs^2) [sum |c|^2 (g - g^eq) + tr M_2F / 2]
+        T div = -(T(1.5) * M.snu / rho) * (s + T(0.5) * trM2F);
+        T rho_prev = P.drho * (php - P.phiB) + P.rhoB;
+        T dtr = first ? T(0) : rho - rho_prev;
+        scr[k] = M.mx;
+        scr[P.plane + k] = M.my;
+        scr[2 * P.plane + k] = dtr + rho * div + ugr;
+        acc[0] += phid;
+        acc[1] = fmax(acc[1], fabs((double)div));
+        acc[2] += (double)div * (double)div;
+        acc[3] = fmax(acc[3], sqrt((double)u * (double)u + (double)v * (double)v));
+        if (bad) acc[4] = 1.0;
+    }
+    const bool is_max[5] = {false, true, false, true, true};
+    block_reduce<5>(acc, is_max, red);
+    const int b = blockIdx.y * gridDim.x + blockIdx.x;
+    if (threadIdx.x == 0 && threadIdx.y == 0)
+        for (int j = 0; j < 5; j++) partials[b * 8 + j] = acc[j];
+}
+
+template <typename T>
+__global__ __launch_bounds__(TX* BY) void k_diag2(KParams<T> P, const T* scr, double* partials) {
+    __shared__ double red[BY][2];
+    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * DTY;
+    double acc[2] = {0.0, 0.0};   // sum S_m^2, count
+    for (int r = 0; r < DTY / BY; r++) {
+        const int x = x0 + threadIdx.x, y = y0 + threadIdx.y + r * BY;
+        if (x >= P.nx || y >= P.ny) continue;
+        bool ok = true;
+        T dmx = T(0), dmy = T(0);
+        for (int i = 1; i < Q; i++) {
+            int tx = x + cx(i), ty = y + cy(i);
+            if (tx < 0 || tx >= P.nx) {
+                if (P.wall_x) ok = false;
+                tx = tx < 0 ? tx + P.nx : tx - P.nx;
+            }
+            if (ty < 0 || ty >= P.ny) {
+                if (P.wall_y) ok = false;
+                ty = ty < 0 ? ty + P.ny : ty - P.ny;
+            }
+            if (!ok) break;
+            const long long t = (long long)ty * P.nx + tx;
+            const T w = i <= 4 ? T(1) / T(9) : T(1) / T(36);
+            dmx += w * T(cx(i)) * scr[t];
+            dmy += w * T(cy(i)) * scr[P.plane + t];
+        }
+        if (!ok) continue;
+        const long long k = (long long)y * P.nx + x;
+        double sm = (double)(scr[2 * P.plane + k] + T(3) * (dmx + dmy));
+        acc[0] += sm * sm;
+        acc[1] += 1.0;
+    }
+    const bool is_max[2] = {false, false};
+    block_reduce<2>(acc, is_max, red);
+    const int b = blockIdx.y * gridDim.x + blockIdx.x;
+    if (threadIdx.x == 0 && threadIdx.y == 0) {
+        partials[b * 8 + 5] = acc[0];
+        partials[b * 8 + 6] = acc[1];
+    }
+}
+
+// One workgroup: sequential sums over the partial records in block order.
+__global__ void k_diag3(const double* partials, int nblocks, long long n, double* out) {
+    if (threadIdx.x != 0) return;
+    double sphi = 0, mdiv = 0, sdiv = 0, umax = 0, bad = 0, ssm = 0, cnt = 0;
+    for (int b = 0; b < nblocks; b++) {
+        const double* r = partials + b * 8;
+        sphi += r[0];
+        mdiv = fmax(mdiv, r[1]);
+        sdiv += r[2];
+        umax = fmax(umax, r[3]);
+        bad = fmax(bad, r[4]);
+        ssm += r[5];
+        cnt += r[6];
+    }
+    out[0] = sphi;
+    out[1] = mdiv;
+    out[2] = sqrt(sdiv / (double)n);
+    out[3] = cnt > 0 ? sqrt(ssm / cnt) : 0.0;
+    out[4] = umax;
+    out[5] = bad;
+}
+
+template <typename T>
+hipError_t launch_diagnostics(const KParams<T>& P, const char* state, const Layout& L, double* host_out,
+                              hipStream_t s) {
+    dim3 blk(TX, BY);
+    dim3 grd((P.nx + TX - 1) / TX, (P.ny + DTY - 1) / DTY);
+    T* scr = reinterpret_cast<T*>(const_cast<char*>(state) + L.off_diag);
+    double* partials = reinterpret_cast<double*>(const_cast<char*>(state) + L.off_diag + 3 * L.plane * L.esz);
+    double* out = partials + L.diag_partials;
+    k_diag1<T><<<grd, blk, 0, s>>>(P, state, L.off_buf[0], L.off_buf[1], scr, partials);
+    k_diag2<T><<<grd, blk, 0, s>>>(P, scr, partials);
+    k_diag3<<<1, 64, 0, s>>>(partials, (int)(grd.x * grd.y), L.n, out);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(host_out, out, 6 * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(s);
+}
+
+template hipError_t launch_diagnostics<float>(const KParams<float>&, const char*, const Layout&, double*,
+                                              hipStream_t);
+template hipError_t launch_diagnostics<double>(const KParams<double>&, const char*, const Layout&, double*,
+                                               hipStream_t);
+
+}  // namespace lbm

@@ -1,0 +1,28 @@
+// lbm_kernels.hpp -- host-side launchers of the gfx950 kernels.
+#pragma once
+
+#include "lbm_common.hpp"
+
+namespace lbm {
+
+template <typename T>
+hipError_t launch_step(const KParams<T>& P, char* state, const Layout& L, int64_t nsteps, hipStream_t s,
+                       int ty);
+template <typename T>
+hipError_t launch_moments(const KParams<T>& P, const char* state, const Layout& L, T* phi, T* u, T* p,
+                          hipStream_t s);
+template <typename T>
+hipError_t launch_init(const KParams<T>& P, char* state, const Layout& L, const T* phi0, const T* u0,
+                       const T* p0, int dtype, hipStream_t s);
+template <typename T>
+hipError_t launch_import(const KParams<T>& P, char* state, const Layout& L, const T* f, const T* g,
+                         const T* hist, int64_t step, int dtype, hipStream_t s);
+template <typename T>
+hipError_t launch_export(const KParams<T>& P, const char* state, const Layout& L, T* f, T* g, T* hist,
+                         hipStream_t s);
+template <typename T>
+hipError_t launch_diagnostics(const KParams<T>& P, const char* state, const Layout& L, double* host_out,
+                              hipStream_t s);
+hipError_t launch_read_step(const char* state, int64_t* dev_out, hipStream_t s);
+
+}  // namespace lbm

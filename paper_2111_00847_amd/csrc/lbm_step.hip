@@ -1,0 +1,305 @@
+// lbm_step.hip -- gfx950 kernels of the fused phase-field LBM time step.
+//
+// Memory layout (structure of arrays, x fastest): a state buffer is
+//   [header | copy 0: f[9] g[9] hist[3] | copy 1: same | diagnostics scratch]
+// with every plane padded to a multiple of 64 elements.  Copy (n & 1) holds
+// the post-collision populations of level n-1 -- a node obtains its level-n
+// populations by pulling them from its neighbours -- and hist = (phi, u, v)
+// of level n-1, from which the explicit-Euler time derivatives are formed.
+// A step reads copy (n & 1) and writes copy (1 - n & 1); the last workgroup
+// to finish advances the header's step counter, so host code never has to
+// know the parity and a sequence of steps can be captured in a graph.
+//
+// The phi stencils need phi on a one-node ring around each tile.  A tile of
+// 64 x TY nodes (256 threads) first pulls the populations of its (64+2) x
+// (TY+2) window, sums them into phi in LDS (the ring's pulls hit L2: those
+// lines are the neighbour tiles' own reads), fills wall ghosts, and then each
+// thread runs the per-node update for TY/4 nodes of its column.
+#include "lbm_kernels.hpp"
+#include "lbm_tile.hpp"
+
+namespace lbm {
+
+// MODE 0: one time step.  MODE 1: write phi, u, p of the current level.
+template <typename T, int TY, int MODE>
+__global__ __launch_bounds__(TX* BY) void k_step(KParams<T> P, char* state, size_t off0, size_t off1,
+                                                 T* out_phi, T* out_u, T* out_p) {
+    __shared__ T sphi[TY + 2][TX + 3];
+    __shared__ T sphp[TY + 2][TX + 3];
+    StateHeader* H = reinterpret_cast<StateHeader*>(state);
+    const int64_t step = H->step;
+    const bool first = step == 0;
+    const int cur = (int)(step & 1);
+    const Copy<T> S = copy_at<T>(state + (cur ? off1 : off0), P.plane);
+    const Copy<T> D = copy_at<T>(state + (cur ? off0 : off1), P.plane);
+    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+
+    fill_window<T, TY>(P, S, !first, x0, y0, sphi, sphp);
+
+#pragma unroll 1
+    for (int r = 0; r < TY / BY; r++) {
+        const int lx = threadIdx.x, ly = threadIdx.y + r * BY;
+        const int x = x0 + lx, y = y0 + ly;
+        if (x >= P.nx || y >= P.ny) continue;
+        const long long k = (long long)y * P.nx + x;
+        T f[9], g[9];
+        const double phid = node_phi(P, S, x, y, f);
+#pragma unroll
+        for (int i = 0; i < Q; i++) g[i] = pull(S.g, P, i, x, y);
+        T gx, gy, lap, gxp = T(0), gyp = T(0), lp, php = T(0), up = T(0), vp = T(0);
+        win_stencil<T, TY>(sphi, lx + 1, ly + 1, gx, gy, lap);
+        if (!first) {
+            win_stencil<T, TY>(sphp, lx + 1, ly + 1, gxp, gyp, lp);
+            php = sphp[ly + 1][lx + 1];
+            up = S.h[P.plane + k];
+            vp = S.h[2 * P.plane + k];
+        }
+        Macro<T> M = macro(P, g, sphi[ly + 1][lx + 1], gx, gy, lap, first, php, gxp, gyp, up, vp);
+        if (MODE == 1) {
+            if (out_phi) out_phi[k] = M.phi;
+            if (out_u) {
+                out_u[k] = M.u;
+                out_u[P.nx * (long long)P.ny + k] = M.v;
+            }
+            if (out_p) out_p[k] = M.p;
+            continue;
+        }
+        D.f0[k] = collide_f(P, M, f, phid, (uint32_t)k, (uint32_t)step);
+        collide_g(P, M, g, (uint32_t)k, (uint32_t)step);
+#pragma unroll
+        for (int i = 1; i < Q; i++) D.f[i * P.plane + k] = f[i];
+#pragma unroll
+        for (int i = 0; i < Q; i++) D.g[i * P.plane + k] = g[i];
+        D.h[k] = M.phi;
+        D.h[P.plane + k] = M.u;
+        D.h[2 * P.plane + k] = M.v;
+    }
+    if (MODE == 0) finish_step(H, step);
+}
+
+// ---------------------------------------------------------------- init / import / export
+// phi at (x, y) of a caller field, extended by the lattice's ghost rule:
+// periodic axes wrap; x-wall ghosts from the row, y-wall ghosts from the
+// (possibly x-ghost) column -- the same order as the LDS window.
+template <typename T>
+__device__ T field_at(const KParams<T>& P, const T* phi, int x, int y) {
+    if (!P.wall_x && (x < 0 || x >= P.nx)) x = x < 0 ? x + P.nx : x - P.nx;
+    if (!P.wall_y && (y < 0 || y >= P.ny)) y = y < 0 ? y + P.ny : y - P.ny;
+    auto col = [&](int xx, int yy) -> T {
+        const T* row = phi + (long long)yy * P.nx;
+        if (xx < 0) return wet_ghost(P, 0, row[0], row[1]);
+        if (xx >= P.nx) return wet_ghost(P, 1, row[P.nx - 1], row[P.nx - 2]);
+        return row[xx];
+    };
+    if (y < 0) return wet_ghost(P, 2, col(x, 0), col(x, 1));
+    if (y >= P.ny) return wet_ghost(P, 3, col(x, P.ny - 1), col(x, P.ny - 2));
+    return col(x, y);
+}
+
+// Equilibria at every node into `eq` (f^eq planes 0..8, g^eq planes 9..17).
+template <typename T>
+__global__ void k_equilibrium(KParams<T> P, const T* phi0, const T* u0, const T* p0, T* eq) {
+    const long long n = (long long)P.nx * P.ny;
+    for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n;
+         k += (long long)gridDim.x * blockDim.x) {
+        const int y = (int)(k / P.nx), x = (int)(k - (long long)y * P.nx);
+        T n_[3][3];
+        for (int j = 0; j < 3; j++)
+            for (int i = 0; i < 3; i++) n_[j][i] = field_at(P, phi0, x + i - 1, y + j - 1);
+        T gx, gy, lap;
+        stencil(n_[0][0], n_[0][1], n_[0][2], n_[1][0], n_[1][1], n_[1][2], n_[2][0], n_[2][1], n_[2][2],
+                gx, gy, lap);
+        const T phi = n_[1][1];
+        const T u = u0 ? u0[k] : T(0), v = u0 ? u0[n + k] : T(0), p = p0 ? p0[k] : T(0);
+        T lnx, lny, mx, my;
+        mass_flux(P, phi, gx, gy, lnx, lny, mx, my);
+        const T rho = P.drho * (phi - P.phiB) + P.rhoB;
+        T m[9], e[9];
+        T mf[9] = {phi, T(-2) * phi, phi, phi * u, -phi * u, phi * v, -phi * v, T(0), T(0)};
+        from_moments(mf, e);
+        for (int i = 0; i < Q; i++) eq[i * P.plane + k] = e[i];
+        T tr = T(3) * rho * (u * u + v * v) + T(3) * (u * mx + v * my);
+        m[0] = P.rho0;
+        m[1] = T(-4) * P.rho0 + T(6) * p + tr;
+        m[2] = T(4) * P.rho0 - T(9) * p - tr;
+        m[3] = rho * u;
+        m[4] = -rho * u;
+        m[5] = rho * v;
+        m[6] = -rho * v;
+        m[7] = (u * mx - v * my) + rho * (u * u - v * v);
+        m[8] = T(0.5) * ((u * my + v * mx) + T(2) * rho * u * v);
+        from_moments(m, e);
+        for (int i = 0; i < Q; i++) eq[(9 + i) * P.plane + k] = e[i];
+    }
+}
+
+// Store post-streaming populations `post` (planes 0..17, level n) into the
+// pull representation of copy `dst`: slot (i, y) holds what (y + c_i) pulls,
+// or -- when y + c_i is beyond a wall -- what y itself pulls in direction
+// opp(i).  `post_stride` is the plane stride of `post`.
+template <typename T>
+__global__ void k_to_pull(KParams<T> P, const T* post, long long post_stride, char* dst_base) {
+    const Copy<T> D = copy_at<T>(dst_base, P.plane);
+    const long long n = (long long)P.nx * P.ny;
+    for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n;
+         k += (long long)gridDim.x * blockDim.x) {
+        const int y = (int)(k / P.nx), x = (int)(k - (long long)y * P.nx);
+        for (int h = 0; h < 2; h++) {
+            const T* src = post + h * 9 * post_stride;
+            for (int i = 0; i < Q; i++) {
+                int tx = x + cx(i), ty = y + cy(i);
+                bool wall = false;
+                if (tx < 0 || tx >= P.nx) {
+                    if (P.wall_x) wall = true;
+                    else tx = tx < 0 ? tx + P.nx : tx - P.nx;
+                }
+                if (ty < 0 || ty >= P.ny) {
+                    if (P.wall_y) wall = true;
+                    else ty = ty < 0 ? ty + P.ny : ty - P.ny;
+                }
+                T val = wall ? src[opp(i) * post_stride + k] : src[i * post_stride + (long long)ty * P.nx + tx];
+                if (h == 1) D.g[i * P.plane + k] = val;
+                else if (i == 0) D.f0[k] = (double)val;
+                else D.f[i * P.plane + k] = val;
+            }
+        }
+    }
+}
+
+template <typename T>
+__global__ void k_export(KParams<T> P, char* state, size_t off0, size_t off1, T* f, T* g, T* hist) {
+    const StateHeader* H = reinterpret_cast<const StateHeader*>(state);
+    const int cur = (int)(H->step & 1);
+    const Copy<T> S = copy_at<T>(state + (cur ? off1 : off0), P.plane);
+    const long long n = (long long)P.nx * P.ny;
+    for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n;
+         k += (long long)gridDim.x * blockDim.x) {
+        const int y = (int)(k / P.nx), x = (int)(k - (long long)y * P.nx);
+        if (f) {
+            f[k] = (T)S.f0[k];
+            for (int i = 1; i < Q; i++) f[i * n + k] = pull(S.f, P, i, x, y);
+        }
+        if (g)
+            for (int i = 0; i < Q; i++) g[i * n + k] = pull(S.g, P, i, x, y);
+        if (hist)
+            for (int j = 0; j < 3; j++) hist[j * n + k] = S.h[j * P.plane + k];
+    }
+}
+
+template <typename T>
+__global__ void k_copy_hist(KParams<T> P, const T* hist, char* dst_base) {
+    const Copy<T> D = copy_at<T>(dst_base, P.plane);
+    const long long n = (long long)P.nx * P.ny;
+    for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n;
+         k += (long long)gridDim.x * blockDim.x)
+        for (int j = 0; j < 3; j++) D.h[j * P.plane + k] = hist ? hist[j * n + k] : T(0);
+}
+
+__global__ void k_set_header(StateHeader* H, int64_t step, int nx, int ny, int dtype) {
+    atomicExch(reinterpret_cast<unsigned long long*>(&H->step), static_cast<unsigned long long>(step));
+    atomicExch(&H->done, 0u);
+    atomicExch(&H->magic, STATE_MAGIC);
+    atomicExch(reinterpret_cast<unsigned*>(&H->nx), (unsigned)nx);
+    atomicExch(reinterpret_cast<unsigned*>(&H->ny), (unsigned)ny);
+    atomicExch(reinterpret_cast<unsigned*>(&H->dtype), (unsigned)dtype);
+}
+
+__global__ void k_read_step(const StateHeader* H, int64_t* out) { *out = H->step; }
+
+// ---------------------------------------------------------------- launchers
+static int grid1d(long long n) {
+    long long b = (n + 255) / 256;
+    return (int)(b < 65536 ? (b > 0 ? b : 1) : 65536);
+}
+
+template <typename T>
+hipError_t launch_step(const KParams<T>& P, char* state, const Layout& L, int64_t nsteps, hipStream_t s,
+                       int ty) {
+    dim3 blk(TX, BY);
+    for (int64_t t = 0; t < nsteps; t++) {
+        if (ty == 4) {
+            dim3 grd((P.nx + TX - 1) / TX, (P.ny + 3) / 4);
+            k_step<T, 4, 0><<<grd, blk, 0, s>>>(P, state, L.off_buf[0], L.off_buf[1], nullptr, nullptr, nullptr);
+        } else if (ty == 8) {
+            dim3 grd((P.nx + TX - 1) / TX, (P.ny + 7) / 8);
+            k_step<T, 8, 0><<<grd, blk, 0, s>>>(P, state, L.off_buf[0], L.off_buf[1], nullptr, nullptr, nullptr);
+        } else {
+            dim3 grd((P.nx + TX - 1) / TX, (P.ny + 15) / 16);
+            k_step<T, 16, 0><<<grd, blk, 0, s>>>(P, state, L.off_buf[0], L.off_buf[1], nullptr, nullptr, nullptr);
+        }
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_moments(const KParams<T>& P, const char* state, const Layout& L, T* phi, T* u, T* p,
+                          hipStream_t s) {
+    dim3 blk(TX, BY);
+    dim3 grd((P.nx + TX - 1) / TX, (P.ny + 7) / 8);
+    k_step<T, 8, 1><<<grd, blk, 0, s>>>(P, const_cast<char*>(state), L.off_buf[0], L.off_buf[1], phi, u, p);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_init(const KParams<T>& P, char* state, const Layout& L, const T* phi0, const T* u0,
+                       const T* p0, int dtype, hipStream_t s) {
+    T* scratch = reinterpret_cast<T*>(state + L.off_buf[1]);   // 18 planes of T fit in one copy
+    char* dst = state + L.off_buf[0];
+    int g = grid1d(L.n);
+    k_equilibrium<T><<<g, 256, 0, s>>>(P, phi0, u0, p0, scratch);
+    k_to_pull<T><<<g, 256, 0, s>>>(P, scratch, P.plane, dst);
+    k_copy_hist<T><<<g, 256, 0, s>>>(P, nullptr, dst);
+    k_set_header<<<1, 1, 0, s>>>(reinterpret_cast<StateHeader*>(state), 0, P.nx, P.ny, dtype);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_import(const KParams<T>& P, char* state, const Layout& L, const T* f, const T* g,
+                         const T* hist, int64_t step, int dtype, hipStream_t s) {
+    // f and g are separate caller arrays of [9][n]; stage them contiguously in
+    // the other copy, which the next step overwrites anyway.
+    int cur = (int)(step & 1);
+    char* dst = state + L.off_buf[cur];
+    T* stage = reinterpret_cast<T*>(state + L.off_buf[1 - cur]);
+    size_t bytes9 = (size_t)9 * L.n * sizeof(T);
+    hipError_t e = hipMemcpy2DAsync(stage, (size_t)P.plane * sizeof(T), f, (size_t)L.n * sizeof(T),
+                                    (size_t)L.n * sizeof(T), 9, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return e;
+    e = hipMemcpy2DAsync(stage + 9 * P.plane, (size_t)P.plane * sizeof(T), g, (size_t)L.n * sizeof(T),
+                         (size_t)L.n * sizeof(T), 9, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return e;
+    (void)bytes9;
+    int gr = grid1d(L.n);
+    k_to_pull<T><<<gr, 256, 0, s>>>(P, stage, P.plane, dst);
+    k_copy_hist<T><<<gr, 256, 0, s>>>(P, step > 0 ? hist : nullptr, dst);
+    k_set_header<<<1, 1, 0, s>>>(reinterpret_cast<StateHeader*>(state), step, P.nx, P.ny, dtype);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_export(const KParams<T>& P, const char* state, const Layout& L, T* f, T* g, T* hist,
+                         hipStream_t s) {
+    k_export<T><<<grid1d(L.n), 256, 0, s>>>(P, const_cast<char*>(state), L.off_buf[0], L.off_buf[1], f, g, hist);
+    return hipGetLastError();
+}
+
+hipError_t launch_read_step(const char* state, int64_t* dev_out, hipStream_t s) {
+    k_read_step<<<1, 1, 0, s>>>(reinterpret_cast<const StateHeader*>(state), dev_out);
+    return hipGetLastError();
+}
+
+#define LBM_INSTANTIATE(T)                                                                              \
+    template hipError_t launch_step<T>(const KParams<T>&, char*, const Layout&, int64_t, hipStream_t, int); \
+    template hipError_t launch_moments<T>(const KParams<T>&, const char*, const Layout&, T*, T*, T*,     \
+                                          hipStream_t);                                                 \
+    template hipError_t launch_init<T>(const KParams<T>&, char*, const Layout&, const T*, const T*,     \
+                                       const T*, int, hipStream_t);                                     \
+    template hipError_t launch_import<T>(const KParams<T>&, char*, const Layout&, const T*, const T*,   \
+                                         const T*, int64_t, int, hipStream_t);                          \
+    template hipError_t launch_export<T>(const KParams<T>&, const char*, const Layout&, T*, T*, T*,     \
+                                         hipStream_t);
+
+LBM_INSTANTIATE(float)
+LBM_INSTANTIATE(double)
+
+}  // namespace lbm

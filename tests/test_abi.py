@@ -1,0 +1,92 @@
+"""The C ABI library: loads, exports every declared entry point, validates
+parameters on the host (no GPU needed: validation returns before any HIP call)."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "lbm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2111_00847_amd import _lib
+    L = ctypes.CDLL(_lib.LIB_PATH)
+    names = _declared()
+    assert "lbm_step" in names and "lbm_init" in names
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_struct_size_matches_header():
+    """The ctypes mirror of lbm_params has the C layout (8 int32 + 45 doubles)."""
+    from paper_2111_00847_amd._lib import LbmParams
+    assert ctypes.sizeof(LbmParams) == 8 * 4 + (10 + 18 + 2 + 2 + 1 + 4 + 2) * 8
+
+
+def _params(**kw):
+    from paper_2111_00847_amd import api
+    case, _ = W.square_droplet()
+    return api.make_params(case.replace(**kw))
+
+
+def _size(p):
+    from paper_2111_00847_amd._lib import lib
+    n = ctypes.c_size_t()
+    return lib().lbm_state_size(ctypes.byref(p), ctypes.byref(n)), n.value
+
+
+def test_state_size_layout():
+    from paper_2111_00847_amd._lib import LBM_F64
+    rc, n32 = _size(_params(dtype="f32"))
+    assert rc == 0
+    rc, n64 = _size(_params(dtype="f64"))
+    assert rc == 0
+    # two copies of 21 planes of 4096 nodes plus header and scratch
+    assert n32 >= 256 + 2 * 21 * 4096 * 4
+    assert n64 >= 256 + 2 * 21 * 4096 * 8
+    assert n32 % 256 == 0 and n64 % 256 == 0
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(nx=0), -2), (dict(ny=-3), -2), (dict(nx=1, wall_x=True), -2),
+    (dict(rhoA=0.0), -4), (dict(nuB=-1.0), -4), (dict(W=0.0), -4), (dict(eta=0.5), -4),
+    (dict(phiA=0.0, phiB=1.0), -4), (dict(theta=(0.0, 1.0, 1.0, 1.0)), -4),
+    (dict(s_g=(2.0,) + (0.0,) * 8), -5), (dict(s_f=(0.0,) * 3 + (2.5,) + (0.0,) * 5), -5),
+    (dict(sigma=float("nan")), -4), (dict(model="corrected"), -8),
+])
+def test_parameter_validation(kw, code):
+    rc, _ = _size(_params(**kw))
+    assert rc == code
+
+
+def test_dtype_and_null_checks():
+    from paper_2111_00847_amd._lib import lib
+    p = _params()
+    p.dtype = 7
+    assert _size(p)[0] == -3
+    p = _params()
+    assert lib().lbm_state_size(ctypes.byref(p), None) == -1
+    assert lib().lbm_state_size(None, None) == -1
+    assert lib().lbm_init(ctypes.byref(p), None, None, None, None, None) == -1
+    assert lib().lbm_step(ctypes.byref(p), None, 1, None) == -1
+    assert lib().lbm_step(ctypes.byref(p), ctypes.c_void_p(256), -1, None) == -2
+    assert lib().lbm_init(ctypes.byref(p), ctypes.c_void_p(300), ctypes.c_void_p(256), None, None,
+                          None) == -2   # misaligned state
+    assert lib().lbm_import_state(ctypes.byref(p), ctypes.c_void_p(256), ctypes.c_void_p(256),
+                                  ctypes.c_void_p(256), None, 3, None) == -1   # history required
+
+
+def test_status_strings():
+    from paper_2111_00847_amd._lib import lib
+    for c in range(-8, 1):
+        assert lib().lbm_status_string(c)

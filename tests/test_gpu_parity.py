@@ -1,0 +1,235 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerances: FP64 GPU runs within 1e-10 of the oracle; FP32 GPU runs within
+max|dphi| <= 1e-5 and max|du| / Umax <= 1e-4 (Umax = max |u| of the oracle at
+the compared level).  One-step maps from an arbitrary imported state are
+compared population by population.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _gpu():
+    from paper_2111_00847_amd.sim import Sim
+    return Sim
+
+
+def _compare_macro(gs, os_, tol_phi, tol_u, what=""):
+    phi_g, u_g, p_g = gs.moments_np()
+    phi_o, u_o, p_o = os_.moments()
+    dphi = np.abs(phi_g - phi_o).max()
+    umax = np.abs(u_o).max()
+    du = np.abs(u_g - u_o).max() / max(umax, 1e-30)
+    print(f"{what}: max|dphi|={dphi:.3e} max|du|/Umax={du:.3e} (Umax={umax:.3e})", flush=True)
+    assert np.isfinite(phi_g).all() and np.isfinite(u_g).all()
+    assert dphi <= tol_phi, dphi
+    assert du <= tol_u, du
+    return dphi, du
+
+
+def _run_pair(case, phi0, steps, u0=None, p0=None):
+    if p0 is None:
+        p0 = W.hydrostatic_pressure(case, phi0)
+    Sim = _gpu()
+    g = Sim(case).init(phi0, u0, p0).step(steps)
+    o = oracle.OracleSim(case.replace(dtype="f64")).init(phi0, u0, p0).step(steps)
+    torch.cuda.synchronize()
+    return g, o
+
+
+# ------------------------------------------------------------------ one-step map
+def _random_state(case, seed):
+    """A smooth random level-n state (post-streaming populations near equilibrium
+    plus noise, and a level n-1 history) built by the oracle from random fields."""
+    phi0, u0, p0 = W.random_state_fields(case, seed=seed)
+    o = oracle.OracleSim(case.replace(dtype="f64")).init(phi0, u0, p0)
+    st = o.get_state()
+    rng = np.random.default_rng(seed + 1)
+    f = st["f"] + 1e-4 * rng.standard_normal(st["f"].shape)
+    g = st["g"] + 1e-5 * rng.standard_normal(st["g"].shape)
+    phi_prev = phi0 + 1e-3 * rng.standard_normal(phi0.shape)
+    u_prev = u0 + 1e-4 * rng.standard_normal(u0.shape)
+    return f, g, phi_prev, u_prev
+
+
+GEOMS = {
+    "periodic": dict(),
+    "walls_y": dict(wall_y=True, theta=(math.pi / 2, math.pi / 2, math.radians(50), math.radians(120))),
+    "walls_xy": dict(wall_x=True, wall_y=True,
+                     theta=(math.radians(70), math.radians(110), math.radians(40), math.radians(140))),
+}
+
+
+@pytest.mark.parametrize("geom", list(GEOMS))
+@pytest.mark.parametrize("shape", [(37, 23), (130, 19), (5, 70)])
+@pytest.mark.parametrize("step", [0, 5])
+def test_one_step_map_fp64(geom, shape, step):
+    """One GPU step from an imported state equals one oracle step from the same
+    state (populations, FP64, ragged tiles, walls with four contact angles)."""
+    nx, ny = shape
+    case = W.Case(nx=nx, ny=ny, rhoA=20.0, rhoB=1.0, nuA=0.05, nuB=0.2, sigma=0.01, W=4.0, M=0.05,
+                  body_force=(1e-6, -2e-6), gravity=(0.0, -1e-5), rho_ref=3.0, dtype="f64",
+                  **GEOMS[geom])
+    f, g, php, upr = _random_state(case, seed=nx * 7 + ny)
+    hist = np.concatenate([php[None], upr], 0)
+    Sim = _gpu()
+    gs = Sim(case).import_state(f, g, hist if step > 0 else None, step)
+    exp = gs.export_state()
+    assert exp["step"] == step
+    np.testing.assert_array_equal(exp["f"].cpu().numpy(), f)
+    np.testing.assert_array_equal(exp["g"].cpu().numpy(), g)
+    gs.step(1)
+    o = oracle.OracleSim(case).set_state(f, g, step, php, upr).step(1)
+    so = o.get_state()
+    sg = gs.export_state()
+    assert sg["step"] == step + 1
+    df = np.abs(sg["f"].cpu().numpy() - so["f"]).max()
+    dg = np.abs(sg["g"].cpu().numpy() - so["g"]).max()
+    print(f"{geom} {shape} step {step}: max|df|={df:.3e} max|dg|={dg:.3e}", flush=True)
+    assert df < 1e-14 and dg < 1e-14
+    # the level-n history the GPU stored is phi and u of level n
+    phi_o, u_o, _ = oracle.OracleSim(case).set_state(f, g, step, php, upr).moments()
+    h = sg["hist"].cpu().numpy()
+    np.testing.assert_allclose(h[0], phi_o, atol=1e-14)
+    np.testing.assert_allclose(h[1:], u_o, atol=1e-15)
+
+
+def test_moments_fp64_equal_oracle():
+    case = W.Case(nx=45, ny=33, wall_y=True, rhoA=5.0, rhoB=1.0, sigma=0.02, W=4.0, M=0.05,
+                  gravity=(0, -1e-5), theta=(1.5708, 1.5708, 0.9, 2.1), dtype="f64")
+    f, g, php, upr = _random_state(case, seed=3)
+    hist = np.concatenate([php[None], upr], 0)
+    gs = _gpu()(case).import_state(f, g, hist, 9)
+    o = oracle.OracleSim(case).set_state(f, g, 9, php, upr)
+    for a, b in zip(gs.moments_np(), o.moments()):
+        np.testing.assert_allclose(a, b, rtol=0, atol=1e-14)
+
+
+# ------------------------------------------------------------------ trajectories, FP64
+def test_square_droplet_fp64_2000_steps():
+    """64 x 64 periodic square droplet, FP64, 2000 steps: within 1e-10 of the oracle;
+    total phi drift at round-off."""
+    case, phi0 = W.square_droplet()
+    g, o = _run_pair(case, phi0, 2000)
+    _compare_macro(g, o, 1e-10, 1e-10, "square droplet fp64")
+    dg = g.diagnostics()
+    do = o.diagnostics()
+    assert abs(dg["sum_phi"] - phi0.sum()) / phi0.sum() < 1e-12
+    for key in ("max_div", "Du_rms", "Sm_rms", "umax"):
+        assert abs(dg[key] - do[key]) <= 1e-8 * abs(do[key]) + 1e-18, (key, dg[key], do[key])
+
+
+def test_dam_break_small_fp64():
+    """64 x 32 copy of the dam break (walls on all faces, one contact angle,
+    inverse-nu law, gravity): FP64, 600 steps, within 1e-10."""
+    case, phi0 = W.dam_break(nx=64, ny=32, column=16, dtype="f64", theta_deg=70.0)
+    g, o = _run_pair(case, phi0, 600)
+    _compare_macro(g, o, 1e-10, 1e-10, "dam break 64x32 fp64")
+
+
+# ------------------------------------------------------------------ trajectories, FP32
+def test_square_droplet_fp32_2000_steps():
+    case, phi0 = W.square_droplet(dtype="f32")
+    g, o = _run_pair(case, phi0, 2000)
+    _compare_macro(g, o, 1e-5, 1e-4, "square droplet fp32")
+    dg = g.diagnostics()
+    assert abs(dg["sum_phi"] - phi0.sum()) / phi0.sum() < 1e-5
+
+
+def test_layered_poiseuille_fp32_50000_steps():
+    """4 x 256 two-layer channel (density ratio 100, viscosity ratio 10), FP32,
+    50000 steps from rest."""
+    case, phi0 = W.layered_poiseuille()
+    g, o = _run_pair(case, phi0, 50000)
+    _compare_macro(g, o, 1e-5, 1e-4, "layered poiseuille fp32")
+
+
+def test_rti_fp32_2000_steps_full_size():
+    """256 x 1024 Rayleigh-Taylor, FP32, 2000 steps (0.22 t*): the horizon over which
+    the FP64 model itself is reproducible to 1e-8 under FP32 rounding of its inputs;
+    later the instability amplifies round-off (reported by bench, checked one step
+    at a time by test_one_step_at_horizon)."""
+    case, phi0 = W.rti()
+    g, o = _run_pair(case, phi0, 2000)
+    _compare_macro(g, o, 1e-5, 1e-4, "rti 256x1024 fp32 2000 steps")
+
+
+def test_rti_fp64_2000_steps_full_size():
+    case, phi0 = W.rti(dtype="f64")
+    g, o = _run_pair(case, phi0, 2000)
+    _compare_macro(g, o, 1e-10, 1e-10, "rti 256x1024 fp64 2000 steps")
+
+
+def test_dam_break_fp32_prefix_full_size():
+    """1024 x 512 dam break at full size, FP32, first 50 steps.  Later the collapse
+    pushes the bulk water off phi_A by more than eps_n W/4, where the sharpening term
+    is ill-conditioned (the FP64 model is then not reproducible under FP32 rounding
+    of its own inputs either); the full horizon is checked one step at a time."""
+    case, phi0 = W.dam_break()
+    g, o = _run_pair(case, phi0, 50)
+    _compare_macro(g, o, 1e-5, 1e-4, "dam break 1024x512 fp32 50 steps")
+
+
+# ------------------------------------------------------------------ one step at the full horizon
+HORIZON = {
+    "rti_256x1024": (lambda dt: W.rti(dtype=dt), 20000),
+    "dam_break_1024x512": (lambda dt: W.dam_break(dtype=dt), 4000),
+    "spreading_512x256": (lambda dt: W.spreading_case(512, 256, 47.0, dtype=dt), 10000),
+    "layered_poiseuille_4x256": (lambda dt: W.layered_poiseuille(dtype=dt), 50000),
+}
+
+
+@pytest.mark.parametrize("name", list(HORIZON))
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_one_step_at_horizon(name, dtype):
+    """At the stated step count of each workload, in the launch configuration the
+    benchmark uses, one more GPU step from the GPU's own state equals one oracle
+    step from the exported state (FP64: populations within 1e-13; FP32: phi within
+    1e-6 and u within 1e-5 Umax after the step); total phi is conserved."""
+    make, steps = HORIZON[name]
+    case, phi0 = make(dtype)
+    p0 = W.hydrostatic_pressure(case, phi0)
+    gs = _gpu()(case).init(phi0, None, p0).step(steps)
+    st = gs.export_state()
+    assert st["step"] == steps
+    f = st["f"].double().cpu().numpy()
+    g = st["g"].double().cpu().numpy()
+    h = st["hist"].double().cpu().numpy()
+    assert np.isfinite(f).all() and np.isfinite(g).all()
+    m0 = float(np.sum(phi0))
+    d = gs.diagnostics()
+    drift = abs(d["sum_phi"] - m0) / m0
+    print(f"{name} {dtype} at {steps}: mass drift {drift:.2e}", flush=True)
+    assert drift < (1e-12 if dtype == "f64" else 1e-7)
+    o = oracle.OracleSim(case.replace(dtype="f64")).set_state(f, g, steps, h[0], h[1:])
+    gs.step(1)
+    o.step(1)
+    if dtype == "f64":
+        so, sg = o.get_state(), gs.export_state()
+        df = np.abs(sg["f"].cpu().numpy() - so["f"]).max()
+        dg = np.abs(sg["g"].cpu().numpy() - so["g"]).max()
+        print(f"{name} fp64 step {steps}->{steps + 1}: max|df|={df:.2e} max|dg|={dg:.2e}", flush=True)
+        assert df < 1e-13 and dg < 1e-13
+    else:
+        _compare_macro(gs, o, 1e-6, 1e-5, f"{name} fp32 step {steps}->{steps + 1}")
+
+
+@pytest.mark.parametrize("k", [0, 1, 2])
+def test_spreading_fp32_prefix(k):
+    """Representative cases of the batched spreading mix, FP32, 500 steps."""
+    cases = W.spreading_batch()
+    sizes = [(c[0].nx, c[0].ny) for c in cases]
+    want = W.SPREAD_SIZES[k]
+    case, phi0 = cases[sizes.index(want)]
+    g, o = _run_pair(case, phi0, 500)
+    _compare_macro(g, o, 1e-5, 1e-4, f"spreading {want} fp32 500 steps")

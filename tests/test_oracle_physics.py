@@ -70,8 +70,8 @@ def test_flat_interface_tanh_profile_second_order():
 def test_laplace_law_converges():
     """Static droplet: p_in - p_out -> sigma / R.  The surface force mu_phi grad phi on
     a tanh profile integrates to sigma/R (k kappa int phi'^2 = sigma / R); the lattice
-    value approaches it at second order in dx/W: ~0.934 at W = 4, R = 16 and ~0.985
-    at W = 8, R = 32 (deficit ratio ~4)."""
+    value approaches it at (at least) second order in dx/W: ~0.935 at W = 4, R = 16
+    and ~0.990 at W = 8, R = 32 (deficit ratio ~7 with eps_n = 1e-3, ~4.5 with 1e-6)."""
     ratios = []
     for R, n, Wd, steps in [(16.0, 64, 4.0, 12000), (32.0, 128, 8.0, 24000)]:
         case, phi0 = W.static_droplet(n=n, R=R, W=Wd, M=0.02 * Wd / 4)
@@ -85,7 +85,7 @@ def test_laplace_law_converges():
     assert 0.90 < ratios[0] < 0.97
     assert 0.97 < ratios[1] < 1.01
     deficit_ratio = (1 - ratios[0]) / (1 - ratios[1])
-    assert 3.0 < deficit_ratio < 6.0, ratios
+    assert 3.0 < deficit_ratio < 9.0, ratios
 
 
 # ------------------------------------------------------------------ layered Poiseuille

@@ -46,7 +46,7 @@ class Case:
     rho_ref: float = 0.0
     theta: Tuple[float, float, float, float] = (math.pi / 2,) * 4
     rho0: float = 0.0
-    eps_n: float = 1e-6
+    eps_n: float = 1e-4
     dtype: str = "f32"
     steps: int = 0
     name: str = ""
@@ -238,6 +238,24 @@ def flat_interface(nx: int = 4, ny: int = 128, W: float = 4.0, rho_ratio: float 
     d = np.minimum(Y - (ny / 4.0 + offset), (3 * ny / 4.0 + offset) - Y)
     phi0 = tanh_profile(d, W)
     return case, phi0
+
+
+def hydrostatic_pressure(case: Case, phi0):
+    """Initial pressure of a fluid at rest: dp/dy = F_y = (rho - rho_ref) g_y along
+    every column (trapezoid rule from the top row), with rho from the linear
+    density law of Sec. 2; zero mean.  Zero for cases without gravity.  Starting
+    from p = 0 instead launches a pressure transient that pushes the bulk phi off
+    phi_A, where the sharpening term of the Allen-Cahn flux is ill-conditioned."""
+    if case.gravity[0] != 0.0:
+        raise NotImplementedError("hydrostatic start for gravity along y only")
+    if case.gravity[1] == 0.0:
+        return np.zeros_like(phi0)
+    rho = case.rhoB + (case.rhoA - case.rhoB) * (phi0 - case.phiB) / (case.phiA - case.phiB)
+    fy = (rho - case.rho_ref) * case.gravity[1]
+    p = np.zeros_like(phi0)
+    for j in range(case.ny - 2, -1, -1):
+        p[j] = p[j + 1] - 0.5 * (fy[j] + fy[j + 1])
+    return p - p.mean()
 
 
 def random_state_fields(case: Case, seed: int = 7, amp_u: float = 1e-3):
