@@ -89,27 +89,8 @@ def cpu_baseline(budget_s=15.0):
             "sample": f"FP64 oracle, rti 256x1024, {steps} steps after 2 untimed ({dt:.1f} s)"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--large-steps", type=int, default=200)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-large", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
-              "a lattice is not sharded across GPUs here.", file=sys.stderr)
-        sys.exit(2)
-
-    import torch
-    import workloads as W
-    from paper_2111_00847_amd.sim import Sim
-
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    torch.cuda.set_device(0)
-
+def measure_main(args, torch, W, Sim):
+    """The headline: RTI 256 x 1024, FP32, K steps after W warm-up steps."""
     case, phi0 = W.rti()
     sim = Sim(case, "cuda:0").init(phi0, None, W.hydrostatic_pressure(case, phi0))
     sim.step(args.warmup)
@@ -119,11 +100,11 @@ def main():
     mlups = nodes * args.steps / (ms * 1e-3) / 1e6
     alg = ALG_BYTES[case.dtype] * nodes
     achieved = alg / (ms_launch * 1e-3) / 1e9
-    traffic = measured_traffic(nodes)
     d = sim.diagnostics()
     assert d["nonfinite"] == 0, "non-finite state after the timed steps"
-
-    out = {
+    del sim
+    torch.cuda.empty_cache()
+    return {
         "metric": "MLUPS (fused FP32 phase-field LBM step, single launch per step)",
         "value": round(mlups, 2),
         "unit": "MLUPS",
@@ -139,28 +120,70 @@ def main():
         "config": {"workload": "rayleigh_taylor_256x1024", "nx": case.nx, "ny": case.ny,
                    "lattice": "D2Q9 x2 (phase field + flow), MRT", "boundaries": "periodic x, walls y"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(nodes),
                      "kernel": "k_step<float>", "alg_bytes_per_launch": alg,
                      "avg_launch_ms": round(ms_launch, 5)},
     }
-    del sim
+
+
+def measure_large(args, torch, W, Sim):
+    """The same kernel on a 4096 x 4096 lattice (state 2.9 GB, beyond the 256 MB cache)."""
+    caseL, phiL = W.rti(nx=4096, ny=4096)
+    simL = Sim(caseL, "cuda:0").init(phiL, None, W.hydrostatic_pressure(caseL, phiL))
+    simL.step(10)
+    msL, msLl = time_steps(simL, args.large_steps, torch)
+    algL = ALG_BYTES["f32"] * caseL.nodes
+    achL = algL / (msLl * 1e-3) / 1e9
+    del simL
     torch.cuda.empty_cache()
+    return {"workload": "rayleigh_taylor_4096x4096", "steps": args.large_steps,
+            "value": round(caseL.nodes * args.large_steps / (msL * 1e-3) / 1e6, 1),
+            "unit": "MLUPS", "achieved_GBs": round(achL, 1),
+            "frac": round(achL / HBM_PEAK_GBS, 4), "avg_launch_ms": round(msLl, 4)}
 
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--large-steps", type=int, default=200)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-large", action="store_true")
+    ap.add_argument("--only-large", action="store_true",
+                    help="run only the 4096 x 4096 measurement (profiling runs)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="instead of the benchmark: copy a MIB-sized device buffer 20 times "
+                         "(a plain copy kernel of known size, to scale HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
+              "a lattice is not sharded across GPUs here.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads as W
+    from paper_2111_00847_amd.sim import Sim
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+
+    if args.calibrate_copy:
+        n = args.calibrate_copy * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(20):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes_each_way": n * 4, "launches": 20}))
+        return
+
+    out = {}
+    if not args.only_large:
+        out.update(measure_main(args, torch, W, Sim))
     if not args.no_large:
-        caseL, phiL = W.rti(nx=4096, ny=4096)
-        simL = Sim(caseL, "cuda:0").init(phiL, None, W.hydrostatic_pressure(caseL, phiL))
-        simL.step(10)
-        msL, msLl = time_steps(simL, args.large_steps, torch)
-        algL = ALG_BYTES["f32"] * caseL.nodes
-        achL = algL / (msLl * 1e-3) / 1e9
-        out["large_grid"] = {"workload": "rayleigh_taylor_4096x4096", "steps": args.large_steps,
-                             "value": round(caseL.nodes * args.large_steps / (msL * 1e-3) / 1e6, 1),
-                             "unit": "MLUPS", "achieved_GBs": round(achL, 1),
-                             "frac": round(achL / HBM_PEAK_GBS, 4), "avg_launch_ms": round(msLl, 4)}
-        del simL
-        torch.cuda.empty_cache()
-
-    if not args.no_cpu_baseline:
+        out["large_grid"] = measure_large(args, torch, W, Sim)
+    if not args.no_cpu_baseline and not args.only_large:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
 

@@ -214,62 +214,18 @@ __device__ __forceinline__ void from_moments(const T* m, T* f) {
     f[0] = m[0] - moving_sum(f);
 }
 
-// ---------------------------------------------------------------------------
-// Storage rounding of the post-collision populations.  FP64 state: plain sum.
-// FP32 state: the exact FP64 sum is rounded stochastically to one of its two
-// FP32 neighbours with probability proportional to proximity, drawn from a
-// counter-based hash of (node, step, population).  The expected stored value
-// equals the exact one, so round-off cannot add the same bias on every step of
-// a steady flow (with round-to-nearest, a node whose populations repeat keeps
-// re-adding an identical rounding error -- in a heavy phase driven by a weak
-// force that acts like a spurious body force).  Deterministic: the same run
-// gives the same bits.
-__device__ __forceinline__ uint32_t mix_hash(uint32_t a, uint32_t b, uint32_t c) {
-    uint32_t h = a * 0x9E3779B1u;
-    h ^= (b + 0x7F4A7C15u) * 0x85EBCA77u;
-    h ^= (c + 0x165667B1u) * 0xC2B2AE3Du;
-    h ^= h >> 16;
-    h *= 0x7FEB352Du;
-    h ^= h >> 15;
-    h *= 0x846CA68Bu;
-    h ^= h >> 16;
-    return h;
-}
-
-template <typename T>
-struct Rounder;
-
-template <>
-struct Rounder<double> {
-    __device__ __forceinline__ static double store(double x, uint32_t) { return x; }
-};
-
-template <>
-struct Rounder<float> {
-    __device__ __forceinline__ static float store(double x, uint32_t h) {
-        float a = (float)x;                       // nearest
-        double e = x - (double)a;
-        if (e == 0.0) return a;
-        float b = nextafterf(a, e > 0.0 ? INFINITY : -INFINITY);
-        double p = e / ((double)b - (double)a);   // in (0, 1/2]
-        return (double)h * (1.0 / 4294967296.0) < p ? b : a;
-    }
-};
-
 // Both collisions are applied in increment form: the moment change
 // dm = -S (m - m^eq) + (I - S/2) m_R is mapped back through M1^-1 and added to
 // the incoming populations, so each stored population takes one rounding per
-// step -- in FP32 the forcing of a heavy phase is only tens of ulps of its
-// populations, and steady states would otherwise accumulate several roundings
-// per step coherently.
+// step (in FP32 the forcing of a heavy phase is only tens of ulps of its
+// populations).
 
 // Phase-field collision (Eq. evoPF, moment form; Eq. MfMRAC1 with eta = 1).
 // phid: phi of the node in FP64 (rest population + moving sum); returns the
 // post-collision rest population phid - sum of the moving ones (m_0 is
 // collision-invariant: m_0^eq = phi and m_R has no zeroth moment).
 template <typename T>
-__device__ __forceinline__ double collide_f(const KParams<T>& P, const Macro<T>& M, T* f, double phid,
-                                            uint32_t node, uint32_t step) {
+__device__ __forceinline__ double collide_f(const KParams<T>& P, const Macro<T>& M, T* f, double phid) {
     T m[9];
     to_moments(f, m);
     const T phi = M.phi;
@@ -283,14 +239,13 @@ __device__ __forceinline__ double collide_f(const KParams<T>& P, const Macro<T>&
     for (int k = 1; k < 9; k++) dm[k] = -P.sf[k] * (m[k] - meq[k]) + (T(1) - T(0.5) * P.sf[k]) * mR[k];
     from_moments(dm, d);
 #pragma unroll
-    for (int i = 1; i < 9; i++) f[i] = Rounder<T>::store((double)f[i] + (double)d[i], mix_hash(node, step, i));
+    for (int i = 1; i < 9; i++) f[i] += d[i];
     return phid - moving_sum_d(f);
 }
 
 // Hydrodynamic collision (Remark 2, moment form; Eq. MgMF1).
 template <typename T>
-__device__ __forceinline__ void collide_g(const KParams<T>& P, const Macro<T>& M, T* g, uint32_t node,
-                                          uint32_t step) {
+__device__ __forceinline__ void collide_g(const KParams<T>& P, const Macro<T>& M, T* g) {
     T m[9];
     to_moments(g, m);
     const T u = M.u, v = M.v, rho = M.rho;
@@ -337,7 +292,7 @@ __device__ __forceinline__ void collide_g(const KParams<T>& P, const Macro<T>& M
     dm[5] = M.Fy;
     from_moments(dm, d);
 #pragma unroll
-    for (int i = 0; i < 9; i++) g[i] = Rounder<T>::store((double)g[i] + (double)d[i], mix_hash(node, step, 9 + i));
+    for (int i = 0; i < 9; i++) g[i] += d[i];
 }
 
 }  // namespace lbm

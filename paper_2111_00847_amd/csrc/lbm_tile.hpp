@@ -9,10 +9,6 @@ namespace lbm {
 constexpr int TX = 64;
 constexpr int BY = 4;
 
-// Fill the LDS window of phi (and of phi_prev when `need_prev`) for the tile
-// at (x0, y0).  Window (wx, wy) is node (x0 - 1 + wx, y0 - 1 + wy).  Periodic
-// axes wrap; wall ghosts follow Eq. (Dwetting): x-walls first, then y-walls
-// across the extended rows, which fixes the corners.
 // phi of node (x, y) in FP64: rest population plus the pulled moving ones.
 template <typename T>
 __device__ __forceinline__ double node_phi(const KParams<T>& P, const Copy<T>& C, int x, int y, T* f) {
@@ -23,34 +19,14 @@ __device__ __forceinline__ double node_phi(const KParams<T>& P, const Copy<T>& C
     return f0 + moving_sum_d(f);
 }
 
+// Wall ghosts of the window (Eq. Dwetting): x-walls first, then y-walls
+// across the extended rows, which fixes the corners.  Call after the window
+// interior and ring are filled and synchronised; ends synchronised.
 template <typename T, int TY>
-__device__ __forceinline__ void fill_window(const KParams<T>& P, const Copy<T>& C, bool need_prev, int x0,
-                                            int y0, T (*sphi)[TX + 3], T (*sphp)[TX + 3]) {
+__device__ __forceinline__ void wall_ghosts(const KParams<T>& P, bool need_prev, int x0, int y0,
+                                            T (*sphi)[TX + 3], T (*sphp)[TX + 3]) {
     constexpr int WX = TX + 2, WY = TY + 2;
     const int tid = threadIdx.y * TX + threadIdx.x;
-    for (int idx = tid; idx < WX * WY; idx += TX * BY) {
-        int wy = idx / WX, wx = idx - wy * WX;
-        int gx = x0 - 1 + wx, gy = y0 - 1 + wy;
-        if (gx > P.nx || gy > P.ny) continue;
-        bool ghost = false;
-        if (gx < 0 || gx >= P.nx) {
-            if (P.wall_x) ghost = true;
-            else gx = gx < 0 ? gx + P.nx : gx - P.nx;
-        }
-        if (gy < 0 || gy >= P.ny) {
-            if (P.wall_y) ghost = true;
-            else gy = gy < 0 ? gy + P.ny : gy - P.ny;
-        }
-        if (ghost) continue;
-        T fw[9];
-        sphi[wy][wx] = (T)node_phi(P, C, gx, gy, fw);
-        if (need_prev) sphp[wy][wx] = C.h[(long long)gy * P.nx + gx];
-    }
-    if (!P.wall_x && !P.wall_y) {
-        __syncthreads();
-        return;
-    }
-    __syncthreads();
     if (P.wall_x) {
         const int wxr = P.nx - x0 + 1;  // window column of x = nx
         for (int wy = tid; wy < WY; wy += TX * BY) {
@@ -85,6 +61,37 @@ __device__ __forceinline__ void fill_window(const KParams<T>& P, const Copy<T>& 
     }
 }
 
+// Fill the LDS window of phi (and of phi_prev when `need_prev`) for the tile
+// at (x0, y0).  Window (wx, wy) is node (x0 - 1 + wx, y0 - 1 + wy).  Periodic
+// axes wrap; wall ghosts follow Eq. (Dwetting): x-walls first, then y-walls
+// across the extended rows, which fixes the corners.
+template <typename T, int TY>
+__device__ __forceinline__ void fill_window(const KParams<T>& P, const Copy<T>& C, bool need_prev, int x0,
+                                            int y0, T (*sphi)[TX + 3], T (*sphp)[TX + 3]) {
+    constexpr int WX = TX + 2, WY = TY + 2;
+    const int tid = threadIdx.y * TX + threadIdx.x;
+    for (int idx = tid; idx < WX * WY; idx += TX * BY) {
+        int wy = idx / WX, wx = idx - wy * WX;
+        int gx = x0 - 1 + wx, gy = y0 - 1 + wy;
+        if (gx > P.nx || gy > P.ny) continue;
+        bool ghost = false;
+        if (gx < 0 || gx >= P.nx) {
+            if (P.wall_x) ghost = true;
+            else gx = gx < 0 ? gx + P.nx : gx - P.nx;
+        }
+        if (gy < 0 || gy >= P.ny) {
+            if (P.wall_y) ghost = true;
+            else gy = gy < 0 ? gy + P.ny : gy - P.ny;
+        }
+        if (ghost) continue;
+        T fw[9];
+        sphi[wy][wx] = (T)node_phi(P, C, gx, gy, fw);
+        if (need_prev) sphp[wy][wx] = C.h[(long long)gy * P.nx + gx];
+    }
+    __syncthreads();
+    wall_ghosts<T, TY>(P, need_prev, x0, y0, sphi, sphp);
+}
+
 template <typename T, int TY>
 __device__ __forceinline__ void win_stencil(T (*s)[TX + 3], int wx, int wy, T& gx, T& gy, T& lap) {
     stencil(s[wy - 1][wx - 1], s[wy - 1][wx], s[wy - 1][wx + 1], s[wy][wx - 1], s[wy][wx],
@@ -92,17 +99,20 @@ __device__ __forceinline__ void win_stencil(T (*s)[TX + 3], int wx, int wy, T& g
 }
 
 // Signal the end of a workgroup; the last one advances the step counter.
+// No memory fence: the data written by this step is read only by later
+// launches (ordered by the stream), and every wave of the workgroup consumed
+// its load of `step` (it addresses all of the step's loads and stores) before
+// the barrier, hence before the device-scope atomic below.  A release fence
+// here would write back the XCD's whole L2 once per workgroup.
 __device__ __forceinline__ void finish_step(StateHeader* H, int64_t step) {
     __syncthreads();
     if (threadIdx.x == 0 && threadIdx.y == 0) {
-        __threadfence();
-        unsigned nb = gridDim.x * gridDim.y;
-        unsigned prev = atomicAdd(&H->done, 1u);
+        const unsigned nb = gridDim.x * gridDim.y;
+        const unsigned prev = atomicAdd(&H->done, 1u);
         if (prev == nb - 1) {
             atomicExch(reinterpret_cast<unsigned long long*>(&H->step),
                        static_cast<unsigned long long>(step + 1));
             atomicExch(&H->done, 0u);
-            __threadfence();
         }
     }
 }
