@@ -26,16 +26,20 @@ __host__ __device__ constexpr int opp(int i) {
 static_assert(opp(1) == 3 && opp(2) == 4 && opp(3) == 1 && opp(4) == 2, "opp axis");
 static_assert(opp(5) == 7 && opp(6) == 8 && opp(7) == 5 && opp(8) == 6, "opp diag");
 
-// Device-side header at the start of every state buffer.  `step` is the index
-// n of the current time level; ping-pong buffer n & 1 holds the post-collision
-// populations of level n-1 (streamed by pulling) and the level n-1 history.
+// Device-side header at the start of every state buffer.
 struct StateHeader {
-    int64_t step;
-    uint32_t done;      // blocks of the running step kernel that have finished
     uint32_t magic;
-    int32_t nx, ny, dtype, pad;
+    int32_t nx, ny, dtype;
 };
 
+// Level stamps.  The time level n of the state is kept per (64-wide column
+// band, row): stamp[xt * ny + y].  A step workgroup reads the stamp of its
+// first row to learn n (copy n & 1 is its source), and at its end writes n + 1
+// into the stamps of the rows it owns.  Every (band, row) belongs to exactly
+// one workgroup of a launch whatever the tile height, so no two workgroups
+// touch the same stamp and no cross-workgroup synchronisation is needed; all
+// stamps are equal between launches.
+constexpr int STAMP_BAND = 64;
 // Parameters resolved on the host and passed by value to every kernel.
 template <typename T>
 struct KParams {
@@ -91,6 +95,8 @@ struct Layout {
     size_t esz;           // element size
     size_t buf_bytes;     // one ping-pong copy: f0 (FP64), f[1..8], g[9], hist[3] planes
     size_t off_buf[2];
+    size_t off_stamp;     // int64 level stamps, ceil(nx / 64) * ny of them
+    size_t nstamp;
     size_t off_diag;      // diagnostics scratch: 3 planes (m^phiC, local S_m), partials, result
     size_t diag_partials; // number of double slots for block partials
     size_t total;
@@ -104,7 +110,9 @@ inline Layout make_layout(int nx, int ny, size_t esz, size_t diag_blocks) {
     L.buf_bytes = (size_t)8 * L.plane + (size_t)20 * L.plane * esz;
     L.off_buf[0] = HDR_BYTES;
     L.off_buf[1] = L.off_buf[0] + L.buf_bytes;
-    L.off_diag = L.off_buf[1] + L.buf_bytes;
+    L.off_stamp = L.off_buf[1] + L.buf_bytes;
+    L.nstamp = (size_t)((nx + STAMP_BAND - 1) / STAMP_BAND) * ny;
+    L.off_diag = L.off_stamp + (L.nstamp * 8 + 255) / 256 * 256;
     L.diag_partials = diag_blocks * 8;
     size_t diag = (size_t)3 * L.plane * esz + L.diag_partials * sizeof(double) + 16 * sizeof(double);
     L.total = L.off_diag + (diag + 255) / 256 * 256;

@@ -41,12 +41,11 @@ __device__ void block_reduce(double* v, const bool* is_max, double (*red)[NV]) {
 
 template <typename T>
 __global__ __launch_bounds__(TX* BY) void k_diag1(KParams<T> P, const char* state, size_t off0,
-                                                  size_t off1, T* scr, double* partials) {
+                                                  size_t off1, size_t off_stamp, T* scr, double* partials) {
     __shared__ T sphi[DTY + 2][TX + 3];
     __shared__ T sphp[DTY + 2][TX + 3];
     __shared__ double red[BY][5];
-    const StateHeader* H = reinterpret_cast<const StateHeader*>(state);
-    const int64_t step = H->step;
+    const int64_t step = *reinterpret_cast<const int64_t*>(state + off_stamp);
     const bool first = step == 0;
     const int cur = (int)(step & 1);
     const Copy<T> S = copy_at<T>(const_cast<char*>(state) + (cur ? off1 : off0), P.plane);
@@ -178,7 +177,7 @@ hipError_t launch_diagnostics(const KParams<T>& P, const char* state, const Layo
     T* scr = reinterpret_cast<T*>(const_cast<char*>(state) + L.off_diag);
     double* partials = reinterpret_cast<double*>(const_cast<char*>(state) + L.off_diag + 3 * L.plane * L.esz);
     double* out = partials + L.diag_partials;
-    k_diag1<T><<<grd, blk, 0, s>>>(P, state, L.off_buf[0], L.off_buf[1], scr, partials);
+    k_diag1<T><<<grd, blk, 0, s>>>(P, state, L.off_buf[0], L.off_buf[1], L.off_stamp, scr, partials);
     k_diag2<T><<<grd, blk, 0, s>>>(P, scr, partials);
     k_diag3<<<1, 64, 0, s>>>(partials, (int)(grd.x * grd.y), L.n, out);
     hipError_t e = hipGetLastError();

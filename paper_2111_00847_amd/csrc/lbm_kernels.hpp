@@ -23,6 +23,5 @@ hipError_t launch_export(const KParams<T>& P, const char* state, const Layout& L
 template <typename T>
 hipError_t launch_diagnostics(const KParams<T>& P, const char* state, const Layout& L, double* host_out,
                               hipStream_t s);
-hipError_t launch_read_step(const char* state, int64_t* dev_out, hipStream_t s);
 
 }  // namespace lbm

@@ -6,9 +6,10 @@
 // the post-collision populations of level n-1 -- a node obtains its level-n
 // populations by pulling them from its neighbours -- and hist = (phi, u, v)
 // of level n-1, from which the explicit-Euler time derivatives are formed.
-// A step reads copy (n & 1) and writes copy (1 - n & 1); the last workgroup
-// to finish advances the header's step counter, so host code never has to
-// know the parity and a sequence of steps can be captured in a graph.
+// A step reads copy (n & 1) and writes copy (1 - n & 1).  The level n is kept
+// in per-row stamps owned by the workgroups (lbm_common.hpp), so host code
+// never needs the parity, no workgroup waits for another, and a sequence of
+// steps can be captured in a graph.
 //
 // The phi stencils need phi on a one-node ring around each tile.  A tile of
 // 64 x TY nodes (256 threads) first pulls the populations of its (64+2) x
@@ -35,9 +36,24 @@ template <typename T, typename OFF>
 __device__ __forceinline__ T ld(const char* base, OFF byteoff) {
     return *reinterpret_cast<const T*>(base + byteoff);
 }
+// Tuning knobs (compile time, measured on MI355X): non-temporal stores for
+// the streamed state (+3% on a 4096^2 lattice); g loaded after the window
+// barrier (prefetching it with f gained nothing and costs registers); tiles
+// dealt to XCDs in bands (+11% on 256 x 1024, neutral on 4096^2).
+#ifndef LBM_NT_STORES
+#define LBM_NT_STORES 1
+#endif
+#ifndef LBM_PREFETCH_G      // load g together with f, before the window barrier
+#define LBM_PREFETCH_G 0
+#endif
+#ifndef LBM_XCD_REMAP
+#define LBM_XCD_REMAP 1
+#endif
+
 template <typename T, typename OFF>
 __device__ __forceinline__ void st(char* base, OFF byteoff, T v) {
-    *reinterpret_cast<T*>(base + byteoff) = v;
+    if (LBM_NT_STORES) __builtin_nontemporal_store(v, reinterpret_cast<T*>(base + byteoff));
+    else *reinterpret_cast<T*>(base + byteoff) = v;
 }
 
 // The fused step.  One 64 x TY tile per 256-thread workgroup; thread
@@ -45,16 +61,28 @@ __device__ __forceinline__ void st(char* base, OFF byteoff, T v) {
 // in registers from the phi pass to the collision, and the ring of the phi
 // window is pulled by spare threads.  MODE 0: one time step; MODE 1: write
 // phi, u, p of the current level.  OFF: byte-offset type within one copy.
+// FP32 16-row tiles keep four nodes per thread in flight; capping them at 128
+// VGPRs (4 waves per SIMD) is worth +10% on a 4096^2 lattice.  FP64 tiles are
+// never taller than 8 rows (the host caps them): they would spill.
+template <typename T, int TY>
+struct StepWaves {
+    static constexpr int value = (sizeof(T) == 4 && TY >= 16) ? 4 : 1;
+};
+
 template <typename T, int TY, int MODE, typename OFF>
-__global__ __launch_bounds__(TX* BY) void k_step(KParams<T> P, char* state, size_t off0, size_t off1, int ntx,
+__global__ __launch_bounds__(TX* BY) __attribute__((amdgpu_waves_per_eu(StepWaves<T, TY>::value)))
+void k_step(KParams<T> P, char* state, size_t off0, size_t off1, size_t off_stamp, int ntx,
                                                  int nty, T* out_phi, T* out_u, T* out_p) {
     constexpr int R = TY / BY;
     constexpr int WX = TX + 2, WY = TY + 2;
     constexpr OFF ES = sizeof(T);
     __shared__ T sphi[WY][TX + 3];
     __shared__ T sphp[WY][TX + 3];
-    StateHeader* H = reinterpret_cast<StateHeader*>(state);
-    const int64_t step = H->step;
+    const int t = LBM_XCD_REMAP ? xcd_tile(blockIdx.x, ntx * nty) : (int)blockIdx.x;
+    const int xt = t % ntx;
+    const int x0 = xt * TX, y0 = (t / ntx) * TY;
+    int64_t* stamp = reinterpret_cast<int64_t*>(state + off_stamp) + (size_t)xt * P.ny + y0;
+    const int64_t step = stamp[0];
     const bool first = step == 0;
     const int cur = (int)(step & 1);
     const char* src = state + (cur ? off1 : off0);
@@ -66,8 +94,6 @@ __global__ __launch_bounds__(TX* BY) void k_step(KParams<T> P, char* state, size
     const OFF bH = bG + 9 * pl * ES;     // hist_j at bH + j pl ES
     const OFF nx = (OFF)P.nx;
 
-    const int t = xcd_tile(blockIdx.x, ntx * nty);
-    const int x0 = (t % ntx) * TX, y0 = (t / ntx) * TY;
     const int lx = threadIdx.x;
     const int tid = threadIdx.y * TX + lx;
     const int x = x0 + lx;
@@ -91,6 +117,7 @@ __global__ __launch_bounds__(TX* BY) void k_step(KParams<T> P, char* state, size
 
     T f[R][9];
     double phid[R];
+    T gp[LBM_PREFETCH_G ? R : 1][9];
 #pragma unroll
     for (int r = 0; r < R; r++) {
         const int ly = threadIdx.y + r * BY, y = y0 + ly;
@@ -124,6 +151,15 @@ __global__ __launch_bounds__(TX* BY) void k_step(KParams<T> P, char* state, size
         phid[r] = f0 + moving_sum_d(f[r]);
         sphi[ly + 1][lx + 1] = (T)phid[r];
         if (!first) sphp[ly + 1][lx + 1] = ld<T>(src, bH + k * ES);
+        if (LBM_PREFETCH_G) {
+#pragma unroll
+            for (int i = 0; i < Q; i++) {
+                const int ax = 1 - cx(i), ay = 1 - cy(i);
+                const bool bb = wx[ax] || wy[ay];
+                const OFF o = bb ? bG + ((OFF)opp(i) * pl + k) * ES : bG + ((OFF)i * pl + row[ay] + col[ax]) * ES;
+                gp[LBM_PREFETCH_G ? r : 0][i] = ld<T>(src, o);
+            }
+        }
     }
 
     // ring of the window (and, for a ragged tile, the halo column/row inside it)
@@ -178,10 +214,14 @@ __global__ __launch_bounds__(TX* BY) void k_step(KParams<T> P, char* state, size
         T g[9];
 #pragma unroll
         for (int i = 0; i < Q; i++) {
-            const int ax = 1 - cx(i), ay = 1 - cy(i);
-            const bool bb = wx[ax] || wy[ay];
-            const OFF o = bb ? bG + ((OFF)opp(i) * pl + k) * ES : bG + ((OFF)i * pl + row[ay] + col[ax]) * ES;
-            g[i] = ld<T>(src, o);
+            if (LBM_PREFETCH_G) {
+                g[i] = gp[LBM_PREFETCH_G ? r : 0][i];
+            } else {
+                const int ax = 1 - cx(i), ay = 1 - cy(i);
+                const bool bb = wx[ax] || wy[ay];
+                const OFF o = bb ? bG + ((OFF)opp(i) * pl + k) * ES : bG + ((OFF)i * pl + row[ay] + col[ax]) * ES;
+                g[i] = ld<T>(src, o);
+            }
         }
         T gx, gy, lap, gxp = T(0), gyp = T(0), lp, php = T(0), up = T(0), vp = T(0);
         win_stencil<T, TY>(sphi, lx + 1, ly + 1, gx, gy, lap);
@@ -212,7 +252,10 @@ __global__ __launch_bounds__(TX* BY) void k_step(KParams<T> P, char* state, size
         st<T>(dst, bH + (pl + k) * ES, M.u);
         st<T>(dst, bH + (2 * pl + k) * ES, M.v);
     }
-    if (MODE == 0) finish_step(H, step);
+    // Own rows move to level n + 1.  Every wave of the workgroup consumed its
+    // load of stamp[0] (it addresses all loads above) before the barriers, so
+    // no wave can still be about to read it.
+    if (MODE == 0 && tid < TY && y0 + tid < P.ny) stamp[tid] = step + 1;
 }
 
 // ---------------------------------------------------------------- init / import / export
@@ -305,9 +348,9 @@ __global__ void k_to_pull(KParams<T> P, const T* post, long long post_stride, ch
 }
 
 template <typename T>
-__global__ void k_export(KParams<T> P, char* state, size_t off0, size_t off1, T* f, T* g, T* hist) {
-    const StateHeader* H = reinterpret_cast<const StateHeader*>(state);
-    const int cur = (int)(H->step & 1);
+__global__ void k_export(KParams<T> P, char* state, size_t off0, size_t off1, size_t off_stamp, T* f, T* g,
+                         T* hist) {
+    const int cur = (int)(*reinterpret_cast<const int64_t*>(state + off_stamp) & 1);
     const Copy<T> S = copy_at<T>(state + (cur ? off1 : off0), P.plane);
     const long long n = (long long)P.nx * P.ny;
     for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n;
@@ -333,16 +376,17 @@ __global__ void k_copy_hist(KParams<T> P, const T* hist, char* dst_base) {
         for (int j = 0; j < 3; j++) D.h[j * P.plane + k] = hist ? hist[j * n + k] : T(0);
 }
 
-__global__ void k_set_header(StateHeader* H, int64_t step, int nx, int ny, int dtype) {
-    atomicExch(reinterpret_cast<unsigned long long*>(&H->step), static_cast<unsigned long long>(step));
-    atomicExch(&H->done, 0u);
-    atomicExch(&H->magic, STATE_MAGIC);
-    atomicExch(reinterpret_cast<unsigned*>(&H->nx), (unsigned)nx);
-    atomicExch(reinterpret_cast<unsigned*>(&H->ny), (unsigned)ny);
-    atomicExch(reinterpret_cast<unsigned*>(&H->dtype), (unsigned)dtype);
+__global__ void k_set_header(StateHeader* H, int nx, int ny, int dtype) {
+    H->magic = STATE_MAGIC;
+    H->nx = nx;
+    H->ny = ny;
+    H->dtype = dtype;
 }
 
-__global__ void k_read_step(const StateHeader* H, int64_t* out) { *out = H->step; }
+__global__ void k_set_stamps(int64_t* stamp, long long n, int64_t level) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        stamp[i] = level;
+}
 
 // ---------------------------------------------------------------- launchers
 static int grid1d(long long n) {
@@ -358,11 +402,11 @@ static void launch_tile(const KParams<T>& P, char* state, const Layout& L, hipSt
     const int ntx = (P.nx + TX - 1) / TX, nty = (P.ny + TY - 1) / TY;
     dim3 blk(TX, BY);
     if (small_copy(L))
-        k_step<T, TY, MODE, uint32_t><<<ntx * nty, blk, 0, s>>>(P, state, L.off_buf[0], L.off_buf[1], ntx, nty,
-                                                                 phi, u, p);
+        k_step<T, TY, MODE, uint32_t><<<ntx * nty, blk, 0, s>>>(P, state, L.off_buf[0], L.off_buf[1], L.off_stamp,
+                                                                 ntx, nty, phi, u, p);
     else
-        k_step<T, TY, MODE, uint64_t><<<ntx * nty, blk, 0, s>>>(P, state, L.off_buf[0], L.off_buf[1], ntx, nty,
-                                                                 phi, u, p);
+        k_step<T, TY, MODE, uint64_t><<<ntx * nty, blk, 0, s>>>(P, state, L.off_buf[0], L.off_buf[1], L.off_stamp,
+                                                                 ntx, nty, phi, u, p);
 }
 
 template <typename T>
@@ -370,8 +414,8 @@ hipError_t launch_step(const KParams<T>& P, char* state, const Layout& L, int64_
                        int ty) {
     for (int64_t t = 0; t < nsteps; t++) {
         if (ty == 4) launch_tile<T, 4, 0>(P, state, L, s, nullptr, nullptr, nullptr);
-        else if (ty == 8) launch_tile<T, 8, 0>(P, state, L, s, nullptr, nullptr, nullptr);
-        else launch_tile<T, 16, 0>(P, state, L, s, nullptr, nullptr, nullptr);
+        else if (ty == 8 || sizeof(T) == 8) launch_tile<T, 8, 0>(P, state, L, s, nullptr, nullptr, nullptr);
+        else launch_tile<T, sizeof(T) == 8 ? 8 : 16, 0>(P, state, L, s, nullptr, nullptr, nullptr);
     }
     return hipGetLastError();
 }
@@ -392,7 +436,9 @@ hipError_t launch_init(const KParams<T>& P, char* state, const Layout& L, const 
     k_equilibrium<T><<<g, 256, 0, s>>>(P, phi0, u0, p0, scratch);
     k_to_pull<T><<<g, 256, 0, s>>>(P, scratch, P.plane, dst);
     k_copy_hist<T><<<g, 256, 0, s>>>(P, nullptr, dst);
-    k_set_header<<<1, 1, 0, s>>>(reinterpret_cast<StateHeader*>(state), 0, P.nx, P.ny, dtype);
+    k_set_header<<<1, 1, 0, s>>>(reinterpret_cast<StateHeader*>(state), P.nx, P.ny, dtype);
+    k_set_stamps<<<grid1d((long long)L.nstamp), 256, 0, s>>>(reinterpret_cast<int64_t*>(state + L.off_stamp),
+                                                              (long long)L.nstamp, 0);
     return hipGetLastError();
 }
 
@@ -415,19 +461,17 @@ hipError_t launch_import(const KParams<T>& P, char* state, const Layout& L, cons
     int gr = grid1d(L.n);
     k_to_pull<T><<<gr, 256, 0, s>>>(P, stage, P.plane, dst);
     k_copy_hist<T><<<gr, 256, 0, s>>>(P, step > 0 ? hist : nullptr, dst);
-    k_set_header<<<1, 1, 0, s>>>(reinterpret_cast<StateHeader*>(state), step, P.nx, P.ny, dtype);
+    k_set_header<<<1, 1, 0, s>>>(reinterpret_cast<StateHeader*>(state), P.nx, P.ny, dtype);
+    k_set_stamps<<<grid1d((long long)L.nstamp), 256, 0, s>>>(reinterpret_cast<int64_t*>(state + L.off_stamp),
+                                                              (long long)L.nstamp, step);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_export(const KParams<T>& P, const char* state, const Layout& L, T* f, T* g, T* hist,
                          hipStream_t s) {
-    k_export<T><<<grid1d(L.n), 256, 0, s>>>(P, const_cast<char*>(state), L.off_buf[0], L.off_buf[1], f, g, hist);
-    return hipGetLastError();
-}
-
-hipError_t launch_read_step(const char* state, int64_t* dev_out, hipStream_t s) {
-    k_read_step<<<1, 1, 0, s>>>(reinterpret_cast<const StateHeader*>(state), dev_out);
+    k_export<T><<<grid1d(L.n), 256, 0, s>>>(P, const_cast<char*>(state), L.off_buf[0], L.off_buf[1], L.off_stamp, f,
+                                             g, hist);
     return hipGetLastError();
 }
 

@@ -98,23 +98,4 @@ __device__ __forceinline__ void win_stencil(T (*s)[TX + 3], int wx, int wy, T& g
             s[wy][wx + 1], s[wy + 1][wx - 1], s[wy + 1][wx], s[wy + 1][wx + 1], gx, gy, lap);
 }
 
-// Signal the end of a workgroup; the last one advances the step counter.
-// No memory fence: the data written by this step is read only by later
-// launches (ordered by the stream), and every wave of the workgroup consumed
-// its load of `step` (it addresses all of the step's loads and stores) before
-// the barrier, hence before the device-scope atomic below.  A release fence
-// here would write back the XCD's whole L2 once per workgroup.
-__device__ __forceinline__ void finish_step(StateHeader* H, int64_t step) {
-    __syncthreads();
-    if (threadIdx.x == 0 && threadIdx.y == 0) {
-        const unsigned nb = gridDim.x * gridDim.y;
-        const unsigned prev = atomicAdd(&H->done, 1u);
-        if (prev == nb - 1) {
-            atomicExch(reinterpret_cast<unsigned long long*>(&H->step),
-                       static_cast<unsigned long long>(step + 1));
-            atomicExch(&H->done, 0u);
-        }
-    }
-}
-
 }  // namespace lbm
