@@ -18,6 +18,10 @@ The JSON line also carries:
                   current kernel source, else null;
   large_grid   -- the same kernel at 4096 x 4096 (state 2.8 GB, far beyond the
                   256 MB Infinity Cache), where HBM is the real bound;
+  batched      -- 64 droplet-spreading cases of uneven sizes (Sec. 4.3 set-up,
+                  FP32): one autotuned persistent launch per step replayed from a
+                  captured graph, against the same cases advanced one after
+                  another with the plain step (graph-captured, and eager);
   cpu_baseline -- the FP64 oracle timed on the host on a bounded sample.
 """
 import argparse
@@ -33,7 +37,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 ALG_BYTES = {"f32": 168, "f64": 336}   # per lattice update: f, g read+write, (phi, u, v) history read+write
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "k_step_rti_256x1024_traffic.json")
-KERNEL_SOURCES = ["paper_2111_00847_amd/csrc/lbm_step.hip", "paper_2111_00847_amd/csrc/lbm_tile.hpp",
+KERNEL_SOURCES = ["paper_2111_00847_amd/csrc/lbm_step.hip", "paper_2111_00847_amd/csrc/lbm_fused.hpp",
+                  "paper_2111_00847_amd/csrc/lbm_tile.hpp",
                   "paper_2111_00847_amd/csrc/lbm_device.hpp", "paper_2111_00847_amd/csrc/lbm_common.hpp"]
 
 
@@ -142,12 +147,56 @@ def measure_large(args, torch, W, Sim):
             "frac": round(achL / HBM_PEAK_GBS, 4), "avg_launch_ms": round(msLl, 4)}
 
 
+def _timed(stream, torch, fn):
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def measure_batched(args, torch, W, Sim, BatchSim):
+    """64 spreading cases: batched launch vs the plain step case by case."""
+    cases = W.spreading_batch()
+    phis = [p for _, p in cases]
+    nodes = sum(c.nodes for c, _ in cases)
+    K = args.batch_steps
+    s = torch.cuda.Stream()
+    B = BatchSim([c for c, _ in cases], autotune=True, stream=s).init(phis)
+    B.step(64)
+    ms_b = _timed(s, torch, lambda: B.step(K))
+    tun = B.tuning()
+    nonfinite = sum(B.case(c).diagnostics()["nonfinite"] for c in range(len(cases)))
+    assert nonfinite == 0, "non-finite batched state"
+    del B
+    sims = [Sim(c, stream=s).init(p) for c, p in cases]
+    for sm in sims:
+        sm.step(64)                      # captures each case's graph
+    ms_g = _timed(s, torch, lambda: [sm.step(K) for sm in sims])
+    eager = [Sim(c).init(p) for c, p in cases]   # default stream: one launch per step
+    ms_e = _timed(torch.cuda.current_stream(), torch, lambda: [sm.step(K) for sm in eager])
+    del sims, eager
+    torch.cuda.empty_cache()
+    mlups = lambda ms: round(nodes * K / (ms * 1e-3) / 1e6, 1)
+    return {"workload": "spreading_batch_64_cases", "cases": len(cases), "nodes": nodes, "steps": K,
+            "batched_MLUPS": mlups(ms_b), "sequential_graph_MLUPS": mlups(ms_g),
+            "sequential_eager_MLUPS": mlups(ms_e), "speedup_vs_sequential_graph": round(ms_g / ms_b, 3),
+            "speedup_vs_sequential_eager": round(ms_e / ms_b, 3),
+            "batched_frac": round(ALG_BYTES["f32"] * nodes * K / (ms_b * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "tuning": tun}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--large-steps", type=int, default=200)
+    ap.add_argument("--batch-steps", type=int, default=1000)
+    ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--only-large", action="store_true",
@@ -163,7 +212,7 @@ def main():
 
     import torch
     import workloads as W
-    from paper_2111_00847_amd.sim import Sim
+    from paper_2111_00847_amd.sim import BatchSim, Sim
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
@@ -183,6 +232,8 @@ def main():
         out.update(measure_main(args, torch, W, Sim))
     if not args.no_large:
         out["large_grid"] = measure_large(args, torch, W, Sim)
+    if not args.no_batched and not args.only_large:
+        out["batched"] = measure_batched(args, torch, W, Sim, BatchSim)
     if not args.no_cpu_baseline and not args.only_large:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

@@ -138,6 +138,35 @@ int lbm_export_state(const lbm_params *p, const void *state, void *f, void *g, v
 int lbm_import_state(const lbm_params *p, void *state, const void *f, const void *g,
                      const void *hist, int64_t step, void *stream);
 
+/* ---- batches: many independent lattices, one launch per time step ---------
+ * (the batched execution row of the build: the per-step update above applied
+ * to every case; a case advanced in a batch is bitwise identical to the same
+ * case advanced alone with lbm_step).  All cases share one dtype.  The plan is
+ * library-owned (a small device table of the cases and, once lbm_batch_step
+ * runs on a non-NULL stream with nsteps >= 32, a captured hipGraph of 32
+ * steps for that state and stream). */
+typedef struct lbm_batch lbm_batch;
+
+/* Plan a batch of `ncases` lattices (cases: host array of ncases lbm_params).
+ * autotune != 0: the first lbm_batch_init times the candidate tile heights and
+ * persistent grid sizes on the batch itself and keeps the fastest. */
+int lbm_batch_create(const lbm_params *cases, int32_t ncases, int32_t autotune, lbm_batch **out);
+/* Bytes of the caller-allocated batch state (every case's state back to back). */
+int lbm_batch_state_size(const lbm_batch *batch, size_t *nbytes /* host */);
+/* Byte offset of case c's state inside the batch state: lbm_moments,
+ * lbm_diagnostics, lbm_export_state accept (state + offset) with case c's params. */
+int lbm_batch_case_offset(const lbm_batch *batch, int32_t c, size_t *offset /* host */);
+/* Initialise every case as lbm_init does.  phi0, p0: HOST arrays of ncases
+ * device pointers (p0 may be NULL, or hold NULLs).  Runs the autotuner first
+ * when requested (it synchronises the stream and overwrites the state). */
+int lbm_batch_init(lbm_batch *batch, void *state, const void *const *phi0, const void *const *p0,
+                   void *stream);
+/* Advance every case by nsteps. */
+int lbm_batch_step(lbm_batch *batch, void *state, int64_t nsteps, void *stream);
+/* The tuning in use: tile rows, workgroups per launch, work items per step. */
+int lbm_batch_tuning(const lbm_batch *batch, int32_t *tile_rows, int32_t *grid, int32_t *items);
+int lbm_batch_destroy(lbm_batch *batch);
+
 #ifdef __cplusplus
 }
 #endif

@@ -59,6 +59,13 @@ _SIGS = {
     "lbm_diagnostics": [P(LbmParams), vp, P(ctypes.c_double), vp],
     "lbm_export_state": [P(LbmParams), vp, vp, vp, vp, P(ctypes.c_int64), vp],
     "lbm_import_state": [P(LbmParams), vp, vp, vp, vp, ctypes.c_int64, vp],
+    "lbm_batch_create": [P(LbmParams), ctypes.c_int32, ctypes.c_int32, P(vp)],
+    "lbm_batch_state_size": [vp, P(ctypes.c_size_t)],
+    "lbm_batch_case_offset": [vp, ctypes.c_int32, P(ctypes.c_size_t)],
+    "lbm_batch_init": [vp, vp, P(vp), P(vp), vp],
+    "lbm_batch_step": [vp, vp, ctypes.c_int64, vp],
+    "lbm_batch_tuning": [vp, P(ctypes.c_int32), P(ctypes.c_int32), P(ctypes.c_int32)],
+    "lbm_batch_destroy": [vp],
 }
 _RESTYPE = {"lbm_status_string": ctypes.c_char_p}
 

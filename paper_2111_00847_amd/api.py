@@ -130,3 +130,60 @@ def lbm_import_state(p, state, f, g, hist, step, stream=None):
     call("lbm_import_state", ctypes.byref(p), _state_ptr(state), _ptr(f, p, (9,) + shp, "f"),
          _ptr(g, p, (9,) + shp, "g"), _ptr(hist, p, (3,) + shp, "hist"), int(step),
          _stream(stream))
+
+
+# ---------------------------------------------------------------- batches
+def lbm_batch_create(params, autotune=False) -> ctypes.c_void_p:
+    """Plan a batch of lattices (a list of LbmParams, one dtype); returns the
+    opaque handle, to be released with lbm_batch_destroy."""
+    arr = (LbmParams * len(params))(*params)
+    h = ctypes.c_void_p()
+    call("lbm_batch_create", arr, len(params), 1 if autotune else 0, ctypes.byref(h))
+    return h
+
+
+def lbm_batch_state_size(batch) -> int:
+    n = ctypes.c_size_t()
+    call("lbm_batch_state_size", batch, ctypes.byref(n))
+    return n.value
+
+
+def lbm_batch_case_offset(batch, c: int) -> int:
+    n = ctypes.c_size_t()
+    call("lbm_batch_case_offset", batch, int(c), ctypes.byref(n))
+    return n.value
+
+
+def new_batch_state(batch, device="cuda") -> torch.Tensor:
+    n = lbm_batch_state_size(batch)
+    buf = torch.empty(n + 256, dtype=torch.uint8, device=device)
+    off = (-buf.data_ptr()) % 256
+    return buf[off:off + n]
+
+
+def lbm_batch_init(batch, params, state, phi0s, p0s=None, stream=None):
+    """phi0s / p0s: lists of GPU tensors, one per case (p0s or its entries may be None)."""
+    n = len(params)
+    if len(phi0s) != n or (p0s is not None and len(p0s) != n):
+        raise ValueError("one initial field per case expected")
+    phis = (ctypes.c_void_p * n)(*[_ptr(t, params[c], (params[c].ny, params[c].nx), f"phi0[{c}]")
+                                    for c, t in enumerate(phi0s)])
+    ps = None
+    if p0s is not None:
+        ps = (ctypes.c_void_p * n)(*[_ptr(t, params[c], (params[c].ny, params[c].nx), f"p0[{c}]")
+                                      for c, t in enumerate(p0s)])
+    call("lbm_batch_init", batch, _state_ptr(state), phis, ps, _stream(stream))
+
+
+def lbm_batch_step(batch, state, nsteps=1, stream=None):
+    call("lbm_batch_step", batch, _state_ptr(state), int(nsteps), _stream(stream))
+
+
+def lbm_batch_tuning(batch):
+    ty, g, items = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    call("lbm_batch_tuning", batch, ctypes.byref(ty), ctypes.byref(g), ctypes.byref(items))
+    return dict(tile_rows=ty.value, grid=g.value, items=items.value)
+
+
+def lbm_batch_destroy(batch):
+    call("lbm_batch_destroy", batch)

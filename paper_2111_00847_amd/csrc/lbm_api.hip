@@ -4,6 +4,9 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
+#include <vector>
+
 #include "../../include/lbm.h"
 #include "lbm_kernels.hpp"
 
@@ -132,6 +135,20 @@ int step_tile_rows(const lbm_params* p) {
 
 static thread_local char g_last_error[256];
 
+// Captured graphs of GRAPH_K plain steps, reused while (params, state, stream,
+// tile height) match; a small most-recently-used cache.
+constexpr int GRAPH_K = 32;
+constexpr size_t GRAPH_CACHE = 256;
+struct StepGraph {
+    lbm_params p;
+    void* state;
+    hipStream_t stream;
+    int ty;
+    hipGraphExec_t exec;
+};
+static std::mutex g_graph_mu;
+static std::vector<StepGraph> g_graphs;   // front = most recent
+
 int hip_fail(hipError_t e) {
     snprintf(g_last_error, sizeof g_last_error, "%s", hipGetErrorString(e));
     return LBM_E_HIP;
@@ -192,11 +209,52 @@ int lbm_step(const lbm_params* p, void* state, int64_t nsteps, void* stream) {
     Layout L = layout_of(p);
     hipStream_t s = (hipStream_t)stream;
     int ty = step_tile_rows(p);
+    auto launch = [&](int64_t n) -> hipError_t {
+        if (p->dtype == LBM_F32) return launch_step<float>(resolve<float>(p, L), (char*)state, L, n, s, ty);
+        return launch_step<double>(resolve<double>(p, L), (char*)state, L, n, s, ty);
+    };
     hipError_t e;
-    if (p->dtype == LBM_F32)
-        e = launch_step<float>(resolve<float>(p, L), (char*)state, L, nsteps, s, ty);
-    else
-        e = launch_step<double>(resolve<double>(p, L), (char*)state, L, nsteps, s, ty);
+    // Long runs on a capturable (non-NULL) stream replay a graph of GRAPH_K steps.
+    if (s != nullptr && nsteps >= 2 * GRAPH_K) {
+        std::lock_guard<std::mutex> lock(g_graph_mu);
+        size_t hit = g_graphs.size();
+        for (size_t i = 0; i < g_graphs.size(); i++)
+            if (g_graphs[i].state == state && g_graphs[i].stream == s && g_graphs[i].ty == ty &&
+                memcmp(&g_graphs[i].p, p, sizeof(lbm_params)) == 0) {
+                hit = i;
+                break;
+            }
+        if (hit == g_graphs.size()) {
+            hipGraph_t g;
+            e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) return hip_fail(e);
+            hipError_t le = launch(GRAPH_K);
+            e = hipStreamEndCapture(s, &g);
+            if (le != hipSuccess) return hip_fail(le);
+            if (e != hipSuccess) return hip_fail(e);
+            StepGraph sg{*p, state, s, ty, nullptr};
+            e = hipGraphInstantiate(&sg.exec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) return hip_fail(e);
+            if (g_graphs.size() == GRAPH_CACHE) {
+                (void)hipGraphExecDestroy(g_graphs.back().exec);
+                g_graphs.pop_back();
+            }
+            g_graphs.insert(g_graphs.begin(), sg);
+            hit = 0;
+        } else if (hit != 0) {
+            StepGraph sg = g_graphs[hit];
+            g_graphs.erase(g_graphs.begin() + hit);
+            g_graphs.insert(g_graphs.begin(), sg);
+            hit = 0;
+        }
+        for (int64_t t = 0; t + GRAPH_K <= nsteps; t += GRAPH_K) {
+            e = hipGraphLaunch(g_graphs[0].exec, s);
+            if (e != hipSuccess) return hip_fail(e);
+        }
+        nsteps %= GRAPH_K;
+    }
+    e = launch(nsteps);
     return e == hipSuccess ? LBM_OK : hip_fail(e);
 }
 

@@ -1,0 +1,317 @@
+// lbm_batch.hip -- many independent lattices of uneven sizes advanced by one
+// persistent launch per time step.
+//
+// The batch state is one caller buffer holding every case's own state
+// (same layout as a single lattice, 256-byte aligned, back to back).  A work
+// item is one 64 x TY tile of one case; items are numbered case by case and
+// a persistent grid of G workgroups takes items b, b + G, b + 2G, ...  Each
+// item runs exactly the single-lattice tile body (lbm_fused.hpp) with its
+// case's parameters and level stamps, so a case advanced in a batch is
+// bitwise identical to the same case advanced alone.  The tile height and G
+// are picked per batch by timing the candidates on the batch itself (the
+// autotuner), and K steps are captured once into a hipGraph and replayed.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "lbm_fused.hpp"
+#include "lbm_kernels.hpp"
+
+namespace lbm {
+
+Layout layout_of(const lbm_params* p);
+int validate(const lbm_params* p);
+int hip_fail(hipError_t e);
+template <typename T>
+KParams<T> resolve(const lbm_params* p, const Layout& L);
+
+template <typename T>
+struct BatchCase {
+    KParams<T> P;
+    size_t base;                 // byte offset of the case's state in the batch buffer
+    size_t off0, off1, off_stamp;
+    int ntx, nty;
+    int item_begin;              // first work item of this case
+    int pad;
+};
+
+template <typename T, int TY>
+__global__ __launch_bounds__(TX* BY) __attribute__((amdgpu_waves_per_eu(StepWaves<T, TY>::value)))
+void k_step_batch(const BatchCase<T>* __restrict__ cases, int ncases, int nitems, char* batch_state) {
+    __shared__ T sphi[TY + 2][TX + 3];
+    __shared__ T sphp[TY + 2][TX + 3];
+    for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
+        int lo = 0, hi = ncases - 1;   // last case with item_begin <= w
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (cases[mid].item_begin <= w) lo = mid;
+            else hi = mid - 1;
+        }
+        const BatchCase<T>& C = cases[lo];
+        const int local = w - C.item_begin;
+        step_tile<T, TY, 0, uint32_t>(C.P, batch_state + C.base, C.off0, C.off1, C.off_stamp, local % C.ntx,
+                                      local / C.ntx, nullptr, nullptr, nullptr, sphi, sphp);
+        __syncthreads();   // the next item reuses the LDS window
+    }
+}
+
+}  // namespace lbm
+
+using namespace lbm;
+
+// Library-owned plan of a batch: per-case parameters and state offsets, the
+// device case table for the chosen tile height, the tuning choice and the
+// captured graph.
+struct lbm_batch {
+    int ncases = 0;
+    int dtype = 0;
+    std::vector<lbm_params> params;
+    std::vector<Layout> layouts;
+    std::vector<size_t> base;
+    size_t total = 0;
+    int autotune = 0;
+    bool tuned = false;
+    int ty = 8;
+    int grid = 0;
+    int nitems = 0;
+    void* d_cases = nullptr;
+    int cus = 256;
+    // graph of `graph_steps` launches for (graph_state, graph_stream)
+    hipGraphExec_t graph = nullptr;
+    void* graph_state = nullptr;
+    hipStream_t graph_stream = nullptr;
+    int graph_steps = 0;
+};
+
+namespace {
+
+int tiles_for(const lbm_params& p, int ty, int* ntx, int* nty) {
+    *ntx = (p.nx + TX - 1) / TX;
+    *nty = (p.ny + ty - 1) / ty;
+    return *ntx * *nty;
+}
+
+template <typename T>
+hipError_t upload_cases(lbm_batch* B, int ty) {
+    std::vector<BatchCase<T>> h(B->ncases);
+    int items = 0;
+    for (int c = 0; c < B->ncases; c++) {
+        BatchCase<T>& C = h[c];
+        memset(&C, 0, sizeof(C));
+        C.P = resolve<T>(&B->params[c], B->layouts[c]);
+        C.base = B->base[c];
+        C.off0 = B->layouts[c].off_buf[0];
+        C.off1 = B->layouts[c].off_buf[1];
+        C.off_stamp = B->layouts[c].off_stamp;
+        C.item_begin = items;
+        items += tiles_for(B->params[c], ty, &C.ntx, &C.nty);
+    }
+    B->nitems = items;
+    if (!B->d_cases) {
+        hipError_t e = hipMalloc(&B->d_cases, sizeof(BatchCase<T>) * B->ncases);
+        if (e != hipSuccess) return e;
+    }
+    return hipMemcpy(B->d_cases, h.data(), sizeof(BatchCase<T>) * B->ncases, hipMemcpyHostToDevice);
+}
+
+template <typename T>
+void launch_batch_once(lbm_batch* B, char* state, hipStream_t s) {
+    const int g = B->grid > 0 ? B->grid : B->nitems;
+    const BatchCase<T>* cases = reinterpret_cast<const BatchCase<T>*>(B->d_cases);
+    dim3 blk(TX, BY);
+    if (B->ty == 4) k_step_batch<T, 4><<<g, blk, 0, s>>>(cases, B->ncases, B->nitems, state);
+    else if (B->ty == 8 || sizeof(T) == 8) k_step_batch<T, 8><<<g, blk, 0, s>>>(cases, B->ncases, B->nitems, state);
+    else k_step_batch<T, sizeof(T) == 8 ? 8 : 16><<<g, blk, 0, s>>>(cases, B->ncases, B->nitems, state);
+}
+
+void drop_graph(lbm_batch* B) {
+    if (B->graph) (void)hipGraphExecDestroy(B->graph);
+    B->graph = nullptr;
+    B->graph_state = nullptr;
+    B->graph_stream = nullptr;
+    B->graph_steps = 0;
+}
+
+template <typename T>
+int batch_step_t(lbm_batch* B, char* state, int64_t nsteps, hipStream_t s) {
+    constexpr int K = 32;   // steps per captured graph
+    hipError_t e;
+    if (s != nullptr && nsteps >= K) {
+        if (!B->graph || B->graph_state != state || B->graph_stream != s) {
+            drop_graph(B);
+            hipGraph_t g;
+            e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) return hip_fail(e);
+            for (int k = 0; k < K; k++) launch_batch_once<T>(B, state, s);
+            e = hipStreamEndCapture(s, &g);
+            if (e != hipSuccess) return hip_fail(e);
+            e = hipGraphInstantiate(&B->graph, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) return hip_fail(e);
+            B->graph_state = state;
+            B->graph_stream = s;
+            B->graph_steps = K;
+        }
+        for (int64_t t = 0; t + K <= nsteps; t += K) {
+            e = hipGraphLaunch(B->graph, s);
+            if (e != hipSuccess) return hip_fail(e);
+        }
+        nsteps %= K;
+    }
+    for (int64_t t = 0; t < nsteps; t++) launch_batch_once<T>(B, state, s);
+    e = hipGetLastError();
+    return e == hipSuccess ? LBM_OK : hip_fail(e);
+}
+
+template <typename T>
+int batch_init_cases(lbm_batch* B, char* state, const void* const* phi0, const void* const* p0, hipStream_t s) {
+    for (int c = 0; c < B->ncases; c++) {
+        int rc = lbm_init(&B->params[c], state + B->base[c], phi0[c], nullptr, p0 ? p0[c] : nullptr, s);
+        if (rc) return rc;
+    }
+    return LBM_OK;
+}
+
+// Time every candidate (tile height, persistent grid) on the batch itself and
+// keep the fastest; the state is re-initialised afterwards by the caller.
+template <typename T>
+int autotune_t(lbm_batch* B, char* state, const void* const* phi0, const void* const* p0, hipStream_t s) {
+    const int tys[3] = {4, 8, 16};
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return LBM_E_HIP;
+    float best = 1e30f;
+    int best_ty = 8, best_grid = 0;
+    for (int ty : tys) {
+        if (ty == 16 && sizeof(T) == 8) continue;
+        B->ty = ty;
+        hipError_t e = upload_cases<T>(B, ty);
+        if (e != hipSuccess) return hip_fail(e);
+        const int grids[4] = {0, 2 * B->cus, 4 * B->cus, 8 * B->cus};
+        for (int g : grids) {
+            if (g > B->nitems) continue;
+            B->grid = g;
+            int rc = batch_init_cases<T>(B, state, phi0, p0, s);
+            if (rc) return rc;
+            for (int w = 0; w < 3; w++) launch_batch_once<T>(B, state, s);
+            (void)hipEventRecord(e0, s);
+            for (int w = 0; w < 10; w++) launch_batch_once<T>(B, state, s);
+            (void)hipEventRecord(e1, s);
+            e = hipEventSynchronize(e1);
+            if (e != hipSuccess) return hip_fail(e);
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (ms < best) {
+                best = ms;
+                best_ty = ty;
+                best_grid = g;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    B->ty = best_ty;
+    B->grid = best_grid;
+    hipError_t e = upload_cases<T>(B, best_ty);
+    if (e != hipSuccess) return hip_fail(e);
+    B->tuned = true;
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_batch_create(const lbm_params* cases, int32_t ncases, int32_t autotune, lbm_batch** out) {
+    if (!cases || !out) return LBM_E_NULL;
+    if (ncases < 1) return LBM_E_SIZE;
+    for (int c = 0; c < ncases; c++) {
+        int rc = validate(&cases[c]);
+        if (rc) return rc;
+        if (cases[c].dtype != cases[0].dtype) return LBM_E_DTYPE;
+        Layout L = layout_of(&cases[c]);
+        if (L.buf_bytes >= (size_t(1) << 32)) return LBM_E_SIZE;   // 32-bit offsets within a case
+    }
+    lbm_batch* B = new lbm_batch();
+    B->ncases = ncases;
+    B->dtype = cases[0].dtype;
+    B->autotune = autotune;
+    B->params.assign(cases, cases + ncases);
+    size_t off = 0;
+    for (int c = 0; c < ncases; c++) {
+        Layout L = layout_of(&cases[c]);
+        B->layouts.push_back(L);
+        B->base.push_back(off);
+        off += (L.total + 255) / 256 * 256;
+    }
+    B->total = off;
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess)
+        (void)hipDeviceGetAttribute(&B->cus, hipDeviceAttributeMultiprocessorCount, dev);
+    // default (untuned) choice: 8-row tiles, one workgroup per item
+    B->ty = 8;
+    B->grid = 0;
+    hipError_t e = B->dtype == LBM_F32 ? upload_cases<float>(B, B->ty) : upload_cases<double>(B, B->ty);
+    if (e != hipSuccess) {
+        lbm_batch_destroy(B);
+        return hip_fail(e);
+    }
+    *out = B;
+    return LBM_OK;
+}
+
+int lbm_batch_state_size(const lbm_batch* B, size_t* nbytes) {
+    if (!B || !nbytes) return LBM_E_NULL;
+    *nbytes = B->total;
+    return LBM_OK;
+}
+
+int lbm_batch_case_offset(const lbm_batch* B, int32_t c, size_t* offset) {
+    if (!B || !offset) return LBM_E_NULL;
+    if (c < 0 || c >= B->ncases) return LBM_E_SIZE;
+    *offset = B->base[c];
+    return LBM_OK;
+}
+
+int lbm_batch_init(lbm_batch* B, void* state, const void* const* phi0, const void* const* p0, void* stream) {
+    if (!B || !state || !phi0) return LBM_E_NULL;
+    if ((uintptr_t)state % 256) return LBM_E_SIZE;
+    for (int c = 0; c < B->ncases; c++)
+        if (!phi0[c]) return LBM_E_NULL;
+    hipStream_t s = (hipStream_t)stream;
+    drop_graph(B);
+    if (B->autotune && !B->tuned) {
+        int rc = B->dtype == LBM_F32 ? autotune_t<float>(B, (char*)state, phi0, p0, s)
+                                     : autotune_t<double>(B, (char*)state, phi0, p0, s);
+        if (rc) return rc;
+    }
+    return B->dtype == LBM_F32 ? batch_init_cases<float>(B, (char*)state, phi0, p0, s)
+                               : batch_init_cases<double>(B, (char*)state, phi0, p0, s);
+}
+
+int lbm_batch_step(lbm_batch* B, void* state, int64_t nsteps, void* stream) {
+    if (!B || !state) return LBM_E_NULL;
+    if (nsteps < 0) return LBM_E_SIZE;
+    hipStream_t s = (hipStream_t)stream;
+    return B->dtype == LBM_F32 ? batch_step_t<float>(B, (char*)state, nsteps, s)
+                               : batch_step_t<double>(B, (char*)state, nsteps, s);
+}
+
+int lbm_batch_tuning(const lbm_batch* B, int32_t* tile_rows, int32_t* grid, int32_t* items) {
+    if (!B) return LBM_E_NULL;
+    if (tile_rows) *tile_rows = B->ty;
+    if (grid) *grid = B->grid > 0 ? B->grid : B->nitems;
+    if (items) *items = B->nitems;
+    return LBM_OK;
+}
+
+int lbm_batch_destroy(lbm_batch* B) {
+    if (!B) return LBM_E_NULL;
+    drop_graph(B);
+    if (B->d_cases) (void)hipFree(B->d_cases);
+    delete B;
+    return LBM_OK;
+}
+
+}  // extern "C"

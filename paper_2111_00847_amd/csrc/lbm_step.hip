@@ -16,246 +16,25 @@
 // (TY+2) window, sums them into phi in LDS (the ring's pulls hit L2: those
 // lines are the neighbour tiles' own reads), fills wall ghosts, and then each
 // thread runs the per-node update for TY/4 nodes of its column.
+#include "lbm_fused.hpp"
 #include "lbm_kernels.hpp"
-#include "lbm_tile.hpp"
 
 namespace lbm {
 
-// Tile order: consecutive workgroup ids are dealt round-robin to the 8 XCDs,
-// each with its own L2.  Remap so that XCD j gets a contiguous band of tiles,
-// whose shared halo rows/columns then hit the same L2.
-__device__ __forceinline__ int xcd_tile(int b, int nb) {
-    constexpr int NX = 8;
-    const int q = nb / NX, rem = nb % NX;
-    const int xcd = b % NX, slot = b / NX;
-    // XCDs 0..rem-1 own q+1 tiles, the others q
-    return xcd < rem ? xcd * (q + 1) + slot : rem * (q + 1) + (xcd - rem) * q + slot;
-}
-
-template <typename T, typename OFF>
-__device__ __forceinline__ T ld(const char* base, OFF byteoff) {
-    return *reinterpret_cast<const T*>(base + byteoff);
-}
-// Tuning knobs (compile time, measured on MI355X): non-temporal stores for
-// the streamed state (+3% on a 4096^2 lattice); g loaded after the window
-// barrier (prefetching it with f gained nothing and costs registers); tiles
-// dealt to XCDs in bands (+11% on 256 x 1024, neutral on 4096^2).
-#ifndef LBM_NT_STORES
-#define LBM_NT_STORES 1
-#endif
-#ifndef LBM_PREFETCH_G      // load g together with f, before the window barrier
-#define LBM_PREFETCH_G 0
-#endif
-#ifndef LBM_XCD_REMAP
-#define LBM_XCD_REMAP 1
-#endif
-
-template <typename T, typename OFF>
-__device__ __forceinline__ void st(char* base, OFF byteoff, T v) {
-    if (LBM_NT_STORES) __builtin_nontemporal_store(v, reinterpret_cast<T*>(base + byteoff));
-    else *reinterpret_cast<T*>(base + byteoff) = v;
-}
-
-// The fused step.  One 64 x TY tile per 256-thread workgroup; thread
-// (lx, ly) owns nodes (x0 + lx, y0 + ly + 4 r), r < TY/4, keeps their pulled f
-// in registers from the phi pass to the collision, and the ring of the phi
-// window is pulled by spare threads.  MODE 0: one time step; MODE 1: write
-// phi, u, p of the current level.  OFF: byte-offset type within one copy.
-// FP32 16-row tiles keep four nodes per thread in flight; capping them at 128
-// VGPRs (4 waves per SIMD) is worth +10% on a 4096^2 lattice.  FP64 tiles are
-// never taller than 8 rows (the host caps them): they would spill.
-template <typename T, int TY>
-struct StepWaves {
-    static constexpr int value = (sizeof(T) == 4 && TY >= 16) ? 4 : 1;
-};
-
 template <typename T, int TY, int MODE, typename OFF>
 __global__ __launch_bounds__(TX* BY) __attribute__((amdgpu_waves_per_eu(StepWaves<T, TY>::value)))
-void k_step(KParams<T> P, char* state, size_t off0, size_t off1, size_t off_stamp, int ntx,
-                                                 int nty, T* out_phi, T* out_u, T* out_p) {
-    constexpr int R = TY / BY;
-    constexpr int WX = TX + 2, WY = TY + 2;
-    constexpr OFF ES = sizeof(T);
-    __shared__ T sphi[WY][TX + 3];
-    __shared__ T sphp[WY][TX + 3];
-    const int t = LBM_XCD_REMAP ? xcd_tile(blockIdx.x, ntx * nty) : (int)blockIdx.x;
-    const int xt = t % ntx;
-    const int x0 = xt * TX, y0 = (t / ntx) * TY;
-    int64_t* stamp = reinterpret_cast<int64_t*>(state + off_stamp) + (size_t)xt * P.ny + y0;
-    const int64_t step = stamp[0];
-    const bool first = step == 0;
-    const int cur = (int)(step & 1);
-    const char* src = state + (cur ? off1 : off0);
-    char* dst = state + (cur ? off0 : off1);
-    const Copy<T> S = copy_at<T>(const_cast<char*>(src), P.plane);
-    const OFF pl = (OFF)P.plane;
-    const OFF bF = 8 * pl;               // byte base of f_1; f_i at bF + (i - 1) pl ES
-    const OFF bG = bF + 8 * pl * ES;     // g_i at bG + i pl ES
-    const OFF bH = bG + 9 * pl * ES;     // hist_j at bH + j pl ES
-    const OFF nx = (OFF)P.nx;
-
-    const int lx = threadIdx.x;
-    const int tid = threadIdx.y * TX + lx;
-    const int x = x0 + lx;
-
-    // column neighbours of this thread: index 0 = x-1, 1 = x, 2 = x+1
-    OFF col[3];
-    bool wx[3] = {false, false, false};
-    col[1] = (OFF)x;
-    if (x == 0) {
-        wx[0] = P.wall_x;
-        col[0] = (OFF)(P.nx - 1);
+void k_step(KParams<T> P, char* state, size_t off0, size_t off1, size_t off_stamp, int ntx, int nty, T* out_phi,
+            T* out_u, T* out_p) {
+    __shared__ T sphi[TY + 2][TX + 3];
+    __shared__ T sphp[TY + 2][TX + 3];
+    int xt, yt;
+    if (LBM_XCD_REMAP) {
+        xcd_tile(blockIdx.x, ntx, nty, xt, yt);
     } else {
-        col[0] = (OFF)(x - 1);
+        xt = blockIdx.x % ntx;
+        yt = blockIdx.x / ntx;
     }
-    if (x == P.nx - 1) {
-        wx[2] = P.wall_x;
-        col[2] = 0;
-    } else {
-        col[2] = (OFF)(x + 1);
-    }
-
-    T f[R][9];
-    double phid[R];
-    T gp[LBM_PREFETCH_G ? R : 1][9];
-#pragma unroll
-    for (int r = 0; r < R; r++) {
-        const int ly = threadIdx.y + r * BY, y = y0 + ly;
-        phid[r] = 0.0;
-        if (x >= P.nx || y >= P.ny) continue;
-        OFF row[3];
-        bool wy[3] = {false, false, false};
-        row[1] = (OFF)y * nx;
-        if (y == 0) {
-            wy[0] = P.wall_y;
-            row[0] = (OFF)(P.ny - 1) * nx;
-        } else {
-            row[0] = (OFF)(y - 1) * nx;
-        }
-        if (y == P.ny - 1) {
-            wy[2] = P.wall_y;
-            row[2] = 0;
-        } else {
-            row[2] = (OFF)(y + 1) * nx;
-        }
-        const OFF k = row[1] + col[1];
-        const double f0 = ld<double>(src, (OFF)8 * k);
-        f[r][0] = (T)f0;
-#pragma unroll
-        for (int i = 1; i < Q; i++) {
-            const int ax = 1 - cx(i), ay = 1 - cy(i);
-            const bool bb = wx[ax] || wy[ay];
-            const OFF o = bb ? bF + ((OFF)(opp(i) - 1) * pl + k) * ES : bF + ((OFF)(i - 1) * pl + row[ay] + col[ax]) * ES;
-            f[r][i] = ld<T>(src, o);
-        }
-        phid[r] = f0 + moving_sum_d(f[r]);
-        sphi[ly + 1][lx + 1] = (T)phid[r];
-        if (!first) sphp[ly + 1][lx + 1] = ld<T>(src, bH + k * ES);
-        if (LBM_PREFETCH_G) {
-#pragma unroll
-            for (int i = 0; i < Q; i++) {
-                const int ax = 1 - cx(i), ay = 1 - cy(i);
-                const bool bb = wx[ax] || wy[ay];
-                const OFF o = bb ? bG + ((OFF)opp(i) * pl + k) * ES : bG + ((OFF)i * pl + row[ay] + col[ax]) * ES;
-                gp[LBM_PREFETCH_G ? r : 0][i] = ld<T>(src, o);
-            }
-        }
-    }
-
-    // ring of the window (and, for a ragged tile, the halo column/row inside it)
-    auto fill_node = [&](int wxi, int wyi) {
-        int gx = x0 - 1 + wxi, gy = y0 - 1 + wyi;
-        if (gx > P.nx || gy > P.ny) return;
-        if (gx < 0 || gx >= P.nx) {
-            if (P.wall_x) return;
-            gx = gx < 0 ? gx + P.nx : gx - P.nx;
-        }
-        if (gy < 0 || gy >= P.ny) {
-            if (P.wall_y) return;
-            gy = gy < 0 ? gy + P.ny : gy - P.ny;
-        }
-        T fw[9];
-        sphi[wyi][wxi] = (T)node_phi(P, S, gx, gy, fw);
-        if (!first) sphp[wyi][wxi] = S.h[(long long)gy * P.nx + gx];
-    };
-    for (int idx = tid; idx < 2 * WX + 2 * TY; idx += TX * BY) {
-        if (idx < WX) fill_node(idx, 0);
-        else if (idx < 2 * WX) fill_node(idx - WX, WY - 1);
-        else if (idx < 2 * WX + TY) fill_node(0, 1 + idx - 2 * WX);
-        else fill_node(WX - 1, 1 + idx - 2 * WX - TY);
-    }
-    if (x0 + TX > P.nx)
-        for (int wy = tid; wy < WY; wy += TX * BY) fill_node(P.nx - x0 + 1, wy);
-    if (y0 + TY > P.ny)
-        for (int wxi = tid; wxi < WX; wxi += TX * BY) fill_node(wxi, P.ny - y0 + 1);
-    __syncthreads();
-    wall_ghosts<T, TY>(P, !first, x0, y0, sphi, sphp);
-
-#pragma unroll
-    for (int r = 0; r < R; r++) {
-        const int ly = threadIdx.y + r * BY, y = y0 + ly;
-        if (x >= P.nx || y >= P.ny) continue;
-        OFF row[3];
-        bool wy[3] = {false, false, false};
-        row[1] = (OFF)y * nx;
-        if (y == 0) {
-            wy[0] = P.wall_y;
-            row[0] = (OFF)(P.ny - 1) * nx;
-        } else {
-            row[0] = (OFF)(y - 1) * nx;
-        }
-        if (y == P.ny - 1) {
-            wy[2] = P.wall_y;
-            row[2] = 0;
-        } else {
-            row[2] = (OFF)(y + 1) * nx;
-        }
-        const OFF k = row[1] + col[1];
-        T g[9];
-#pragma unroll
-        for (int i = 0; i < Q; i++) {
-            if (LBM_PREFETCH_G) {
-                g[i] = gp[LBM_PREFETCH_G ? r : 0][i];
-            } else {
-                const int ax = 1 - cx(i), ay = 1 - cy(i);
-                const bool bb = wx[ax] || wy[ay];
-                const OFF o = bb ? bG + ((OFF)opp(i) * pl + k) * ES : bG + ((OFF)i * pl + row[ay] + col[ax]) * ES;
-                g[i] = ld<T>(src, o);
-            }
-        }
-        T gx, gy, lap, gxp = T(0), gyp = T(0), lp, php = T(0), up = T(0), vp = T(0);
-        win_stencil<T, TY>(sphi, lx + 1, ly + 1, gx, gy, lap);
-        if (!first) {
-            win_stencil<T, TY>(sphp, lx + 1, ly + 1, gxp, gyp, lp);
-            php = sphp[ly + 1][lx + 1];
-            up = ld<T>(src, bH + (pl + k) * ES);
-            vp = ld<T>(src, bH + (2 * pl + k) * ES);
-        }
-        Macro<T> M = macro(P, g, sphi[ly + 1][lx + 1], gx, gy, lap, first, php, gxp, gyp, up, vp);
-        if (MODE == 1) {
-            if (out_phi) out_phi[k] = M.phi;
-            if (out_u) {
-                out_u[k] = M.u;
-                out_u[(long long)P.nx * P.ny + k] = M.v;
-            }
-            if (out_p) out_p[k] = M.p;
-            continue;
-        }
-        const double f0n = collide_f(P, M, f[r], phid[r]);
-        collide_g(P, M, g);
-        st<double>(dst, (OFF)8 * k, f0n);
-#pragma unroll
-        for (int i = 1; i < Q; i++) st<T>(dst, bF + ((OFF)(i - 1) * pl + k) * ES, f[r][i]);
-#pragma unroll
-        for (int i = 0; i < Q; i++) st<T>(dst, bG + ((OFF)i * pl + k) * ES, g[i]);
-        st<T>(dst, bH + k * ES, M.phi);
-        st<T>(dst, bH + (pl + k) * ES, M.u);
-        st<T>(dst, bH + (2 * pl + k) * ES, M.v);
-    }
-    // Own rows move to level n + 1.  Every wave of the workgroup consumed its
-    // load of stamp[0] (it addresses all loads above) before the barriers, so
-    // no wave can still be about to read it.
-    if (MODE == 0 && tid < TY && y0 + tid < P.ny) stamp[tid] = step + 1;
+    step_tile<T, TY, MODE, OFF>(P, state, off0, off1, off_stamp, xt, yt, out_phi, out_u, out_p, sphi, sphp);
 }
 
 // ---------------------------------------------------------------- init / import / export

@@ -90,3 +90,20 @@ def test_status_strings():
     from paper_2111_00847_amd._lib import lib
     for c in range(-8, 1):
         assert lib().lbm_status_string(c)
+
+
+def test_batch_create_validation():
+    """lbm_batch_create rejects bad arguments on the host before any HIP call."""
+    from paper_2111_00847_amd._lib import LbmParams, lib
+    L = lib()
+    h = ctypes.c_void_p()
+    good = _params(dtype="f32")
+    arr1 = (LbmParams * 1)(good)
+    assert L.lbm_batch_create(None, 1, 0, ctypes.byref(h)) == -1
+    assert L.lbm_batch_create(arr1, 1, 0, None) == -1
+    assert L.lbm_batch_create(arr1, 0, 0, ctypes.byref(h)) == -2
+    assert L.lbm_batch_create((LbmParams * 2)(good, _params(dtype="f64")), 2, 0, ctypes.byref(h)) == -3
+    assert L.lbm_batch_create((LbmParams * 2)(good, _params(W=-1.0)), 2, 0, ctypes.byref(h)) == -4
+    assert L.lbm_batch_state_size(None, None) == -1
+    assert L.lbm_batch_step(None, None, 1, None) == -1
+    assert L.lbm_batch_destroy(None) == -1

@@ -1,0 +1,113 @@
+"""Batched execution of many uneven lattices (one persistent launch per step)
+and the captured-graph path of the plain step, through the C ABI.
+
+A case advanced inside a batch runs the same per-node arithmetic as the case
+advanced alone, so the two are compared bitwise; one FP64 batch is also
+compared with the oracle directly.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _mods():
+    from paper_2111_00847_amd.sim import BatchSim, Sim
+    return Sim, BatchSim
+
+
+def _mixed_cases(dtype):
+    """Six cases of unequal, partly ragged sizes and both boundary kinds."""
+    out = []
+    for k, (nx, ny, th) in enumerate([(128, 64, 40.0), (70, 37, 120.0), (256, 128, 95.0),
+                                       (33, 90, 60.0), (128, 64, 150.0), (200, 9, 75.0)]):
+        case, phi0 = W.spreading_case(nx, ny, th, dtype=dtype, R0=min(nx, 2 * ny) / 6.0)
+        out.append((case, phi0))
+    dam, phid = W.dam_break(nx=96, ny=40, column=24, dtype=dtype, theta_deg=70.0)
+    out.append((dam, phid))
+    return out
+
+
+def _assert_same_state(a, b, what):
+    sa, sb = a.export_state(), b.export_state()
+    assert sa["step"] == sb["step"], what
+    for key in ("f", "g", "hist"):
+        ta, tb = sa[key].cpu().numpy(), sb[key].cpu().numpy()
+        assert np.array_equal(ta, tb), (what, key, float(np.abs(ta - tb).max()))
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("mode", ["eager_default_stream", "graph_side_stream", "autotuned_graph"])
+def test_batch_bitwise_equals_single(dtype, mode):
+    Sim, BatchSim = _mods()
+    cases = _mixed_cases(dtype)
+    p0s = [W.hydrostatic_pressure(c, p) for c, p in cases]
+    stream = None if mode == "eager_default_stream" else torch.cuda.Stream()
+    B = BatchSim([c for c, _ in cases], autotune=(mode == "autotuned_graph"), stream=stream)
+    B.init([p for _, p in cases], p0s)
+    print(f"batch {dtype} {mode}: tuning {B.tuning()}", flush=True)
+    steps = 75                         # two graph replays of 32 plus 11 eager launches
+    B.step(steps)
+    for c, ((case, phi0), p0) in enumerate(zip(cases, p0s)):
+        alone = Sim(case).init(phi0, None, p0).step(steps)
+        torch.cuda.synchronize()
+        _assert_same_state(B.case(c), alone, f"case {c} {case.name}")
+    d = B.case(2).diagnostics()
+    assert d["nonfinite"] == 0
+
+
+def test_batch_fp64_against_oracle():
+    Sim, BatchSim = _mods()
+    cases = _mixed_cases("f64")[:3]
+    B = BatchSim([c for c, _ in cases], stream=torch.cuda.Stream())
+    B.init([p for _, p in cases], [W.hydrostatic_pressure(c, p) for c, p in cases]).step(120)
+    torch.cuda.synchronize()
+    for c, (case, phi0) in enumerate(cases):
+        o = oracle.OracleSim(case).init(phi0, None, W.hydrostatic_pressure(case, phi0)).step(120)
+        for a, b in zip(B.case(c).moments_np(), o.moments()):
+            assert np.abs(a - b).max() <= 1e-10 * max(1.0, np.abs(b).max())
+
+
+def test_batch_autotune_choice_and_reinit():
+    """The autotuner returns a valid tuning and leaves every case at step 0 with
+    its initial field."""
+    Sim, BatchSim = _mods()
+    cases = W.spreading_batch(ncases=8, dtype="f32")
+    B = BatchSim([c for c, _ in cases], autotune=True)
+    B.init([p for _, p in cases])
+    t = B.tuning()
+    assert t["tile_rows"] in (4, 8, 16) and 1 <= t["grid"] <= t["items"]
+    for c, (case, phi0) in enumerate(cases):
+        s = B.case(c)
+        assert s.export_state()["step"] == 0
+        phi, _, _ = s.moments_np()
+        assert np.abs(phi - phi0).max() < 1e-6
+
+
+def test_plain_step_graph_equals_eager():
+    """lbm_step on a side stream replays a captured graph of 32 steps; the result
+    equals the eager launches on the default stream bitwise."""
+    Sim, _ = _mods()
+    case, phi0 = W.rti(nx=128, ny=256)
+    p0 = W.hydrostatic_pressure(case, phi0)
+    a = Sim(case).init(phi0, None, p0).step(101)
+    s = torch.cuda.Stream()
+    b = Sim(case, stream=s).init(phi0, None, p0)
+    b.step(70)
+    b.step(31)                         # graph cache hit, then eager remainder
+    torch.cuda.synchronize()
+    _assert_same_state(a, b, "rti 128x256 graph vs eager")
+
+
+def test_batch_case_view_rejects_bad_index():
+    from paper_2111_00847_amd._lib import LbmError
+    _, BatchSim = _mods()
+    cases = _mixed_cases("f32")[:2]
+    B = BatchSim([c for c, _ in cases])
+    with pytest.raises(LbmError):
+        B.case(2)
