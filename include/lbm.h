@@ -33,7 +33,7 @@
  *  - A state buffer is opaque: its size is given by lbm_state_size, it must
  *    be 256-byte aligned, it is written only by lbm_init / lbm_import_state /
  *    lbm_step, and it holds everything a step needs (both ping-pong copies of
- *    the populations, the Euler history, the step counter).  A device-to-
+ *    the populations, the Euler history, the level stamps).  A device-to-
  *    device copy of it is a checkpoint; a state may only be used with the
  *    lbm_params it was initialised with.
  */
@@ -137,6 +137,55 @@ int lbm_export_state(const lbm_params *p, const void *state, void *f, void *g, v
  * n-1 history (ignored when n == 0) as the state of step n. */
 int lbm_import_state(const lbm_params *p, void *state, const void *f, const void *g,
                      const void *hist, int64_t step, void *stream);
+
+/* ---- reverse mode: tapes and the adjoint step ------------------------------
+ * The adjoint of the step map S^n -> S^{n+1} (Sec. 3, as lbm_step computes it)
+ * for a loss L(phi^N): given dL/dS^{n+1}, lbm_adjoint_step forms
+ * dL/dS^n = (dS^{n+1}/dS^n)^T dL/dS^{n+1} and accumulates dL/d(gravity) and
+ * dL/d(theta) of that step.  The adjoint of level n holds dL/df^n, dL/dg^n
+ * (post-streaming populations, [9][ny][nx] each) and dL/d(phi, u, v) of the
+ * history stored at level n (the fields of level n-1, [3][ny][nx]).
+ * A backward pass over levels N-1 .. 0:
+ *   lbm_adjoint_phi(state at level N, dL/dphi^N)        -- starts the pass
+ *   for each segment, newest first: lbm_tape_record from the segment's first
+ *   level, then lbm_adjoint_step(tape, j) for j = L-1 .. 0
+ *   lbm_adjoint_init -> dL/dphi0; lbm_adjoint_params -> dL/dgravity, dL/dtheta.
+ * Level mismatches (a step whose tape level is not one below the adjoint's)
+ * are detected on the device; the step is skipped and lbm_adjoint_params then
+ * returns LBM_E_PARAM.  Adjoint and tape buffers are caller-owned device
+ * memory, 256-byte aligned, in the dtype of the params. */
+
+/* Bytes of a tape of `nlevels` consecutive levels. */
+int lbm_tape_size(const lbm_params *p, int32_t nlevels, size_t *nbytes /* host */);
+/* Record levels n .. n + nlevels - 1 into `tape`, n being the level of
+ * `state` (which is not modified): a copy of its current level, then
+ * nlevels - 1 ordinary steps run from tape slot to tape slot (bitwise the
+ * levels lbm_step would produce). */
+int lbm_tape_record(const lbm_params *p, const void *state, void *tape, int32_t nlevels, void *stream);
+/* Bytes of an adjoint buffer. */
+int lbm_adjoint_size(const lbm_params *p, size_t *nbytes /* host */);
+/* Start a backward pass at the level N of `state`: dL/df_i^N = dL/dphi^N for
+ * all i (phi = sum_i f_i), all other adjoints and the parameter sums zero.
+ * dL_dphi: [ny][nx]. */
+int lbm_adjoint_phi(const lbm_params *p, const void *state, void *adj, const void *dL_dphi, void *stream);
+/* One adjoint step: adj holds level n + 1 on entry and level n on return,
+ * n = (first level of the tape) + j; the forward level n is tape slot j. */
+int lbm_adjoint_step(const lbm_params *p, const void *tape, int32_t j, void *adj, void *stream);
+/* dL/dphi0 ([ny][nx]) from the adjoint of level 0, through lbm_init with
+ * u0 = NULL (f^0 = w_i phi0; p0 is held fixed).  Writes NaN if the adjoint is
+ * not at level 0. */
+int lbm_adjoint_init(const lbm_params *p, const void *adj, void *dL_dphi0, void *stream);
+/* Sums of the parameter derivatives accumulated since the pass started, to
+ * HOST out[6] = dL/dgravity[0..1], dL/dtheta[0..3]; `level` (host, may be
+ * NULL) receives the adjoint's level.  Synchronises the stream. */
+int lbm_adjoint_params(const lbm_params *p, const void *adj, double *out /* host [6] */, int64_t *level,
+                       void *stream);
+/* Copy the adjoint of the current level out ([9][ny][nx], [9][ny][nx],
+ * [3][ny][nx]; any may be NULL), or load one as the adjoint of `level`
+ * (NULL arrays load zeros; the parameter sums restart at zero). */
+int lbm_adjoint_export(const lbm_params *p, const void *adj, void *fbar, void *gbar, void *hbar, void *stream);
+int lbm_adjoint_import(const lbm_params *p, void *adj, const void *fbar, const void *gbar, const void *hbar,
+                       int64_t level, void *stream);
 
 /* ---- batches: many independent lattices, one launch per time step ---------
  * (the batched execution row of the build: the per-step update above applied

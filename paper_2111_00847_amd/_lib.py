@@ -59,6 +59,15 @@ _SIGS = {
     "lbm_diagnostics": [P(LbmParams), vp, P(ctypes.c_double), vp],
     "lbm_export_state": [P(LbmParams), vp, vp, vp, vp, P(ctypes.c_int64), vp],
     "lbm_import_state": [P(LbmParams), vp, vp, vp, vp, ctypes.c_int64, vp],
+    "lbm_tape_size": [P(LbmParams), ctypes.c_int32, P(ctypes.c_size_t)],
+    "lbm_tape_record": [P(LbmParams), vp, vp, ctypes.c_int32, vp],
+    "lbm_adjoint_size": [P(LbmParams), P(ctypes.c_size_t)],
+    "lbm_adjoint_phi": [P(LbmParams), vp, vp, vp, vp],
+    "lbm_adjoint_step": [P(LbmParams), vp, ctypes.c_int32, vp, vp],
+    "lbm_adjoint_init": [P(LbmParams), vp, vp, vp],
+    "lbm_adjoint_params": [P(LbmParams), vp, P(ctypes.c_double), P(ctypes.c_int64), vp],
+    "lbm_adjoint_export": [P(LbmParams), vp, vp, vp, vp, vp],
+    "lbm_adjoint_import": [P(LbmParams), vp, vp, vp, vp, ctypes.c_int64, vp],
     "lbm_batch_create": [P(LbmParams), ctypes.c_int32, ctypes.c_int32, P(vp)],
     "lbm_batch_state_size": [vp, P(ctypes.c_size_t)],
     "lbm_batch_case_offset": [vp, ctypes.c_int32, P(ctypes.c_size_t)],

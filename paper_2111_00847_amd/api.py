@@ -132,6 +132,74 @@ def lbm_import_state(p, state, f, g, hist, step, stream=None):
          _stream(stream))
 
 
+# ---------------------------------------------------------------- reverse mode
+def _buffer(nbytes, device):
+    buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    off = (-buf.data_ptr()) % 256
+    return buf[off:off + nbytes]
+
+
+def lbm_tape_size(p, nlevels) -> int:
+    n = ctypes.c_size_t()
+    call("lbm_tape_size", ctypes.byref(p), int(nlevels), ctypes.byref(n))
+    return n.value
+
+
+def new_tape(p, nlevels, device="cuda") -> torch.Tensor:
+    return _buffer(lbm_tape_size(p, nlevels), device)
+
+
+def lbm_tape_record(p, state, tape, nlevels, stream=None):
+    call("lbm_tape_record", ctypes.byref(p), _state_ptr(state), _state_ptr(tape), int(nlevels), _stream(stream))
+
+
+def lbm_adjoint_size(p) -> int:
+    n = ctypes.c_size_t()
+    call("lbm_adjoint_size", ctypes.byref(p), ctypes.byref(n))
+    return n.value
+
+
+def new_adjoint(p, device="cuda") -> torch.Tensor:
+    return _buffer(lbm_adjoint_size(p), device)
+
+
+def lbm_adjoint_phi(p, state, adj, dL_dphi, stream=None):
+    call("lbm_adjoint_phi", ctypes.byref(p), _state_ptr(state), _state_ptr(adj),
+         _ptr(dL_dphi, p, (p.ny, p.nx), "dL_dphi"), _stream(stream))
+
+
+def lbm_adjoint_step(p, tape, j, adj, stream=None):
+    call("lbm_adjoint_step", ctypes.byref(p), _state_ptr(tape), int(j), _state_ptr(adj), _stream(stream))
+
+
+def lbm_adjoint_init(p, adj, dL_dphi0, stream=None):
+    call("lbm_adjoint_init", ctypes.byref(p), _state_ptr(adj), _ptr(dL_dphi0, p, (p.ny, p.nx), "dL_dphi0"),
+         _stream(stream))
+
+
+ADJ_PARAM_NAMES = ("gravity_x", "gravity_y", "theta_xm", "theta_xp", "theta_ym", "theta_yp")
+
+
+def lbm_adjoint_params(p, adj, stream=None):
+    """Returns (out[6], level): dL/dgravity (2), dL/dtheta (4) and the adjoint's level."""
+    out = (ctypes.c_double * 6)()
+    lev = ctypes.c_int64()
+    call("lbm_adjoint_params", ctypes.byref(p), _state_ptr(adj), out, ctypes.byref(lev), _stream(stream))
+    return list(out), lev.value
+
+
+def lbm_adjoint_export(p, adj, fbar=None, gbar=None, hbar=None, stream=None):
+    shp = (p.ny, p.nx)
+    call("lbm_adjoint_export", ctypes.byref(p), _state_ptr(adj), _ptr(fbar, p, (9,) + shp, "fbar"),
+         _ptr(gbar, p, (9,) + shp, "gbar"), _ptr(hbar, p, (3,) + shp, "hbar"), _stream(stream))
+
+
+def lbm_adjoint_import(p, adj, fbar, gbar, hbar, level, stream=None):
+    shp = (p.ny, p.nx)
+    call("lbm_adjoint_import", ctypes.byref(p), _state_ptr(adj), _ptr(fbar, p, (9,) + shp, "fbar"),
+         _ptr(gbar, p, (9,) + shp, "gbar"), _ptr(hbar, p, (3,) + shp, "hbar"), int(level), _stream(stream))
+
+
 # ---------------------------------------------------------------- batches
 def lbm_batch_create(params, autotune=False) -> ctypes.c_void_p:
     """Plan a batch of lattices (a list of LbmParams, one dtype); returns the

@@ -109,6 +109,7 @@ KParams<T> resolve(const lbm_params* p, const Layout& L) {
         K.wa[k] = (T)a;
         K.wb[k] = (T)(8.0 / 3.0 - a * (p->phi_A + p->phi_B));
         K.wc0[k] = (T)(a * p->phi_A * p->phi_B);
+        K.wda[k] = (T)(-4.0 * sin(p->theta[k]) / (p->W * dphi));
     }
     K.rho0 = (T)p->rho0;
     K.eps2 = (T)(p->eps_n * p->eps_n);

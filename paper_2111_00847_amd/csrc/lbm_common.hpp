@@ -60,6 +60,7 @@ struct KParams {
     T sf[9], sg[9];
     T Gx, Gy, gx, gy, rho_ref;
     T wa[4], wb[4], wc0[4];  // wetting quadratic per wall (x-, x+, y-, y+): a, b, a phiA phiB
+    T wda[4];                // d a / d theta per wall
     T rho0, eps2;
     T Hp;                 // H of App. C: (s_g^2 - s_g^0)/(9 s_g^0 s_g^2)
 };

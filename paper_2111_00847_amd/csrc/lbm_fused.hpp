@@ -64,20 +64,18 @@ struct StepWaves {
     static constexpr int value = (sizeof(T) == 4 && TY >= 16) ? 4 : 1;
 };
 
+// The tile body between explicit buffers: `src` holds level `step` (one copy:
+// post-collision populations of the previous step and the history), `dst`
+// receives level step + 1.
 template <typename T, int TY, int MODE, typename OFF>
-__device__ __forceinline__ void step_tile(const KParams<T>& P, char* state, size_t off0, size_t off1,
-                                          size_t off_stamp, int xt, int yt, T* out_phi, T* out_u, T* out_p,
-                                          T (*sphi)[TX + 3], T (*sphp)[TX + 3]) {
+__device__ __forceinline__ void step_core(const KParams<T>& P, const char* src, char* dst, int64_t step, int xt,
+                                          int yt, T* out_phi, T* out_u, T* out_p, T (*sphi)[TX + 3],
+                                          T (*sphp)[TX + 3]) {
     constexpr int R = TY / BY;
     constexpr int WX = TX + 2, WY = TY + 2;
     constexpr OFF ES = sizeof(T);
     const int x0 = xt * TX, y0 = yt * TY;
-    int64_t* stamp = reinterpret_cast<int64_t*>(state + off_stamp) + (size_t)xt * P.ny + y0;
-    const int64_t step = stamp[0];
     const bool first = step == 0;
-    const int cur = (int)(step & 1);
-    const char* src = state + (cur ? off1 : off0);
-    char* dst = state + (cur ? off0 : off1);
     const Copy<T> S = copy_at<T>(const_cast<char*>(src), P.plane);
     const OFF pl = (OFF)P.plane;
     const OFF bF = 8 * pl;               // byte base of f_1; f_i at bF + (i - 1) pl ES
@@ -229,9 +227,24 @@ __device__ __forceinline__ void step_tile(const KParams<T>& P, char* state, size
         st<T>(dst, bH + (pl + k) * ES, M.u);
         st<T>(dst, bH + (2 * pl + k) * ES, M.v);
     }
+}
+
+// The tile body on a ping-pong state: the level stamp of the tile's first row
+// selects the source copy, and the tile's rows move to the next level.
+template <typename T, int TY, int MODE, typename OFF>
+__device__ __forceinline__ void step_tile(const KParams<T>& P, char* state, size_t off0, size_t off1,
+                                          size_t off_stamp, int xt, int yt, T* out_phi, T* out_u, T* out_p,
+                                          T (*sphi)[TX + 3], T (*sphp)[TX + 3]) {
+    const int y0 = yt * TY;
+    int64_t* stamp = reinterpret_cast<int64_t*>(state + off_stamp) + (size_t)xt * P.ny + y0;
+    const int64_t step = stamp[0];
+    const int cur = (int)(step & 1);
+    step_core<T, TY, MODE, OFF>(P, state + (cur ? off1 : off0), state + (cur ? off0 : off1), step, xt, yt, out_phi,
+                                out_u, out_p, sphi, sphp);
     // Own rows move to level n + 1.  Every wave of the workgroup consumed its
-    // load of stamp[0] (it addresses all loads above) before the barriers, so
-    // no wave can still be about to read it.
+    // load of stamp[0] (it addresses all loads above) before the barriers of
+    // the body, so no wave can still be about to read it.
+    const int tid = threadIdx.y * TX + threadIdx.x;
     if (MODE == 0 && tid < TY && y0 + tid < P.ny) stamp[tid] = step + 1;
 }
 

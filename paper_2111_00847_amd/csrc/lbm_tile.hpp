@@ -30,8 +30,10 @@ __device__ __forceinline__ void wall_ghosts(const KParams<T>& P, bool need_prev,
     if (P.wall_x) {
         const int wxr = P.nx - x0 + 1;  // window column of x = nx
         for (int wy = tid; wy < WY; wy += TX * BY) {
-            int gy = y0 - 1 + wy;
-            if (gy < 0 || gy >= P.ny) continue;
+            // rows beyond a y-wall get their ghosts below; on a periodic y axis
+            // the halo rows -1 and ny hold wrapped rows and need x-ghosts too
+            const int gy = y0 - 1 + wy;
+            if (gy > P.ny || (P.wall_y && (gy < 0 || gy >= P.ny))) continue;
             if (x0 == 0) {
                 sphi[wy][0] = wet_ghost(P, 0, sphi[wy][1], sphi[wy][2]);
                 if (need_prev) sphp[wy][0] = wet_ghost(P, 0, sphp[wy][1], sphp[wy][2]);

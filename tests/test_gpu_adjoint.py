@@ -1,0 +1,235 @@
+"""The hand-written adjoint (lbm_adjoint_step and the autograd Function) against
+the differentiable CPU reference (oracle/torch_ref.py) and against central
+finite differences of the GPU forward.
+
+FP64 throughout, except the last test: one adjoint step equals the autograd
+vector-Jacobian product of one reference step element by element (1e-11 of
+the largest entry); whole-trajectory gradients equal the reference's to 1e-9
+relative; on the 64 x 32 copy of the dam break the gradients equal central
+finite differences to 1e-4 relative.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+GEOMS = {
+    "periodic": dict(),
+    "walls_x": dict(wall_x=True, theta=(math.radians(60), math.radians(130), math.pi / 2, math.pi / 2)),
+    "walls_y": dict(wall_y=True, theta=(math.pi / 2, math.pi / 2, math.radians(50), math.radians(120))),
+    "walls_xy": dict(wall_x=True, wall_y=True,
+                     theta=(math.radians(70), math.radians(110), math.radians(40), math.radians(140))),
+}
+
+
+def _case(geom, nx=37, ny=23, **kw):
+    base = dict(nx=nx, ny=ny, rhoA=20.0, rhoB=1.0, nuA=0.05, nuB=0.2, sigma=0.01, W=4.0, M=0.05,
+                body_force=(1e-6, -2e-6), gravity=(3e-6, -1e-5), rho_ref=3.0, dtype="f64")
+    return W.Case(**{**base, **GEOMS[geom], **kw})
+
+
+def _random_state(case, seed):
+    phi0, u0, p0 = W.random_state_fields(case, seed=seed)
+    st = oracle.OracleSim(case).init(phi0, u0, p0).get_state()
+    rng = np.random.default_rng(seed + 1)
+    f = st["f"] + 1e-4 * rng.standard_normal(st["f"].shape)
+    g = st["g"] + 1e-5 * rng.standard_normal(st["g"].shape)
+    php = phi0 + 1e-3 * rng.standard_normal(phi0.shape)
+    upr = u0 + 1e-4 * rng.standard_normal(u0.shape)
+    return f, g, php, upr
+
+
+def _api():
+    from paper_2111_00847_amd import api
+    from paper_2111_00847_amd.sim import Sim
+    return api, Sim
+
+
+def _close(a, b, tol, what):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    scale = max(np.abs(b).max(), 1e-300)
+    err = np.abs(a - b).max() / scale
+    print(f"{what}: rel err {err:.2e} (scale {scale:.3e})", flush=True)
+    assert err <= tol, (what, err)
+
+
+@pytest.mark.parametrize("geom", list(GEOMS))
+@pytest.mark.parametrize("n", [0, 5])
+@pytest.mark.parametrize("visc", ["linear_mu", "inverse_nu"])
+def test_one_adjoint_step_equals_reference_vjp(geom, n, visc):
+    from oracle.torch_ref import TorchRef, as_params
+    api, Sim = _api()
+    case = _case(geom, visc_law=visc)
+    f, g, php, upr = _random_state(case, seed=3 + n)
+    hist = np.concatenate([php[None], upr], 0)
+    s = Sim(case).import_state(f, g, hist if n > 0 else None, n)
+    p = s.p
+    tape = api.new_tape(p, 1)
+    api.lbm_tape_record(p, s.state, tape, 1)
+    rng = np.random.default_rng(100 + n)
+    fb1 = rng.standard_normal((9, case.ny, case.nx))
+    gb1 = rng.standard_normal((9, case.ny, case.nx))
+    hb1 = rng.standard_normal((3, case.ny, case.nx))
+    cuda = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")
+    adj = api.new_adjoint(p)
+    api.lbm_adjoint_import(p, adj, cuda(fb1), cuda(gb1), cuda(hb1), n + 1)
+    api.lbm_adjoint_step(p, tape, 0, adj)
+    fb0 = torch.empty((9, case.ny, case.nx), dtype=torch.float64, device="cuda")
+    gb0 = torch.empty_like(fb0)
+    hb0 = torch.empty((3, case.ny, case.nx), dtype=torch.float64, device="cuda")
+    api.lbm_adjoint_export(p, adj, fb0, gb0, hb0)
+    prm, level = api.lbm_adjoint_params(p, adj)
+    assert level == n
+
+    ref = TorchRef(case)
+    grav, theta = as_params(case)
+    st = dict(f=torch.tensor(f, requires_grad=True), g=torch.tensor(g, requires_grad=True),
+              phi_prev=torch.tensor(php, requires_grad=True), u_prev=torch.tensor(upr, requires_grad=True), n=n)
+    out = ref.step(st, grav, theta)
+    J = (out["f"] * torch.tensor(fb1)).sum() + (out["g"] * torch.tensor(gb1)).sum() \
+        + (out["phi_prev"] * torch.tensor(hb1[0])).sum() + (out["u_prev"] * torch.tensor(hb1[1:])).sum()
+    J.backward()
+    tag = f"{geom} n={n} {visc}"
+    _close(fb0.cpu().numpy(), st["f"].grad.numpy(), 1e-11, tag + " fbar")
+    _close(gb0.cpu().numpy(), st["g"].grad.numpy(), 1e-11, tag + " gbar")
+    if n > 0:
+        _close(hb0[0].cpu().numpy(), st["phi_prev"].grad.numpy(), 1e-11, tag + " phi_prev bar")
+        _close(hb0[1:].cpu().numpy(), st["u_prev"].grad.numpy(), 1e-11, tag + " u_prev bar")
+    else:
+        assert float(hb0.abs().max()) == 0.0
+    _close(prm[0:2], grav.grad.numpy(), 1e-10, tag + " dgravity")
+    if geom != "periodic":
+        _close(prm[2:6], theta.grad.numpy(), 1e-10, tag + " dtheta")
+    else:
+        assert max(abs(v) for v in prm[2:6]) == 0.0
+
+
+def _traj_case(kind):
+    if kind == "walls_xy_inverse_nu":
+        case = _case("walls_xy", nx=24, ny=14, visc_law="inverse_nu", gravity=(0.0, -2e-4))
+        phi0, _, _ = W.random_state_fields(case, seed=4)
+    else:
+        case, phi0 = W.dam_break(nx=32, ny=16, column=8, dtype="f64", theta_deg=75.0, g=5e-5)
+        case = case.replace(theta=tuple(math.radians(t) for t in (75.0, 82.0, 68.0, 101.0)))
+    rng = np.random.default_rng(5)
+    target = np.clip(phi0 + 0.05 * rng.standard_normal(phi0.shape), 0, 1)
+    return case, phi0, target
+
+
+@pytest.mark.parametrize("kind", ["walls_xy_inverse_nu", "dam_break_32x16"])
+def test_trajectory_gradient_equals_reference(kind):
+    from oracle.torch_ref import loss_and_grads
+    from paper_2111_00847_amd.autograd import trajectory_phi
+    case, phi0, target = _traj_case(kind)
+    nsteps, chk = 25, 7
+    L_ref, dphi_ref, dg_ref, dth_ref = loss_and_grads(case, phi0, target, nsteps, None)
+    phi0_t = torch.tensor(phi0, dtype=torch.float64, device="cuda", requires_grad=True)
+    grav = torch.tensor(list(case.gravity), dtype=torch.float64, requires_grad=True)
+    theta = torch.tensor(list(case.theta), dtype=torch.float64, requires_grad=True)
+    phiN = trajectory_phi(phi0_t, grav, theta, case, nsteps, None, chk)
+    L = ((phiN - torch.tensor(target, device="cuda")) ** 2).sum()
+    L.backward()
+    assert abs(float(L) - L_ref) <= 1e-12 * L_ref
+    _close(phi0_t.grad.cpu().numpy(), dphi_ref, 1e-9, f"{kind} dL/dphi0")
+    _close(grav.grad.numpy(), dg_ref, 1e-9, f"{kind} dL/dgravity")
+    _close(theta.grad.numpy(), dth_ref, 1e-9, f"{kind} dL/dtheta")
+
+
+# ---------------------------------------------------------------- cfg: differentiable dam break, 64 x 32 copy
+def _dam_small(dtype="f64"):
+    """64 x 32 copy of the dam break; the target is phi of a run with seeded
+    perturbed parameters: g (1 + 0.1 xi), theta ~ U[60, 120] degrees."""
+    case, phi0 = W.dam_break(nx=64, ny=32, column=16, dtype=dtype, theta_deg=90.0, g=1e-6)
+    rng = np.random.default_rng(W.SEED)
+    g_t = 1e-6 * (1.0 + 0.1 * rng.standard_normal())
+    th_t = math.radians(rng.uniform(60.0, 120.0))
+    return case, phi0, case.replace(gravity=(0.0, -g_t), theta=(th_t,) * 4)
+
+
+def _gpu_phi(case, phi0, nsteps):
+    _, Sim = _api()
+    phi, _, _ = Sim(case).init(phi0).step(nsteps).moments_np()
+    return phi
+
+
+def test_dam_break_64x32_gradients_equal_finite_differences():
+    """dL/dg (gravity (0, -g)), dL/dtheta (one angle on all walls) and eight
+    seeded directional derivatives in phi0, adjoint vs central differences of
+    the FP64 GPU forward, 1000 steps, checkpoints every 200."""
+    from paper_2111_00847_amd.autograd import trajectory_phi
+    case, phi0, tcase = _dam_small()
+    nsteps = 1000
+    target = _gpu_phi(tcase, phi0, nsteps)
+    loss = lambda c, ph: float(np.sum((_gpu_phi(c, ph, nsteps) - target) ** 2))
+
+    phi0_t = torch.tensor(phi0, dtype=torch.float64, device="cuda", requires_grad=True)
+    gs = torch.tensor(1e-6, dtype=torch.float64, requires_grad=True)
+    th = torch.tensor(math.pi / 2, dtype=torch.float64, requires_grad=True)
+    grav = torch.stack([torch.zeros((), dtype=torch.float64), -gs])
+    theta = th.expand(4)
+    phiN = trajectory_phi(phi0_t, grav, theta, case, nsteps, None, 200)
+    L = ((phiN - torch.tensor(target, device="cuda")) ** 2).sum()
+    L.backward()
+    checks = []
+    h = 1e-9
+    checks.append(((loss(case.replace(gravity=(0.0, -(1e-6 + h))), phi0)
+                    - loss(case.replace(gravity=(0.0, -(1e-6 - h))), phi0)) / (2 * h), float(gs.grad), "dL/dg"))
+    h = 1e-5
+    checks.append(((loss(case.replace(theta=(math.pi / 2 + h,) * 4), phi0)
+                    - loss(case.replace(theta=(math.pi / 2 - h,) * 4), phi0)) / (2 * h), float(th.grad), "dL/dtheta"))
+    rng = np.random.default_rng(W.SEED + 1)
+    gphi = phi0_t.grad.cpu().numpy()
+    for k in range(8):
+        d = rng.standard_normal(phi0.shape)
+        h = 1e-6
+        checks.append(((loss(case, phi0 + h * d) - loss(case, phi0 - h * d)) / (2 * h), float(np.sum(gphi * d)),
+                       f"dL/dphi0 . d{k}"))
+    for fd, ad, what in checks:
+        print(f"{what}: fd={fd:.8e} adjoint={ad:.8e}", flush=True)
+    for fd, ad, what in checks:
+        assert abs(fd - ad) <= 1e-4 * abs(ad), (what, fd, ad)
+
+
+def test_level_mismatch_is_reported():
+    """An adjoint step whose tape level is not one below the adjoint's level is
+    skipped on the device and reported by lbm_adjoint_params."""
+    api, Sim = _api()
+    case, phi0, _ = _dam_small()
+    s = Sim(case).init(phi0).step(3)
+    tape = api.new_tape(s.p, 2)
+    api.lbm_tape_record(s.p, s.state, tape, 2)            # levels 3, 4
+    adj = api.new_adjoint(s.p)
+    z = torch.zeros((case.ny, case.nx), dtype=torch.float64, device="cuda")
+    api.lbm_adjoint_phi(s.p, s.state, adj, z)             # adjoint at level 3
+    api.lbm_adjoint_step(s.p, tape, 1, adj)               # would need level 5
+    from paper_2111_00847_amd._lib import LbmError
+    with pytest.raises(LbmError):
+        api.lbm_adjoint_params(s.p, adj)
+
+
+def test_fp32_adjoint_tracks_fp64():
+    """The FP32 adjoint of the 64 x 32 dam break (200 steps) agrees with the FP64
+    adjoint to 1e-3 relative in every gradient."""
+    from paper_2111_00847_amd.autograd import trajectory_phi
+    res = {}
+    for dt in ("f64", "f32"):
+        case, phi0, tcase = _dam_small(dt)
+        target = _gpu_phi(tcase.replace(dtype="f64"), phi0, 200)
+        tdt = torch.float64 if dt == "f64" else torch.float32
+        phi0_t = torch.tensor(phi0, dtype=tdt, device="cuda", requires_grad=True)
+        grav = torch.tensor([0.0, -1e-6], dtype=torch.float64, requires_grad=True)
+        theta = torch.tensor([math.radians(80.0)] * 4, dtype=torch.float64, requires_grad=True)
+        phiN = trajectory_phi(phi0_t, grav, theta, case, 200, None, 64)
+        L = ((phiN.double() - torch.tensor(target, device="cuda")) ** 2).sum()
+        L.backward()
+        res[dt] = (phi0_t.grad.double().cpu().numpy(), grav.grad.numpy(), theta.grad.numpy())
+    for k, name in enumerate(("dL/dphi0", "dL/dgravity", "dL/dtheta")):
+        _close(res["f32"][k], res["f64"][k], 1e-3, f"fp32 vs fp64 {name}")

@@ -65,6 +65,7 @@ def _random_state(case, seed):
 GEOMS = {
     "periodic": dict(),
     "walls_y": dict(wall_y=True, theta=(math.pi / 2, math.pi / 2, math.radians(50), math.radians(120))),
+    "walls_x": dict(wall_x=True, theta=(math.radians(60), math.radians(130), math.pi / 2, math.pi / 2)),
     "walls_xy": dict(wall_x=True, wall_y=True,
                      theta=(math.radians(70), math.radians(110), math.radians(40), math.radians(140))),
 }
