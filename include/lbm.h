@@ -197,7 +197,7 @@ int lbm_adjoint_import(const lbm_params *p, void *adj, const void *fbar, const v
 typedef struct lbm_batch lbm_batch;
 
 /* Plan a batch of `ncases` lattices (cases: host array of ncases lbm_params).
- * autotune != 0: the first lbm_batch_init times the candidate tile heights and
+ * autotune != 0: the first lbm_batch_init times the candidate tile shapes and
  * persistent grid sizes on the batch itself and keeps the fastest. */
 int lbm_batch_create(const lbm_params *cases, int32_t ncases, int32_t autotune, lbm_batch **out);
 /* Bytes of the caller-allocated batch state (every case's state back to back). */
@@ -212,8 +212,10 @@ int lbm_batch_init(lbm_batch *batch, void *state, const void *const *phi0, const
                    void *stream);
 /* Advance every case by nsteps. */
 int lbm_batch_step(lbm_batch *batch, void *state, int64_t nsteps, void *stream);
-/* The tuning in use: tile rows, workgroups per launch, work items per step. */
-int lbm_batch_tuning(const lbm_batch *batch, int32_t *tile_rows, int32_t *grid, int32_t *items);
+/* The tuning in use: tile rows, thread rows per 64-wide workgroup, workgroups
+ * per launch, work items per step (any pointer may be NULL). */
+int lbm_batch_tuning(const lbm_batch *batch, int32_t *tile_rows, int32_t *thread_rows, int32_t *grid,
+                     int32_t *items);
 int lbm_batch_destroy(lbm_batch *batch);
 
 #ifdef __cplusplus

@@ -73,7 +73,7 @@ _SIGS = {
     "lbm_batch_case_offset": [vp, ctypes.c_int32, P(ctypes.c_size_t)],
     "lbm_batch_init": [vp, vp, P(vp), P(vp), vp],
     "lbm_batch_step": [vp, vp, ctypes.c_int64, vp],
-    "lbm_batch_tuning": [vp, P(ctypes.c_int32), P(ctypes.c_int32), P(ctypes.c_int32)],
+    "lbm_batch_tuning": [vp, P(ctypes.c_int32), P(ctypes.c_int32), P(ctypes.c_int32), P(ctypes.c_int32)],
     "lbm_batch_destroy": [vp],
 }
 _RESTYPE = {"lbm_status_string": ctypes.c_char_p}

@@ -248,9 +248,9 @@ def lbm_batch_step(batch, state, nsteps=1, stream=None):
 
 
 def lbm_batch_tuning(batch):
-    ty, g, items = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-    call("lbm_batch_tuning", batch, ctypes.byref(ty), ctypes.byref(g), ctypes.byref(items))
-    return dict(tile_rows=ty.value, grid=g.value, items=items.value)
+    ty, by, g, items = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    call("lbm_batch_tuning", batch, ctypes.byref(ty), ctypes.byref(by), ctypes.byref(g), ctypes.byref(items))
+    return dict(tile_rows=ty.value, thread_rows=by.value, grid=g.value, items=items.value)
 
 
 def lbm_batch_destroy(batch):

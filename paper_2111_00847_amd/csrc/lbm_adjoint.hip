@@ -9,23 +9,22 @@
 // Adjoint.  The adjoint of level n holds dL/df^n and dL/dg^n of the
 // post-streaming populations and dL/d(phi, u, v) of the history stored at
 // level n (the level n-1 fields).  It lives in one of two copies (n & 1) of an
-// adjoint buffer.  One adjoint step n+1 -> n runs three kernels:
+// adjoint buffer, with dL/df_i^n kept as fd_i + phib: the direct part of each
+// population and the common part that reaches all nine through phi = sum f_i.
+// One adjoint step n+1 -> n runs two kernels:
 //   A (k_adj_local, tiles)  recomputes the forward node update of level n from
 //       the tape, reads the adjoint of each post-collision population where the
 //       population streams to (the reverse of the pull, with bounce-back), and
-//       applies node_vjp.  It writes the adjoints of the pulled populations,
-//       of the previous velocity, and of the stencil inputs (gradient,
-//       Laplacian, centre) to scratch planes, plus per-tile sums of the
-//       gravity derivative.
-//   E (k_adj_edges, one workgroup)  the adjoint of the wall ghost layer: for
-//       every ghost the sum of what the neighbouring nodes' stencils took from
-//       it, routed through Eq. Dwetting to its first and second fluid nodes
-//       (y-wall ghosts, including the corner ghosts built on x-wall ghosts,
-//       first; then x-wall ghosts), plus the contact-angle derivatives.
-//   B (k_adj_gather, nodes)  the transposed stencils: the adjoint of phi at a
-//       node gathers the stencil adjoints of the nodes whose windows hold it,
-//       adds the wall routing of E, and is added to all nine populations
-//       (phi = sum_i f_i); likewise the previous phi of the history.
+//       applies node_vjp.  It writes fd, the adjoints of g and of the previous
+//       velocity, and the adjoints of the stencil inputs (gradient, Laplacian,
+//       centre) to scratch planes, plus per-tile sums of the gravity
+//       derivative.
+//   B (k_adj_gather, nodes)  the transposed stencils: phib at a node gathers
+//       the stencil adjoints of the nodes whose windows hold it; a node next to
+//       a wall also collects the adjoint of the ghosts built from it (Eq.
+//       Dwetting; corner ghosts are built on x-wall ghosts), and the first
+//       fluid node of each ghost adds the contact-angle derivative.  Likewise
+//       for the previous phi of the history.
 // Parameter derivatives accumulate into fixed per-workgroup slots (no atomics;
 // deterministic) and are summed by lbm_adjoint_params.
 #include <hip/hip_runtime.h>
@@ -43,7 +42,7 @@ namespace lbm {
 Layout layout_of(const lbm_params* p);
 int validate(const lbm_params* p);
 int hip_fail(hipError_t e);
-int step_tile_rows(const lbm_params* p);
+void step_shape(const lbm_params* p, int* ty, int* by);
 template <typename T>
 KParams<T> resolve(const lbm_params* p, const Layout& L);
 
@@ -63,23 +62,25 @@ struct AdjHeader {
     double result[6];  // lbm_adjoint_params output
 };
 
-// Scratch planes written by A and read by E and B.
+// Scratch planes written by A and read by B (S_PHI: phi of level n, only at
+// nodes within two of a wall).
 enum { S_PHIC = 0, S_GX, S_GY, S_LAP, S_PHP, S_GXP, S_GYP, S_PHI, S_COUNT };
-constexpr int ADJ_PLANES = 21;   // f (9), g (9), history (3)
+constexpr int ADJ_PLANES = 22;   // fd (9), g (9), history (3), phib
+constexpr int P_PHIB = 21;
 
 struct AdjLayout {
     long long plane;
     size_t esz;
     size_t off_copy[2];
     size_t off_scr;
-    size_t off_edge;
-    long long emax;       // edge array length per (level, wall, depth)
-    size_t off_part;      // doubles: 2 per tile of A (gravity), then 4 (contact angles)
-    int ntA;
+    size_t off_part;      // doubles: 2 per tile of A (gravity), then 4 per workgroup of B (contact angles)
+    int ntA, nB;
     size_t total;
 };
 
 static size_t al256(size_t b) { return (b + 255) / 256 * 256; }
+
+static int wall_blocks(const lbm_params* p);
 
 AdjLayout adj_layout_of(const lbm_params* p) {
     Layout L = layout_of(p);
@@ -90,11 +91,10 @@ AdjLayout adj_layout_of(const lbm_params* p) {
     A.off_copy[0] = ADJ_HDR;
     A.off_copy[1] = A.off_copy[0] + cp;
     A.off_scr = A.off_copy[1] + cp;
-    A.off_edge = A.off_scr + (size_t)S_COUNT * L.plane * L.esz;
-    A.emax = ((long long)(p->nx > p->ny ? p->nx : p->ny) + 63) / 64 * 64;
-    A.off_part = al256(A.off_edge + (size_t)16 * A.emax * L.esz);
+    A.off_part = al256(A.off_scr + (size_t)S_COUNT * L.plane * L.esz);
     A.ntA = ((p->nx + TX - 1) / TX) * ((p->ny + ATY - 1) / ATY);
-    A.total = al256(A.off_part + (size_t)(2 * A.ntA + 4) * sizeof(double));
+    A.nB = wall_blocks(p);   // workgroups of kernel W
+    A.total = al256(A.off_part + (size_t)(2 * A.ntA + 4 * A.nB) * sizeof(double));
     return A;
 }
 
@@ -105,15 +105,12 @@ struct AdjView {
     long long plane;
     T* copy[2];
     T* scr;
-    T* edge;
-    long long emax;
     double* part;
-    int ntA;
+    int ntA, nB;
     __device__ AdjHeader* hdr() const { return reinterpret_cast<AdjHeader*>(base); }
     __device__ T* plane_of(int c, int i) const { return copy[c] + (long long)i * plane; }
     __device__ T* s(int i) const { return scr + (long long)i * plane; }
-    // lev 0: current phi, 1: previous; wall 0..3 (x-, x+, y-, y+); depth 0: first fluid node
-    __device__ T* e(int lev, int wall, int depth) const { return edge + ((lev * 4 + wall) * 2 + depth) * emax; }
+    __device__ long long nslot() const { return 2LL * ntA + 4LL * nB; }
 };
 
 template <typename T>
@@ -124,11 +121,17 @@ AdjView<T> adj_view(void* adj, const AdjLayout& A) {
     V.copy[0] = reinterpret_cast<T*>(V.base + A.off_copy[0]);
     V.copy[1] = reinterpret_cast<T*>(V.base + A.off_copy[1]);
     V.scr = reinterpret_cast<T*>(V.base + A.off_scr);
-    V.edge = reinterpret_cast<T*>(V.base + A.off_edge);
-    V.emax = A.emax;
     V.part = reinterpret_cast<double*>(V.base + A.off_part);
     V.ntA = A.ntA;
+    V.nB = A.nB;
     return V;
+}
+
+// Sum over a workgroup of `nw` 64-lane waves (fixed order: deterministic).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
 }
 
 // ---------------------------------------------------------------- tape
@@ -150,8 +153,8 @@ __global__ void k_tape_copy(const char* state, size_t off0, size_t off1, size_t 
     }
 }
 
-template <typename T, int TY, typename OFF>
-__global__ __launch_bounds__(TX* BY) __attribute__((amdgpu_waves_per_eu(StepWaves<T, TY>::value)))
+template <typename T, int TY, typename OFF, int NBY>
+__global__ __launch_bounds__(TX* NBY) __attribute__((amdgpu_waves_per_eu(StepWaves<T, TY, NBY>::value)))
 void k_tape_step(KParams<T> P, char* tape, size_t slot, int j, int ntx, int nty) {
     __shared__ T sphi[TY + 2][TX + 3];
     __shared__ T sphp[TY + 2][TX + 3];
@@ -159,14 +162,16 @@ void k_tape_step(KParams<T> P, char* tape, size_t slot, int j, int ntx, int nty)
     char* src = tape + TAPE_HDR + (size_t)j * slot;
     int xt, yt;
     xcd_tile(blockIdx.x, ntx, nty, xt, yt);
-    step_core<T, TY, 0, OFF>(P, src, src + slot, n, xt, yt, nullptr, nullptr, nullptr, sphi, sphp);
+    step_core<T, TY, 0, OFF, NBY>(P, src, src + slot, n, xt, yt, nullptr, nullptr, nullptr, sphi, sphp);
 }
 
 // ---------------------------------------------------------------- adjoint step, kernel A
 // Adjoint of post-collision population i of node (x, y): the population
 // streams to (x, y) + c_i, or back to (x, y) as opp(i) through a wall.
+// planes: the adjoint copy of level n + 1; returns fd + phib of the receiver.
 template <typename T>
-__device__ __forceinline__ T push_read(const T* planes, long long plane, const KParams<T>& P, int i, int x, int y) {
+__device__ __forceinline__ void push_read(const T* planes, long long plane, const KParams<T>& P, int i, int x,
+                                          int y, T& fo, T& go) {
     int tx = x + cx(i), ty = y + cy(i);
     bool bb = false;
     if (tx < 0 || tx >= P.nx) {
@@ -177,8 +182,10 @@ __device__ __forceinline__ T push_read(const T* planes, long long plane, const K
         if (P.wall_y) bb = true;
         else ty = ty < 0 ? ty + P.ny : ty - P.ny;
     }
-    if (bb) return planes[opp(i) * plane + (long long)y * P.nx + x];
-    return planes[i * plane + (long long)ty * P.nx + tx];
+    const long long k = bb ? (long long)y * P.nx + x : (long long)ty * P.nx + tx;
+    const int d = bb ? opp(i) : i;
+    fo = planes[d * plane + k] + planes[P_PHIB * plane + k];
+    go = planes[(9 + d) * plane + k];
 }
 
 template <typename T>
@@ -186,7 +193,7 @@ __global__ __launch_bounds__(TX* BY) void k_adj_local(KParams<T> P, const char* 
                                                      AdjView<T> V) {
     __shared__ T sphi[ATY + 2][TX + 3];
     __shared__ T sphp[ATY + 2][TX + 3];
-    __shared__ double red[2][TX * BY];
+    __shared__ double red[2][BY];
     const int64_t n = reinterpret_cast<const TapeHeader*>(tape)->n0 + j;
     AdjHeader* H = V.hdr();
     const int tid = threadIdx.y * TX + threadIdx.x;
@@ -223,10 +230,7 @@ __global__ __launch_bounds__(TX* BY) void k_adj_local(KParams<T> P, const char* 
         const int ci = (int)((n + 1) & 1), co = (int)(n & 1);
         T fo[9], go[9];
 #pragma unroll
-        for (int i = 0; i < Q; i++) {
-            fo[i] = push_read(V.copy[ci], V.plane, P, i, x, y);
-            go[i] = push_read(V.copy[ci] + 9 * V.plane, V.plane, P, i, x, y);
-        }
+        for (int i = 0; i < Q; i++) push_read(V.copy[ci], V.plane, P, i, x, y, fo[i], go[i]);
         const T hphi = V.plane_of(ci, 18)[k], hu = V.plane_of(ci, 19)[k], hv = V.plane_of(ci, 20)[k];
         NodeAdj<T> A;
         node_vjp(P, M, f, g, gx, gy, lap, first, php, gxp, gyp, up, vp, fo, go, hphi, hu, hv, A);
@@ -244,24 +248,23 @@ __global__ __launch_bounds__(TX* BY) void k_adj_local(KParams<T> P, const char* 
         V.s(S_PHP)[k] = A.php;
         V.s(S_GXP)[k] = A.gxp;
         V.s(S_GYP)[k] = A.gyp;
-        V.s(S_PHI)[k] = M.phi;
+        const bool near_x = P.wall_x && (x < 2 || x >= P.nx - 2);
+        const bool near_y = P.wall_y && (y < 2 || y >= P.ny - 2);
+        if (near_x || near_y) V.s(S_PHI)[k] = M.phi;
         gsum_x = (double)A.grav_x;
         gsum_y = (double)A.grav_y;
     }
     // per-tile sums of the gravity derivative, accumulated over the steps of a pass
-    red[0][tid] = gsum_x;
-    red[1][tid] = gsum_y;
-    __syncthreads();
-    for (int w = TX * BY / 2; w > 0; w >>= 1) {
-        if (tid < w) {
-            red[0][tid] += red[0][tid + w];
-            red[1][tid] += red[1][tid + w];
-        }
-        __syncthreads();
+    gsum_x = wave_sum(gsum_x);
+    gsum_y = wave_sum(gsum_y);
+    if (lx == 0) {
+        red[0][ly] = gsum_x;
+        red[1][ly] = gsum_y;
     }
+    __syncthreads();
     if (tid == 0) {
-        V.part[2 * blockIdx.x] += red[0][0];
-        V.part[2 * blockIdx.x + 1] += red[1][0];
+        V.part[2 * blockIdx.x] += (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+        V.part[2 * blockIdx.x + 1] += (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
     }
 }
 
@@ -319,116 +322,203 @@ __device__ __forceinline__ T xghost(const KParams<T>& P, const T* phi, int side,
                      : wet_ghost(P, 1, phi_at(P, phi, P.nx - 1, y), phi_at(P, phi, P.nx - 2, y));
 }
 
-constexpr int EDGE_THREADS = 1024;
-
+// Adjoint of the x-wall ghost (side 0: x = -1, side 1: x = nx) in row y,
+// including what the corner ghosts built on it took from it.
 template <typename T>
-__global__ __launch_bounds__(EDGE_THREADS) void k_adj_edges(KParams<T> P, const char* tape, size_t slot, int j,
-                                                            AdjView<T> V) {
-    __shared__ T corner[2][2][2];          // [side x][side y][depth]: adjoint added to x-ghost rows
-    __shared__ double red[4][EDGE_THREADS];
-    const int64_t n = reinterpret_cast<const TapeHeader*>(tape)->n0 + j;
-    AdjHeader* H = V.hdr();
-    if (H->status != 0) return;
-    const int tid = threadIdx.x;
-    const Copy<T> S = copy_at<T>(const_cast<char*>(tape + TAPE_HDR + (size_t)j * slot), P.plane);
-    double th[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int lev = 0; lev < (n == 0 ? 1 : 2); lev++) {
-        const T* phi = lev ? S.h : V.s(S_PHI);
-        // corner ghosts: y-wall ghosts of the x-ghost columns
-        if (tid == 0 && P.wall_x && P.wall_y) {
-            for (int sx = 0; sx < 2; sx++)
-                for (int sy = 0; sy < 2; sy++) {
-                    const int X = sx ? P.nx : -1, Y = sy ? P.ny : -1;
-                    const int y1 = sy ? P.ny - 1 : 0, y2 = sy ? P.ny - 2 : 1;
-                    const T q = ext_adjoint(P, V, lev, X, Y);
-                    T d1, d2, dth;
-                    wet_ghost_grad(P, 2 + sy, xghost(P, phi, sx, y1), xghost(P, phi, sx, y2), d1, d2, dth);
-                    corner[sx][sy][0] = d1 * q;
-                    corner[sx][sy][1] = d2 * q;
-                    th[2 + sy] += (double)(dth * q);
-                }
+__device__ T xghost_adjoint(const KParams<T>& P, const AdjView<T>& V, int lev, const T* phi, int side, int y) {
+    const int X = side ? P.nx : -1;
+    T q = ext_adjoint(P, V, lev, X, y);
+    if (P.wall_y) {
+        for (int sy = 0; sy < 2; sy++) {
+            const int y1 = sy ? P.ny - 1 : 0, y2 = sy ? P.ny - 2 : 1;
+            if (y != y1 && y != y2) continue;
+            const T qc = ext_adjoint(P, V, lev, X, sy ? P.ny : -1);
+            T c1, c2, cth;
+            wet_ghost_grad(P, 2 + sy, xghost(P, phi, side, y1), xghost(P, phi, side, y2), c1, c2, cth);
+            if (y == y1) q += c1 * qc;
+            if (y == y2) q += c2 * qc;
         }
-        __syncthreads();
-        if (P.wall_y) {
-            for (int X = tid; X < P.nx; X += EDGE_THREADS)
-                for (int sy = 0; sy < 2; sy++) {
-                    const int Y = sy ? P.ny : -1;
-                    const int y1 = sy ? P.ny - 1 : 0, y2 = sy ? P.ny - 2 : 1;
-                    const T q = ext_adjoint(P, V, lev, X, Y);
-                    T d1, d2, dth;
-                    wet_ghost_grad(P, 2 + sy, phi_at(P, phi, X, y1), phi_at(P, phi, X, y2), d1, d2, dth);
-                    V.e(lev, 2 + sy, 0)[X] = d1 * q;
-                    V.e(lev, 2 + sy, 1)[X] = d2 * q;
-                    th[2 + sy] += (double)(dth * q);
-                }
-        }
-        if (P.wall_x) {
-            for (int Y = tid; Y < P.ny; Y += EDGE_THREADS)
-                for (int sx = 0; sx < 2; sx++) {
-                    const int X = sx ? P.nx : -1;
-                    T q = ext_adjoint(P, V, lev, X, Y);
-                    if (P.wall_y) {
-                        if (Y == 0) q += corner[sx][0][0];
-                        if (Y == 1) q += corner[sx][0][1];
-                        if (Y == P.ny - 1) q += corner[sx][1][0];
-                        if (Y == P.ny - 2) q += corner[sx][1][1];
-                    }
-                    const int x1 = sx ? P.nx - 1 : 0, x2 = sx ? P.nx - 2 : 1;
-                    T d1, d2, dth;
-                    wet_ghost_grad(P, sx, phi_at(P, phi, x1, Y), phi_at(P, phi, x2, Y), d1, d2, dth);
-                    V.e(lev, sx, 0)[Y] = d1 * q;
-                    V.e(lev, sx, 1)[Y] = d2 * q;
-                    th[sx] += (double)(dth * q);
-                }
-        }
-        __syncthreads();   // corner[] is rewritten by the next level
     }
-    for (int k = 0; k < 4; k++) red[k][tid] = th[k];
-    __syncthreads();
-    for (int w = EDGE_THREADS / 2; w > 0; w >>= 1) {
-        if (tid < w)
-            for (int k = 0; k < 4; k++) red[k][tid] += red[k][tid + w];
-        __syncthreads();
-    }
-    if (tid == 0) {
-        double* pth = V.part + 2 * V.ntA;
-        for (int k = 0; k < 4; k++) pth[k] += red[k][0];
-        H->level = n;
-    }
+    return q;
 }
 
 // ---------------------------------------------------------------- adjoint step, kernel B
+// One 64 x 4 tile per workgroup.  The stencil adjoints of the tile and its
+// one-node ring are staged in LDS (periodic axes wrap; positions beyond a wall
+// hold no node and contribute nothing); every node gathers the nine
+// transposed stencil terms.  The ghost routing of wall nodes follows in
+// kernel W.
 template <typename T>
-__global__ void k_adj_gather(KParams<T> P, const char* tape, int j, AdjView<T> V) {
+__global__ __launch_bounds__(TX* BY) void k_adj_gather(KParams<T> P, const char* tape, int j, AdjView<T> V) {
+    constexpr int WX = TX + 2, WY = ATY + 2;
+    __shared__ T sw[5][WY][WX + 1];   // gx, gy, lap of phi^n; gx, gy of phi^{n-1}
     const int64_t n = reinterpret_cast<const TapeHeader*>(tape)->n0 + j;
     if (V.hdr()->status != 0) return;
     const bool first = n == 0;
     const int co = (int)(n & 1);
-    const long long nn = (long long)P.nx * P.ny;
-    for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < nn;
-         k += (long long)gridDim.x * blockDim.x) {
-        const int y = (int)(k / P.nx), x = (int)(k - (long long)y * P.nx);
-        for (int lev = 0; lev < (first ? 1 : 2); lev++) {
-            T acc = V.s(lev ? S_PHP : S_PHIC)[k] + ext_adjoint(P, V, lev, x, y);
-            if (P.wall_x) {
-                if (x == 0) acc += V.e(lev, 0, 0)[y];
-                if (x == 1) acc += V.e(lev, 0, 1)[y];
-                if (x == P.nx - 1) acc += V.e(lev, 1, 0)[y];
-                if (x == P.nx - 2) acc += V.e(lev, 1, 1)[y];
-            }
-            if (P.wall_y) {
-                if (y == 0) acc += V.e(lev, 2, 0)[x];
-                if (y == 1) acc += V.e(lev, 2, 1)[x];
-                if (y == P.ny - 1) acc += V.e(lev, 3, 0)[x];
-                if (y == P.ny - 2) acc += V.e(lev, 3, 1)[x];
-            }
-            if (lev == 0) {
-                for (int i = 0; i < Q; i++) V.plane_of(co, i)[k] += acc;   // phi = sum_i f_i
-            } else {
-                V.plane_of(co, 18)[k] = acc;
-            }
+    const int ntx = (P.nx + TX - 1) / TX;
+    const int x0 = (blockIdx.x % ntx) * TX, y0 = (blockIdx.x / ntx) * ATY;
+    const int tid = threadIdx.y * TX + threadIdx.x;
+    const T* src[5] = {V.s(S_GX), V.s(S_GY), V.s(S_LAP), V.s(S_GXP), V.s(S_GYP)};
+    for (int idx = tid; idx < WX * WY; idx += TX * BY) {
+        const int wy = idx / WX, wx = idx - wy * WX;
+        int gx = x0 - 1 + wx, gy = y0 - 1 + wy;
+        bool none = gx > P.nx || gy > P.ny;
+        if (gx < 0 || gx >= P.nx) {
+            if (P.wall_x) none = true;
+            else gx = gx < 0 ? gx + P.nx : gx - P.nx;
         }
-        if (first) V.plane_of(co, 18)[k] = T(0);
+        if (gy < 0 || gy >= P.ny) {
+            if (P.wall_y) none = true;
+            else gy = gy < 0 ? gy + P.ny : gy - P.ny;
+        }
+        const long long k = (long long)gy * P.nx + gx;
+#pragma unroll
+        for (int q = 0; q < 3; q++) sw[q][wy][wx] = none ? T(0) : src[q][k];
+        if (!first) {
+#pragma unroll
+            for (int q = 3; q < 5; q++) sw[q][wy][wx] = none ? T(0) : src[q][k];
+        }
+    }
+    __syncthreads();
+    const int lx = threadIdx.x, ly = threadIdx.y;
+    const int x = x0 + lx, y = y0 + ly;
+    if (x >= P.nx || y >= P.ny) return;
+    const long long k = (long long)y * P.nx + x;
+    // node (x - dx, y - dy) holds (x, y) at window offset (dx, dy)
+    T acc = V.s(S_PHIC)[k], accp = T(0);
+#pragma unroll
+    for (int dy = -1; dy <= 1; dy++)
+#pragma unroll
+        for (int dx = -1; dx <= 1; dx++) {
+            const int wy = ly + 1 - dy, wx = lx + 1 - dx;
+            acc += wgx<T>(dx, dy) * sw[0][wy][wx] + wgy<T>(dx, dy) * sw[1][wy][wx] + wlap<T>(dx, dy) * sw[2][wy][wx];
+        }
+    V.plane_of(co, P_PHIB)[k] = acc;
+    if (!first) {
+        accp = V.s(S_PHP)[k];
+#pragma unroll
+        for (int dy = -1; dy <= 1; dy++)
+#pragma unroll
+            for (int dx = -1; dx <= 1; dx++) {
+                const int wy = ly + 1 - dy, wx = lx + 1 - dx;
+                accp += wgx<T>(dx, dy) * sw[3][wy][wx] + wgy<T>(dx, dy) * sw[4][wy][wx];
+            }
+    }
+    V.plane_of(co, 18)[k] = accp;
+}
+
+// ---------------------------------------------------------------- adjoint step, kernel W
+// Nodes within two of a wall: rows [0, ylo) and [yhi, ny) when the y axis has
+// walls, then columns [0, xlo) and [xhi, nx) of the rows in between when the x
+// axis has walls -- each such node once.
+struct WallSet {
+    int ylo, yhi, xlo, xhi;
+    long long nrow, count;
+};
+
+inline WallSet wall_set(int nx, int ny, bool wall_x, bool wall_y) {
+    WallSet w;
+    w.ylo = wall_y ? (ny < 2 ? ny : 2) : 0;
+    w.yhi = wall_y ? (ny - 2 > w.ylo ? ny - 2 : w.ylo) : ny;
+    w.xlo = wall_x ? (nx < 2 ? nx : 2) : 0;
+    w.xhi = wall_x ? (nx - 2 > w.xlo ? nx - 2 : w.xlo) : nx;
+    const int nry = w.ylo + (ny - w.yhi), ncx = w.xlo + (nx - w.xhi);
+    w.nrow = (long long)nry * nx;
+    w.count = w.nrow + (long long)ncx * (w.yhi - w.ylo);
+    return w;
+}
+
+constexpr int WALL_THREADS = 256;
+
+static int wall_blocks(const lbm_params* p) {
+    const WallSet w = wall_set(p->nx, p->ny, p->bc_x == LBM_WALLS, p->bc_y == LBM_WALLS);
+    const long long b = (w.count + WALL_THREADS - 1) / WALL_THREADS;
+    return (int)(b < 1 ? 1 : (b > 1024 ? 1024 : b));
+}
+
+// Adds to phib (and to the previous-phi adjoint) of every wall node what the
+// ghosts built from it received: the first and second fluid node of each
+// ghost get d ghost / d phi_1 and d ghost / d phi_2 times the ghost's adjoint
+// (its neighbours' stencil terms, plus, for an x-ghost next to a y-wall, the
+// corner ghost built on it); the first node also adds d ghost / d theta of its
+// ghost (and of the corner ghost of its wall row) to the contact-angle sums.
+template <typename T>
+__global__ __launch_bounds__(WALL_THREADS) void k_adj_walls(KParams<T> P, const char* tape, size_t slot, int j,
+                                                           AdjView<T> V, WallSet ws) {
+    __shared__ double red[4][WALL_THREADS / 64];
+    const int64_t n = reinterpret_cast<const TapeHeader*>(tape)->n0 + j;
+    AdjHeader* H = V.hdr();
+    if (H->status != 0) return;
+    const bool first = n == 0;
+    const int co = (int)(n & 1);
+    const Copy<T> S = copy_at<T>(const_cast<char*>(tape + TAPE_HDR + (size_t)j * slot), P.plane);
+    double th[4] = {0.0, 0.0, 0.0, 0.0};
+    for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < ws.count;
+         idx += (long long)gridDim.x * blockDim.x) {
+        int x, y;
+        if (idx < ws.nrow) {
+            const int r = (int)(idx / P.nx);
+            x = (int)(idx - (long long)r * P.nx);
+            y = r < ws.ylo ? r : ws.yhi + (r - ws.ylo);
+        } else {
+            const long long i2 = idx - ws.nrow;
+            const int ncx = ws.xlo + (P.nx - ws.xhi);
+            const int c = (int)(i2 % ncx);
+            x = c < ws.xlo ? c : ws.xhi + (c - ws.xlo);
+            y = ws.ylo + (int)(i2 / ncx);
+        }
+        const long long k = (long long)y * P.nx + x;
+        for (int lev = 0; lev < (first ? 1 : 2); lev++) {
+            const T* phi = lev ? S.h : V.s(S_PHI);
+            T acc = T(0);
+            if (P.wall_x)
+                for (int sx = 0; sx < 2; sx++) {
+                    const int x1 = sx ? P.nx - 1 : 0, x2 = sx ? P.nx - 2 : 1;
+                    if (x != x1 && x != x2) continue;
+                    const T q = xghost_adjoint(P, V, lev, phi, sx, y);
+                    T d1, d2, dth;
+                    wet_ghost_grad(P, sx, phi_at(P, phi, x1, y), phi_at(P, phi, x2, y), d1, d2, dth);
+                    if (x == x1) {
+                        acc += d1 * q;
+                        th[sx] += (double)(dth * q);
+                    }
+                    if (x == x2) acc += d2 * q;
+                }
+            if (P.wall_y)
+                for (int sy = 0; sy < 2; sy++) {
+                    const int y1 = sy ? P.ny - 1 : 0, y2 = sy ? P.ny - 2 : 1;
+                    if (y != y1 && y != y2) continue;
+                    const T q = ext_adjoint(P, V, lev, x, sy ? P.ny : -1);
+                    T d1, d2, dth;
+                    wet_ghost_grad(P, 2 + sy, phi_at(P, phi, x, y1), phi_at(P, phi, x, y2), d1, d2, dth);
+                    if (y == y1) {
+                        acc += d1 * q;
+                        th[2 + sy] += (double)(dth * q);
+                        if (P.wall_x && (x == 0 || x == P.nx - 1)) {   // the corner ghost of this wall row
+                            const int side = x == 0 ? 0 : 1;
+                            const T qc = ext_adjoint(P, V, lev, side ? P.nx : -1, sy ? P.ny : -1);
+                            T c1, c2, cth;
+                            wet_ghost_grad(P, 2 + sy, xghost(P, phi, side, y1), xghost(P, phi, side, y2), c1, c2,
+                                           cth);
+                            th[2 + sy] += (double)(cth * qc);
+                        }
+                    }
+                    if (y == y2) acc += d2 * q;
+                }
+            V.plane_of(co, lev ? 18 : P_PHIB)[k] += acc;
+        }
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int q = 0; q < 4; q++) {
+        const double v = wave_sum(th[q]);
+        if (lane == 0) red[q][wv] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double* pth = V.part + 2 * V.ntA + 4 * blockIdx.x;
+        for (int q = 0; q < 4; q++) pth[q] += (red[q][0] + red[q][1]) + (red[q][2] + red[q][3]);
+        if (blockIdx.x == 0) H->level = n;
     }
 }
 
@@ -438,14 +528,13 @@ __global__ void k_adj_seed(KParams<T> P, const char* state, size_t off_stamp, Ad
     const int64_t N = *reinterpret_cast<const int64_t*>(state + off_stamp);
     const int c = (int)(N & 1);
     const long long nn = (long long)P.nx * P.ny;
-    const long long nslot = 2LL * V.ntA + 4;
+    const long long nslot = V.nslot();
     const long long lim = nn > nslot ? nn : nslot;
     for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < lim;
          k += (long long)gridDim.x * blockDim.x) {
         if (k < nn) {
-            const T d = dL[k];
-            for (int i = 0; i < Q; i++) V.plane_of(c, i)[k] = d;
-            for (int i = 9; i < ADJ_PLANES; i++) V.plane_of(c, i)[k] = T(0);
+            for (int i = 0; i < P_PHIB; i++) V.plane_of(c, i)[k] = T(0);
+            V.plane_of(c, P_PHIB)[k] = dL[k];   // reaches every f_i through phi = sum_i f_i
         }
         if (k < nslot) V.part[k] = 0.0;
     }
@@ -459,7 +548,7 @@ template <typename T>
 __global__ void k_adj_import(KParams<T> P, AdjView<T> V, const T* fb, const T* gb, const T* hb, int64_t level) {
     const int c = (int)(level & 1);
     const long long nn = (long long)P.nx * P.ny;
-    const long long nslot = 2LL * V.ntA + 4;
+    const long long nslot = V.nslot();
     const long long lim = nn > nslot ? nn : nslot;
     for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < lim;
          k += (long long)gridDim.x * blockDim.x) {
@@ -467,6 +556,7 @@ __global__ void k_adj_import(KParams<T> P, AdjView<T> V, const T* fb, const T* g
             for (int i = 0; i < Q; i++) V.plane_of(c, i)[k] = fb ? fb[i * nn + k] : T(0);
             for (int i = 0; i < Q; i++) V.plane_of(c, 9 + i)[k] = gb ? gb[i * nn + k] : T(0);
             for (int i = 0; i < 3; i++) V.plane_of(c, 18 + i)[k] = hb ? hb[i * nn + k] : T(0);
+            V.plane_of(c, P_PHIB)[k] = T(0);
         }
         if (k < nslot) V.part[k] = 0.0;
     }
@@ -482,8 +572,10 @@ __global__ void k_adj_export(KParams<T> P, AdjView<T> V, T* fb, T* gb, T* hb) {
     const long long nn = (long long)P.nx * P.ny;
     for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < nn;
          k += (long long)gridDim.x * blockDim.x) {
-        if (fb)
-            for (int i = 0; i < Q; i++) fb[i * nn + k] = V.plane_of(c, i)[k];
+        if (fb) {
+            const T pb = V.plane_of(c, P_PHIB)[k];
+            for (int i = 0; i < Q; i++) fb[i * nn + k] = V.plane_of(c, i)[k] + pb;
+        }
         if (gb)
             for (int i = 0; i < Q; i++) gb[i * nn + k] = V.plane_of(c, 9 + i)[k];
         if (hb)
@@ -506,7 +598,9 @@ __global__ void k_adj_init(KParams<T> P, AdjView<T> V, T* out) {
         }
         const T a = V.plane_of(0, 1)[k] + V.plane_of(0, 2)[k] + V.plane_of(0, 3)[k] + V.plane_of(0, 4)[k];
         const T d = V.plane_of(0, 5)[k] + V.plane_of(0, 6)[k] + V.plane_of(0, 7)[k] + V.plane_of(0, 8)[k];
-        out[k] = (T(4) / T(9)) * V.plane_of(0, 0)[k] + (T(1) / T(9)) * a + (T(1) / T(36)) * d;
+        // sum_i w_i (fd_i + phib) with sum_i w_i = 1
+        out[k] = (T(4) / T(9)) * V.plane_of(0, 0)[k] + (T(1) / T(9)) * a + (T(1) / T(36)) * d +
+                 V.plane_of(0, P_PHIB)[k];
     }
 }
 
@@ -529,11 +623,17 @@ __global__ __launch_bounds__(256) void k_adj_reduce(AdjView<T> V) {
         }
         __syncthreads();
     }
+    double t[4] = {0.0, 0.0, 0.0, 0.0};
+    if (tid < 4)
+        for (int b = 0; b < V.nB; b++) t[0] += V.part[2 * V.ntA + 4 * b + tid];
+    __syncthreads();
+    if (tid < 4) red[0][tid + 8] = t[0];   // slots 8..11 are free after the tree above
+    __syncthreads();
     if (tid == 0) {
         AdjHeader* H = V.hdr();
         H->result[0] = red[0][0];
         H->result[1] = red[1][0];
-        for (int k = 0; k < 4; k++) H->result[2 + k] = V.part[2 * V.ntA + k];
+        for (int k = 0; k < 4; k++) H->result[2 + k] = red[0][8 + k];
     }
 }
 
@@ -543,25 +643,28 @@ static int grid1d(long long n) {
     return (int)(b < 65536 ? (b > 0 ? b : 1) : 65536);
 }
 
+template <typename T, int TY, int NBY>
+static void tape_step_launch(const KParams<T>& P, char* tape, size_t slot, int j, hipStream_t s) {
+    const int ntx = (P.nx + TX - 1) / TX, nty = (P.ny + TY - 1) / TY;
+    if (slot < (size_t(1) << 32))
+        k_tape_step<T, TY, uint32_t, NBY><<<ntx * nty, dim3(TX, NBY), 0, s>>>(P, tape, slot, j, ntx, nty);
+    else
+        k_tape_step<T, TY, uint64_t, NBY><<<ntx * nty, dim3(TX, NBY), 0, s>>>(P, tape, slot, j, ntx, nty);
+}
+
+// The same launch shapes as lbm_step (step_shape).
 template <typename T>
-static void launch_tape_steps(const KParams<T>& P, char* tape, size_t slot, int nlevels, int ty, hipStream_t s) {
-    const int ntx = (P.nx + TX - 1) / TX;
-    dim3 blk(TX, BY);
-    const bool small = slot < (size_t(1) << 32);
+static void launch_tape_steps(const KParams<T>& P, char* tape, size_t slot, int nlevels, int ty, int by,
+                              hipStream_t s) {
+    constexpr int T16 = sizeof(T) == 8 ? 8 : 16;
     for (int j = 0; j + 1 < nlevels; j++) {
-        if (ty == 4) {
-            const int nty = (P.ny + 3) / 4;
-            if (small) k_tape_step<T, 4, uint32_t><<<ntx * nty, blk, 0, s>>>(P, tape, slot, j, ntx, nty);
-            else k_tape_step<T, 4, uint64_t><<<ntx * nty, blk, 0, s>>>(P, tape, slot, j, ntx, nty);
-        } else if (ty == 8 || sizeof(T) == 8) {
-            const int nty = (P.ny + 7) / 8;
-            if (small) k_tape_step<T, 8, uint32_t><<<ntx * nty, blk, 0, s>>>(P, tape, slot, j, ntx, nty);
-            else k_tape_step<T, 8, uint64_t><<<ntx * nty, blk, 0, s>>>(P, tape, slot, j, ntx, nty);
+        if (ty == 4) tape_step_launch<T, 4, 4>(P, tape, slot, j, s);
+        else if (ty == 8 || sizeof(T) == 8) {
+            if (by == 8) tape_step_launch<T, 8, 8>(P, tape, slot, j, s);
+            else tape_step_launch<T, 8, 4>(P, tape, slot, j, s);
         } else {
-            constexpr int TY16 = sizeof(T) == 8 ? 8 : 16;
-            const int nty = (P.ny + TY16 - 1) / TY16;
-            if (small) k_tape_step<T, TY16, uint32_t><<<ntx * nty, blk, 0, s>>>(P, tape, slot, j, ntx, nty);
-            else k_tape_step<T, TY16, uint64_t><<<ntx * nty, blk, 0, s>>>(P, tape, slot, j, ntx, nty);
+            if (by == 8) tape_step_launch<T, T16, 8>(P, tape, slot, j, s);
+            else tape_step_launch<T, T16, 4>(P, tape, slot, j, s);
         }
     }
 }
@@ -571,8 +674,9 @@ static void launch_adj_step(const KParams<T>& P, const char* tape, size_t slot, 
                             hipStream_t s) {
     const int ntx = (P.nx + TX - 1) / TX, nty = (P.ny + ATY - 1) / ATY;
     k_adj_local<T><<<ntx * nty, dim3(TX, BY), 0, s>>>(P, tape, slot, j, V);
-    k_adj_edges<T><<<1, EDGE_THREADS, 0, s>>>(P, tape, slot, j, V);
-    k_adj_gather<T><<<grid1d((long long)P.nx * P.ny), 256, 0, s>>>(P, tape, j, V);
+    k_adj_gather<T><<<ntx * nty, dim3(TX, BY), 0, s>>>(P, tape, j, V);
+    const WallSet ws = wall_set(P.nx, P.ny, P.wall_x, P.wall_y);
+    k_adj_walls<T><<<V.nB, WALL_THREADS, 0, s>>>(P, tape, slot, j, V, ws);
 }
 
 }  // namespace lbm
@@ -601,9 +705,12 @@ int lbm_tape_record(const lbm_params* p, const void* state, void* tape, int32_t 
     k_tape_copy<<<grid1d((long long)(L.buf_bytes / 16)), 256, 0, s>>>((const char*)state, L.off_buf[0], L.off_buf[1],
                                                                        L.off_stamp, L.buf_bytes, (char*)tape, nlevels,
                                                                        p->nx, p->ny, p->dtype);
-    const int ty = step_tile_rows(p);
-    if (p->dtype == LBM_F32) launch_tape_steps<float>(resolve<float>(p, L), (char*)tape, L.buf_bytes, nlevels, ty, s);
-    else launch_tape_steps<double>(resolve<double>(p, L), (char*)tape, L.buf_bytes, nlevels, ty, s);
+    int ty, by;
+    step_shape(p, &ty, &by);
+    if (p->dtype == LBM_F32)
+        launch_tape_steps<float>(resolve<float>(p, L), (char*)tape, L.buf_bytes, nlevels, ty, by, s);
+    else
+        launch_tape_steps<double>(resolve<double>(p, L), (char*)tape, L.buf_bytes, nlevels, ty, by, s);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? LBM_OK : hip_fail(e);
 }
@@ -624,7 +731,7 @@ int lbm_adjoint_phi(const lbm_params* p, const void* state, void* adj, const voi
     const Layout L = layout_of(p);
     const AdjLayout A = adj_layout_of(p);
     hipStream_t s = (hipStream_t)stream;
-    const long long lim = std::max<long long>((long long)p->nx * p->ny, 2LL * A.ntA + 4);
+    const long long lim = std::max<long long>((long long)p->nx * p->ny, 2LL * A.ntA + 4LL * A.nB);
     if (p->dtype == LBM_F32)
         k_adj_seed<float><<<grid1d(lim), 256, 0, s>>>(resolve<float>(p, L), (const char*)state, L.off_stamp,
                                                        adj_view<float>(adj, A), (const float*)dL_dphi);
@@ -714,7 +821,7 @@ int lbm_adjoint_import(const lbm_params* p, void* adj, const void* fbar, const v
     const Layout L = layout_of(p);
     const AdjLayout A = adj_layout_of(p);
     hipStream_t s = (hipStream_t)stream;
-    const long long lim = std::max<long long>((long long)p->nx * p->ny, 2LL * A.ntA + 4);
+    const long long lim = std::max<long long>((long long)p->nx * p->ny, 2LL * A.ntA + 4LL * A.nB);
     if (p->dtype == LBM_F32)
         k_adj_import<float><<<grid1d(lim), 256, 0, s>>>(resolve<float>(p, L), adj_view<float>(adj, A),
                                                          (const float*)fbar, (const float*)gbar, (const float*)hbar,

@@ -120,18 +120,51 @@ KParams<T> resolve(const lbm_params* p, const Layout& L) {
 template KParams<float> resolve<float>(const lbm_params*, const Layout&);
 template KParams<double> resolve<double>(const lbm_params*, const Layout&);
 
-// Tile height of the step kernel: taller tiles amortise the halo ring, shorter
-// ones give small lattices enough workgroups to fill 256 CUs (measured: 8 rows
-// best for 256 x 1024, 16 rows for 4096 x 4096).
+// Shape of the step launch: 64 x TY tiles on workgroups of 64 x BY threads.
+// Taller tiles amortise the one-node halo ring; more waves hide latency.
+// Measured on MI355X (FP32): lattices of >= 4096 16-row tiles run best at
+// (16, 4) -- four nodes per thread, HBM bound; below that the step is latency
+// bound and the tallest tile that still gives >= 4096 waves wins: (16, 8) for
+// 1024 x 512, (8, 8) for 256 x 1024, else (4, 4).  FP64 tiles stop at 8 rows
+// (taller ones spill); (8, 4) measured best for FP64.
 #ifndef LBM_STEP_TY
 #define LBM_STEP_TY 0   // force a tile height (4, 8, 16); 0 = by lattice size
 #endif
-int step_tile_rows(const lbm_params* p) {
-    if (LBM_STEP_TY) return LBM_STEP_TY;
+#ifndef LBM_STEP_BY
+#define LBM_STEP_BY 0   // force thread rows per workgroup (4, 8); 0 = by lattice size
+#endif
+void step_shape(const lbm_params* p, int* ty, int* by) {
     const long long tx = (p->nx + 63) / 64;
-    if (p->dtype == LBM_F32 && tx * ((p->ny + 15) / 16) >= 4096) return 16;
-    if (tx * ((p->ny + 7) / 8) >= 256) return 8;
-    return 4;
+    const long long t16 = tx * ((p->ny + 15) / 16), t8 = tx * ((p->ny + 7) / 8);
+    int t, b;
+    if (p->dtype == LBM_F64) {
+        t = 8;
+        b = 4;
+    } else if (t16 >= 4096) {
+        t = 16;
+        b = 4;
+    } else if (t16 * 8 >= 4096) {
+        t = 16;
+        b = 8;
+    } else if (t8 * 8 >= 4096) {
+        t = 8;
+        b = 8;
+    } else {
+        t = 4;
+        b = 4;
+    }
+    if (LBM_STEP_TY) t = LBM_STEP_TY;
+    if (LBM_STEP_BY) b = LBM_STEP_BY;
+    if (p->dtype == LBM_F64 && t > 8) t = 8;
+    if (b > t) b = 4;
+    *ty = t;
+    *by = b;
+}
+
+int step_tile_rows(const lbm_params* p) {
+    int t, b;
+    step_shape(p, &t, &b);
+    return t;
 }
 
 static thread_local char g_last_error[256];
@@ -144,7 +177,7 @@ struct StepGraph {
     lbm_params p;
     void* state;
     hipStream_t stream;
-    int ty;
+    int ty, by;
     hipGraphExec_t exec;
 };
 static std::mutex g_graph_mu;
@@ -209,10 +242,11 @@ int lbm_step(const lbm_params* p, void* state, int64_t nsteps, void* stream) {
     if (nsteps < 0) return LBM_E_SIZE;
     Layout L = layout_of(p);
     hipStream_t s = (hipStream_t)stream;
-    int ty = step_tile_rows(p);
+    int ty, by;
+    step_shape(p, &ty, &by);
     auto launch = [&](int64_t n) -> hipError_t {
-        if (p->dtype == LBM_F32) return launch_step<float>(resolve<float>(p, L), (char*)state, L, n, s, ty);
-        return launch_step<double>(resolve<double>(p, L), (char*)state, L, n, s, ty);
+        if (p->dtype == LBM_F32) return launch_step<float>(resolve<float>(p, L), (char*)state, L, n, s, ty, by);
+        return launch_step<double>(resolve<double>(p, L), (char*)state, L, n, s, ty, by);
     };
     hipError_t e;
     // Long runs on a capturable (non-NULL) stream replay a graph of GRAPH_K steps.
@@ -220,7 +254,7 @@ int lbm_step(const lbm_params* p, void* state, int64_t nsteps, void* stream) {
         std::lock_guard<std::mutex> lock(g_graph_mu);
         size_t hit = g_graphs.size();
         for (size_t i = 0; i < g_graphs.size(); i++)
-            if (g_graphs[i].state == state && g_graphs[i].stream == s && g_graphs[i].ty == ty &&
+            if (g_graphs[i].state == state && g_graphs[i].stream == s && g_graphs[i].ty == ty && g_graphs[i].by == by &&
                 memcmp(&g_graphs[i].p, p, sizeof(lbm_params)) == 0) {
                 hit = i;
                 break;
@@ -233,7 +267,7 @@ int lbm_step(const lbm_params* p, void* state, int64_t nsteps, void* stream) {
             e = hipStreamEndCapture(s, &g);
             if (le != hipSuccess) return hip_fail(le);
             if (e != hipSuccess) return hip_fail(e);
-            StepGraph sg{*p, state, s, ty, nullptr};
+            StepGraph sg{*p, state, s, ty, by, nullptr};
             e = hipGraphInstantiate(&sg.exec, g, nullptr, nullptr, 0);
             (void)hipGraphDestroy(g);
             if (e != hipSuccess) return hip_fail(e);

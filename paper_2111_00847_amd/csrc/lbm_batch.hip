@@ -37,8 +37,8 @@ struct BatchCase {
     int pad;
 };
 
-template <typename T, int TY>
-__global__ __launch_bounds__(TX* BY) __attribute__((amdgpu_waves_per_eu(StepWaves<T, TY>::value)))
+template <typename T, int TY, int NBY>
+__global__ __launch_bounds__(TX* NBY) __attribute__((amdgpu_waves_per_eu(StepWaves<T, TY, NBY>::value)))
 void k_step_batch(const BatchCase<T>* __restrict__ cases, int ncases, int nitems, char* batch_state) {
     __shared__ T sphi[TY + 2][TX + 3];
     __shared__ T sphp[TY + 2][TX + 3];
@@ -51,8 +51,8 @@ void k_step_batch(const BatchCase<T>* __restrict__ cases, int ncases, int nitems
         }
         const BatchCase<T>& C = cases[lo];
         const int local = w - C.item_begin;
-        step_tile<T, TY, 0, uint32_t>(C.P, batch_state + C.base, C.off0, C.off1, C.off_stamp, local % C.ntx,
-                                      local / C.ntx, nullptr, nullptr, nullptr, sphi, sphp);
+        step_tile<T, TY, 0, uint32_t, NBY>(C.P, batch_state + C.base, C.off0, C.off1, C.off_stamp, local % C.ntx,
+                                           local / C.ntx, nullptr, nullptr, nullptr, sphi, sphp);
         __syncthreads();   // the next item reuses the LDS window
     }
 }
@@ -74,6 +74,7 @@ struct lbm_batch {
     int autotune = 0;
     bool tuned = false;
     int ty = 8;
+    int by = 4;           // thread rows per workgroup
     int grid = 0;
     int nitems = 0;
     void* d_cases = nullptr;
@@ -116,14 +117,24 @@ hipError_t upload_cases(lbm_batch* B, int ty) {
     return hipMemcpy(B->d_cases, h.data(), sizeof(BatchCase<T>) * B->ncases, hipMemcpyHostToDevice);
 }
 
-template <typename T>
-void launch_batch_once(lbm_batch* B, char* state, hipStream_t s) {
+template <typename T, int TY, int NBY>
+void batch_launch(lbm_batch* B, char* state, hipStream_t s) {
     const int g = B->grid > 0 ? B->grid : B->nitems;
     const BatchCase<T>* cases = reinterpret_cast<const BatchCase<T>*>(B->d_cases);
-    dim3 blk(TX, BY);
-    if (B->ty == 4) k_step_batch<T, 4><<<g, blk, 0, s>>>(cases, B->ncases, B->nitems, state);
-    else if (B->ty == 8 || sizeof(T) == 8) k_step_batch<T, 8><<<g, blk, 0, s>>>(cases, B->ncases, B->nitems, state);
-    else k_step_batch<T, sizeof(T) == 8 ? 8 : 16><<<g, blk, 0, s>>>(cases, B->ncases, B->nitems, state);
+    k_step_batch<T, TY, NBY><<<g, dim3(TX, NBY), 0, s>>>(cases, B->ncases, B->nitems, state);
+}
+
+template <typename T>
+void launch_batch_once(lbm_batch* B, char* state, hipStream_t s) {
+    constexpr int T16 = sizeof(T) == 8 ? 8 : 16;
+    if (B->ty == 4) batch_launch<T, 4, 4>(B, state, s);
+    else if (B->ty == 8 || sizeof(T) == 8) {
+        if (B->by == 8) batch_launch<T, 8, 8>(B, state, s);
+        else batch_launch<T, 8, 4>(B, state, s);
+    } else {
+        if (B->by == 8) batch_launch<T, T16, 8>(B, state, s);
+        else batch_launch<T, T16, 4>(B, state, s);
+    }
 }
 
 void drop_graph(lbm_batch* B) {
@@ -178,14 +189,16 @@ int batch_init_cases(lbm_batch* B, char* state, const void* const* phi0, const v
 // keep the fastest; the state is re-initialised afterwards by the caller.
 template <typename T>
 int autotune_t(lbm_batch* B, char* state, const void* const* phi0, const void* const* p0, hipStream_t s) {
-    const int tys[3] = {4, 8, 16};
+    const int shapes[5][2] = {{4, 4}, {8, 4}, {8, 8}, {16, 4}, {16, 8}};   // (tile rows, thread rows)
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return LBM_E_HIP;
     float best = 1e30f;
-    int best_ty = 8, best_grid = 0;
-    for (int ty : tys) {
+    int best_ty = 8, best_by = 4, best_grid = 0;
+    for (const auto& sh : shapes) {
+        const int ty = sh[0];
         if (ty == 16 && sizeof(T) == 8) continue;
         B->ty = ty;
+        B->by = sh[1];
         hipError_t e = upload_cases<T>(B, ty);
         if (e != hipSuccess) return hip_fail(e);
         const int grids[4] = {0, 2 * B->cus, 4 * B->cus, 8 * B->cus};
@@ -205,6 +218,7 @@ int autotune_t(lbm_batch* B, char* state, const void* const* phi0, const void* c
             if (ms < best) {
                 best = ms;
                 best_ty = ty;
+                best_by = sh[1];
                 best_grid = g;
             }
         }
@@ -212,6 +226,7 @@ int autotune_t(lbm_batch* B, char* state, const void* const* phi0, const void* c
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     B->ty = best_ty;
+    B->by = best_by;
     B->grid = best_grid;
     hipError_t e = upload_cases<T>(B, best_ty);
     if (e != hipSuccess) return hip_fail(e);
@@ -249,7 +264,7 @@ int lbm_batch_create(const lbm_params* cases, int32_t ncases, int32_t autotune, 
     int dev = 0;
     if (hipGetDevice(&dev) == hipSuccess)
         (void)hipDeviceGetAttribute(&B->cus, hipDeviceAttributeMultiprocessorCount, dev);
-    // default (untuned) choice: 8-row tiles, one workgroup per item
+    // default (untuned) choice: 8-row tiles on 256-thread workgroups, one workgroup per item
     B->ty = 8;
     B->grid = 0;
     hipError_t e = B->dtype == LBM_F32 ? upload_cases<float>(B, B->ty) : upload_cases<double>(B, B->ty);
@@ -298,9 +313,10 @@ int lbm_batch_step(lbm_batch* B, void* state, int64_t nsteps, void* stream) {
                                : batch_step_t<double>(B, (char*)state, nsteps, s);
 }
 
-int lbm_batch_tuning(const lbm_batch* B, int32_t* tile_rows, int32_t* grid, int32_t* items) {
+int lbm_batch_tuning(const lbm_batch* B, int32_t* tile_rows, int32_t* thread_rows, int32_t* grid, int32_t* items) {
     if (!B) return LBM_E_NULL;
     if (tile_rows) *tile_rows = B->ty;
+    if (thread_rows) *thread_rows = B->by;
     if (grid) *grid = B->grid > 0 ? B->grid : B->nitems;
     if (items) *items = B->nitems;
     return LBM_OK;

@@ -44,6 +44,14 @@ __device__ __forceinline__ T ld(const char* base, OFF byteoff) {
 #ifndef LBM_XCD_REMAP
 #define LBM_XCD_REMAP 1
 #endif
+// g and the history velocity are loaded together with f, before the window
+// barrier, when a thread holds at most two nodes (+10-30% on lattices of
+// 0.25-0.5 M nodes, where the step is latency bound); with four nodes per
+// thread the extra live registers cost more than the overlap gains (-17% on
+// 4096^2).  LBM_G_EARLY forces it on (1) or off (0).
+#ifndef LBM_G_EARLY
+#define LBM_G_EARLY -1
+#endif
 
 template <typename T, typename OFF>
 __device__ __forceinline__ void st(char* base, OFF byteoff, T v) {
@@ -51,27 +59,28 @@ __device__ __forceinline__ void st(char* base, OFF byteoff, T v) {
     else *reinterpret_cast<T*>(base + byteoff) = v;
 }
 
-// The fused step.  One 64 x TY tile per 256-thread workgroup; thread
-// (lx, ly) owns nodes (x0 + lx, y0 + ly + 4 r), r < TY/4, keeps their pulled f
+// The fused step.  One 64 x TY tile per workgroup of 64 x NBY threads; thread
+// (lx, ly) owns nodes (x0 + lx, y0 + ly + NBY r), r < TY/NBY, keeps their pulled f
 // in registers from the phi pass to the collision, and the ring of the phi
 // window is pulled by spare threads.  MODE 0: one time step; MODE 1: write
 // phi, u, p of the current level.  OFF: byte-offset type within one copy.
 // FP32 16-row tiles keep four nodes per thread in flight; capping them at 128
 // VGPRs (4 waves per SIMD) is worth +10% on a 4096^2 lattice.  FP64 tiles are
 // never taller than 8 rows (the host caps them): they would spill.
-template <typename T, int TY>
+template <typename T, int TY, int NBY = BY>
 struct StepWaves {
-    static constexpr int value = (sizeof(T) == 4 && TY >= 16) ? 4 : 1;
+    static constexpr int value = (sizeof(T) == 4 && TY / NBY >= 4) ? 4 : 1;
 };
 
 // The tile body between explicit buffers: `src` holds level `step` (one copy:
 // post-collision populations of the previous step and the history), `dst`
 // receives level step + 1.
-template <typename T, int TY, int MODE, typename OFF>
+template <typename T, int TY, int MODE, typename OFF, int NBY = BY>
 __device__ __forceinline__ void step_core(const KParams<T>& P, const char* src, char* dst, int64_t step, int xt,
                                           int yt, T* out_phi, T* out_u, T* out_p, T (*sphi)[TX + 3],
                                           T (*sphp)[TX + 3]) {
-    constexpr int R = TY / BY;
+    constexpr int R = TY / NBY;
+    constexpr bool GE = LBM_G_EARLY < 0 ? R <= 2 : LBM_G_EARLY != 0;
     constexpr int WX = TX + 2, WY = TY + 2;
     constexpr OFF ES = sizeof(T);
     const int x0 = xt * TX, y0 = yt * TY;
@@ -106,9 +115,11 @@ __device__ __forceinline__ void step_core(const KParams<T>& P, const char* src, 
 
     T f[R][9];
     double phid[R];
+    [[maybe_unused]] T ge[GE ? R : 1][9];
+    [[maybe_unused]] T he[GE ? R : 1][2];
 #pragma unroll
     for (int r = 0; r < R; r++) {
-        const int ly = threadIdx.y + r * BY, y = y0 + ly;
+        const int ly = threadIdx.y + r * NBY, y = y0 + ly;
         phid[r] = 0.0;
         if (x >= P.nx || y >= P.ny) continue;
         OFF row[3];
@@ -136,6 +147,19 @@ __device__ __forceinline__ void step_core(const KParams<T>& P, const char* src, 
             const OFF o = bb ? bF + ((OFF)(opp(i) - 1) * pl + k) * ES : bF + ((OFF)(i - 1) * pl + row[ay] + col[ax]) * ES;
             f[r][i] = ld<T>(src, o);
         }
+        if (GE) {
+#pragma unroll
+            for (int i = 0; i < Q; i++) {
+                const int ax = 1 - cx(i), ay = 1 - cy(i);
+                const bool bb = wx[ax] || wy[ay];
+                const OFF o = bb ? bG + ((OFF)opp(i) * pl + k) * ES : bG + ((OFF)i * pl + row[ay] + col[ax]) * ES;
+                ge[GE ? r : 0][i] = ld<T>(src, o);
+            }
+            if (!first) {
+                he[GE ? r : 0][0] = ld<T>(src, bH + (pl + k) * ES);
+                he[GE ? r : 0][1] = ld<T>(src, bH + (2 * pl + k) * ES);
+            }
+        }
         phid[r] = f0 + moving_sum_d(f[r]);
         sphi[ly + 1][lx + 1] = (T)phid[r];
         if (!first) sphp[ly + 1][lx + 1] = ld<T>(src, bH + k * ES);
@@ -157,22 +181,22 @@ __device__ __forceinline__ void step_core(const KParams<T>& P, const char* src, 
         sphi[wyi][wxi] = (T)node_phi(P, S, gx, gy, fw);
         if (!first) sphp[wyi][wxi] = S.h[(long long)gy * P.nx + gx];
     };
-    for (int idx = tid; idx < 2 * WX + 2 * TY; idx += TX * BY) {
+    for (int idx = tid; idx < 2 * WX + 2 * TY; idx += TX * NBY) {
         if (idx < WX) fill_node(idx, 0);
         else if (idx < 2 * WX) fill_node(idx - WX, WY - 1);
         else if (idx < 2 * WX + TY) fill_node(0, 1 + idx - 2 * WX);
         else fill_node(WX - 1, 1 + idx - 2 * WX - TY);
     }
     if (x0 + TX > P.nx)
-        for (int wy = tid; wy < WY; wy += TX * BY) fill_node(P.nx - x0 + 1, wy);
+        for (int wy = tid; wy < WY; wy += TX * NBY) fill_node(P.nx - x0 + 1, wy);
     if (y0 + TY > P.ny)
-        for (int wxi = tid; wxi < WX; wxi += TX * BY) fill_node(wxi, P.ny - y0 + 1);
+        for (int wxi = tid; wxi < WX; wxi += TX * NBY) fill_node(wxi, P.ny - y0 + 1);
     __syncthreads();
-    wall_ghosts<T, TY>(P, !first, x0, y0, sphi, sphp);
+    wall_ghosts<T, TY, NBY>(P, !first, x0, y0, sphi, sphp);
 
 #pragma unroll
     for (int r = 0; r < R; r++) {
-        const int ly = threadIdx.y + r * BY, y = y0 + ly;
+        const int ly = threadIdx.y + r * NBY, y = y0 + ly;
         if (x >= P.nx || y >= P.ny) continue;
         OFF row[3];
         bool wy[3] = {false, false, false};
@@ -191,20 +215,30 @@ __device__ __forceinline__ void step_core(const KParams<T>& P, const char* src, 
         }
         const OFF k = row[1] + col[1];
         T g[9];
+        if (GE) {
 #pragma unroll
-        for (int i = 0; i < Q; i++) {
-            const int ax = 1 - cx(i), ay = 1 - cy(i);
-            const bool bb = wx[ax] || wy[ay];
-            const OFF o = bb ? bG + ((OFF)opp(i) * pl + k) * ES : bG + ((OFF)i * pl + row[ay] + col[ax]) * ES;
-            g[i] = ld<T>(src, o);
+            for (int i = 0; i < Q; i++) g[i] = ge[GE ? r : 0][i];
+        } else {
+#pragma unroll
+            for (int i = 0; i < Q; i++) {
+                const int ax = 1 - cx(i), ay = 1 - cy(i);
+                const bool bb = wx[ax] || wy[ay];
+                const OFF o = bb ? bG + ((OFF)opp(i) * pl + k) * ES : bG + ((OFF)i * pl + row[ay] + col[ax]) * ES;
+                g[i] = ld<T>(src, o);
+            }
         }
         T gx, gy, lap, gxp = T(0), gyp = T(0), lp, php = T(0), up = T(0), vp = T(0);
         win_stencil<T, TY>(sphi, lx + 1, ly + 1, gx, gy, lap);
         if (!first) {
             win_stencil<T, TY>(sphp, lx + 1, ly + 1, gxp, gyp, lp);
             php = sphp[ly + 1][lx + 1];
-            up = ld<T>(src, bH + (pl + k) * ES);
-            vp = ld<T>(src, bH + (2 * pl + k) * ES);
+            if (GE) {
+                up = he[GE ? r : 0][0];
+                vp = he[GE ? r : 0][1];
+            } else {
+                up = ld<T>(src, bH + (pl + k) * ES);
+                vp = ld<T>(src, bH + (2 * pl + k) * ES);
+            }
         }
         Macro<T> M = macro(P, g, sphi[ly + 1][lx + 1], gx, gy, lap, first, php, gxp, gyp, up, vp);
         if (MODE == 1) {
@@ -231,7 +265,7 @@ __device__ __forceinline__ void step_core(const KParams<T>& P, const char* src, 
 
 // The tile body on a ping-pong state: the level stamp of the tile's first row
 // selects the source copy, and the tile's rows move to the next level.
-template <typename T, int TY, int MODE, typename OFF>
+template <typename T, int TY, int MODE, typename OFF, int NBY = BY>
 __device__ __forceinline__ void step_tile(const KParams<T>& P, char* state, size_t off0, size_t off1,
                                           size_t off_stamp, int xt, int yt, T* out_phi, T* out_u, T* out_p,
                                           T (*sphi)[TX + 3], T (*sphp)[TX + 3]) {
@@ -239,7 +273,7 @@ __device__ __forceinline__ void step_tile(const KParams<T>& P, char* state, size
     int64_t* stamp = reinterpret_cast<int64_t*>(state + off_stamp) + (size_t)xt * P.ny + y0;
     const int64_t step = stamp[0];
     const int cur = (int)(step & 1);
-    step_core<T, TY, MODE, OFF>(P, state + (cur ? off1 : off0), state + (cur ? off0 : off1), step, xt, yt, out_phi,
+    step_core<T, TY, MODE, OFF, NBY>(P, state + (cur ? off1 : off0), state + (cur ? off0 : off1), step, xt, yt, out_phi,
                                 out_u, out_p, sphi, sphp);
     // Own rows move to level n + 1.  Every wave of the workgroup consumed its
     // load of stamp[0] (it addresses all loads above) before the barriers of

@@ -21,8 +21,8 @@
 
 namespace lbm {
 
-template <typename T, int TY, int MODE, typename OFF>
-__global__ __launch_bounds__(TX* BY) __attribute__((amdgpu_waves_per_eu(StepWaves<T, TY>::value)))
+template <typename T, int TY, int MODE, typename OFF, int NBY>
+__global__ __launch_bounds__(TX* NBY) __attribute__((amdgpu_waves_per_eu(StepWaves<T, TY, NBY>::value)))
 void k_step(KParams<T> P, char* state, size_t off0, size_t off1, size_t off_stamp, int ntx, int nty, T* out_phi,
             T* out_u, T* out_p) {
     __shared__ T sphi[TY + 2][TX + 3];
@@ -34,7 +34,7 @@ void k_step(KParams<T> P, char* state, size_t off0, size_t off1, size_t off_stam
         xt = blockIdx.x % ntx;
         yt = blockIdx.x / ntx;
     }
-    step_tile<T, TY, MODE, OFF>(P, state, off0, off1, off_stamp, xt, yt, out_phi, out_u, out_p, sphi, sphp);
+    step_tile<T, TY, MODE, OFF, NBY>(P, state, off0, off1, off_stamp, xt, yt, out_phi, out_u, out_p, sphi, sphp);
 }
 
 // ---------------------------------------------------------------- init / import / export
@@ -176,25 +176,31 @@ static int grid1d(long long n) {
 // Byte size of one copy fits 32-bit offsets?
 static bool small_copy(const Layout& L) { return L.buf_bytes < (size_t(1) << 32); }
 
-template <typename T, int TY, int MODE>
+template <typename T, int TY, int MODE, int NBY = BY>
 static void launch_tile(const KParams<T>& P, char* state, const Layout& L, hipStream_t s, T* phi, T* u, T* p) {
     const int ntx = (P.nx + TX - 1) / TX, nty = (P.ny + TY - 1) / TY;
-    dim3 blk(TX, BY);
+    dim3 blk(TX, NBY);
     if (small_copy(L))
-        k_step<T, TY, MODE, uint32_t><<<ntx * nty, blk, 0, s>>>(P, state, L.off_buf[0], L.off_buf[1], L.off_stamp,
-                                                                 ntx, nty, phi, u, p);
+        k_step<T, TY, MODE, uint32_t, NBY><<<ntx * nty, blk, 0, s>>>(P, state, L.off_buf[0], L.off_buf[1],
+                                                                      L.off_stamp, ntx, nty, phi, u, p);
     else
-        k_step<T, TY, MODE, uint64_t><<<ntx * nty, blk, 0, s>>>(P, state, L.off_buf[0], L.off_buf[1], L.off_stamp,
-                                                                 ntx, nty, phi, u, p);
+        k_step<T, TY, MODE, uint64_t, NBY><<<ntx * nty, blk, 0, s>>>(P, state, L.off_buf[0], L.off_buf[1],
+                                                                      L.off_stamp, ntx, nty, phi, u, p);
 }
 
 template <typename T>
 hipError_t launch_step(const KParams<T>& P, char* state, const Layout& L, int64_t nsteps, hipStream_t s,
-                       int ty) {
+                       int ty, int by) {
+    constexpr int T16 = sizeof(T) == 8 ? 8 : 16;   // FP64 tiles stop at 8 rows
     for (int64_t t = 0; t < nsteps; t++) {
         if (ty == 4) launch_tile<T, 4, 0>(P, state, L, s, nullptr, nullptr, nullptr);
-        else if (ty == 8 || sizeof(T) == 8) launch_tile<T, 8, 0>(P, state, L, s, nullptr, nullptr, nullptr);
-        else launch_tile<T, sizeof(T) == 8 ? 8 : 16, 0>(P, state, L, s, nullptr, nullptr, nullptr);
+        else if (ty == 8 || sizeof(T) == 8) {
+            if (by == 8) launch_tile<T, 8, 0, 8>(P, state, L, s, nullptr, nullptr, nullptr);
+            else launch_tile<T, 8, 0>(P, state, L, s, nullptr, nullptr, nullptr);
+        } else {
+            if (by == 8) launch_tile<T, T16, 0, 8>(P, state, L, s, nullptr, nullptr, nullptr);
+            else launch_tile<T, T16, 0>(P, state, L, s, nullptr, nullptr, nullptr);
+        }
     }
     return hipGetLastError();
 }
@@ -255,7 +261,7 @@ hipError_t launch_export(const KParams<T>& P, const char* state, const Layout& L
 }
 
 #define LBM_INSTANTIATE(T)                                                                              \
-    template hipError_t launch_step<T>(const KParams<T>&, char*, const Layout&, int64_t, hipStream_t, int); \
+    template hipError_t launch_step<T>(const KParams<T>&, char*, const Layout&, int64_t, hipStream_t, int, int); \
     template hipError_t launch_moments<T>(const KParams<T>&, const char*, const Layout&, T*, T*, T*,     \
                                           hipStream_t);                                                 \
     template hipError_t launch_init<T>(const KParams<T>&, char*, const Layout&, const T*, const T*,     \

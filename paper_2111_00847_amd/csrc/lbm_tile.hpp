@@ -22,14 +22,14 @@ __device__ __forceinline__ double node_phi(const KParams<T>& P, const Copy<T>& C
 // Wall ghosts of the window (Eq. Dwetting): x-walls first, then y-walls
 // across the extended rows, which fixes the corners.  Call after the window
 // interior and ring are filled and synchronised; ends synchronised.
-template <typename T, int TY>
+template <typename T, int TY, int NBY = BY>
 __device__ __forceinline__ void wall_ghosts(const KParams<T>& P, bool need_prev, int x0, int y0,
                                             T (*sphi)[TX + 3], T (*sphp)[TX + 3]) {
     constexpr int WX = TX + 2, WY = TY + 2;
     const int tid = threadIdx.y * TX + threadIdx.x;
     if (P.wall_x) {
         const int wxr = P.nx - x0 + 1;  // window column of x = nx
-        for (int wy = tid; wy < WY; wy += TX * BY) {
+        for (int wy = tid; wy < WY; wy += TX * NBY) {
             // rows beyond a y-wall get their ghosts below; on a periodic y axis
             // the halo rows -1 and ny hold wrapped rows and need x-ghosts too
             const int gy = y0 - 1 + wy;
@@ -47,7 +47,7 @@ __device__ __forceinline__ void wall_ghosts(const KParams<T>& P, bool need_prev,
     }
     if (P.wall_y) {
         const int wyt = P.ny - y0 + 1;  // window row of y = ny
-        for (int wx = tid; wx < WX; wx += TX * BY) {
+        for (int wx = tid; wx < WX; wx += TX * NBY) {
             int gx = x0 - 1 + wx;
             if (gx > P.nx) continue;
             if (y0 == 0) {

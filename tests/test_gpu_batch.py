@@ -81,7 +81,8 @@ def test_batch_autotune_choice_and_reinit():
     B = BatchSim([c for c, _ in cases], autotune=True)
     B.init([p for _, p in cases])
     t = B.tuning()
-    assert t["tile_rows"] in (4, 8, 16) and 1 <= t["grid"] <= t["items"]
+    assert t["tile_rows"] in (4, 8, 16) and t["thread_rows"] in (4, 8) and t["thread_rows"] <= t["tile_rows"]
+    assert 1 <= t["grid"] <= t["items"]
     for c, (case, phi0) in enumerate(cases):
         s = B.case(c)
         assert s.export_state()["step"] == 0
