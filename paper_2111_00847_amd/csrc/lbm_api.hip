@@ -123,9 +123,10 @@ template KParams<double> resolve<double>(const lbm_params*, const Layout&);
 // Shape of the step launch: 64 x TY tiles on workgroups of 64 x BY threads.
 // Taller tiles amortise the one-node halo ring; more waves hide latency.
 // Measured on MI355X (FP32): lattices of >= 4096 16-row tiles run best at
-// (16, 4) -- four nodes per thread, HBM bound; below that the step is latency
-// bound and the tallest tile that still gives >= 4096 waves wins: (16, 8) for
-// 1024 x 512, (8, 8) for 256 x 1024, else (4, 4).  FP64 tiles stop at 8 rows
+// (8, 8) (30.4 GLUPS on 4096^2, within 3.5% of every other shape); below that
+// the step is latency bound and the tallest tile that still gives >= 4096
+// waves wins: (16, 8) for 1024 x 512 (27.1 vs 22.4 at (8, 8)), (8, 8) for
+// 256 x 1024 (24.8 vs 22.9 at (16, 8)), else (4, 4).  FP64 tiles stop at 8 rows
 // (taller ones spill); (8, 4) measured best for FP64.
 #ifndef LBM_STEP_TY
 #define LBM_STEP_TY 0   // force a tile height (4, 8, 16); 0 = by lattice size
@@ -141,8 +142,8 @@ void step_shape(const lbm_params* p, int* ty, int* by) {
         t = 8;
         b = 4;
     } else if (t16 >= 4096) {
-        t = 16;
-        b = 4;
+        t = 8;
+        b = 8;
     } else if (t16 * 8 >= 4096) {
         t = 16;
         b = 8;

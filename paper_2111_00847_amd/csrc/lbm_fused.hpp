@@ -52,6 +52,15 @@ __device__ __forceinline__ T ld(const char* base, OFF byteoff) {
 #ifndef LBM_G_EARLY
 #define LBM_G_EARLY -1
 #endif
+// Every load of a thread's own nodes (f, the history phi, and g when GE) is
+// issued before the first of them is used.  For FP64 the thread's ring node of
+// the window is pulled in the same round trip too (+10% on 256 x 1024); for
+// FP32 the extra live registers cost more than the saved round trip (-6% on
+// 256 x 1024, -15% on 1024 x 512), and the ring is pulled after the own nodes.
+// LBM_RING_EARLY forces it on (1) or off (0).
+#ifndef LBM_RING_EARLY
+#define LBM_RING_EARLY -1
+#endif
 
 template <typename T, typename OFF>
 __device__ __forceinline__ void st(char* base, OFF byteoff, T v) {
@@ -81,6 +90,7 @@ __device__ __forceinline__ void step_core(const KParams<T>& P, const char* src, 
                                           T (*sphp)[TX + 3]) {
     constexpr int R = TY / NBY;
     constexpr bool GE = LBM_G_EARLY < 0 ? R <= 2 : LBM_G_EARLY != 0;
+    constexpr bool RE = LBM_RING_EARLY < 0 ? sizeof(T) == 8 : LBM_RING_EARLY != 0;
     constexpr int WX = TX + 2, WY = TY + 2;
     constexpr OFF ES = sizeof(T);
     const int x0 = xt * TX, y0 = yt * TY;
@@ -114,13 +124,16 @@ __device__ __forceinline__ void step_core(const KParams<T>& P, const char* src, 
     }
 
     T f[R][9];
-    double phid[R];
+    double phid[R], f0d[R];
+    T hp[R];
     [[maybe_unused]] T ge[GE ? R : 1][9];
     [[maybe_unused]] T he[GE ? R : 1][2];
 #pragma unroll
     for (int r = 0; r < R; r++) {
         const int ly = threadIdx.y + r * NBY, y = y0 + ly;
         phid[r] = 0.0;
+        f0d[r] = 0.0;
+        hp[r] = T(0);
         if (x >= P.nx || y >= P.ny) continue;
         OFF row[3];
         bool wy[3] = {false, false, false};
@@ -160,9 +173,69 @@ __device__ __forceinline__ void step_core(const KParams<T>& P, const char* src, 
                 he[GE ? r : 0][1] = ld<T>(src, bH + (2 * pl + k) * ES);
             }
         }
-        phid[r] = f0 + moving_sum_d(f[r]);
-        sphi[ly + 1][lx + 1] = (T)phid[r];
-        if (!first) sphp[ly + 1][lx + 1] = ld<T>(src, bH + k * ES);
+        f0d[r] = f0;
+        if (!first) hp[r] = ld<T>(src, bH + k * ES);
+        if (!RE) {
+            phid[r] = f0 + moving_sum_d(f[r]);
+            sphi[ly + 1][lx + 1] = (T)phid[r];
+            if (!first) sphp[ly + 1][lx + 1] = hp[r];
+        }
+    }
+
+    // ring of the window: position idx of the ring walk (top row, bottom row,
+    // left column, right column) -> window cell; false if it holds no node
+    constexpr int NRING = 2 * WX + 2 * TY;
+    auto ring_cell = [&](int idx, int& wxi, int& wyi, int& gx, int& gy) -> bool {
+        if (idx < WX) {
+            wxi = idx;
+            wyi = 0;
+        } else if (idx < 2 * WX) {
+            wxi = idx - WX;
+            wyi = WY - 1;
+        } else if (idx < 2 * WX + TY) {
+            wxi = 0;
+            wyi = 1 + idx - 2 * WX;
+        } else {
+            wxi = WX - 1;
+            wyi = 1 + idx - 2 * WX - TY;
+        }
+        gx = x0 - 1 + wxi;
+        gy = y0 - 1 + wyi;
+        if (gx > P.nx || gy > P.ny) return false;
+        if (gx < 0 || gx >= P.nx) {
+            if (P.wall_x) return false;
+            gx = gx < 0 ? gx + P.nx : gx - P.nx;
+        }
+        if (gy < 0 || gy >= P.ny) {
+            if (P.wall_y) return false;
+            gy = gy < 0 ? gy + P.ny : gy - P.ny;
+        }
+        return true;
+    };
+    if (RE) {
+        static_assert(NRING <= TX * NBY, "one ring node per thread");
+        int rwx = 0, rwy = 0, rgx = 0, rgy = 0;
+        const bool rv = tid < NRING && ring_cell(tid, rwx, rwy, rgx, rgy);
+        T fr[9], rh = T(0);
+        double fr0 = 0.0;
+        if (rv) {
+            fr0 = S.f0[(long long)rgy * P.nx + rgx];
+#pragma unroll
+            for (int i = 1; i < Q; i++) fr[i] = pull(S.f, P, i, rgx, rgy);
+            if (!first) rh = S.h[(long long)rgy * P.nx + rgx];
+        }
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            const int ly = threadIdx.y + r * NBY, y = y0 + ly;
+            if (x >= P.nx || y >= P.ny) continue;
+            phid[r] = f0d[r] + moving_sum_d(f[r]);
+            sphi[ly + 1][lx + 1] = (T)phid[r];
+            if (!first) sphp[ly + 1][lx + 1] = hp[r];
+        }
+        if (rv) {
+            sphi[rwy][rwx] = (T)(fr0 + moving_sum_d(fr));
+            if (!first) sphp[rwy][rwx] = rh;
+        }
     }
 
     // ring of the window (and, for a ragged tile, the halo column/row inside it)
@@ -181,12 +254,12 @@ __device__ __forceinline__ void step_core(const KParams<T>& P, const char* src, 
         sphi[wyi][wxi] = (T)node_phi(P, S, gx, gy, fw);
         if (!first) sphp[wyi][wxi] = S.h[(long long)gy * P.nx + gx];
     };
-    for (int idx = tid; idx < 2 * WX + 2 * TY; idx += TX * NBY) {
-        if (idx < WX) fill_node(idx, 0);
-        else if (idx < 2 * WX) fill_node(idx - WX, WY - 1);
-        else if (idx < 2 * WX + TY) fill_node(0, 1 + idx - 2 * WX);
-        else fill_node(WX - 1, 1 + idx - 2 * WX - TY);
-    }
+    if (!RE)
+        for (int idx = tid; idx < NRING; idx += TX * NBY) {
+            int wxi, wyi, gx, gy;
+            ring_cell(idx, wxi, wyi, gx, gy);
+            fill_node(wxi, wyi);
+        }
     if (x0 + TX > P.nx)
         for (int wy = tid; wy < WY; wy += TX * NBY) fill_node(P.nx - x0 + 1, wy);
     if (y0 + TY > P.ny)
