@@ -11,7 +11,7 @@
 // level n (the level n-1 fields).  It lives in one of two copies (n & 1) of an
 // adjoint buffer, with dL/df_i^n kept as fd_i + phib: the direct part of each
 // population and the common part that reaches all nine through phi = sum f_i.
-// One adjoint step n+1 -> n runs two kernels:
+// One adjoint step n+1 -> n runs three kernels:
 //   A (k_adj_local, tiles)  recomputes the forward node update of level n from
 //       the tape, reads the adjoint of each post-collision population where the
 //       population streams to (the reverse of the pull, with bounce-back), and
@@ -19,12 +19,14 @@
 //       velocity, and the adjoints of the stencil inputs (gradient, Laplacian,
 //       centre) to scratch planes, plus per-tile sums of the gravity
 //       derivative.
-//   B (k_adj_gather, nodes)  the transposed stencils: phib at a node gathers
-//       the stencil adjoints of the nodes whose windows hold it; a node next to
-//       a wall also collects the adjoint of the ghosts built from it (Eq.
-//       Dwetting; corner ghosts are built on x-wall ghosts), and the first
-//       fluid node of each ghost adds the contact-angle derivative.  Likewise
-//       for the previous phi of the history.
+//   G (k_adj_ghosts, one thread per wall ghost)  the adjoint of each ghost (what
+//       its neighbours' stencils took from it; for an x-wall ghost next to a
+//       y-wall also what the corner ghost built on it took), routed through
+//       Eq. Dwetting to its first and second fluid node (edge arrays), and the
+//       contact-angle derivatives.
+//   B (k_adj_gather, tiles)  the transposed stencils: phib at a node gathers the
+//       stencil adjoints of the nodes whose windows hold it and adds the edge
+//       arrays of G; likewise for the previous phi of the history.
 // Parameter derivatives accumulate into fixed per-workgroup slots (no atomics;
 // deterministic) and are summed by lbm_adjoint_params.
 #include <hip/hip_runtime.h>
@@ -73,14 +75,16 @@ struct AdjLayout {
     size_t esz;
     size_t off_copy[2];
     size_t off_scr;
-    size_t off_part;      // doubles: 2 per tile of A (gravity), then 4 per workgroup of B (contact angles)
+    size_t off_edge;      // G -> B: [level][wall][depth][position along the wall]
+    long long emax;
+    size_t off_part;      // doubles: 2 per tile of A (gravity), then 4 per workgroup of G (contact angles)
     int ntA, nB;
     size_t total;
 };
 
 static size_t al256(size_t b) { return (b + 255) / 256 * 256; }
 
-static int wall_blocks(const lbm_params* p);
+static int ghost_blocks(const lbm_params* p);
 
 AdjLayout adj_layout_of(const lbm_params* p) {
     Layout L = layout_of(p);
@@ -91,9 +95,11 @@ AdjLayout adj_layout_of(const lbm_params* p) {
     A.off_copy[0] = ADJ_HDR;
     A.off_copy[1] = A.off_copy[0] + cp;
     A.off_scr = A.off_copy[1] + cp;
-    A.off_part = al256(A.off_scr + (size_t)S_COUNT * L.plane * L.esz);
+    A.off_edge = A.off_scr + (size_t)S_COUNT * L.plane * L.esz;
+    A.emax = ((long long)(p->nx > p->ny ? p->nx : p->ny) + 63) / 64 * 64;
+    A.off_part = al256(A.off_edge + (size_t)16 * A.emax * L.esz);
     A.ntA = ((p->nx + TX - 1) / TX) * ((p->ny + ATY - 1) / ATY);
-    A.nB = wall_blocks(p);   // workgroups of kernel W
+    A.nB = ghost_blocks(p);   // workgroups of kernel G
     A.total = al256(A.off_part + (size_t)(2 * A.ntA + 4 * A.nB) * sizeof(double));
     return A;
 }
@@ -105,11 +111,15 @@ struct AdjView {
     long long plane;
     T* copy[2];
     T* scr;
+    T* edge;
+    long long emax;
     double* part;
     int ntA, nB;
     __device__ AdjHeader* hdr() const { return reinterpret_cast<AdjHeader*>(base); }
     __device__ T* plane_of(int c, int i) const { return copy[c] + (long long)i * plane; }
     __device__ T* s(int i) const { return scr + (long long)i * plane; }
+    // lev 0: phi of level n, 1: previous phi; wall 0..3 (x-, x+, y-, y+); depth 0: first fluid node
+    __device__ T* e(int lev, int wall, int depth) const { return edge + ((lev * 4 + wall) * 2 + depth) * emax; }
     __device__ long long nslot() const { return 2LL * ntA + 4LL * nB; }
 };
 
@@ -121,6 +131,8 @@ AdjView<T> adj_view(void* adj, const AdjLayout& A) {
     V.copy[0] = reinterpret_cast<T*>(V.base + A.off_copy[0]);
     V.copy[1] = reinterpret_cast<T*>(V.base + A.off_copy[1]);
     V.scr = reinterpret_cast<T*>(V.base + A.off_scr);
+    V.edge = reinterpret_cast<T*>(V.base + A.off_edge);
+    V.emax = A.emax;
     V.part = reinterpret_cast<double*>(V.base + A.off_part);
     V.ntA = A.ntA;
     V.nB = A.nB;
@@ -381,12 +393,30 @@ __global__ __launch_bounds__(TX* BY) void k_adj_gather(KParams<T> P, const char*
         }
     }
     __syncthreads();
+    if (blockIdx.x == 0 && tid == 0) V.hdr()->level = n;
     const int lx = threadIdx.x, ly = threadIdx.y;
     const int x = x0 + lx, y = y0 + ly;
     if (x >= P.nx || y >= P.ny) return;
     const long long k = (long long)y * P.nx + x;
+    // what the wall ghosts built from this node received (kernel G)
+    auto edges = [&](int lev) -> T {
+        T a = T(0);
+        if (P.wall_x) {
+            if (x == 0) a += V.e(lev, 0, 0)[y];
+            if (x == 1) a += V.e(lev, 0, 1)[y];
+            if (x == P.nx - 1) a += V.e(lev, 1, 0)[y];
+            if (x == P.nx - 2) a += V.e(lev, 1, 1)[y];
+        }
+        if (P.wall_y) {
+            if (y == 0) a += V.e(lev, 2, 0)[x];
+            if (y == 1) a += V.e(lev, 2, 1)[x];
+            if (y == P.ny - 1) a += V.e(lev, 3, 0)[x];
+            if (y == P.ny - 2) a += V.e(lev, 3, 1)[x];
+        }
+        return a;
+    };
     // node (x - dx, y - dy) holds (x, y) at window offset (dx, dy)
-    T acc = V.s(S_PHIC)[k], accp = T(0);
+    T acc = V.s(S_PHIC)[k] + edges(0), accp = T(0);
 #pragma unroll
     for (int dy = -1; dy <= 1; dy++)
 #pragma unroll
@@ -396,7 +426,7 @@ __global__ __launch_bounds__(TX* BY) void k_adj_gather(KParams<T> P, const char*
         }
     V.plane_of(co, P_PHIB)[k] = acc;
     if (!first) {
-        accp = V.s(S_PHP)[k];
+        accp = V.s(S_PHP)[k] + edges(1);
 #pragma unroll
         for (int dy = -1; dy <= 1; dy++)
 #pragma unroll
@@ -408,105 +438,64 @@ __global__ __launch_bounds__(TX* BY) void k_adj_gather(KParams<T> P, const char*
     V.plane_of(co, 18)[k] = accp;
 }
 
-// ---------------------------------------------------------------- adjoint step, kernel W
-// Nodes within two of a wall: rows [0, ylo) and [yhi, ny) when the y axis has
-// walls, then columns [0, xlo) and [xhi, nx) of the rows in between when the x
-// axis has walls -- each such node once.
-struct WallSet {
-    int ylo, yhi, xlo, xhi;
-    long long nrow, count;
-};
+// ---------------------------------------------------------------- adjoint step, kernel G
+// Items, per level (the previous level only when n > 0): y-wall ghosts
+// (2 nx, when the y axis has walls), then x-wall ghosts (2 ny, when the x axis
+// has walls).
+constexpr int GHOST_THREADS = 256;
 
-inline WallSet wall_set(int nx, int ny, bool wall_x, bool wall_y) {
-    WallSet w;
-    w.ylo = wall_y ? (ny < 2 ? ny : 2) : 0;
-    w.yhi = wall_y ? (ny - 2 > w.ylo ? ny - 2 : w.ylo) : ny;
-    w.xlo = wall_x ? (nx < 2 ? nx : 2) : 0;
-    w.xhi = wall_x ? (nx - 2 > w.xlo ? nx - 2 : w.xlo) : nx;
-    const int nry = w.ylo + (ny - w.yhi), ncx = w.xlo + (nx - w.xhi);
-    w.nrow = (long long)nry * nx;
-    w.count = w.nrow + (long long)ncx * (w.yhi - w.ylo);
-    return w;
+__host__ __device__ inline long long ghost_items(int nx, int ny, bool wall_x, bool wall_y) {
+    return (wall_y ? 2LL * nx : 0LL) + (wall_x ? 2LL * ny : 0LL);
 }
 
-constexpr int WALL_THREADS = 256;
-
-static int wall_blocks(const lbm_params* p) {
-    const WallSet w = wall_set(p->nx, p->ny, p->bc_x == LBM_WALLS, p->bc_y == LBM_WALLS);
-    const long long b = (w.count + WALL_THREADS - 1) / WALL_THREADS;
+static int ghost_blocks(const lbm_params* p) {
+    const long long items = 2 * ghost_items(p->nx, p->ny, p->bc_x == LBM_WALLS, p->bc_y == LBM_WALLS);
+    const long long b = (items + GHOST_THREADS - 1) / GHOST_THREADS;
     return (int)(b < 1 ? 1 : (b > 1024 ? 1024 : b));
 }
 
-// Adds to phib (and to the previous-phi adjoint) of every wall node what the
-// ghosts built from it received: the first and second fluid node of each
-// ghost get d ghost / d phi_1 and d ghost / d phi_2 times the ghost's adjoint
-// (its neighbours' stencil terms, plus, for an x-ghost next to a y-wall, the
-// corner ghost built on it); the first node also adds d ghost / d theta of its
-// ghost (and of the corner ghost of its wall row) to the contact-angle sums.
 template <typename T>
-__global__ __launch_bounds__(WALL_THREADS) void k_adj_walls(KParams<T> P, const char* tape, size_t slot, int j,
-                                                           AdjView<T> V, WallSet ws) {
-    __shared__ double red[4][WALL_THREADS / 64];
+__global__ __launch_bounds__(GHOST_THREADS) void k_adj_ghosts(KParams<T> P, const char* tape, size_t slot, int j,
+                                                             AdjView<T> V) {
+    __shared__ double red[4][GHOST_THREADS / 64];
     const int64_t n = reinterpret_cast<const TapeHeader*>(tape)->n0 + j;
-    AdjHeader* H = V.hdr();
-    if (H->status != 0) return;
+    if (V.hdr()->status != 0) return;
     const bool first = n == 0;
-    const int co = (int)(n & 1);
     const Copy<T> S = copy_at<T>(const_cast<char*>(tape + TAPE_HDR + (size_t)j * slot), P.plane);
+    const long long per = ghost_items(P.nx, P.ny, P.wall_x, P.wall_y);
+    const long long ny2 = P.wall_y ? 2LL * P.nx : 0LL;
     double th[4] = {0.0, 0.0, 0.0, 0.0};
-    for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < ws.count;
+    for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < (first ? 1 : 2) * per;
          idx += (long long)gridDim.x * blockDim.x) {
-        int x, y;
-        if (idx < ws.nrow) {
-            const int r = (int)(idx / P.nx);
-            x = (int)(idx - (long long)r * P.nx);
-            y = r < ws.ylo ? r : ws.yhi + (r - ws.ylo);
-        } else {
-            const long long i2 = idx - ws.nrow;
-            const int ncx = ws.xlo + (P.nx - ws.xhi);
-            const int c = (int)(i2 % ncx);
-            x = c < ws.xlo ? c : ws.xhi + (c - ws.xlo);
-            y = ws.ylo + (int)(i2 / ncx);
-        }
-        const long long k = (long long)y * P.nx + x;
-        for (int lev = 0; lev < (first ? 1 : 2); lev++) {
-            const T* phi = lev ? S.h : V.s(S_PHI);
-            T acc = T(0);
-            if (P.wall_x)
-                for (int sx = 0; sx < 2; sx++) {
-                    const int x1 = sx ? P.nx - 1 : 0, x2 = sx ? P.nx - 2 : 1;
-                    if (x != x1 && x != x2) continue;
-                    const T q = xghost_adjoint(P, V, lev, phi, sx, y);
-                    T d1, d2, dth;
-                    wet_ghost_grad(P, sx, phi_at(P, phi, x1, y), phi_at(P, phi, x2, y), d1, d2, dth);
-                    if (x == x1) {
-                        acc += d1 * q;
-                        th[sx] += (double)(dth * q);
-                    }
-                    if (x == x2) acc += d2 * q;
-                }
-            if (P.wall_y)
-                for (int sy = 0; sy < 2; sy++) {
-                    const int y1 = sy ? P.ny - 1 : 0, y2 = sy ? P.ny - 2 : 1;
-                    if (y != y1 && y != y2) continue;
-                    const T q = ext_adjoint(P, V, lev, x, sy ? P.ny : -1);
-                    T d1, d2, dth;
-                    wet_ghost_grad(P, 2 + sy, phi_at(P, phi, x, y1), phi_at(P, phi, x, y2), d1, d2, dth);
-                    if (y == y1) {
-                        acc += d1 * q;
-                        th[2 + sy] += (double)(dth * q);
-                        if (P.wall_x && (x == 0 || x == P.nx - 1)) {   // the corner ghost of this wall row
-                            const int side = x == 0 ? 0 : 1;
-                            const T qc = ext_adjoint(P, V, lev, side ? P.nx : -1, sy ? P.ny : -1);
-                            T c1, c2, cth;
-                            wet_ghost_grad(P, 2 + sy, xghost(P, phi, side, y1), xghost(P, phi, side, y2), c1, c2,
-                                           cth);
-                            th[2 + sy] += (double)(cth * qc);
-                        }
-                    }
-                    if (y == y2) acc += d2 * q;
-                }
-            V.plane_of(co, lev ? 18 : P_PHIB)[k] += acc;
+        const int lev = (int)(idx / per);
+        const long long it = idx - lev * per;
+        const T* phi = lev ? S.h : V.s(S_PHI);
+        if (it < ny2) {   // y-wall ghost (x, -1) or (x, ny)
+            const int sy = (int)(it / P.nx), x = (int)(it - (long long)sy * P.nx);
+            const int y1 = sy ? P.ny - 1 : 0, y2 = sy ? P.ny - 2 : 1;
+            const T q = ext_adjoint(P, V, lev, x, sy ? P.ny : -1);
+            T d1, d2, dth;
+            wet_ghost_grad(P, 2 + sy, phi_at(P, phi, x, y1), phi_at(P, phi, x, y2), d1, d2, dth);
+            V.e(lev, 2 + sy, 0)[x] = d1 * q;
+            V.e(lev, 2 + sy, 1)[x] = d2 * q;
+            th[2 + sy] += (double)(dth * q);
+            if (P.wall_x && (x == 0 || x == P.nx - 1)) {   // the corner ghost beside it
+                const int side = x == 0 ? 0 : 1;
+                const T qc = ext_adjoint(P, V, lev, side ? P.nx : -1, sy ? P.ny : -1);
+                T c1, c2, cth;
+                wet_ghost_grad(P, 2 + sy, xghost(P, phi, side, y1), xghost(P, phi, side, y2), c1, c2, cth);
+                th[2 + sy] += (double)(cth * qc);
+            }
+        } else {          // x-wall ghost (-1, y) or (nx, y)
+            const long long i2 = it - ny2;
+            const int sx = (int)(i2 / P.ny), y = (int)(i2 - (long long)sx * P.ny);
+            const int x1 = sx ? P.nx - 1 : 0, x2 = sx ? P.nx - 2 : 1;
+            const T q = xghost_adjoint(P, V, lev, phi, sx, y);
+            T d1, d2, dth;
+            wet_ghost_grad(P, sx, phi_at(P, phi, x1, y), phi_at(P, phi, x2, y), d1, d2, dth);
+            V.e(lev, sx, 0)[y] = d1 * q;
+            V.e(lev, sx, 1)[y] = d2 * q;
+            th[sx] += (double)(dth * q);
         }
     }
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -518,7 +507,6 @@ __global__ __launch_bounds__(WALL_THREADS) void k_adj_walls(KParams<T> P, const 
     if (threadIdx.x == 0) {
         double* pth = V.part + 2 * V.ntA + 4 * blockIdx.x;
         for (int q = 0; q < 4; q++) pth[q] += (red[q][0] + red[q][1]) + (red[q][2] + red[q][3]);
-        if (blockIdx.x == 0) H->level = n;
     }
 }
 
@@ -674,9 +662,8 @@ static void launch_adj_step(const KParams<T>& P, const char* tape, size_t slot, 
                             hipStream_t s) {
     const int ntx = (P.nx + TX - 1) / TX, nty = (P.ny + ATY - 1) / ATY;
     k_adj_local<T><<<ntx * nty, dim3(TX, BY), 0, s>>>(P, tape, slot, j, V);
+    if (P.wall_x || P.wall_y) k_adj_ghosts<T><<<V.nB, GHOST_THREADS, 0, s>>>(P, tape, slot, j, V);
     k_adj_gather<T><<<ntx * nty, dim3(TX, BY), 0, s>>>(P, tape, j, V);
-    const WallSet ws = wall_set(P.nx, P.ny, P.wall_x, P.wall_y);
-    k_adj_walls<T><<<V.nB, WALL_THREADS, 0, s>>>(P, tape, slot, j, V, ws);
 }
 
 }  // namespace lbm
