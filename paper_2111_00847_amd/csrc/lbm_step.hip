@@ -1,21 +1,22 @@
 // lbm_step.hip -- gfx950 kernels of the fused phase-field LBM time step.
 //
 // Memory layout (structure of arrays, x fastest): a state buffer is
-//   [header | copy 0: f[9] g[9] hist[3] | copy 1: same | diagnostics scratch]
-// with every plane padded to a multiple of 64 elements.  Copy (n & 1) holds
-// the post-collision populations of level n-1 -- a node obtains its level-n
-// populations by pulling them from its neighbours -- and hist = (phi, u, v)
-// of level n-1, from which the explicit-Euler time derivatives are formed.
-// A step reads copy (n & 1) and writes copy (1 - n & 1).  The level n is kept
-// in per-row stamps owned by the workgroups (lbm_common.hpp), so host code
-// never needs the parity, no workgroup waits for another, and a sequence of
-// steps can be captured in a graph.
+//   [header | copy 0 | copy 1 | level stamps | diagnostics scratch],
+// a copy being f_0 (FP64) | f_1..f_8 | g_0..g_8 | hist = (phi, u, v), every
+// plane padded to a multiple of 64 elements.  Copy (n & 1) holds the
+// post-collision populations of level n-1 -- a node obtains its level-n
+// populations by pulling them from its neighbours -- and the history of level
+// n-1, from which the explicit-Euler time derivatives are formed.  A step
+// reads copy (n & 1) and writes the other.  The level n is kept in per-row
+// stamps owned by the workgroups (lbm_common.hpp), so host code never needs
+// the parity, no workgroup waits for another, and a sequence of steps can be
+// captured in a graph.
 //
 // The phi stencils need phi on a one-node ring around each tile.  A tile of
-// 64 x TY nodes (256 threads) first pulls the populations of its (64+2) x
-// (TY+2) window, sums them into phi in LDS (the ring's pulls hit L2: those
-// lines are the neighbour tiles' own reads), fills wall ghosts, and then each
-// thread runs the per-node update for TY/4 nodes of its column.
+// 64 x TY nodes first pulls the populations of its (64+2) x (TY+2) window,
+// sums them into phi in LDS (the ring's pulls hit L2: those lines are the
+// neighbour tiles' own reads), fills wall ghosts, and then each thread runs
+// the per-node update for its nodes (lbm_fused.hpp).
 #include "lbm_fused.hpp"
 #include "lbm_kernels.hpp"
 
