@@ -16,8 +16,10 @@ The JSON line also carries:
                   `traffic` is the measured HBM bytes per launch from the
                   committed rocprofv3 counter summary when it matches the
                   current kernel source, else null;
-  large_grid   -- the same kernel at 4096 x 4096 (state 2.8 GB, far beyond the
-                  256 MB Infinity Cache), where HBM is the real bound;
+  large_grid   -- the same kernel at 4096 x 4096 (state 2.9 GB, far beyond the
+                  256 MB Infinity Cache), where HBM is the real bound, next to
+                  the bandwidth of torch's own device copy; large_grid_fp64 the
+                  FP64 kernel there;
   batched      -- 64 droplet-spreading cases of uneven sizes (Sec. 4.3 set-up,
                   FP32): one autotuned persistent launch per step replayed from a
                   captured graph, against the same cases advanced one after
@@ -135,20 +137,35 @@ def measure_main(args, torch, W, Sim):
     }
 
 
-def measure_large(args, torch, W, Sim):
-    """The same kernel on a 4096 x 4096 lattice (state 2.9 GB, beyond the 256 MB cache)."""
-    caseL, phiL = W.rti(nx=4096, ny=4096)
+def measure_large(args, torch, W, Sim, dtype="f32"):
+    """The same kernel on a 4096 x 4096 lattice (state 2.9 GB in FP32, 5.6 GB in
+    FP64: far beyond the 256 MB cache), where HBM is the bound."""
+    caseL, phiL = W.rti(nx=4096, ny=4096, dtype=dtype)
     simL = Sim(caseL, "cuda:0").init(phiL, None, W.hydrostatic_pressure(caseL, phiL))
     simL.step(10)
-    msL, msLl = time_steps(simL, args.large_steps, torch)
-    algL = ALG_BYTES["f32"] * caseL.nodes
+    steps = args.large_steps if dtype == "f32" else max(args.large_steps // 2, 1)
+    msL, msLl = time_steps(simL, steps, torch)
+    algL = ALG_BYTES[dtype] * caseL.nodes
     achL = algL / (msLl * 1e-3) / 1e9
     del simL
     torch.cuda.empty_cache()
-    return {"workload": "rayleigh_taylor_4096x4096", "steps": args.large_steps,
-            "value": round(caseL.nodes * args.large_steps / (msL * 1e-3) / 1e6, 1),
+    return {"workload": "rayleigh_taylor_4096x4096", "dtype": dtype, "steps": steps,
+            "value": round(caseL.nodes * steps / (msL * 1e-3) / 1e6, 1),
             "unit": "MLUPS", "achieved_GBs": round(achL, 1),
             "frac": round(achL / HBM_PEAK_GBS, 4), "avg_launch_ms": round(msLl, 4)}
+
+
+def measure_copy(torch, mib=1024, reps=20):
+    """Bandwidth of torch's device-to-device copy of a `mib` MiB buffer (read + write
+    bytes per second): a measured ceiling next to the nominal HBM peak."""
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    ms = _timed(torch.cuda.current_stream(), torch, lambda: [b.copy_(a) for _ in range(reps)])
+    del a, b
+    torch.cuda.empty_cache()
+    return round(2 * n * 4 * reps / (ms * 1e-3) / 1e9, 1)
 
 
 def _timed(stream, torch, fn):
@@ -277,6 +294,11 @@ def main():
         out.update(measure_main(args, torch, W, Sim))
     if not args.no_large:
         out["large_grid"] = measure_large(args, torch, W, Sim)
+        copy_gbs = measure_copy(torch)
+        out["large_grid"]["torch_copy_GBs"] = copy_gbs
+        out["large_grid"]["frac_of_copy"] = round(out["large_grid"]["achieved_GBs"] / copy_gbs, 4)
+        if not args.only_large:
+            out["large_grid_fp64"] = measure_large(args, torch, W, Sim, "f64")
     if not args.no_batched and not args.only_large:
         out["batched"] = measure_batched(args, torch, W, Sim, BatchSim)
     if not args.no_adjoint and not args.only_large:

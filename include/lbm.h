@@ -148,7 +148,7 @@ int lbm_import_state(const lbm_params *p, void *state, const void *f, const void
  * A backward pass over levels N-1 .. 0:
  *   lbm_adjoint_phi(state at level N, dL/dphi^N)        -- starts the pass
  *   for each segment, newest first: lbm_tape_record from the segment's first
- *   level, then lbm_adjoint_step(tape, j) for j = L-1 .. 0
+ *   level, then lbm_adjoint_step(tape, j) for j = L-1 .. 0 (or one lbm_adjoint_run)
  *   lbm_adjoint_init -> dL/dphi0; lbm_adjoint_params -> dL/dgravity, dL/dtheta.
  * Level mismatches (a step whose tape level is not one below the adjoint's)
  * are detected on the device; the step is skipped and lbm_adjoint_params then
@@ -171,6 +171,10 @@ int lbm_adjoint_phi(const lbm_params *p, const void *state, void *adj, const voi
 /* One adjoint step: adj holds level n + 1 on entry and level n on return,
  * n = (first level of the tape) + j; the forward level n is tape slot j. */
 int lbm_adjoint_step(const lbm_params *p, const void *tape, int32_t j, void *adj, void *stream);
+/* `count` adjoint steps over tape slots j_first, j_first - 1, ..., j_first - count + 1
+ * (the same as that many lbm_adjoint_step calls, launched from one call). */
+int lbm_adjoint_run(const lbm_params *p, const void *tape, int32_t j_first, int32_t count, void *adj,
+                    void *stream);
 /* dL/dphi0 ([ny][nx]) from the adjoint of level 0, through lbm_init with
  * u0 = NULL (f^0 = w_i phi0; p0 is held fixed).  Writes NaN if the adjoint is
  * not at level 0. */

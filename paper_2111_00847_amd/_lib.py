@@ -64,6 +64,7 @@ _SIGS = {
     "lbm_adjoint_size": [P(LbmParams), P(ctypes.c_size_t)],
     "lbm_adjoint_phi": [P(LbmParams), vp, vp, vp, vp],
     "lbm_adjoint_step": [P(LbmParams), vp, ctypes.c_int32, vp, vp],
+    "lbm_adjoint_run": [P(LbmParams), vp, ctypes.c_int32, ctypes.c_int32, vp, vp],
     "lbm_adjoint_init": [P(LbmParams), vp, vp, vp],
     "lbm_adjoint_params": [P(LbmParams), vp, P(ctypes.c_double), P(ctypes.c_int64), vp],
     "lbm_adjoint_export": [P(LbmParams), vp, vp, vp, vp, vp],

@@ -172,6 +172,11 @@ def lbm_adjoint_step(p, tape, j, adj, stream=None):
     call("lbm_adjoint_step", ctypes.byref(p), _state_ptr(tape), int(j), _state_ptr(adj), _stream(stream))
 
 
+def lbm_adjoint_run(p, tape, j_first, count, adj, stream=None):
+    call("lbm_adjoint_run", ctypes.byref(p), _state_ptr(tape), int(j_first), int(count), _state_ptr(adj),
+         _stream(stream))
+
+
 def lbm_adjoint_init(p, adj, dL_dphi0, stream=None):
     call("lbm_adjoint_init", ctypes.byref(p), _state_ptr(adj), _ptr(dL_dphi0, p, (p.ny, p.nx), "dL_dphi0"),
          _stream(stream))

@@ -58,8 +58,7 @@ class LBMFunction(torch.autograd.Function):
             start = seg * ctx.chk
             L = min(ctx.chk, ctx.nsteps - start)
             api.lbm_tape_record(p, ctx.snaps[seg], tape, L)
-            for j in range(L - 1, -1, -1):
-                api.lbm_adjoint_step(p, tape, j, adj)
+            api.lbm_adjoint_run(p, tape, L - 1, L, adj)
         dphi0 = torch.empty((p.ny, p.nx), dtype=dt, device=dev)
         api.lbm_adjoint_init(p, adj, dphi0)
         out, level = api.lbm_adjoint_params(p, adj)

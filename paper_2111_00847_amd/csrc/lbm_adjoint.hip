@@ -745,6 +745,26 @@ int lbm_adjoint_step(const lbm_params* p, const void* tape, int32_t j, void* adj
     return e == hipSuccess ? LBM_OK : hip_fail(e);
 }
 
+int lbm_adjoint_run(const lbm_params* p, const void* tape, int32_t j_first, int32_t count, void* adj,
+                    void* stream) {
+    int rc = validate(p);
+    if (rc) return rc;
+    if (!tape || !adj) return LBM_E_NULL;
+    if (count < 0 || j_first - count + 1 < 0) return LBM_E_SIZE;
+    const Layout L = layout_of(p);
+    const AdjLayout A = adj_layout_of(p);
+    hipStream_t s = (hipStream_t)stream;
+    for (int32_t j = j_first; j > j_first - count; j--) {
+        if (p->dtype == LBM_F32)
+            launch_adj_step<float>(resolve<float>(p, L), (const char*)tape, L.buf_bytes, j, adj_view<float>(adj, A), s);
+        else
+            launch_adj_step<double>(resolve<double>(p, L), (const char*)tape, L.buf_bytes, j, adj_view<double>(adj, A),
+                                    s);
+    }
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? LBM_OK : hip_fail(e);
+}
+
 int lbm_adjoint_init(const lbm_params* p, const void* adj, void* dL_dphi0, void* stream) {
     int rc = validate(p);
     if (rc) return rc;

@@ -68,6 +68,39 @@ __device__ __forceinline__ void st(char* base, OFF byteoff, T v) {
     else *reinterpret_cast<T*>(base + byteoff) = v;
 }
 
+// Pulled moving populations f_1..f_8 and the FP64 rest population of node
+// (x, y) of a copy, addressed by byte offsets of type OFF from the copy base
+// (bF: offset of plane f_1, pl: plane length, ES: element size).  Returns the
+// node's element index.
+template <typename T, typename OFF>
+__device__ __forceinline__ OFF pull_f_at(const KParams<T>& P, const char* src, OFF bF, OFF pl, int x, int y, T* f,
+                                         double& f0) {
+    constexpr OFF ES = sizeof(T);
+    const OFF nx = (OFF)P.nx;
+    OFF col[3], row[3];
+    bool wx[3] = {false, false, false}, wy[3] = {false, false, false};
+    col[1] = (OFF)x;
+    col[0] = x == 0 ? (OFF)(P.nx - 1) : (OFF)(x - 1);
+    col[2] = x == P.nx - 1 ? (OFF)0 : (OFF)(x + 1);
+    if (x == 0) wx[0] = P.wall_x;
+    if (x == P.nx - 1) wx[2] = P.wall_x;
+    row[1] = (OFF)y * nx;
+    row[0] = y == 0 ? (OFF)(P.ny - 1) * nx : (OFF)(y - 1) * nx;
+    row[2] = y == P.ny - 1 ? (OFF)0 : (OFF)(y + 1) * nx;
+    if (y == 0) wy[0] = P.wall_y;
+    if (y == P.ny - 1) wy[2] = P.wall_y;
+    const OFF k = row[1] + col[1];
+    f0 = ld<double>(src, (OFF)8 * k);
+#pragma unroll
+    for (int i = 1; i < Q; i++) {
+        const int ax = 1 - cx(i), ay = 1 - cy(i);
+        const bool bb = wx[ax] || wy[ay];
+        const OFF o = bb ? bF + ((OFF)(opp(i) - 1) * pl + k) * ES : bF + ((OFF)(i - 1) * pl + row[ay] + col[ax]) * ES;
+        f[i] = ld<T>(src, o);
+    }
+    return k;
+}
+
 // The fused step.  One 64 x TY tile per workgroup of 64 x NBY threads; thread
 // (lx, ly) owns nodes (x0 + lx, y0 + ly + NBY r), r < TY/NBY, keeps their pulled f
 // in registers from the phi pass to the collision, and the ring of the phi
@@ -95,7 +128,6 @@ __device__ __forceinline__ void step_core(const KParams<T>& P, const char* src, 
     constexpr OFF ES = sizeof(T);
     const int x0 = xt * TX, y0 = yt * TY;
     const bool first = step == 0;
-    const Copy<T> S = copy_at<T>(const_cast<char*>(src), P.plane);
     const OFF pl = (OFF)P.plane;
     const OFF bF = 8 * pl;               // byte base of f_1; f_i at bF + (i - 1) pl ES
     const OFF bG = bF + 8 * pl * ES;     // g_i at bG + i pl ES
@@ -219,10 +251,8 @@ __device__ __forceinline__ void step_core(const KParams<T>& P, const char* src, 
         T fr[9], rh = T(0);
         double fr0 = 0.0;
         if (rv) {
-            fr0 = S.f0[(long long)rgy * P.nx + rgx];
-#pragma unroll
-            for (int i = 1; i < Q; i++) fr[i] = pull(S.f, P, i, rgx, rgy);
-            if (!first) rh = S.h[(long long)rgy * P.nx + rgx];
+            const OFF rk = pull_f_at<T, OFF>(P, src, bF, pl, rgx, rgy, fr, fr0);
+            if (!first) rh = ld<T>(src, bH + rk * ES);
         }
 #pragma unroll
         for (int r = 0; r < R; r++) {
@@ -251,8 +281,12 @@ __device__ __forceinline__ void step_core(const KParams<T>& P, const char* src, 
             gy = gy < 0 ? gy + P.ny : gy - P.ny;
         }
         T fw[9];
-        sphi[wyi][wxi] = (T)node_phi(P, S, gx, gy, fw);
-        if (!first) sphp[wyi][wxi] = S.h[(long long)gy * P.nx + gx];
+        double fw0;
+        const OFF wk = pull_f_at<T, OFF>(P, src, bF, pl, gx, gy, fw, fw0);
+        [[maybe_unused]] T wh = T(0);
+        if (!first) wh = ld<T>(src, bH + wk * ES);
+        sphi[wyi][wxi] = (T)(fw0 + moving_sum_d(fw));
+        if (!first) sphp[wyi][wxi] = wh;
     };
     if (!RE)
         for (int idx = tid; idx < NRING; idx += TX * NBY) {

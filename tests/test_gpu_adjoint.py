@@ -160,13 +160,14 @@ def _gpu_phi(case, phi0, nsteps):
     return phi
 
 
-def test_dam_break_64x32_gradients_equal_finite_differences():
+@pytest.mark.parametrize("nsteps", [1000, 4000])
+def test_dam_break_64x32_gradients_equal_finite_differences(nsteps):
     """dL/dg (gravity (0, -g)), dL/dtheta (one angle on all walls) and eight
     seeded directional derivatives in phi0, adjoint vs central differences of
-    the FP64 GPU forward, 1000 steps, checkpoints every 200."""
+    the FP64 GPU forward, checkpoints every 200 (4000 steps: the horizon of the
+    differentiable dam break)."""
     from paper_2111_00847_amd.autograd import trajectory_phi
     case, phi0, tcase = _dam_small()
-    nsteps = 1000
     target = _gpu_phi(tcase, phi0, nsteps)
     loss = lambda c, ph: float(np.sum((_gpu_phi(c, ph, nsteps) - target) ** 2))
 
@@ -193,7 +194,7 @@ def test_dam_break_64x32_gradients_equal_finite_differences():
         checks.append(((loss(case, phi0 + h * d) - loss(case, phi0 - h * d)) / (2 * h), float(np.sum(gphi * d)),
                        f"dL/dphi0 . d{k}"))
     for fd, ad, what in checks:
-        print(f"{what}: fd={fd:.8e} adjoint={ad:.8e}", flush=True)
+        print(f"{nsteps} steps {what}: fd={fd:.8e} adjoint={ad:.8e}", flush=True)
     for fd, ad, what in checks:
         assert abs(fd - ad) <= 1e-4 * abs(ad), (what, fd, ad)
 
