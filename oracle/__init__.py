@@ -37,7 +37,7 @@ class OrcParams(ctypes.Structure):
     _fields_ = [
         ("nx", ctypes.c_int), ("ny", ctypes.c_int),
         ("wall_x", ctypes.c_int), ("wall_y", ctypes.c_int),
-        ("visc_law", ctypes.c_int), ("model", ctypes.c_int),
+        ("visc_law", ctypes.c_int), ("model", ctypes.c_int), ("pf", ctypes.c_int),
         ("phiA", ctypes.c_double), ("phiB", ctypes.c_double),
         ("rhoA", ctypes.c_double), ("rhoB", ctypes.c_double),
         ("nuA", ctypes.c_double), ("nuB", ctypes.c_double),
@@ -78,6 +78,7 @@ def lib():
         L.orc_wetting.argtypes = [P(OrcParams), ctypes.c_double, ctypes.c_double,
                                   ctypes.c_double, d, d]
         L.orc_moments_f.argtypes = [P(OrcParams)] + [ctypes.c_double] * 7 + [d, d]
+        L.orc_moments_f_ch.argtypes = [P(OrcParams)] + [ctypes.c_double] * 6 + [d, d]
         L.orc_moments_g.argtypes = [P(OrcParams)] + [ctypes.c_double] * 13 + [d, d]
         L.orc_direct_g.argtypes = [P(OrcParams)] + [ctypes.c_double] * 13 + [d, d]
         for name in ("orc_init", "orc_step", "orc_moments", "orc_diagnostics",
@@ -104,6 +105,7 @@ def make_params(case) -> OrcParams:
     p.wall_x, p.wall_y = int(bool(case.wall_x)), int(bool(case.wall_y))
     p.visc_law = {"linear_mu": 0, "inverse_nu": 1}[case.visc_law]
     p.model = {"present": 0, "original": 1, "corrected": 2}[case.model]
+    p.pf = {"allen_cahn": 0, "cahn_hilliard": 1}[case.phase_eq]
     p.phiA, p.phiB = case.phiA, case.phiB
     p.rhoA, p.rhoB = case.rhoA, case.rhoB
     p.nuA, p.nuB = case.nuA, case.nuB
@@ -229,6 +231,14 @@ def moments_f(case, phi, u, v, lam_nx, lam_ny, dphiu, dphiv):
     meq = np.empty(9)
     mR = np.empty(9)
     lib().orc_moments_f(ctypes.byref(p), phi, u, v, lam_nx, lam_ny, dphiu, dphiv, _dp(meq), _dp(mR))
+    return meq, mR
+
+
+def moments_f_ch(case, phi, mu, u, v, dphiu, dphiv):
+    p = make_params(case)
+    meq = np.empty(9)
+    mR = np.empty(9)
+    lib().orc_moments_f_ch(ctypes.byref(p), phi, mu, u, v, dphiu, dphiv, _dp(meq), _dp(mR))
     return meq, mR
 
 

@@ -68,6 +68,7 @@ struct orc_sim {
     double *phi, *ext, *gx, *gy, *lap;
     double *rho, *mu, *lam, *nxv, *nyv, *mx, *my, *Fx, *Fy, *snu;
     double *ux, *uy, *pr, *P5, *dP5;
+    double *muext;      /* (nx+2) x (ny+2) mu with its ghost layer (Cahn-Hilliard) */
 };
 
 /* ------------------------------------------------------------------ */
@@ -133,6 +134,7 @@ static int check_params(const orc_params *p) {
     if (!(p->W > 0 && p->sigma >= 0 && p->M >= 0)) return -4;
     if (p->eta != 1.0) return -4;
     if (p->model != 0 && p->model != 1) return -8;
+    if (p->pf != 0 && p->pf != 1) return -4;
     if (p->visc_law != 0 && p->visc_law != 1) return -4;
     for (int i = 0; i < 9; i++)
         if (p->sf[i] >= 2.0 || p->sg[i] >= 2.0) return -5;
@@ -185,6 +187,7 @@ orc_sim *orc_create(const orc_params *p) {
     s->pr = calloc(n, dz);
     s->P5 = calloc(5 * n, dz);
     s->dP5 = calloc(5 * n, dz);
+    s->muext = calloc((size_t)(p->nx + 2) * (p->ny + 2), dz);
     return s;
 }
 
@@ -192,7 +195,7 @@ void orc_destroy(orc_sim *s) {
     if (!s) return;
     double *bufs[] = {s->f, s->g, s->fs, s->gs, s->H, s->phi_prev, s->phi, s->ext, s->gx, s->gy,
                       s->lap, s->rho, s->mu, s->lam, s->nxv, s->nyv, s->mx, s->my, s->Fx, s->Fy,
-                      s->snu, s->ux, s->uy, s->pr, s->P5, s->dP5};
+                      s->snu, s->ux, s->uy, s->pr, s->P5, s->dP5, s->muext};
     for (size_t i = 0; i < sizeof(bufs) / sizeof(bufs[0]); i++) free(bufs[i]);
     free(s);
 }
@@ -288,6 +291,35 @@ int orc_stencils(const orc_sim *cs, const double *phi, double *gx, double *gy, d
     return 0;
 }
 
+/* Ghost layer of the chemical potential for the Cahn-Hilliard flux: periodic
+ * axes wrap; at a wall the no-flux condition d mu / dn = 0 is imposed by
+ * mirroring the first fluid node (x-walls first, then y-walls over the
+ * extended rows, as for phi). */
+static void fill_ghosts_mirror(const orc_sim *s, const double *v, double *ext) {
+    int nx = s->nx, ny = s->ny, ex = nx + 2;
+    for (int y = 0; y < ny; y++)
+        for (int x = 0; x < nx; x++) ext[(y + 1) * ex + (x + 1)] = v[y * nx + x];
+    for (int y = 0; y < ny; y++) {
+        double *row = ext + (y + 1) * ex;
+        if (!s->P.wall_x) {
+            row[0] = row[nx];
+            row[nx + 1] = row[1];
+        } else {
+            row[0] = row[1];
+            row[nx + 1] = row[nx];
+        }
+    }
+    for (int X = 0; X < ex; X++) {
+        if (!s->P.wall_y) {
+            ext[X] = ext[ny * ex + X];
+            ext[(ny + 1) * ex + X] = ext[1 * ex + X];
+        } else {
+            ext[X] = ext[1 * ex + X];
+            ext[(ny + 1) * ex + X] = ext[ny * ex + X];
+        }
+    }
+}
+
 /* Sec. 2 closure for one node (AC form of D(phi)). */
 typedef struct {
     double rho, drx, dry, mu_phi, lam, nx, ny, mx, my, Fx, Fy, nu, snu;
@@ -350,6 +382,28 @@ void orc_moments_f(const orc_params *p, double phi, double u, double v, double l
     mR[4] = -lam_nx / 3.0 - dphiu;
     mR[5] = lam_ny / 3.0 + dphiv;
     mR[6] = -lam_ny / 3.0 - dphiv;
+    mR[7] = mR[8] = 0.0;
+}
+
+/* App. C, Eq. (MfMRCH1): the Cahn-Hilliard moments carry eta mu_phi in rows 1
+ * and 2 and no lambda n source. */
+void orc_moments_f_ch(const orc_params *p, double phi, double mu, double u, double v, double dphiu,
+                      double dphiv, double meq[9], double mR[9]) {
+    double eta = p->eta;
+    meq[0] = phi;
+    meq[1] = -4.0 * phi + 2.0 * eta * mu;
+    meq[2] = 4.0 * phi - 3.0 * eta * mu;
+    meq[3] = phi * u;
+    meq[4] = -phi * u;
+    meq[5] = phi * v;
+    meq[6] = -phi * v;
+    meq[7] = 0.0;
+    meq[8] = 0.0;
+    mR[0] = mR[1] = mR[2] = 0.0;
+    mR[3] = dphiu;
+    mR[4] = -dphiu;
+    mR[5] = dphiv;
+    mR[6] = -dphiv;
     mR[7] = mR[8] = 0.0;
 }
 
@@ -428,11 +482,27 @@ static void matvec(const double A[9][9], const double *x, double *y) {
     }
 }
 
+/* Cahn-Hilliard mass flux m^phiC = -(drho/dphi) M grad mu_phi (Sec. 2, D =
+ * grad mu for Eq. CHE), grad mu by Eq. central1 on mu with its ghost layer;
+ * zero for the original model. */
+static void ch_flux(orc_sim *s, const double *mu, double *mx, double *my) {
+    const orc_params *p = &s->P;
+    long n = s->n;
+    fill_ghosts_mirror(s, mu, s->muext);
+    stencils(s, s->muext, mx, my, NULL);
+    double c = -(p->rhoA - p->rhoB) / (p->phiA - p->phiB) * p->M;
+    for (long k = 0; k < n; k++) {
+        mx[k] = p->model == 1 ? 0.0 : c * mx[k];
+        my[k] = p->model == 1 ? 0.0 : c * my[k];
+    }
+}
+
 /* Stages 1-7: every macroscopic field of the current level into the scratch
  * arrays of s (phi, ext, gradients, closure, u, history derivatives, p). */
 static void macroscopic(orc_sim *s) {
     long n = s->n;
     int nx = s->nx, ny = s->ny;
+    const orc_params *p = &s->P;
     for (long k = 0; k < n; k++) {
         double a = 0;
         for (int i = 0; i < 9; i++) a += s->f[i * n + k];
@@ -455,18 +525,27 @@ static void macroscopic(orc_sim *s) {
             s->Fx[k] = c.Fx;
             s->Fy[k] = c.Fy;
             s->snu[k] = c.snu;
+        }
+    if (p->pf == 1) ch_flux(s, s->mu, s->mx, s->my);
+    double drho = (p->rhoA - p->rhoB) / (p->phiA - p->phiB);
+#pragma omp parallel for
+    for (int y = 0; y < ny; y++)
+        for (int x = 0; x < nx; x++) {
+            long k = (long)y * nx + x;
+            double rho = s->rho[k], mx = s->mx[k], my = s->my[k], Fx = s->Fx[k], Fy = s->Fy[k];
+            double drx = drho * s->gx[k], dry = drho * s->gy[k];
             /* Eq. (comU): rho u = sum_i c_i g_i + F/2 */
             double jx = 0, jy = 0;
             for (int i = 0; i < 9; i++) {
                 jx += CX[i] * s->g[i * n + k];
                 jy += CY[i] * s->g[i * n + k];
             }
-            double u = (jx + 0.5 * c.Fx) / c.rho;
-            double v = (jy + 0.5 * c.Fy) / c.rho;
+            double u = (jx + 0.5 * Fx) / rho;
+            double v = (jy + 0.5 * Fy) / rho;
             s->ux[k] = u;
             s->uy[k] = v;
             /* history products chi and their explicit-Euler derivatives */
-            double P[5] = {s->phi[k] * u, s->phi[k] * v, u * c.mx, v * c.my, u * c.my + v * c.mx};
+            double P[5] = {s->phi[k] * u, s->phi[k] * v, u * mx, v * my, u * my + v * mx};
             for (int j = 0; j < 5; j++) {
                 s->P5[j * n + k] = P[j];
                 s->dP5[j * n + k] = s->step > 0 ? P[j] - s->H[j * n + k] : 0.0;
@@ -478,11 +557,11 @@ static void macroscopic(orc_sim *s) {
             double Kc = 1.0 / 3.0;
             double sum = 0;
             for (int i = 1; i < 9; i++) sum += s->g[i * n + k];
-            double ugr = u * c.drx + v * c.dry;
-            double trQ = c.rho * (u * u + v * v) + (u * c.mx + v * c.my);
+            double ugr = u * drx + v * dry;
+            double trQ = rho * (u * u + v * v) + (u * mx + v * my);
             double s0 = WT[0] * (-CS2 * trQ) / (2.0 * CS2 * CS2); /* s_0(phi,u) of Eq. geq at c_0 = 0 */
             double dum = s->dP5[2 * n + k] + s->dP5[3 * n + k];
-            double uF = u * c.Fx + v * c.Fy;
+            double uF = u * Fx + v * Fy;
             s->pr[k] = CS2 / (1.0 - WT[0]) * (sum + (0.5 + Hc) * ugr + s0 + Kc * (2.0 * uF + dum));
         }
 }
@@ -502,8 +581,11 @@ static void collide(orc_sim *s) {
             }
             double u = s->ux[k], v = s->uy[k];
             /* Eq. (evoPF), moment form */
-            orc_moments_f(p, s->phi[k], u, v, s->lam[k] * s->nxv[k], s->lam[k] * s->nyv[k],
-                          s->dP5[0 * n + k], s->dP5[1 * n + k], meq, mR);
+            if (p->pf == 1)
+                orc_moments_f_ch(p, s->phi[k], s->mu[k], u, v, s->dP5[0 * n + k], s->dP5[1 * n + k], meq, mR);
+            else
+                orc_moments_f(p, s->phi[k], u, v, s->lam[k] * s->nxv[k], s->lam[k] * s->nyv[k],
+                              s->dP5[0 * n + k], s->dP5[1 * n + k], meq, mR);
             matvec(M1, fv, m);
             for (int j = 0; j < 9; j++)
                 ms[j] = m[j] - s->sf[j] * (m[j] - meq[j]) + (1.0 - s->sf[j] / 2.0) * mR[j];
@@ -579,16 +661,26 @@ int orc_init(orc_sim *s, const double *phi0, const double *u0, const double *p0)
     memcpy(s->phi, phi0, sizeof(double) * n);
     fill_ghosts(s, s->phi, s->ext);
     stencils(s, s->ext, s->gx, s->gy, s->lap);
+    for (long k = 0; k < n; k++) {
+        closure_t c = closure(s, phi0[k], s->gx[k], s->gy[k], s->lap[k]);
+        s->mu[k] = c.mu_phi;
+        s->mx[k] = c.mx;
+        s->my[k] = c.my;
+        s->rho[k] = c.rho;
+    }
+    if (p->pf == 1) ch_flux(s, s->mu, s->mx, s->my);
     for (int y = 0; y < ny; y++)
         for (int x = 0; x < nx; x++) {
             long k = (long)y * nx + x;
             double u = u0 ? u0[k] : 0.0, v = u0 ? u0[n + k] : 0.0, pr = p0 ? p0[k] : 0.0;
-            closure_t c = closure(s, phi0[k], s->gx[k], s->gy[k], s->lap[k]);
             double meq[9], mR[9], out[9];
-            orc_moments_f(p, phi0[k], u, v, 0, 0, 0, 0, meq, mR);
+            if (p->pf == 1)
+                orc_moments_f_ch(p, phi0[k], s->mu[k], u, v, 0, 0, meq, mR);
+            else
+                orc_moments_f(p, phi0[k], u, v, 0, 0, 0, 0, meq, mR);
             matvec(s->Minv, meq, out);
             for (int i = 0; i < 9; i++) s->f[i * n + k] = out[i];
-            orc_moments_g(p, c.rho, pr, u, v, c.mx, c.my, 0, 0, 0, 0, 0, 0, 0, meq, mR);
+            orc_moments_g(p, s->rho[k], pr, u, v, s->mx[k], s->my[k], 0, 0, 0, 0, 0, 0, 0, meq, mR);
             matvec(s->Minv, meq, out);
             for (int i = 0; i < 9; i++) s->g[i * n + k] = out[i];
         }
@@ -629,7 +721,6 @@ int orc_set_state(orc_sim *s, const double *f, const double *g, const double *ph
                   const double *u_prev, long step) {
     if (!s || !f || !g || step < 0) return -1;
     long n = s->n;
-    int nx = s->nx, ny = s->ny;
     memcpy(s->f, f, sizeof(double) * 9 * n);
     memcpy(s->g, g, sizeof(double) * 9 * n);
     s->step = step;
@@ -639,14 +730,19 @@ int orc_set_state(orc_sim *s, const double *f, const double *g, const double *ph
         memcpy(s->phi_prev, phi_prev, sizeof(double) * n);
         fill_ghosts(s, phi_prev, s->ext);
         stencils(s, s->ext, s->gx, s->gy, s->lap);
-        for (int y = 0; y < ny; y++)
-            for (int x = 0; x < nx; x++) {
-                long k = (long)y * nx + x;
-                closure_t c = closure(s, phi_prev[k], s->gx[k], s->gy[k], s->lap[k]);
-                double u = u_prev[k], v = u_prev[n + k], ph = phi_prev[k];
-                double P[5] = {ph * u, ph * v, u * c.mx, v * c.my, u * c.my + v * c.mx};
-                for (int j = 0; j < 5; j++) s->H[j * n + k] = P[j];
-            }
+        for (long k = 0; k < n; k++) {
+            closure_t c = closure(s, phi_prev[k], s->gx[k], s->gy[k], s->lap[k]);
+            s->mu[k] = c.mu_phi;
+            s->mx[k] = c.mx;
+            s->my[k] = c.my;
+        }
+        if (s->P.pf == 1) ch_flux(s, s->mu, s->mx, s->my);
+        for (long k = 0; k < n; k++) {
+            double u = u_prev[k], v = u_prev[n + k], ph = phi_prev[k];
+            double mx = s->mx[k], my = s->my[k];
+            double P[5] = {ph * u, ph * v, u * mx, v * my, u * my + v * mx};
+            for (int j = 0; j < 5; j++) s->H[j * n + k] = P[j];
+        }
     } else {
         long k;
         for (k = 0; k < n; k++) {

@@ -4,7 +4,8 @@
  * Plain FP64 CPU reference of the consistent and conservative phase-field
  * lattice Boltzmann method of Zhan, Chai & Shi (arXiv:2111.00847): the
  * conservative Allen-Cahn MRT model for the order parameter (Sec. 3,
- * Eq. evoPF with the App. C moments of Eq. MfMRAC1) coupled to the
+ * Eq. evoPF with the App. C moments of Eq. MfMRAC1; or the Cahn-Hilliard
+ * model with those of Eq. MfMRCH1) coupled to the
  * incompressible MRT model for the flow (Eq. evoNS, Remark 2, App. C moments
  * of Eq. MgMF1), isotropic finite differences (Eqs. central1, central2),
  * half-way bounce-back (Sec. 4 preamble) and the wetting boundary condition
@@ -29,6 +30,8 @@ typedef struct orc_params {
     int wall_x, wall_y;   /* 0: periodic axis, 1: half-way bounce-back walls on both faces */
     int visc_law;         /* 0: linear dynamic viscosity (Eq. linearMu); 1: inverse-linear nu (Eq. inverseNu) */
     int model;            /* 0: present consistent model; 1: original (m = rho u); 2: corrected (adds F_a) */
+    int pf;               /* phase-field equation: 0 Allen-Cahn (D = grad phi - lambda n, Eq. ACE);
+                             1 Cahn-Hilliard (D = grad mu_phi, Eq. CHE; moments of Eq. MfMRCH1) */
     double phiA, phiB, rhoA, rhoB, nuA, nuB;
     double sigma, W, M, eta;
     double sf[9], sg[9];  /* <= 0 selects the paper's default (Sec. 4 preamble) */
@@ -76,6 +79,9 @@ void orc_wetting(const orc_params *p, double theta, double phi1, double phi2, do
 /* Equilibrium/source moments (App. C) for given macroscopic values. */
 void orc_moments_f(const orc_params *p, double phi, double u, double v, double lam_nx, double lam_ny,
                    double dphiu, double dphiv, double meq[9], double mR[9]);
+/* Cahn-Hilliard equilibrium/source moments (App. C, Eq. MfMRCH1). */
+void orc_moments_f_ch(const orc_params *p, double phi, double mu, double u, double v, double dphiu,
+                      double dphiv, double meq[9], double mR[9]);
 void orc_moments_g(const orc_params *p, double rho, double pr, double u, double v, double mx, double my,
                    double Fx, double Fy, double drx, double dry, double dP_um_x, double dP_vm_y,
                    double dP_cross, double meq[9], double mF[9]);

@@ -1,0 +1,92 @@
+"""Pins of the oracle's Cahn-Hilliard phase field (Sec. 2, Eq. CHE; App. C,
+Eq. MfMRCH1): the moments against the direct CH equilibrium, conservation,
+the tanh interface at rest, Laplace's law, and the mass-source ordering that
+the paper's Table 1 reports (present model below the original one)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+CX = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1])
+CY = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1])
+WT = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+
+
+def test_ch_moments_are_those_of_the_direct_equilibrium():
+    """M1 f^eq with the CH equilibrium f_i = w_i eta mu + w_i phi c_i.u / cs^2
+    (i > 0), f_0 = phi - (1 - w_0) eta mu equals the moment list of Eq. MfMRCH1;
+    the source list carries d_t(phi u) only (no lambda n)."""
+    case, _ = W.to_cahn_hilliard(*W.square_droplet(n=8, side=4.0))
+    _, _, _, M, _ = oracle.lattice()
+    rng = np.random.default_rng(2)
+    for _ in range(5):
+        phi, mu, u, v, du, dv = rng.standard_normal(6)
+        f = WT * mu + WT * phi * 3.0 * (CX * u + CY * v)
+        f[0] = phi - (1 - WT[0]) * mu
+        meq, mR = oracle.moments_f_ch(case, phi, mu, u, v, du, dv)
+        np.testing.assert_allclose(M @ f, meq, atol=1e-14)
+        np.testing.assert_allclose(mR, [0, 0, 0, du, -du, dv, -dv, 0, 0], atol=0)
+
+
+@pytest.mark.parametrize("walls", [False, True])
+def test_ch_total_phi_conserved(walls):
+    case, phi0 = W.to_cahn_hilliard(*W.static_droplet(n=32, R=9.0, rho_ratio=100.0))
+    if walls:
+        case = case.replace(wall_x=True, wall_y=True)
+    phi0 = np.clip(phi0 + 0.05 * np.sin(np.arange(case.nx))[None, :], -0.99, 0.99)   # asymmetric: it moves
+    s = oracle.OracleSim(case).init(phi0).step(400)
+    phi, u, _ = s.moments()
+    assert abs(phi.sum() - phi0.sum()) <= 1e-11 * np.abs(phi0).sum()
+    assert np.abs(u).max() > 0
+
+
+def test_ch_flat_interface_tanh_profile_second_order():
+    """The CH equation is at rest on (phiA+phiB)/2 + (phiA-phiB)/2 tanh(2d/W): mu_phi
+    vanishes on it (Sec. 2: the profile minimises the free energy).  The lattice
+    keeps it to O((dx/W)^2)."""
+    devs = []
+    for Wd in (4.0, 8.0):
+        case, phi0 = W.to_cahn_hilliard(*W.flat_interface(nx=2, ny=int(32 * Wd), W=Wd, M=0.05))
+        s = oracle.OracleSim(case).init(phi0).step(int(2000 * (Wd / 4) ** 2))
+        phi, _, _ = s.moments()
+        devs.append(np.abs(phi - phi0).max())
+    order = math.log2(devs[0] / devs[1])
+    assert devs[0] < 2e-2
+    assert 1.6 < order < 2.6, devs
+
+
+@pytest.mark.slow
+def test_ch_laplace_law():
+    """CH static droplet: p_in - p_out approaches sigma / R (within 8% at W = 4,
+    R = 16; closer at W = 8, R = 32)."""
+    ratios = []
+    for R, n, Wd, steps in [(16.0, 64, 4.0, 12000), (32.0, 128, 8.0, 24000)]:
+        case, phi0 = W.to_cahn_hilliard(*W.static_droplet(n=n, R=R, W=Wd, M=0.02 * Wd / 4))
+        s = oracle.OracleSim(case).init(phi0).step(steps)
+        phi, u, p = s.moments()
+        X, Y = W.grid(case)
+        r = np.hypot(X - n / 2, Y - n / 2)
+        dp = p[r < R - 3 * Wd].mean() - p[r > R + 3 * Wd].mean()
+        ratios.append(dp / (case.sigma / R))
+    assert 0.92 < ratios[0] < 1.08, ratios
+    assert abs(ratios[1] - 1) < abs(ratios[0] - 1) + 1e-3, ratios
+
+
+def test_ch_square_droplet_mass_source_below_original_model():
+    """Table 1's claims at a small size (48^2, density ratio 1000, 2000 steps):
+    with the consistent mass flux (present model) the mass source S_m^rms of the
+    deforming CH square droplet is well below that of the flux rho u (original
+    model; the ratio keeps falling with time: 0.67, 0.38, 0.28 at 300, 2000,
+    6000 steps; the paper's steady value is 0.12), while the velocity divergence
+    D_u^rms is the same for both models, as printed in Table 1."""
+    out = {}
+    for model in ("present", "original"):
+        case, phi0 = W.square_droplet_ch(n=48, R=12.0, sigma=1e-3, model=model)
+        d = oracle.OracleSim(case).init(phi0).step(2000).diagnostics()
+        out[model] = (d["Sm_rms"], d["Du_rms"])
+    print(out)
+    assert out["present"][0] < 0.5 * out["original"][0], out
+    assert abs(out["present"][1] - out["original"][1]) < 0.01 * out["original"][1], out

@@ -29,6 +29,7 @@ class Case:
     wall_y: bool = False
     visc_law: str = "linear_mu"      # "linear_mu" | "inverse_nu"
     model: str = "present"           # "present" | "original" | "corrected"
+    phase_eq: str = "allen_cahn"     # "allen_cahn" | "cahn_hilliard" (Sec. 2, Eqs. ACE / CHE)
     phiA: float = 1.0
     phiB: float = 0.0
     rhoA: float = 1.0
@@ -72,6 +73,35 @@ def tanh_profile(d, W, phiA=1.0, phiB=0.0):
 
 
 # ---------------------------------------------------------------- square droplet
+def to_cahn_hilliard(case: Case, phi0):
+    """The same set-up with the Cahn-Hilliard phase field (Sec. 2, Eq. CHE) and phi
+    in [-1, 1] (phi_A = 1, phi_B = -1, as the paper uses it in Secs. 4.1 and 4.4);
+    phi0 given in [0, 1]."""
+    return case.replace(phase_eq="cahn_hilliard", phiA=1.0, phiB=-1.0), 2.0 * np.asarray(phi0) - 1.0
+
+
+def square_droplet_ch(n: int = 200, R: float = 50.0, W: float = 4.0, rho_ratio: float = 1000.0,
+                      nu: float = 0.1, M: float = 0.1, sigma: float = 1e-5, dtype: str = "f64",
+                      model: str = "present"):
+    """Sec. 4.1 with the Cahn-Hilliard phase field: a square of side
+    D = sqrt(pi R^2 + (4 - pi) W^2 / 4) (the area of the final circle of radius R)
+    in a periodic n x n box, phi in [-1, 1], heavy phase A inside.  The paper's
+    units (domain [-1, 1]^2, W = 4 dx = 0.04, c = 100, nu = 0.1, M = 0.1,
+    sigma = 1e-3) map to lattice units dx = 0.01, dt = 1e-4: n = 200, R = 50,
+    nu = M = 0.1, sigma = 1e-3 dt^2 / dx^3 = 1e-5."""
+    D = math.sqrt(math.pi * R * R + (4.0 - math.pi) * W * W / 4.0)
+    case = Case(nx=n, ny=n, rhoA=rho_ratio, rhoB=1.0, nuA=nu, nuB=nu, sigma=sigma, W=W, M=M, dtype=dtype,
+                phase_eq="cahn_hilliard", phiA=1.0, phiB=-1.0, model=model, name=f"square_droplet_ch_{n}")
+    X, Y = grid(case)
+    a = D / 2.0
+    r = W / 2.0
+    b = a - r
+    qx = np.abs(X - n / 2.0) - b
+    qy = np.abs(Y - n / 2.0) - b
+    outside = np.hypot(np.maximum(qx, 0), np.maximum(qy, 0)) + np.minimum(np.maximum(qx, qy), 0) - r
+    return case, tanh_profile(-outside, W, 1.0, -1.0)
+
+
 def square_droplet(n: int = 64, side: float = 32.0, dtype: str = "f64", steps: int = 2000):
     """Square droplet of side ``side`` centred in an n x n periodic box; density
     ratio 10, nu = 0.1 in both phases, sigma = 0.01, M = 0.02, W = 4.
