@@ -24,6 +24,8 @@ The JSON line also carries:
                   FP32): one autotuned persistent launch per step replayed from a
                   captured graph, against the same cases advanced one after
                   another with the plain step (graph-captured, and eager);
+  cahn_hilliard -- the Cahn-Hilliard variant's step kernel on a 4096 x 4096
+                  square droplet (Sec. 4.1 set-up scaled up, FP32);
   adjoint      -- the differentiable dam break (Sec. 4.5 set-up, 1024 x 512,
                   FP32, 4000 steps, checkpoints every 200): time of the
                   backward pass (tape recompute + adjoint steps) over the time
@@ -155,6 +157,27 @@ def measure_large(args, torch, W, Sim, dtype="f32"):
             "frac": round(achL / HBM_PEAK_GBS, 4), "avg_launch_ms": round(msLl, 4)}
 
 
+def measure_ch(args, torch, W, Sim, n=4096):
+    """The Cahn-Hilliard variant (Sec. 2, Eq. CHE; App. C, Eq. MfMRCH1) on the
+    Sec. 4.1 square droplet scaled to n x n (FP32, density ratio 1000): its step
+    kernel against the HBM peak at the same 168 B of algorithmic traffic per
+    update as the Allen-Cahn step."""
+    case, phi0 = W.square_droplet_ch(n=n, R=n / 4.0, dtype="f32")
+    sim = Sim(case, "cuda:0").init(phi0)
+    sim.step(10)
+    ms, ms_launch = time_steps(sim, args.ch_steps, torch)
+    alg = ALG_BYTES["f32"] * case.nodes
+    ach = alg / (ms_launch * 1e-3) / 1e9
+    d = sim.diagnostics()
+    assert d["nonfinite"] == 0, "non-finite state after the timed CH steps"
+    del sim
+    torch.cuda.empty_cache()
+    return {"workload": f"square_droplet_cahn_hilliard_{n}x{n}", "dtype": "f32", "steps": args.ch_steps,
+            "value": round(case.nodes * args.ch_steps / (ms * 1e-3) / 1e6, 1), "unit": "MLUPS",
+            "kernel": "k_step_ch<float>", "achieved_GBs": round(ach, 1), "frac": round(ach / HBM_PEAK_GBS, 4),
+            "avg_launch_ms": round(ms_launch, 4)}
+
+
 def measure_copy(torch, mib=1024, reps=20):
     """Bandwidth of torch's device-to-device copy of a `mib` MiB buffer (read + write
     bytes per second): a measured ceiling next to the nominal HBM peak."""
@@ -261,6 +284,10 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-large", action="store_true")
+    ap.add_argument("--ch-steps", type=int, default=100)
+    ap.add_argument("--no-ch", action="store_true")
+    ap.add_argument("--only-ch", action="store_true",
+                    help="run only the Cahn-Hilliard measurement (profiling runs)")
     ap.add_argument("--only-large", action="store_true",
                     help="run only the 4096 x 4096 measurement (profiling runs)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -290,6 +317,9 @@ def main():
         return
 
     out = {}
+    if args.only_ch:
+        print(json.dumps({"cahn_hilliard": measure_ch(args, torch, W, Sim)}), flush=True)
+        return
     if not args.only_large:
         out.update(measure_main(args, torch, W, Sim))
     if not args.no_large:
@@ -299,6 +329,8 @@ def main():
         out["large_grid"]["frac_of_copy"] = round(out["large_grid"]["achieved_GBs"] / copy_gbs, 4)
         if not args.only_large:
             out["large_grid_fp64"] = measure_large(args, torch, W, Sim, "f64")
+    if not args.no_ch and not args.only_large:
+        out["cahn_hilliard"] = measure_ch(args, torch, W, Sim)
     if not args.no_batched and not args.only_large:
         out["batched"] = measure_batched(args, torch, W, Sim, BatchSim)
     if not args.no_adjoint and not args.only_large:

@@ -70,6 +70,12 @@ typedef enum {
     LBM_MODEL_ORIGINAL = 1    /* mass flux rho u only (m^phiC = 0 in the flow model; Sec. 4 preamble) */
 } lbm_model;
 
+typedef enum {
+    LBM_ALLEN_CAHN = 0,       /* conservative Allen-Cahn: D = grad phi - lambda n (Sec. 2, Eq. ACE; Eq. MfMRAC1) */
+    LBM_CAHN_HILLIARD = 1     /* Cahn-Hilliard: D = grad mu_phi (Sec. 2, Eq. CHE; Eq. MfMRCH1); mu_phi has
+                                 zero normal derivative at walls; batches and the reverse mode are AC only */
+} lbm_phase_eq;
+
 /* Problem statement in the paper's notation (Sec. 2; Sec. 4 preamble). */
 typedef struct lbm_params {
     int32_t nx, ny;                 /* lattice nodes */
@@ -77,7 +83,7 @@ typedef struct lbm_params {
     int32_t bc_x, bc_y;             /* lbm_bc per axis; WALLS = half-way bounce-back on both faces */
     int32_t visc_law;               /* lbm_visc */
     int32_t model;                  /* lbm_model */
-    int32_t reserved;               /* must be 0 */
+    int32_t phase_eq;               /* lbm_phase_eq: phase-field equation */
     double phi_A, phi_B;            /* order parameter of the two bulk phases, phi_A > phi_B */
     double rho_A, rho_B;            /* densities (Eq. rho-phi) */
     double nu_A, nu_B;              /* kinematic viscosities; mu = rho nu */
@@ -153,7 +159,9 @@ int lbm_import_state(const lbm_params *p, void *state, const void *f, const void
  * Level mismatches (a step whose tape level is not one below the adjoint's)
  * are detected on the device; the step is skipped and lbm_adjoint_params then
  * returns LBM_E_PARAM.  Adjoint and tape buffers are caller-owned device
- * memory, 256-byte aligned, in the dtype of the params. */
+ * memory, 256-byte aligned, in the dtype of the params.  The reverse mode is
+ * that of the Allen-Cahn step: every call below returns LBM_E_UNSUPPORTED for
+ * Cahn-Hilliard params. */
 
 /* Bytes of a tape of `nlevels` consecutive levels. */
 int lbm_tape_size(const lbm_params *p, int32_t nlevels, size_t *nbytes /* host */);
@@ -192,9 +200,10 @@ int lbm_adjoint_import(const lbm_params *p, void *adj, const void *fbar, const v
                        int64_t level, void *stream);
 
 /* ---- batches: many independent lattices, one launch per time step ---------
- * (the batched execution row of the build: the per-step update above applied
- * to every case; a case advanced in a batch is bitwise identical to the same
- * case advanced alone with lbm_step).  All cases share one dtype.  The plan is
+ * (the per-step update above applied to every case; a case advanced in a
+ * batch is bitwise identical to the same case advanced alone with lbm_step).
+ * All cases share one dtype and use the Allen-Cahn phase field (Cahn-Hilliard
+ * cases: LBM_E_UNSUPPORTED).  The plan is
  * library-owned (a small device table of the cases and, once lbm_batch_step
  * runs on a non-NULL stream with nsteps >= 32, a captured hipGraph of 32
  * steps for that state and stream). */

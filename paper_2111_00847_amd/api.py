@@ -27,7 +27,7 @@ def make_params(case) -> LbmParams:
     p.bc_y = LBM_WALLS if case.wall_y else LBM_PERIODIC
     p.visc_law = _VISC[case.visc_law]
     p.model = _MODEL.get(case.model, 99)
-    p.reserved = 0
+    p.phase_eq = {"allen_cahn": 0, "cahn_hilliard": 1}.get(case.phase_eq, 99)
     p.phi_A, p.phi_B = case.phiA, case.phiB
     p.rho_A, p.rho_B = case.rhoA, case.rhoB
     p.nu_A, p.nu_B = case.nuA, case.nuB

@@ -48,6 +48,13 @@ void step_shape(const lbm_params* p, int* ty, int* by);
 template <typename T>
 KParams<T> resolve(const lbm_params* p, const Layout& L);
 
+// The reverse mode covers the Allen-Cahn step only.
+static int validate_ac(const lbm_params* p) {
+    const int rc = validate(p);
+    if (rc) return rc;
+    return p->phase_eq == LBM_ALLEN_CAHN ? LBM_OK : LBM_E_UNSUPPORTED;
+}
+
 constexpr size_t ADJ_HDR = 256;
 constexpr size_t TAPE_HDR = 256;
 constexpr int ATY = BY;   // adjoint tiles: 64 x 4, one node per thread
@@ -673,7 +680,7 @@ using namespace lbm;
 extern "C" {
 
 int lbm_tape_size(const lbm_params* p, int32_t nlevels, size_t* nbytes) {
-    int rc = validate(p);
+    int rc = validate_ac(p);
     if (rc) return rc;
     if (!nbytes) return LBM_E_NULL;
     if (nlevels < 1) return LBM_E_SIZE;
@@ -682,7 +689,7 @@ int lbm_tape_size(const lbm_params* p, int32_t nlevels, size_t* nbytes) {
 }
 
 int lbm_tape_record(const lbm_params* p, const void* state, void* tape, int32_t nlevels, void* stream) {
-    int rc = validate(p);
+    int rc = validate_ac(p);
     if (rc) return rc;
     if (!state || !tape) return LBM_E_NULL;
     if (nlevels < 1) return LBM_E_SIZE;
@@ -703,7 +710,7 @@ int lbm_tape_record(const lbm_params* p, const void* state, void* tape, int32_t 
 }
 
 int lbm_adjoint_size(const lbm_params* p, size_t* nbytes) {
-    int rc = validate(p);
+    int rc = validate_ac(p);
     if (rc) return rc;
     if (!nbytes) return LBM_E_NULL;
     *nbytes = adj_layout_of(p).total;
@@ -711,7 +718,7 @@ int lbm_adjoint_size(const lbm_params* p, size_t* nbytes) {
 }
 
 int lbm_adjoint_phi(const lbm_params* p, const void* state, void* adj, const void* dL_dphi, void* stream) {
-    int rc = validate(p);
+    int rc = validate_ac(p);
     if (rc) return rc;
     if (!state || !adj || !dL_dphi) return LBM_E_NULL;
     if ((uintptr_t)adj % 256) return LBM_E_SIZE;
@@ -730,7 +737,7 @@ int lbm_adjoint_phi(const lbm_params* p, const void* state, void* adj, const voi
 }
 
 int lbm_adjoint_step(const lbm_params* p, const void* tape, int32_t j, void* adj, void* stream) {
-    int rc = validate(p);
+    int rc = validate_ac(p);
     if (rc) return rc;
     if (!tape || !adj) return LBM_E_NULL;
     if (j < 0) return LBM_E_SIZE;
@@ -747,7 +754,7 @@ int lbm_adjoint_step(const lbm_params* p, const void* tape, int32_t j, void* adj
 
 int lbm_adjoint_run(const lbm_params* p, const void* tape, int32_t j_first, int32_t count, void* adj,
                     void* stream) {
-    int rc = validate(p);
+    int rc = validate_ac(p);
     if (rc) return rc;
     if (!tape || !adj) return LBM_E_NULL;
     if (count < 0 || j_first - count + 1 < 0) return LBM_E_SIZE;
@@ -766,7 +773,7 @@ int lbm_adjoint_run(const lbm_params* p, const void* tape, int32_t j_first, int3
 }
 
 int lbm_adjoint_init(const lbm_params* p, const void* adj, void* dL_dphi0, void* stream) {
-    int rc = validate(p);
+    int rc = validate_ac(p);
     if (rc) return rc;
     if (!adj || !dL_dphi0) return LBM_E_NULL;
     const Layout L = layout_of(p);
@@ -784,7 +791,7 @@ int lbm_adjoint_init(const lbm_params* p, const void* adj, void* dL_dphi0, void*
 }
 
 int lbm_adjoint_params(const lbm_params* p, const void* adj, double* out, int64_t* level, void* stream) {
-    int rc = validate(p);
+    int rc = validate_ac(p);
     if (rc) return rc;
     if (!adj || !out) return LBM_E_NULL;
     const AdjLayout A = adj_layout_of(p);
@@ -801,7 +808,7 @@ int lbm_adjoint_params(const lbm_params* p, const void* adj, double* out, int64_
 }
 
 int lbm_adjoint_export(const lbm_params* p, const void* adj, void* fbar, void* gbar, void* hbar, void* stream) {
-    int rc = validate(p);
+    int rc = validate_ac(p);
     if (rc) return rc;
     if (!adj) return LBM_E_NULL;
     const Layout L = layout_of(p);
@@ -820,7 +827,7 @@ int lbm_adjoint_export(const lbm_params* p, const void* adj, void* fbar, void* g
 
 int lbm_adjoint_import(const lbm_params* p, void* adj, const void* fbar, const void* gbar, const void* hbar,
                        int64_t level, void* stream) {
-    int rc = validate(p);
+    int rc = validate_ac(p);
     if (rc) return rc;
     if (!adj) return LBM_E_NULL;
     if (level < 0) return LBM_E_SIZE;

@@ -32,7 +32,7 @@ int validate(const lbm_params* p) {
     if (p->bc_y == LBM_WALLS && p->ny < 2) return LBM_E_SIZE;
     if (p->visc_law != LBM_VISC_LINEAR_MU && p->visc_law != LBM_VISC_INVERSE_NU) return LBM_E_PARAM;
     if (p->model != LBM_MODEL_PRESENT && p->model != LBM_MODEL_ORIGINAL) return LBM_E_UNSUPPORTED;
-    if (p->reserved != 0) return LBM_E_PARAM;
+    if (p->phase_eq != LBM_ALLEN_CAHN && p->phase_eq != LBM_CAHN_HILLIARD) return LBM_E_PARAM;
     const double vals[] = {p->phi_A, p->phi_B, p->rho_A, p->rho_B, p->nu_A, p->nu_B, p->sigma, p->W,
                            p->M_phi, p->eta, p->body_force[0], p->body_force[1], p->gravity[0],
                            p->gravity[1], p->rho_ref, p->rho0, p->eps_n};
@@ -63,6 +63,7 @@ KParams<T> resolve(const lbm_params* p, const Layout& L) {
     K.wall_y = p->bc_y == LBM_WALLS;
     K.visc_law = p->visc_law;
     K.model = p->model;
+    K.pf = p->phase_eq;
     K.plane = L.plane;
     const double dphi = p->phi_A - p->phi_B;
     // Sec. 2: beta = 12 sigma / (W dphi^4), k = 3 sigma W / (2 dphi^2), sqrt(2 beta / k) = 4 / (W dphi)

@@ -47,7 +47,7 @@ struct KParams {
     int wall_x, wall_y;
     int visc_law, model;
     int snu_local;        // s_g^7 = s_g^8 follow nu(phi)
-    int pad0;
+    int pf;               // phase-field equation: 0 Allen-Cahn, 1 Cahn-Hilliard
     long long plane;      // elements between two population planes
     T phiA, phiB, phim;   // phim = (phiA + phiB) / 2
     T beta4, kap;         // 4 beta, k (Sec. 2)

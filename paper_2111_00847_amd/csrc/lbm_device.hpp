@@ -117,23 +117,45 @@ struct Macro {
     T Fx, Fy;          // total force
     T snu;             // s_g^7 = s_g^8
     T d0, d1, d2, d3, d4;  // explicit-Euler d_t of phi u, phi v, u m_x, v m_y, u m_y + v m_x
+    T mu;              // chemical potential mu_phi (Sec. 2)
 };
+
+// Chemical potential mu_phi = psi'(phi) - k lap phi (Sec. 2).
+template <typename T>
+__device__ __forceinline__ T chem_pot(const KParams<T>& P, T phi, T lap) {
+    return P.beta4 * (phi - P.phiA) * (phi - P.phiB) * (phi - P.phim) - P.kap * lap;
+}
+
+// Cahn-Hilliard mass flux m^phiC = -(drho/dphi) M grad mu_phi (Sec. 2, D = grad mu).
+template <typename T>
+__device__ __forceinline__ void mass_flux_ch(const KParams<T>& P, T gmx, T gmy, T& mx, T& my) {
+    mx = P.model == 1 ? T(0) : -P.drhoM * gmx;
+    my = P.model == 1 ? T(0) : -P.drhoM * gmy;
+}
 
 // Closure, velocity (Eq. comU), history derivatives and pressure (Eq. computP,
 // second way of Remark 1) of one node.  g: pulled populations; (gx, gy, lap):
 // stencils of phi; first: level 0 (time derivatives zero); (php, gxp, gyp,
-// up, vp): phi, grad phi and u of the previous level.
-template <typename T>
+// up, vp): phi, grad phi and u of the previous level.  CH: the Cahn-Hilliard
+// flux from grad mu (gmx, gmy) and grad mu of the previous level (gmxp, gmyp).
+template <typename T, bool CH = false>
 __device__ __forceinline__ Macro<T> macro(const KParams<T>& P, const T* g, T phi, T gx, T gy, T lap,
-                                          bool first, T php, T gxp, T gyp, T up, T vp) {
+                                          bool first, T php, T gxp, T gyp, T up, T vp, T gmx = T(0),
+                                          T gmy = T(0), T gmxp = T(0), T gmyp = T(0)) {
     Macro<T> m;
     m.phi = phi;
     T t = phi - P.phiB;
     m.rho = P.drho * t + P.rhoB;
     T mu_phi = P.beta4 * (phi - P.phiA) * t * (phi - P.phim) - P.kap * lap;
+    m.mu = mu_phi;
     m.drx = P.drho * gx;
     m.dry = P.drho * gy;
-    mass_flux(P, phi, gx, gy, m.lnx, m.lny, m.mx, m.my);
+    if (CH) {
+        m.lnx = m.lny = T(0);
+        mass_flux_ch(P, gmx, gmy, m.mx, m.my);
+    } else {
+        mass_flux(P, phi, gx, gy, m.lnx, m.lny, m.mx, m.my);
+    }
     m.Fx = mu_phi * gx + P.Gx + (m.rho - P.rho_ref) * P.gx;
     m.Fy = mu_phi * gy + P.Gy + (m.rho - P.rho_ref) * P.gy;
     if (P.snu_local) {
@@ -158,7 +180,8 @@ __device__ __forceinline__ Macro<T> macro(const KParams<T>& P, const T* g, T phi
         m.d0 = m.d1 = m.d2 = m.d3 = m.d4 = T(0);
     } else {
         T lpx, lpy, mpx, mpy;
-        mass_flux(P, php, gxp, gyp, lpx, lpy, mpx, mpy);
+        if (CH) mass_flux_ch(P, gmxp, gmyp, mpx, mpy);
+        else mass_flux(P, php, gxp, gyp, lpx, lpy, mpx, mpy);
         m.d0 = phi * m.u - php * up;
         m.d1 = phi * m.v - php * vp;
         m.d2 = m.u * m.mx - up * mpx;
@@ -255,7 +278,9 @@ __device__ __forceinline__ void from_moments(const T* m, T* f) {
 // phid: phi of the node in FP64 (rest population + moving sum); returns the
 // post-collision rest population phid - sum of the moving ones (m_0 is
 // collision-invariant: m_0^eq = phi and m_R has no zeroth moment).
-template <typename T>
+// CH: the Cahn-Hilliard moments of Eq. MfMRCH1 (eta mu_phi in rows 1 and 2;
+// lambda n is zero in M).
+template <typename T, bool CH = false>
 __device__ __forceinline__ double collide_f(const KParams<T>& P, const Macro<T>& M, T* f, double phid) {
     T m[9];
     to_moments(f, m);
@@ -268,6 +293,18 @@ __device__ __forceinline__ double collide_f(const KParams<T>& P, const Macro<T>&
     dm[0] = T(0);
 #pragma unroll
     for (int k = 1; k < 9; k++) dm[k] = -P.sf[k] * (m[k] - meq[k]) + (T(1) - T(0.5) * P.sf[k]) * mR[k];
+    if (CH) {
+        // Rows 1, 2 of Eq. MfMRCH1 (eta = 1): m^eq = -4 phi + 2 mu, 4 phi - 3 mu.  With
+        // f_0 = phi - S (S = axis sum a + diagonal sum d) the phi terms cancel exactly:
+        // m_1 - m_1^eq = 3a + 6d - 2 mu and m_2 - m_2^eq = -6a - 3d + 3 mu, both
+        // formed from the small moving populations (in the CH bulk phi = +-1 and the
+        // moving populations are O(mu, phi |u|): the plain form would lose them to
+        // the rounding of f_0 and phi in FP32).
+        const T a = (f[1] + f[2]) + (f[3] + f[4]);
+        const T dd = (f[5] + f[6]) + (f[7] + f[8]);
+        dm[1] = -P.sf[1] * ((T(3) * a + T(6) * dd) - T(2) * M.mu);
+        dm[2] = -P.sf[2] * ((T(-6) * a - T(3) * dd) + T(3) * M.mu);
+    }
     from_moments(dm, d);
 #pragma unroll
     for (int i = 1; i < 9; i++) f[i] += d[i];

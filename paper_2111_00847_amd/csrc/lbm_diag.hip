@@ -8,6 +8,7 @@
 // Pass 2 (tile kernel): div m^phiC from the scratch planes, S_m^2 partials.
 // Pass 3 (one workgroup): fixed-order reduction of the partials.  Every
 // reduction has a fixed order, so results are bitwise reproducible.
+#include "lbm_ch.hpp"
 #include "lbm_kernels.hpp"
 #include "lbm_tile.hpp"
 
@@ -39,6 +40,49 @@ __device__ void block_reduce(double* v, const bool* is_max, double (*red)[NV]) {
     }
 }
 
+// Per-node part of pass 1: div u, the local part of S_m and m^phiC to scratch,
+// the running sums/maxima in acc (sum phi, max|div|, sum div^2, max|u|, bad).
+template <typename T>
+__device__ __forceinline__ void diag_node(const KParams<T>& P, const Macro<T>& M, const T* f, const T* g,
+                                          double phid, bool first, T php, long long k, T* scr, double* acc) {
+    bool bad = !isfinite(phid);
+    for (int i = 0; i < Q; i++) bad = bad || !isfinite(f[i]) || !isfinite(g[i]);
+    // g^eq of the current level (Eq. MgMF1 inverted through M1)
+    const T u = M.u, v = M.v, rho = M.rho;
+    T tr = T(3) * rho * (u * u + v * v) + T(3) * (u * M.mx + v * M.my);
+    T meq[9] = {P.rho0, T(-4) * P.rho0 + T(6) * M.p + tr, T(4) * P.rho0 - T(9) * M.p - tr,
+                rho * u, -rho * u, rho * v, -rho * v,
+                (u * M.mx - v * M.my) + rho * (u * u - v * v),
+                T(0.5) * ((u * M.my + v * M.mx) + T(2) * rho * u * v)};
+    T geq[9];
+    from_moments(meq, geq);
+    T s = T(0);
+    for (int i = 1; i < Q; i++) s += T(cx(i) * cx(i) + cy(i) * cy(i)) * (g[i] - geq[i]);
+    T ugr = u * M.drx + v * M.dry;
+    T trM2F = T(2) * (u * M.Fx + v * M.Fy) + (M.d2 + M.d3) + (T(4) / T(3)) * ugr;
+    // tr S = -s_2 / (2 rho cs^2) [sum |c|^2 (g - g^eq) + tr M_2F / 2]
+    T div = -(T(1.5) * M.snu / rho) * (s + T(0.5) * trM2F);
+    T rho_prev = P.drho * (php - P.phiB) + P.rhoB;
+    T dtr = first ? T(0) : rho - rho_prev;
+    scr[k] = M.mx;
+    scr[P.plane + k] = M.my;
+    scr[2 * P.plane + k] = dtr + rho * div + ugr;
+    acc[0] += phid;
+    acc[1] = fmax(acc[1], fabs((double)div));
+    acc[2] += (double)div * (double)div;
+    acc[3] = fmax(acc[3], sqrt((double)u * (double)u + (double)v * (double)v));
+    if (bad) acc[4] = 1.0;
+}
+
+template <typename T>
+__device__ __forceinline__ void diag_finish(double* acc, double (*red)[5], double* partials) {
+    const bool is_max[5] = {false, true, false, true, true};
+    block_reduce<5>(acc, is_max, red);
+    const int b = blockIdx.y * gridDim.x + blockIdx.x;
+    if (threadIdx.x == 0 && threadIdx.y == 0)
+        for (int j = 0; j < 5; j++) partials[b * 8 + j] = acc[j];
+}
+
 template <typename T>
 __global__ __launch_bounds__(TX* BY) void k_diag1(KParams<T> P, const char* state, size_t off0,
                                                   size_t off1, size_t off_stamp, T* scr, double* partials) {
@@ -52,7 +96,7 @@ __global__ __launch_bounds__(TX* BY) void k_diag1(KParams<T> P, const char* stat
     const int x0 = blockIdx.x * TX, y0 = blockIdx.y * DTY;
     fill_window<T, DTY>(P, S, true, x0, y0, sphi, sphp);
 
-    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // sum phi, max|div|, sum div^2, max|u|, nonfinite
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     for (int r = 0; r < DTY / BY; r++) {
         const int lx = threadIdx.x, ly = threadIdx.y + r * BY;
         const int x = x0 + lx, y = y0 + ly;
@@ -60,11 +104,7 @@ __global__ __launch_bounds__(TX* BY) void k_diag1(KParams<T> P, const char* stat
         const long long k = (long long)y * P.nx + x;
         T f[9], g[9];
         const double phid = node_phi(P, S, x, y, f);
-        bool bad = !isfinite(phid);
-        for (int i = 0; i < Q; i++) {
-            g[i] = pull(S.g, P, i, x, y);
-            bad = bad || !isfinite(f[i]) || !isfinite(g[i]);
-        }
+        for (int i = 0; i < Q; i++) g[i] = pull(S.g, P, i, x, y);
         T gx, gy, lap, gxp = T(0), gyp = T(0), lp, php = sphp[ly + 1][lx + 1], up = T(0), vp = T(0);
         win_stencil<T, DTY>(sphi, lx + 1, ly + 1, gx, gy, lap);
         if (!first) {
@@ -73,37 +113,30 @@ __global__ __launch_bounds__(TX* BY) void k_diag1(KParams<T> P, const char* stat
             vp = S.h[2 * P.plane + k];
         }
         Macro<T> M = macro(P, g, sphi[ly + 1][lx + 1], gx, gy, lap, first, php, gxp, gyp, up, vp);
-        // g^eq of the current level (Eq. MgMF1 inverted through M1)
-        const T u = M.u, v = M.v, rho = M.rho;
-        T tr = T(3) * rho * (u * u + v * v) + T(3) * (u * M.mx + v * M.my);
-        T meq[9] = {P.rho0, T(-4) * P.rho0 + T(6) * M.p + tr, T(4) * P.rho0 - T(9) * M.p - tr,
-                    rho * u, -rho * u, rho * v, -rho * v,
-                    (u * M.mx - v * M.my) + rho * (u * u - v * v),
-                    T(0.5) * ((u * M.my + v * M.mx) + T(2) * rho * u * v)};
-        T geq[9];
-        from_moments(meq, geq);
-        T s = T(0);
-        for (int i = 1; i < Q; i++) s += T(cx(i) * cx(i) + cy(i) * cy(i)) * (g[i] - geq[i]);
-        T ugr = u * M.drx + v * M.dry;
-        T trM2F = T(2) * (u * M.Fx + v * M.Fy) + (M.d2 + M.d3) + (T(4) / T(3)) * ugr;
-        // tr S = -s_2 / (2 rho cs^2) [sum |c|^2 (g - g^eq) + tr M_2F / 2]
-        T div = -(T(1.5) * M.snu / rho) * (s + T(0.5) * trM2F);
-        T rho_prev = P.drho * (php - P.phiB) + P.rhoB;
-        T dtr = first ? T(0) : rho - rho_prev;
-        scr[k] = M.mx;
-        scr[P.plane + k] = M.my;
-        scr[2 * P.plane + k] = dtr + rho * div + ugr;
-        acc[0] += phid;
-        acc[1] = fmax(acc[1], fabs((double)div));
-        acc[2] += (double)div * (double)div;
-        acc[3] = fmax(acc[3], sqrt((double)u * (double)u + (double)v * (double)v));
-        if (bad) acc[4] = 1.0;
+        diag_node(P, M, f, g, phid, first, php, k, scr, acc);
     }
-    const bool is_max[5] = {false, true, false, true, true};
-    block_reduce<5>(acc, is_max, red);
-    const int b = blockIdx.y * gridDim.x + blockIdx.x;
-    if (threadIdx.x == 0 && threadIdx.y == 0)
-        for (int j = 0; j < 5; j++) partials[b * 8 + j] = acc[j];
+    diag_finish<T>(acc, red, partials);
+}
+
+// Pass 1 of the Cahn-Hilliard variant: the same per-node quantities from the CH
+// tile body (m^phiC from grad mu).
+template <typename T>
+__global__ __launch_bounds__(TX* BY) void k_diag1_ch(KParams<T> P, const char* state, size_t off0,
+                                                     size_t off1, size_t off_stamp, T* scr, double* partials) {
+    __shared__ ChWindow<T, DTY> W;
+    __shared__ double red[BY][5];
+    const int64_t step = *reinterpret_cast<const int64_t*>(state + off_stamp);
+    const bool first = step == 0;
+    const int cur = (int)(step & 1);
+    const Copy<T> S = copy_at<T>(const_cast<char*>(state) + (cur ? off1 : off0), P.plane);
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    ch_tile<T, DTY>(P, S, step, blockIdx.x * TX, blockIdx.y * DTY, W,
+                    [&](const Macro<T>& M, T* f, T* g, double phid, int, int, long long k) {
+                        // the previous phi of the node (for d_t rho) is the history plane
+                        const T php = first ? M.phi : S.h[k];
+                        diag_node(P, M, f, g, phid, first, php, k, scr, acc);
+                    });
+    diag_finish<T>(acc, red, partials);
 }
 
 template <typename T>
@@ -177,7 +210,8 @@ hipError_t launch_diagnostics(const KParams<T>& P, const char* state, const Layo
     T* scr = reinterpret_cast<T*>(const_cast<char*>(state) + L.off_diag);
     double* partials = reinterpret_cast<double*>(const_cast<char*>(state) + L.off_diag + 3 * L.plane * L.esz);
     double* out = partials + L.diag_partials;
-    k_diag1<T><<<grd, blk, 0, s>>>(P, state, L.off_buf[0], L.off_buf[1], L.off_stamp, scr, partials);
+    if (P.pf == 1) k_diag1_ch<T><<<grd, blk, 0, s>>>(P, state, L.off_buf[0], L.off_buf[1], L.off_stamp, scr, partials);
+    else k_diag1<T><<<grd, blk, 0, s>>>(P, state, L.off_buf[0], L.off_buf[1], L.off_stamp, scr, partials);
     k_diag2<T><<<grd, blk, 0, s>>>(P, scr, partials);
     k_diag3<<<1, 64, 0, s>>>(partials, (int)(grd.x * grd.y), L.n, out);
     hipError_t e = hipGetLastError();

@@ -17,6 +17,7 @@
 // sums them into phi in LDS (the ring's pulls hit L2: those lines are the
 // neighbour tiles' own reads), fills wall ghosts, and then each thread runs
 // the per-node update for its nodes (lbm_fused.hpp).
+#include "lbm_ch.hpp"
 #include "lbm_fused.hpp"
 #include "lbm_kernels.hpp"
 
@@ -38,6 +39,84 @@ void k_step(KParams<T> P, char* state, size_t off0, size_t off1, size_t off_stam
     step_tile<T, TY, MODE, OFF, NBY>(P, state, off0, off1, off_stamp, xt, yt, out_phi, out_u, out_p, sphi, sphp);
 }
 
+// The Cahn-Hilliard variant (lbm_ch.hpp): one 64 x TY tile per workgroup of
+// 64 x 4 threads, tiles dealt to the XCDs as for the Allen-Cahn step, the same
+// state layout, level stamps and non-temporal stores.  MODE 0: one time step;
+// MODE 1: phi, u, p of the current level.
+// Tile rows (measured on MI355X, square droplet): 8 when that still gives >= 1024
+// tiles (+9% over 4 rows at 4096^2 FP32, +3% at 1024^2, equal in FP64), else 4
+// (+57% over 8 rows at 200^2, where the step is latency-bound); 16 rows lose
+// 4-10% (FP32) and spill to one wave per SIMD in FP64.  LBM_CH_TY forces 4, 8
+// or 16.
+#ifndef LBM_CH_TY
+#define LBM_CH_TY 0
+#endif
+
+template <typename T, int TY, int MODE>
+__global__ __launch_bounds__(TX* BY) void k_step_ch(KParams<T> P, char* state, size_t off0, size_t off1,
+                                                   size_t off_stamp, int ntx, int nty, T* out_phi, T* out_u,
+                                                   T* out_p) {
+    __shared__ ChWindow<T, TY> W;
+    int xt, yt;
+    if (LBM_XCD_REMAP) {
+        xcd_tile(blockIdx.x, ntx, nty, xt, yt);
+    } else {
+        xt = blockIdx.x % ntx;
+        yt = blockIdx.x / ntx;
+    }
+    const int x0 = xt * TX, y0 = yt * TY;
+    int64_t* stamp = reinterpret_cast<int64_t*>(state + off_stamp) + (size_t)xt * P.ny + y0;
+    const int64_t step = stamp[0];
+    const int cur = (int)(step & 1);
+    const Copy<T> S = copy_at<T>(state + (cur ? off1 : off0), P.plane);
+    const Copy<T> D = copy_at<T>(state + (cur ? off0 : off1), P.plane);
+    ch_tile<T, TY>(P, S, step, x0, y0, W, [&](const Macro<T>& M, T* f, T* g, double phid, int, int, long long k) {
+        if (MODE == 1) {
+            if (out_phi) out_phi[k] = M.phi;
+            if (out_u) {
+                out_u[k] = M.u;
+                out_u[(long long)P.nx * P.ny + k] = M.v;
+            }
+            if (out_p) out_p[k] = M.p;
+            return;
+        }
+        const double f0n = collide_f<T, true>(P, M, f, phid);
+        collide_g(P, M, g);
+        const long long pl = P.plane;
+        st<double, long long>(reinterpret_cast<char*>(D.f0), 8 * k, f0n);
+        for (int i = 1; i < Q; i++) st<T, long long>(reinterpret_cast<char*>(D.f), (long long)sizeof(T) * (i * pl + k), f[i]);
+        for (int i = 0; i < Q; i++) st<T, long long>(reinterpret_cast<char*>(D.g), (long long)sizeof(T) * (i * pl + k), g[i]);
+        st<T, long long>(reinterpret_cast<char*>(D.h), (long long)sizeof(T) * k, M.phi);
+        st<T, long long>(reinterpret_cast<char*>(D.h), (long long)sizeof(T) * (pl + k), M.u);
+        st<T, long long>(reinterpret_cast<char*>(D.h), (long long)sizeof(T) * (2 * pl + k), M.v);
+    });
+    // every wave read stamp[0] before the barriers of the tile body
+    const int tid = threadIdx.y * TX + threadIdx.x;
+    if (MODE == 0 && tid < TY && y0 + tid < P.ny) stamp[tid] = step + 1;
+}
+
+static int ch_rows(int nx, int ny) {
+    if (LBM_CH_TY == 4 || LBM_CH_TY == 8 || LBM_CH_TY == 16) return LBM_CH_TY;
+    const long long ntx = (nx + TX - 1) / TX;
+    return ntx * ((ny + 7) / 8) >= 1024 ? 8 : 4;
+}
+
+template <typename T, int MODE>
+static void launch_ch(const KParams<T>& P, char* state, const Layout& L, hipStream_t s, T* phi, T* u, T* p) {
+    const int ty = ch_rows(P.nx, P.ny);
+    const int ntx = (P.nx + TX - 1) / TX, nty = (P.ny + ty - 1) / ty;
+    const dim3 grd(ntx * nty), blk(TX, BY);
+    if (ty == 16)
+        k_step_ch<T, 16, MODE><<<grd, blk, 0, s>>>(P, state, L.off_buf[0], L.off_buf[1], L.off_stamp, ntx, nty, phi,
+                                                   u, p);
+    else if (ty == 8)
+        k_step_ch<T, 8, MODE><<<grd, blk, 0, s>>>(P, state, L.off_buf[0], L.off_buf[1], L.off_stamp, ntx, nty, phi,
+                                                  u, p);
+    else
+        k_step_ch<T, 4, MODE><<<grd, blk, 0, s>>>(P, state, L.off_buf[0], L.off_buf[1], L.off_stamp, ntx, nty, phi,
+                                                  u, p);
+}
+
 // ---------------------------------------------------------------- init / import / export
 // phi at (x, y) of a caller field, extended by the lattice's ghost rule:
 // periodic axes wrap; x-wall ghosts from the row, y-wall ghosts from the
@@ -57,6 +136,20 @@ __device__ T field_at(const KParams<T>& P, const T* phi, int x, int y) {
     return col(x, y);
 }
 
+// mu_phi of a caller field at (x, y) (Sec. 2), positions beyond a wall taking
+// the value of the first fluid node (x first, then y), periodic axes wrapping.
+template <typename T>
+__device__ T mu_at(const KParams<T>& P, const T* phi, int x, int y) {
+    if (x < 0 || x >= P.nx) x = P.wall_x ? (x < 0 ? 0 : P.nx - 1) : (x < 0 ? x + P.nx : x - P.nx);
+    if (y < 0 || y >= P.ny) y = P.wall_y ? (y < 0 ? 0 : P.ny - 1) : (y < 0 ? y + P.ny : y - P.ny);
+    T n_[3][3];
+    for (int j = 0; j < 3; j++)
+        for (int i = 0; i < 3; i++) n_[j][i] = field_at(P, phi, x + i - 1, y + j - 1);
+    T gx, gy, lap;
+    stencil(n_[0][0], n_[0][1], n_[0][2], n_[1][0], n_[1][1], n_[1][2], n_[2][0], n_[2][1], n_[2][2], gx, gy, lap);
+    return chem_pot(P, n_[1][1], lap);
+}
+
 // Equilibria at every node into `eq` (f^eq planes 0..8, g^eq planes 9..17).
 template <typename T>
 __global__ void k_equilibrium(KParams<T> P, const T* phi0, const T* u0, const T* p0, T* eq) {
@@ -73,10 +166,25 @@ __global__ void k_equilibrium(KParams<T> P, const T* phi0, const T* u0, const T*
         const T phi = n_[1][1];
         const T u = u0 ? u0[k] : T(0), v = u0 ? u0[n + k] : T(0), p = p0 ? p0[k] : T(0);
         T lnx, lny, mx, my;
-        mass_flux(P, phi, gx, gy, lnx, lny, mx, my);
+        if (P.pf == 1) {   // Cahn-Hilliard: grad mu of the initial field, mu mirrored at walls
+            T mn[3][3];
+            for (int j = 0; j < 3; j++)
+                for (int i = 0; i < 3; i++) mn[j][i] = mu_at(P, phi0, x + i - 1, y + j - 1);
+            T gmx, gmy, lm;
+            stencil(mn[0][0], mn[0][1], mn[0][2], mn[1][0], mn[1][1], mn[1][2], mn[2][0], mn[2][1], mn[2][2], gmx,
+                    gmy, lm);
+            mass_flux_ch(P, gmx, gmy, mx, my);
+        } else {
+            mass_flux(P, phi, gx, gy, lnx, lny, mx, my);
+        }
         const T rho = P.drho * (phi - P.phiB) + P.rhoB;
         T m[9], e[9];
         T mf[9] = {phi, T(-2) * phi, phi, phi * u, -phi * u, phi * v, -phi * v, T(0), T(0)};
+        if (P.pf == 1) {   // Eq. MfMRCH1
+            const T mu = chem_pot(P, phi, lap);
+            mf[1] = T(-4) * phi + T(2) * mu;
+            mf[2] = T(4) * phi - T(3) * mu;
+        }
         from_moments(mf, e);
         for (int i = 0; i < Q; i++) eq[i * P.plane + k] = e[i];
         T tr = T(3) * rho * (u * u + v * v) + T(3) * (u * mx + v * my);
@@ -194,7 +302,8 @@ hipError_t launch_step(const KParams<T>& P, char* state, const Layout& L, int64_
                        int ty, int by) {
     constexpr int T16 = sizeof(T) == 8 ? 8 : 16;   // FP64 tiles stop at 8 rows
     for (int64_t t = 0; t < nsteps; t++) {
-        if (ty == 4) launch_tile<T, 4, 0>(P, state, L, s, nullptr, nullptr, nullptr);
+        if (P.pf == 1) launch_ch<T, 0>(P, state, L, s, nullptr, nullptr, nullptr);
+        else if (ty == 4) launch_tile<T, 4, 0>(P, state, L, s, nullptr, nullptr, nullptr);
         else if (ty == 8 || sizeof(T) == 8) {
             if (by == 8) launch_tile<T, 8, 0, 8>(P, state, L, s, nullptr, nullptr, nullptr);
             else launch_tile<T, 8, 0>(P, state, L, s, nullptr, nullptr, nullptr);
@@ -209,7 +318,8 @@ hipError_t launch_step(const KParams<T>& P, char* state, const Layout& L, int64_
 template <typename T>
 hipError_t launch_moments(const KParams<T>& P, const char* state, const Layout& L, T* phi, T* u, T* p,
                           hipStream_t s) {
-    launch_tile<T, 8, 1>(P, const_cast<char*>(state), L, s, phi, u, p);
+    if (P.pf == 1) launch_ch<T, 1>(P, const_cast<char*>(state), L, s, phi, u, p);
+    else launch_tile<T, 8, 1>(P, const_cast<char*>(state), L, s, phi, u, p);
     return hipGetLastError();
 }
 

@@ -94,6 +94,13 @@ __device__ __forceinline__ void fill_window(const KParams<T>& P, const Copy<T>& 
     wall_ghosts<T, TY>(P, need_prev, x0, y0, sphi, sphp);
 }
 
+// The same stencils on any 2-D window array, centred at (wx, wy).
+template <typename A, typename T>
+__device__ __forceinline__ void win_stencil_at(const A& s, int wx, int wy, T& gx, T& gy, T& lap) {
+    stencil(s[wy - 1][wx - 1], s[wy - 1][wx], s[wy - 1][wx + 1], s[wy][wx - 1], s[wy][wx], s[wy][wx + 1],
+            s[wy + 1][wx - 1], s[wy + 1][wx], s[wy + 1][wx + 1], gx, gy, lap);
+}
+
 template <typename T, int TY>
 __device__ __forceinline__ void win_stencil(T (*s)[TX + 3], int wx, int wy, T& gx, T& gy, T& lap) {
     stencil(s[wy - 1][wx - 1], s[wy - 1][wx], s[wy - 1][wx + 1], s[wy][wx - 1], s[wy][wx],

@@ -62,7 +62,7 @@ def test_state_size_layout():
     (dict(rhoA=0.0), -4), (dict(nuB=-1.0), -4), (dict(W=0.0), -4), (dict(eta=0.5), -4),
     (dict(phiA=0.0, phiB=1.0), -4), (dict(theta=(0.0, 1.0, 1.0, 1.0)), -4),
     (dict(s_g=(2.0,) + (0.0,) * 8), -5), (dict(s_f=(0.0,) * 3 + (2.5,) + (0.0,) * 5), -5),
-    (dict(sigma=float("nan")), -4), (dict(model="corrected"), -8),
+    (dict(sigma=float("nan")), -4), (dict(model="corrected"), -8), (dict(phase_eq="other"), -4),
 ])
 def test_parameter_validation(kw, code):
     rc, _ = _size(_params(**kw))
@@ -107,3 +107,17 @@ def test_batch_create_validation():
     assert L.lbm_batch_state_size(None, None) == -1
     assert L.lbm_batch_step(None, None, 1, None) == -1
     assert L.lbm_batch_destroy(None) == -1
+
+
+def test_cahn_hilliard_rejected_by_batches_and_reverse_mode():
+    """Batches and the adjoint run the Allen-Cahn step only: CH parameters are
+    refused on the host (before any HIP call)."""
+    from paper_2111_00847_amd._lib import LbmParams, lib
+    L = lib()
+    p = _params(dtype="f32", phase_eq="cahn_hilliard", phiB=-1.0)
+    n = ctypes.c_size_t()
+    assert L.lbm_state_size(ctypes.byref(p), ctypes.byref(n)) == 0
+    h = ctypes.c_void_p()
+    assert L.lbm_batch_create((LbmParams * 1)(p), 1, 0, ctypes.byref(h)) == -8
+    assert L.lbm_tape_record(ctypes.byref(p), ctypes.c_void_p(256), ctypes.c_void_p(256), 1, None) == -8
+    assert L.lbm_adjoint_run(ctypes.byref(p), ctypes.c_void_p(256), 0, 1, ctypes.c_void_p(256), None) == -8
