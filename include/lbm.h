@@ -67,7 +67,11 @@ typedef enum {
 } lbm_visc;
 typedef enum {
     LBM_MODEL_PRESENT = 0,    /* consistent mass flux m^CC (the paper's model) */
-    LBM_MODEL_ORIGINAL = 1    /* mass flux rho u only (m^phiC = 0 in the flow model; Sec. 4 preamble) */
+    LBM_MODEL_ORIGINAL = 1,   /* mass flux rho u only (m^phiC = 0 in the flow model; Sec. 4 preamble) */
+    LBM_MODEL_CORRECTED = 2   /* mass flux rho u plus the interface force F_a = (drho/dphi) u div(M_phi D)
+                                 (Sec. 4 preamble; App. A, Eq. NS2-add); Cahn-Hilliard only, where
+                                 div(M_phi D) = M_phi lap mu_phi (Eq. central2); u solves Eq. comU with
+                                 F = F_0 + F_a exactly.  Allen-Cahn params: LBM_E_UNSUPPORTED */
 } lbm_model;
 
 typedef enum {

@@ -69,6 +69,7 @@ struct orc_sim {
     double *rho, *mu, *lam, *nxv, *nyv, *mx, *my, *Fx, *Fy, *snu;
     double *ux, *uy, *pr, *P5, *dP5;
     double *muext;      /* (nx+2) x (ny+2) mu with its ghost layer (Cahn-Hilliard) */
+    double *fa;         /* [n] corrected model: F_a = fa u (Cahn-Hilliard) */
 };
 
 /* ------------------------------------------------------------------ */
@@ -133,8 +134,8 @@ static int check_params(const orc_params *p) {
     if (!(p->rhoA > 0 && p->rhoB > 0 && p->nuA > 0 && p->nuB > 0)) return -4;
     if (!(p->W > 0 && p->sigma >= 0 && p->M >= 0)) return -4;
     if (p->eta != 1.0) return -4;
-    if (p->model != 0 && p->model != 1) return -8;
     if (p->pf != 0 && p->pf != 1) return -4;
+    if (p->model != 0 && p->model != 1 && !(p->model == 2 && p->pf == 1)) return -8;
     if (p->visc_law != 0 && p->visc_law != 1) return -4;
     for (int i = 0; i < 9; i++)
         if (p->sf[i] >= 2.0 || p->sg[i] >= 2.0) return -5;
@@ -188,6 +189,7 @@ orc_sim *orc_create(const orc_params *p) {
     s->P5 = calloc(5 * n, dz);
     s->dP5 = calloc(5 * n, dz);
     s->muext = calloc((size_t)(p->nx + 2) * (p->ny + 2), dz);
+    s->fa = calloc(n, dz);
     return s;
 }
 
@@ -195,7 +197,7 @@ void orc_destroy(orc_sim *s) {
     if (!s) return;
     double *bufs[] = {s->f, s->g, s->fs, s->gs, s->H, s->phi_prev, s->phi, s->ext, s->gx, s->gy,
                       s->lap, s->rho, s->mu, s->lam, s->nxv, s->nyv, s->mx, s->my, s->Fx, s->Fy,
-                      s->snu, s->ux, s->uy, s->pr, s->P5, s->dP5, s->muext};
+                      s->snu, s->ux, s->uy, s->pr, s->P5, s->dP5, s->muext, s->fa};
     for (size_t i = 0; i < sizeof(bufs) / sizeof(bufs[0]); i++) free(bufs[i]);
     free(s);
 }
@@ -484,16 +486,20 @@ static void matvec(const double A[9][9], const double *x, double *y) {
 
 /* Cahn-Hilliard mass flux m^phiC = -(drho/dphi) M grad mu_phi (Sec. 2, D =
  * grad mu for Eq. CHE), grad mu by Eq. central1 on mu with its ghost layer;
- * zero for the original model. */
+ * zero for the original and corrected models (m = rho u).  The corrected
+ * model's interface force F_a = (drho/dphi) u div(M grad mu_phi) (App. A,
+ * Eq. NS2-add; Sec. 4 preamble) is kept as its coefficient fa = (drho/dphi) M lap mu_phi
+ * of u, lap by Eq. central2 on the same ghost layer; zero for the others. */
 static void ch_flux(orc_sim *s, const double *mu, double *mx, double *my) {
     const orc_params *p = &s->P;
     long n = s->n;
     fill_ghosts_mirror(s, mu, s->muext);
-    stencils(s, s->muext, mx, my, NULL);
-    double c = -(p->rhoA - p->rhoB) / (p->phiA - p->phiB) * p->M;
+    stencils(s, s->muext, mx, my, s->fa);
+    double drho = (p->rhoA - p->rhoB) / (p->phiA - p->phiB);
     for (long k = 0; k < n; k++) {
-        mx[k] = p->model == 1 ? 0.0 : c * mx[k];
-        my[k] = p->model == 1 ? 0.0 : c * my[k];
+        mx[k] = p->model == 0 ? -drho * p->M * mx[k] : 0.0;
+        my[k] = p->model == 0 ? -drho * p->M * my[k] : 0.0;
+        s->fa[k] = p->model == 2 ? drho * p->M * s->fa[k] : 0.0;
     }
 }
 
@@ -540,8 +546,15 @@ static void macroscopic(orc_sim *s) {
                 jx += CX[i] * s->g[i * n + k];
                 jy += CY[i] * s->g[i * n + k];
             }
-            double u = (jx + 0.5 * Fx) / rho;
-            double v = (jy + 0.5 * Fy) / rho;
+            /* corrected model: F = F_0 + fa u in Eq. comU, solved for u exactly
+             * (fa is zero for the other models) */
+            double a = s->fa[k];
+            double u = (jx + 0.5 * Fx) / (rho - 0.5 * a);
+            double v = (jy + 0.5 * Fy) / (rho - 0.5 * a);
+            Fx += a * u;
+            Fy += a * v;
+            s->Fx[k] = Fx;
+            s->Fy[k] = Fy;
             s->ux[k] = u;
             s->uy[k] = v;
             /* history products chi and their explicit-Euler derivatives */

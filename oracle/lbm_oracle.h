@@ -29,7 +29,7 @@ typedef struct orc_params {
     int nx, ny;
     int wall_x, wall_y;   /* 0: periodic axis, 1: half-way bounce-back walls on both faces */
     int visc_law;         /* 0: linear dynamic viscosity (Eq. linearMu); 1: inverse-linear nu (Eq. inverseNu) */
-    int model;            /* 0: present consistent model; 1: original (m = rho u); 2: corrected (adds F_a) */
+    int model;            /* 0: present consistent model; 1: original (m = rho u); 2: corrected (m = rho u plus F_a; Cahn-Hilliard only) */
     int pf;               /* phase-field equation: 0 Allen-Cahn (D = grad phi - lambda n, Eq. ACE);
                              1 Cahn-Hilliard (D = grad mu_phi, Eq. CHE; moments of Eq. MfMRCH1) */
     double phiA, phiB, rhoA, rhoB, nuA, nuB;

@@ -15,7 +15,7 @@ import torch
 from ._lib import (LBM_F32, LBM_F64, LBM_PERIODIC, LBM_WALLS, LbmError, LbmParams, call, lib)
 
 _VISC = {"linear_mu": 0, "inverse_nu": 1}
-_MODEL = {"present": 0, "original": 1}
+_MODEL = {"present": 0, "original": 1, "corrected": 2}
 
 
 def make_params(case) -> LbmParams:

@@ -31,8 +31,10 @@ int validate(const lbm_params* p) {
     if (p->bc_x == LBM_WALLS && p->nx < 2) return LBM_E_SIZE;
     if (p->bc_y == LBM_WALLS && p->ny < 2) return LBM_E_SIZE;
     if (p->visc_law != LBM_VISC_LINEAR_MU && p->visc_law != LBM_VISC_INVERSE_NU) return LBM_E_PARAM;
-    if (p->model != LBM_MODEL_PRESENT && p->model != LBM_MODEL_ORIGINAL) return LBM_E_UNSUPPORTED;
     if (p->phase_eq != LBM_ALLEN_CAHN && p->phase_eq != LBM_CAHN_HILLIARD) return LBM_E_PARAM;
+    if (p->model != LBM_MODEL_PRESENT && p->model != LBM_MODEL_ORIGINAL &&
+        !(p->model == LBM_MODEL_CORRECTED && p->phase_eq == LBM_CAHN_HILLIARD))
+        return LBM_E_UNSUPPORTED;
     const double vals[] = {p->phi_A, p->phi_B, p->rho_A, p->rho_B, p->nu_A, p->nu_B, p->sigma, p->W,
                            p->M_phi, p->eta, p->body_force[0], p->body_force[1], p->gravity[0],
                            p->gravity[1], p->rho_ref, p->rho0, p->eps_n};

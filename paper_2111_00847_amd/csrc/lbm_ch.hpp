@@ -191,18 +191,18 @@ __device__ __forceinline__ void ch_tile(const KParams<T>& P, const Copy<T>& S, i
         if (x >= P.nx || y >= P.ny) continue;
         const long long k = (long long)y * P.nx + x;
         T gx, gy, lap, gmx, gmy, lm, gxp = T(0), gyp = T(0), lp, php = T(0), upr = T(0), vpr = T(0);
-        T gmxp = T(0), gmyp = T(0);
+        T gmxp = T(0), gmyp = T(0), lmp;
         win_stencil_at(W.phi, lx + 2, ly + 2, gx, gy, lap);
         win_stencil_at(W.mu, lx + 1, ly + 1, gmx, gmy, lm);
         if (!first) {
             win_stencil_at(W.php, lx + 2, ly + 2, gxp, gyp, lp);
-            win_stencil_at(W.mup, lx + 1, ly + 1, gmxp, gmyp, lm);
+            win_stencil_at(W.mup, lx + 1, ly + 1, gmxp, gmyp, lmp);
             php = W.php[ly + 2][lx + 2];
             upr = up[r];
             vpr = vp[r];
         }
         const Macro<T> M = macro<T, true>(P, g[r], W.phi[ly + 2][lx + 2], gx, gy, lap, first, php, gxp, gyp, upr,
-                                          vpr, gmx, gmy, gmxp, gmyp);
+                                          vpr, gmx, gmy, gmxp, gmyp, lm);
         per_node(M, f[r], g[r], phid[r], x, y, k);
     }
 }

@@ -129,19 +129,20 @@ __device__ __forceinline__ T chem_pot(const KParams<T>& P, T phi, T lap) {
 // Cahn-Hilliard mass flux m^phiC = -(drho/dphi) M grad mu_phi (Sec. 2, D = grad mu).
 template <typename T>
 __device__ __forceinline__ void mass_flux_ch(const KParams<T>& P, T gmx, T gmy, T& mx, T& my) {
-    mx = P.model == 1 ? T(0) : -P.drhoM * gmx;
-    my = P.model == 1 ? T(0) : -P.drhoM * gmy;
+    mx = P.model != 0 ? T(0) : -P.drhoM * gmx;
+    my = P.model != 0 ? T(0) : -P.drhoM * gmy;
 }
 
 // Closure, velocity (Eq. comU), history derivatives and pressure (Eq. computP,
 // second way of Remark 1) of one node.  g: pulled populations; (gx, gy, lap):
 // stencils of phi; first: level 0 (time derivatives zero); (php, gxp, gyp,
 // up, vp): phi, grad phi and u of the previous level.  CH: the Cahn-Hilliard
-// flux from grad mu (gmx, gmy) and grad mu of the previous level (gmxp, gmyp).
+// flux from grad mu (gmx, gmy) and grad mu of the previous level (gmxp, gmyp);
+// lmu = lap mu for the corrected model's F_a.
 template <typename T, bool CH = false>
 __device__ __forceinline__ Macro<T> macro(const KParams<T>& P, const T* g, T phi, T gx, T gy, T lap,
                                           bool first, T php, T gxp, T gyp, T up, T vp, T gmx = T(0),
-                                          T gmy = T(0), T gmxp = T(0), T gmyp = T(0)) {
+                                          T gmy = T(0), T gmxp = T(0), T gmyp = T(0), T lmu = T(0)) {
     Macro<T> m;
     m.phi = phi;
     T t = phi - P.phiB;
@@ -173,9 +174,20 @@ __device__ __forceinline__ Macro<T> macro(const KParams<T>& P, const T* g, T phi
     }
     T jx = (g[1] - g[3]) + (g[5] - g[6]) + (g[8] - g[7]);
     T jy = (g[2] - g[4]) + (g[5] + g[6]) - (g[7] + g[8]);
-    T irho = rcp(m.rho);
-    m.u = (jx + T(0.5) * m.Fx) * irho;
-    m.v = (jy + T(0.5) * m.Fy) * irho;
+    if (CH && P.model == 2) {
+        // corrected model: F = F_0 + a u with a = (drho/dphi) M lap mu (App. A, Eq. NS2-add);
+        // Eq. comU solved for u exactly
+        const T a = P.drhoM * lmu;
+        const T irho = rcp(m.rho - T(0.5) * a);
+        m.u = (jx + T(0.5) * m.Fx) * irho;
+        m.v = (jy + T(0.5) * m.Fy) * irho;
+        m.Fx += a * m.u;
+        m.Fy += a * m.v;
+    } else {
+        const T irho = rcp(m.rho);
+        m.u = (jx + T(0.5) * m.Fx) * irho;
+        m.v = (jy + T(0.5) * m.Fy) * irho;
+    }
     if (first) {
         m.d0 = m.d1 = m.d2 = m.d3 = m.d4 = T(0);
     } else {

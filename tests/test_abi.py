@@ -121,3 +121,13 @@ def test_cahn_hilliard_rejected_by_batches_and_reverse_mode():
     assert L.lbm_batch_create((LbmParams * 1)(p), 1, 0, ctypes.byref(h)) == -8
     assert L.lbm_tape_record(ctypes.byref(p), ctypes.c_void_p(256), ctypes.c_void_p(256), 1, None) == -8
     assert L.lbm_adjoint_run(ctypes.byref(p), ctypes.c_void_p(256), 0, 1, ctypes.c_void_p(256), None) == -8
+
+
+def test_corrected_model_is_cahn_hilliard_only():
+    from paper_2111_00847_amd._lib import lib
+    L = lib()
+    n = ctypes.c_size_t()
+    p = _params(dtype="f32", phase_eq="cahn_hilliard", phiB=-1.0, model="corrected")
+    assert L.lbm_state_size(ctypes.byref(p), ctypes.byref(n)) == 0
+    p = _params(dtype="f32", model="corrected")
+    assert L.lbm_state_size(ctypes.byref(p), ctypes.byref(n)) == -8

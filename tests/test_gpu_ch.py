@@ -69,6 +69,23 @@ def test_ch_one_step_map_fp64(geom, shape, step):
         np.testing.assert_allclose(a, b, rtol=0, atol=1e-13)
 
 
+@pytest.mark.parametrize("geom", list(GEOMS))
+def test_corrected_model_one_step_map_fp64(geom):
+    """Corrected model (m = rho u plus F_a; App. A, Eq. NS2-add) against the oracle."""
+    case = _ch_case(geom, 37, 23, model="corrected", sigma=0.2, M=0.5)
+    f, g, php, upr = _random_state(case, seed=5)
+    hist = np.concatenate([php[None], upr], 0)
+    gs = _sim()(case).import_state(f, g, hist, 4).step(1)
+    o = oracle.OracleSim(case).set_state(f, g, 4, php, upr).step(1)
+    so, sg = o.get_state(), gs.export_state()
+    df = np.abs(sg["f"].cpu().numpy() - so["f"]).max()
+    dg = np.abs(sg["g"].cpu().numpy() - so["g"]).max()
+    print(f"CH corrected {geom}: max|df|={df:.2e} max|dg|={dg:.2e}", flush=True)
+    assert df < 1e-14 and dg < 1e-14
+    for a, b in zip(gs.moments_np(), o.moments()):
+        np.testing.assert_allclose(a, b, rtol=0, atol=1e-13)
+
+
 def _pair(case, phi0, steps):
     g = _sim()(case).init(phi0).step(steps)
     o = oracle.OracleSim(case.replace(dtype="f64")).init(phi0).step(steps)
@@ -101,6 +118,15 @@ def test_ch_square_droplet_fp32():
     _compare(g, o, 1e-5, 1e-4, "CH square droplet fp32")
 
 
+def test_corrected_model_square_droplet_fp64():
+    case, phi0 = W.square_droplet_ch(n=64, R=16.0, sigma=1e-3, rho_ratio=100.0, model="corrected")
+    g, o = _pair(case, phi0, 1500)
+    _compare(g, o, 1e-10, 1e-9, "CH corrected square droplet fp64")
+    dg, do = g.diagnostics(), o.diagnostics()
+    for key in ("Du_rms", "Sm_rms"):
+        assert abs(dg[key] - do[key]) <= 1e-8 * abs(do[key]), (key, dg[key], do[key])
+
+
 def test_ch_walls_gravity_fp64():
     """A CH interface under gravity in a box with wetting walls (all four faces)."""
     case = _ch_case("walls_xy", 48, 40, gravity=(0.0, -2e-5), rho_ref=0.0, body_force=(0.0, 0.0))
@@ -115,10 +141,12 @@ def test_ch_table1_present_vs_original():
     in lattice units): the present model's mass source S_m^rms falls below the
     original model's and keeps falling relative to it (measured ratios 0.48,
     0.36, 0.29 at 1e5, 3e5, 1e6 steps; the paper's steady value is 0.12), while
-    D_u^rms is the same for both models -- the pattern of Table 1."""
+    D_u^rms is the same for both models, and the corrected model's S_m^rms is
+    the original's -- the pattern of Table 1.  (Table 1's lower D_u^rms of the
+    corrected model is not reproduced: F_a as defined moves it by < 0.1% here.)"""
     marks = (100000, 300000, 1000000)
     out = {}
-    for model in ("present", "original"):
+    for model in ("present", "original", "corrected"):
         case, phi0 = W.square_droplet_ch(model=model)
         s = _sim()(case, stream=torch.cuda.Stream()).init(phi0)
         done = 0
@@ -134,6 +162,8 @@ def test_ch_table1_present_vs_original():
     assert ratios[0] < 0.55 and ratios[1] < ratios[0] and ratios[2] < ratios[1] and ratios[2] < 0.33
     for m in marks:
         assert abs(out["present", m][1] - out["original", m][1]) <= 1e-3 * out["original", m][1]
+        # the corrected model shares the original's mass flux rho u: the same S_m^rms (as printed)
+        assert abs(out["corrected", m][0] - out["original", m][0]) <= 1e-2 * out["original", m][0]
 
 
 @pytest.mark.parametrize("geom", ["periodic", "walls_xy"])

@@ -90,3 +90,59 @@ def test_ch_square_droplet_mass_source_below_original_model():
     print(out)
     assert out["present"][0] < 0.5 * out["original"][0], out
     assert abs(out["present"][1] - out["original"][1]) < 0.01 * out["original"][1], out
+
+
+def test_corrected_model_interface_force_closed_form():
+    """Corrected model (App. A, Eq. NS2-add; Sec. 4 preamble): m = rho u plus
+    F_a = (drho/dphi) u div(M grad mu_phi).  On phi = A sin(kx) with a uniform
+    velocity V along the interface direction y (so F_0 has no y part and the
+    original model returns v = V), Eq. comU with F = F_0 + a u gives
+    v = rho V / (rho - a/2), a = (drho/dphi) M lap mu_phi.  lap mu_phi is taken
+    here from the continuum derivatives of mu = 4 beta (phi^3 - phi) - kappa lap phi
+    (phi_A = 1, phi_B = -1), not from a lattice stencil, so the check holds to the
+    stencils' O(k^2 dx^2) error."""
+    n, A = 128, 0.6
+    base, _ = W.to_cahn_hilliard(*W.square_droplet(n=8, side=4.0))
+    res = {}
+    for model in ("original", "corrected"):
+        case = base.replace(nx=n, ny=4, rhoA=100.0, rhoB=1.0, sigma=0.5, W=4.0, M=1.0, model=model)
+        X, _ = W.grid(case)
+        k = 2 * np.pi / n
+        phi0 = A * np.sin(k * X)
+        u0 = np.zeros((2,) + phi0.shape)
+        u0[1] = 1e-3
+        _, u, _ = oracle.OracleSim(case).init(phi0, u0).moments()
+        res[model] = u[1]
+    # continuum lap mu for phi = A sin(kx)
+    beta = 12 * case.sigma / (case.W * 2.0 ** 4)
+    kap = 1.5 * case.sigma * case.W / 4.0
+    ph = A * np.sin(k * X)
+    d1 = A * k * np.cos(k * X)
+    d2 = -k * k * ph
+    d4 = k ** 4 * ph
+    lap_mu = 4 * beta * (6 * ph * d1 ** 2 + (3 * ph ** 2 - 1) * d2) - kap * d4
+    drho = (case.rhoA - case.rhoB) / 2.0
+    rho = drho * (ph + 1.0) + case.rhoB
+    a = drho * case.M * lap_mu
+    np.testing.assert_allclose(res["original"], 1e-3, rtol=1e-12)
+    expect = rho / (rho - 0.5 * a) - 1.0
+    got = res["corrected"] / res["original"] - 1.0
+    assert np.abs(expect).max() > 1e-4                       # the force is not negligible here
+    np.testing.assert_allclose(got, expect, rtol=0, atol=5e-3 * np.abs(expect).max())
+
+
+def test_corrected_model_mass_source_equals_original():
+    """Table 1 prints the same S_m^rms for the original and the corrected model
+    (both use m = rho u in the mass balance); here they agree to 1e-3 relative
+    on a 48^2 copy of the Sec. 4.1 set-up after 2000 steps."""
+    out = {}
+    for model in ("original", "corrected"):
+        case, phi0 = W.square_droplet_ch(n=48, R=12.0, sigma=1e-3, model=model)
+        out[model] = oracle.OracleSim(case).init(phi0).step(2000).diagnostics()["Sm_rms"]
+    assert abs(out["corrected"] - out["original"]) <= 1e-3 * out["original"], out
+
+
+def test_corrected_model_is_cahn_hilliard_only():
+    case, phi0 = W.square_droplet(n=8, side=4.0)
+    with pytest.raises(Exception):
+        oracle.OracleSim(case.replace(model="corrected")).init(phi0)
