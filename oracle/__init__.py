@@ -37,7 +37,7 @@ class OrcParams(ctypes.Structure):
     _fields_ = [
         ("nx", ctypes.c_int), ("ny", ctypes.c_int),
         ("wall_x", ctypes.c_int), ("wall_y", ctypes.c_int),
-        ("visc_law", ctypes.c_int), ("model", ctypes.c_int), ("pf", ctypes.c_int),
+        ("visc_law", ctypes.c_int), ("model", ctypes.c_int), ("pf", ctypes.c_int), ("grad", ctypes.c_int),
         ("phiA", ctypes.c_double), ("phiB", ctypes.c_double),
         ("rhoA", ctypes.c_double), ("rhoB", ctypes.c_double),
         ("nuA", ctypes.c_double), ("nuB", ctypes.c_double),
@@ -74,6 +74,7 @@ def lib():
         L.orc_set_state.argtypes = [ctypes.c_void_p, d, d, d, d, ctypes.c_long]
         L.orc_rates.argtypes = [ctypes.c_void_p, d, d]
         L.orc_stencils.argtypes = [ctypes.c_void_p, d, d, d, d]
+        L.orc_grad.argtypes = [ctypes.c_void_p, d, d]
         L.orc_lattice.argtypes = [P(ctypes.c_int), P(ctypes.c_int), d, d, d]
         L.orc_wetting.argtypes = [P(OrcParams), ctypes.c_double, ctypes.c_double,
                                   ctypes.c_double, d, d]
@@ -82,7 +83,7 @@ def lib():
         L.orc_moments_g.argtypes = [P(OrcParams)] + [ctypes.c_double] * 13 + [d, d]
         L.orc_direct_g.argtypes = [P(OrcParams)] + [ctypes.c_double] * 13 + [d, d]
         for name in ("orc_init", "orc_step", "orc_moments", "orc_diagnostics",
-                     "orc_get_state", "orc_set_state", "orc_rates"):
+                     "orc_get_state", "orc_set_state", "orc_rates", "orc_grad"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -106,6 +107,7 @@ def make_params(case) -> OrcParams:
     p.visc_law = {"linear_mu": 0, "inverse_nu": 1}[case.visc_law]
     p.model = {"present": 0, "original": 1, "corrected": 2}[case.model]
     p.pf = {"allen_cahn": 0, "cahn_hilliard": 1}[case.phase_eq]
+    p.grad = {"stencil": 0, "local": 1}[case.grad_scheme]
     p.phiA, p.phiB = case.phiA, case.phiB
     p.rhoA, p.rhoB = case.rhoA, case.rhoB
     p.nuA, p.nuB = case.nuA, case.nuB
@@ -180,6 +182,14 @@ class OracleSim:
         st = ctypes.c_long()
         lib().orc_get_state(self.h, _dp(f), _dp(g), _dp(H), _dp(pp), ctypes.byref(st))
         return dict(f=f, g=g, H=H, phi_prev=pp, step=st.value)
+
+    def grad(self):
+        """grad phi of the current level as the closure uses it."""
+        gx = np.empty(self.shape)
+        gy = np.empty(self.shape)
+        rc = lib().orc_grad(self.h, _dp(gx), _dp(gy))
+        assert rc == 0, rc
+        return gx, gy
 
     def set_state(self, f, g, step, phi_prev=None, u_prev=None):
         f = _f64(f).reshape((9,) + self.shape)

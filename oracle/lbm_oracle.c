@@ -136,6 +136,8 @@ static int check_params(const orc_params *p) {
     if (p->eta != 1.0) return -4;
     if (p->pf != 0 && p->pf != 1) return -4;
     if (p->model != 0 && p->model != 1 && !(p->model == 2 && p->pf == 1)) return -8;
+    if (p->grad != 0 && p->grad != 1) return -4;
+    if (p->grad == 1 && p->pf != 0) return -8;
     if (p->visc_law != 0 && p->visc_law != 1) return -4;
     for (int i = 0; i < 9; i++)
         if (p->sf[i] >= 2.0 || p->sg[i] >= 2.0) return -5;
@@ -503,6 +505,48 @@ static void ch_flux(orc_sim *s, const double *mu, double *mx, double *my) {
     }
 }
 
+/* The local scheme for grad phi of the AC model (Eq. local), levels >= 1:
+ * with A = -M - cs^2/2, B = M lambda and C = sum_i c_i f_i - phi u + d_t(phi u)/2,
+ * C = A grad phi + B n.  u depends on grad phi through F_s = mu_phi grad phi
+ * (Eq. comU: u = u0 + mu_phi grad phi / (2 rho), u0 the velocity without F_s),
+ * so with the explicit-Euler d_t(phi u) = phi u - (phi u)^{n-1}
+ *   C0 = sum_i c_i f_i - phi u0 / 2 - (phi u)^{n-1} / 2 = A' grad phi + B n,
+ *   A' = A + phi mu_phi / (4 rho),
+ * whence |grad phi| = (|C0| + B) / (-A') (clamped at 0) and
+ * grad phi = -|grad phi| C0 / |C0| (n points against C0, A' being negative).
+ * mu_phi takes lap phi from Eq. central2.  Overwrites s->gx, s->gy. */
+static void local_gradient(orc_sim *s) {
+    const orc_params *p = &s->P;
+    long n = s->n;
+    double A = -p->M - 0.5 * CS2;
+#pragma omp parallel for
+    for (long k = 0; k < n; k++) {
+        closure_t c = closure(s, s->phi[k], 0.0, 0.0, s->lap[k]);
+        double jfx = 0, jfy = 0, jgx = 0, jgy = 0;
+        for (int i = 0; i < 9; i++) {
+            jfx += CX[i] * s->f[i * n + k];
+            jfy += CY[i] * s->f[i * n + k];
+            jgx += CX[i] * s->g[i * n + k];
+            jgy += CY[i] * s->g[i * n + k];
+        }
+        double u0 = (jgx + 0.5 * (p->Gx + (c.rho - p->rho_ref) * p->gx)) / c.rho;
+        double v0 = (jgy + 0.5 * (p->Gy + (c.rho - p->rho_ref) * p->gy)) / c.rho;
+        double cx = jfx - 0.5 * s->phi[k] * u0 - 0.5 * s->H[0 * n + k];
+        double cy = jfy - 0.5 * s->phi[k] * v0 - 0.5 * s->H[1 * n + k];
+        double Ap = A + s->phi[k] * c.mu_phi / (4.0 * c.rho);
+        double B = p->M * c.lam;
+        double cn = sqrt(cx * cx + cy * cy);
+        double mag = (cn + B) / (-Ap);
+        if (cn > 0 && mag > 0) {
+            s->gx[k] = -mag * cx / cn;
+            s->gy[k] = -mag * cy / cn;
+        } else {
+            s->gx[k] = 0.0;
+            s->gy[k] = 0.0;
+        }
+    }
+}
+
 /* Stages 1-7: every macroscopic field of the current level into the scratch
  * arrays of s (phi, ext, gradients, closure, u, history derivatives, p). */
 static void macroscopic(orc_sim *s) {
@@ -516,6 +560,7 @@ static void macroscopic(orc_sim *s) {
     }
     fill_ghosts(s, s->phi, s->ext);
     stencils(s, s->ext, s->gx, s->gy, s->lap);
+    if (p->grad == 1 && s->step > 0) local_gradient(s);
 #pragma omp parallel for
     for (int y = 0; y < ny; y++)
         for (int x = 0; x < nx; x++) {
@@ -703,6 +748,17 @@ int orc_init(orc_sim *s, const double *phi0, const double *u0, const double *p0)
     return 0;
 }
 
+/* grad phi of the current level as the closure uses it (Eq. central1, or
+ * Eq. local when selected). */
+int orc_grad(const orc_sim *cs, double *gx, double *gy) {
+    orc_sim *s = (orc_sim *)cs;
+    if (!s || !gx || !gy) return -1;
+    macroscopic(s);
+    memcpy(gx, s->gx, sizeof(double) * s->n);
+    memcpy(gy, s->gy, sizeof(double) * s->n);
+    return 0;
+}
+
 int orc_moments(const orc_sim *cs, double *phi, double *u, double *p) {
     orc_sim *s = (orc_sim *)cs;
     if (!s) return -1;
@@ -733,6 +789,7 @@ int orc_get_state(const orc_sim *s, double *f, double *g, double *H, double *phi
 int orc_set_state(orc_sim *s, const double *f, const double *g, const double *phi_prev,
                   const double *u_prev, long step) {
     if (!s || !f || !g || step < 0) return -1;
+    if (s->P.grad == 1 && step > 0) return -8; /* the history of m^phiC would need the local gradient */
     long n = s->n;
     memcpy(s->f, f, sizeof(double) * 9 * n);
     memcpy(s->g, g, sizeof(double) * 9 * n);

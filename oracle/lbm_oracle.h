@@ -32,6 +32,8 @@ typedef struct orc_params {
     int model;            /* 0: present consistent model; 1: original (m = rho u); 2: corrected (m = rho u plus F_a; Cahn-Hilliard only) */
     int pf;               /* phase-field equation: 0 Allen-Cahn (D = grad phi - lambda n, Eq. ACE);
                              1 Cahn-Hilliard (D = grad mu_phi, Eq. CHE; moments of Eq. MfMRCH1) */
+    int grad;             /* grad phi: 0 Eq. central1; 1 the local scheme of Eq. local (Allen-Cahn,
+                             levels >= 1; level 0 and lap phi use the stencils) */
     double phiA, phiB, rhoA, rhoB, nuA, nuB;
     double sigma, W, M, eta;
     double sf[9], sg[9];  /* <= 0 selects the paper's default (Sec. 4 preamble) */
@@ -72,6 +74,7 @@ int orc_num_threads(void);
 
 /* ---- building blocks exposed for the pins ---- */
 /* grad phi and lap phi of an arbitrary field with this lattice's ghost rule. */
+int orc_grad(const orc_sim *s, double *gx, double *gy);
 int orc_stencils(const orc_sim *s, const double *phi, double *gx, double *gy, double *lap);
 void orc_lattice(int cx[9], int cy[9], double w[9], double M[81], double Minv[81]);
 /* Wetting wall value and ghost value for one wall-normal line (Eq. Dwetting). */

@@ -30,6 +30,7 @@ class Case:
     visc_law: str = "linear_mu"      # "linear_mu" | "inverse_nu"
     model: str = "present"           # "present" | "original" | "corrected"
     phase_eq: str = "allen_cahn"     # "allen_cahn" | "cahn_hilliard" (Sec. 2, Eqs. ACE / CHE)
+    grad_scheme: str = "stencil"     # "stencil" (Eq. central1) | "local" (Eq. local, Allen-Cahn)
     phiA: float = 1.0
     phiB: float = 0.0
     rhoA: float = 1.0
