@@ -26,6 +26,8 @@ The JSON line also carries:
                   another with the plain step (graph-captured, and eager);
   cahn_hilliard -- the Cahn-Hilliard variant's step kernel on a 4096 x 4096
                   square droplet (Sec. 4.1 set-up scaled up, FP32);
+  local_gradient -- the Allen-Cahn step with the local gradient scheme (Eq.
+                  local) on the 4096 x 4096 RTI lattice (FP32);
   adjoint      -- the differentiable dam break (Sec. 4.5 set-up, 1024 x 512,
                   FP32, 4000 steps, checkpoints every 200): time of the
                   backward pass (tape recompute + adjoint steps) over the time
@@ -178,6 +180,28 @@ def measure_ch(args, torch, W, Sim, n=4096):
             "avg_launch_ms": round(ms_launch, 4)}
 
 
+def measure_local(args, torch, W, Sim):
+    """The Allen-Cahn step with the local gradient scheme (Eq. local) on the
+    4096 x 4096 Rayleigh-Taylor lattice (FP32).  Its history also carries m^phiC
+    of the previous level: 184 B of algorithmic traffic per update."""
+    case, phi0 = W.rti(nx=4096, ny=4096)
+    case = case.replace(grad_scheme="local")
+    sim = Sim(case, "cuda:0").init(phi0, None, W.hydrostatic_pressure(case, phi0))
+    sim.step(10)
+    steps = args.large_steps
+    ms, ms_launch = time_steps(sim, steps, torch)
+    alg = 184 * case.nodes
+    ach = alg / (ms_launch * 1e-3) / 1e9
+    phi, _, _ = sim.moments()
+    assert bool(torch.isfinite(phi).all()), "non-finite state after the timed local-scheme steps"
+    del sim, phi
+    torch.cuda.empty_cache()
+    return {"workload": "rayleigh_taylor_4096x4096_local_gradient", "dtype": "f32", "steps": steps,
+            "value": round(case.nodes * steps / (ms * 1e-3) / 1e6, 1), "unit": "MLUPS",
+            "kernel": "k_step_local<float>", "achieved_GBs": round(ach, 1), "frac": round(ach / HBM_PEAK_GBS, 4),
+            "avg_launch_ms": round(ms_launch, 4)}
+
+
 def measure_copy(torch, mib=1024, reps=20):
     """Bandwidth of torch's device-to-device copy of a `mib` MiB buffer (read + write
     bytes per second): a measured ceiling next to the nominal HBM peak."""
@@ -286,6 +310,7 @@ def main():
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--ch-steps", type=int, default=100)
     ap.add_argument("--no-ch", action="store_true")
+    ap.add_argument("--no-local", action="store_true")
     ap.add_argument("--only-ch", action="store_true",
                     help="run only the Cahn-Hilliard measurement (profiling runs)")
     ap.add_argument("--only-large", action="store_true",
@@ -331,6 +356,8 @@ def main():
             out["large_grid_fp64"] = measure_large(args, torch, W, Sim, "f64")
     if not args.no_ch and not args.only_large:
         out["cahn_hilliard"] = measure_ch(args, torch, W, Sim)
+    if not args.no_local and not args.only_large:
+        out["local_gradient"] = measure_local(args, torch, W, Sim)
     if not args.no_batched and not args.only_large:
         out["batched"] = measure_batched(args, torch, W, Sim, BatchSim)
     if not args.no_adjoint and not args.only_large:

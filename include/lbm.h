@@ -80,6 +80,19 @@ typedef enum {
                                  zero normal derivative at walls; batches and the reverse mode are AC only */
 } lbm_phase_eq;
 
+typedef enum {
+    LBM_GRAD_STENCIL = 0,     /* grad phi by the isotropic central scheme (Eq. central1) */
+    LBM_GRAD_LOCAL = 1        /* grad phi from the first moment of f by the local scheme of Eq. local
+                                 (Allen-Cahn only; level 0 and lap phi keep the stencils).  u depends on
+                                 grad phi through F_s = mu_phi grad phi, which folds into the scheme's
+                                 coefficient: C0 = sum_i c_i f_i - phi u0/2 - (phi u)^{n-1}/2 = A' grad phi
+                                 + B n with A' = -M_phi - cs^2/2 + phi mu_phi/(4 rho), B = M_phi lambda,
+                                 u0 the velocity without F_s; |grad phi| = (|C0| + B)/(-A') clamped at 0.
+                                 The history then holds m^phiC of the previous level too (22 planes per
+                                 copy instead of 20).  lbm_init, lbm_step and lbm_moments only: the other
+                                 calls return LBM_E_UNSUPPORTED */
+} lbm_grad;
+
 /* Problem statement in the paper's notation (Sec. 2; Sec. 4 preamble). */
 typedef struct lbm_params {
     int32_t nx, ny;                 /* lattice nodes */
@@ -88,6 +101,8 @@ typedef struct lbm_params {
     int32_t visc_law;               /* lbm_visc */
     int32_t model;                  /* lbm_model */
     int32_t phase_eq;               /* lbm_phase_eq: phase-field equation */
+    int32_t grad_scheme;            /* lbm_grad: scheme of grad phi */
+    int32_t reserved;               /* must be 0 */
     double phi_A, phi_B;            /* order parameter of the two bulk phases, phi_A > phi_B */
     double rho_A, rho_B;            /* densities (Eq. rho-phi) */
     double nu_A, nu_B;              /* kinematic viscosities; mu = rho nu */

@@ -514,6 +514,9 @@ static void ch_flux(orc_sim *s, const double *mu, double *mx, double *my) {
  *   A' = A + phi mu_phi / (4 rho),
  * whence |grad phi| = (|C0| + B) / (-A') (clamped at 0) and
  * grad phi = -|grad phi| C0 / |C0| (n points against C0, A' being negative).
+ * Where grad phi vanishes the direction C0 / |C0| is undefined, as n is in the
+ * stencil scheme; it is regularised with the same eps_n:
+ * C0 / sqrt(|C0|^2 + (A' eps_n)^2), |C0| = |A'| |grad phi| in the bulk.
  * mu_phi takes lap phi from Eq. central2.  Overwrites s->gx, s->gy. */
 static void local_gradient(orc_sim *s) {
     const orc_params *p = &s->P;
@@ -537,9 +540,10 @@ static void local_gradient(orc_sim *s) {
         double B = p->M * c.lam;
         double cn = sqrt(cx * cx + cy * cy);
         double mag = (cn + B) / (-Ap);
-        if (cn > 0 && mag > 0) {
-            s->gx[k] = -mag * cx / cn;
-            s->gy[k] = -mag * cy / cn;
+        if (mag > 0) {
+            double inv = 1.0 / sqrt(cn * cn + Ap * Ap * p->eps * p->eps);
+            s->gx[k] = -mag * cx * inv;
+            s->gy[k] = -mag * cy * inv;
         } else {
             s->gx[k] = 0.0;
             s->gy[k] = 0.0;

@@ -25,6 +25,7 @@ class LbmParams(ctypes.Structure):
         ("dtype", ctypes.c_int32),
         ("bc_x", ctypes.c_int32), ("bc_y", ctypes.c_int32),
         ("visc_law", ctypes.c_int32), ("model", ctypes.c_int32), ("phase_eq", ctypes.c_int32),
+        ("grad_scheme", ctypes.c_int32), ("reserved", ctypes.c_int32),
         ("phi_A", ctypes.c_double), ("phi_B", ctypes.c_double),
         ("rho_A", ctypes.c_double), ("rho_B", ctypes.c_double),
         ("nu_A", ctypes.c_double), ("nu_B", ctypes.c_double),

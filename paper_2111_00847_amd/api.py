@@ -28,6 +28,7 @@ def make_params(case) -> LbmParams:
     p.visc_law = _VISC[case.visc_law]
     p.model = _MODEL.get(case.model, 99)
     p.phase_eq = {"allen_cahn": 0, "cahn_hilliard": 1}.get(case.phase_eq, 99)
+    p.grad_scheme = {"stencil": 0, "local": 1}.get(getattr(case, "grad_scheme", "stencil"), 99)
     p.phi_A, p.phi_B = case.phiA, case.phiB
     p.rho_A, p.rho_B = case.rhoA, case.rhoB
     p.nu_A, p.nu_B = case.nuA, case.nuB

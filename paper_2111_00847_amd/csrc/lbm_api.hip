@@ -18,7 +18,7 @@ static size_t elem_size(int dtype) { return dtype == LBM_F64 ? 8 : 4; }
 size_t diag_blocks(const lbm_params* p) { return (size_t)((p->nx + 63) / 64) * ((p->ny + 7) / 8); }
 
 Layout layout_of(const lbm_params* p) {
-    return make_layout(p->nx, p->ny, elem_size(p->dtype), diag_blocks(p));
+    return make_layout(p->nx, p->ny, elem_size(p->dtype), diag_blocks(p), p->grad_scheme == LBM_GRAD_LOCAL ? 5 : 3);
 }
 
 int validate(const lbm_params* p) {
@@ -32,6 +32,9 @@ int validate(const lbm_params* p) {
     if (p->bc_y == LBM_WALLS && p->ny < 2) return LBM_E_SIZE;
     if (p->visc_law != LBM_VISC_LINEAR_MU && p->visc_law != LBM_VISC_INVERSE_NU) return LBM_E_PARAM;
     if (p->phase_eq != LBM_ALLEN_CAHN && p->phase_eq != LBM_CAHN_HILLIARD) return LBM_E_PARAM;
+    if (p->reserved != 0) return LBM_E_PARAM;
+    if (p->grad_scheme != LBM_GRAD_STENCIL && p->grad_scheme != LBM_GRAD_LOCAL) return LBM_E_PARAM;
+    if (p->grad_scheme == LBM_GRAD_LOCAL && p->phase_eq != LBM_ALLEN_CAHN) return LBM_E_UNSUPPORTED;
     if (p->model != LBM_MODEL_PRESENT && p->model != LBM_MODEL_ORIGINAL &&
         !(p->model == LBM_MODEL_CORRECTED && p->phase_eq == LBM_CAHN_HILLIARD))
         return LBM_E_UNSUPPORTED;
@@ -66,6 +69,7 @@ KParams<T> resolve(const lbm_params* p, const Layout& L) {
     K.visc_law = p->visc_law;
     K.model = p->model;
     K.pf = p->phase_eq;
+    K.grad = p->grad_scheme;
     K.plane = L.plane;
     const double dphi = p->phi_A - p->phi_B;
     // Sec. 2: beta = 12 sigma / (W dphi^4), k = 3 sigma W / (2 dphi^2), sqrt(2 beta / k) = 4 / (W dphi)
@@ -81,6 +85,8 @@ KParams<T> resolve(const lbm_params* p, const Layout& L) {
     K.drho = (T)drho;
     K.rhoB = (T)p->rho_B;
     K.drhoM = (T)(drho * p->M_phi);
+    K.Mphi = (T)p->M_phi;
+    K.Aloc = (T)(-p->M_phi - 0.5 / 3.0);
     K.inv_dphi = (T)(1.0 / dphi);
     K.muA = (T)(p->rho_A * p->nu_A);
     K.muB = (T)(p->rho_B * p->nu_B);
@@ -316,6 +322,7 @@ int lbm_moments(const lbm_params* p, const void* state, void* phi, void* u, void
 int lbm_diagnostics(const lbm_params* p, const void* state, double* out, void* stream) {
     int rc = validate(p);
     if (rc) return rc;
+    if (p->grad_scheme == LBM_GRAD_LOCAL) return LBM_E_UNSUPPORTED;
     if (!state || !out) return LBM_E_NULL;
     Layout L = layout_of(p);
     hipStream_t s = (hipStream_t)stream;
@@ -332,6 +339,7 @@ int lbm_export_state(const lbm_params* p, const void* state, void* f, void* g, v
                      void* stream) {
     int rc = validate(p);
     if (rc) return rc;
+    if (p->grad_scheme == LBM_GRAD_LOCAL) return LBM_E_UNSUPPORTED;
     if (!state) return LBM_E_NULL;
     Layout L = layout_of(p);
     hipStream_t s = (hipStream_t)stream;
@@ -357,6 +365,7 @@ int lbm_import_state(const lbm_params* p, void* state, const void* f, const void
                      int64_t step, void* stream) {
     int rc = validate(p);
     if (rc) return rc;
+    if (p->grad_scheme == LBM_GRAD_LOCAL) return LBM_E_UNSUPPORTED;
     if (!state || !f || !g) return LBM_E_NULL;
     if (step < 0) return LBM_E_SIZE;
     if (step > 0 && !hist) return LBM_E_NULL;

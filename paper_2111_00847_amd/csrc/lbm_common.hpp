@@ -48,12 +48,14 @@ struct KParams {
     int visc_law, model;
     int snu_local;        // s_g^7 = s_g^8 follow nu(phi)
     int pf;               // phase-field equation: 0 Allen-Cahn, 1 Cahn-Hilliard
+    int grad;             // grad phi: 0 stencil (Eq. central1), 1 local scheme (Eq. local)
     long long plane;      // elements between two population planes
     T phiA, phiB, phim;   // phim = (phiA + phiB) / 2
     T beta4, kap;         // 4 beta, k (Sec. 2)
     T lamc;               // sqrt(2 beta / k) = 4 / (W dphi)
     T drho, rhoB;         // drho/dphi, rho_B
     T drhoM;              // drho/dphi * M_phi
+    T Mphi, Aloc;         // M_phi; -M_phi - cs^2/2 (the local scheme's A)
     T inv_dphi;
     T muA, muB;           // linear-mu law
     T inv_nuA, inv_nuB;   // inverse-nu law
@@ -69,13 +71,14 @@ struct KParams {
 // whatever the element type T: after each collision it is set to phi minus
 // the eight moving populations in double precision, so the total of phi is
 // conserved to double rounding even when the moving populations are FP32.
-// Planes: f0 (double) | f_1..f_8 | g_0..g_8 | hist phi, u, v (previous level).
+// Planes: f0 (double) | f_1..f_8 | g_0..g_8 | hist phi, u, v (previous level)
+// [| m^phiC_x, m^phiC_y of the previous level, local gradient scheme].
 template <typename T>
 struct Copy {
     double* f0;
     T* f;   // f + i * plane is plane i, i = 1..8 (the pointer sits one plane before f_1)
     T* g;   // g + i * plane, i = 0..8
-    T* h;   // h + j * plane, j = 0..2
+    T* h;   // h + j * plane, j = 0..2 (0..4 for the local gradient scheme)
 };
 
 template <typename T>
@@ -94,7 +97,7 @@ struct Layout {
     long long n;          // nodes
     long long plane;      // padded plane length (elements)
     size_t esz;           // element size
-    size_t buf_bytes;     // one ping-pong copy: f0 (FP64), f[1..8], g[9], hist[3] planes
+    size_t buf_bytes;     // one ping-pong copy: f0 (FP64), f[1..8], g[9], hist[3 or 5] planes
     size_t off_buf[2];
     size_t off_stamp;     // int64 level stamps, ceil(nx / 64) * ny of them
     size_t nstamp;
@@ -103,12 +106,13 @@ struct Layout {
     size_t total;
 };
 
-inline Layout make_layout(int nx, int ny, size_t esz, size_t diag_blocks) {
+// nh: history planes (3: phi, u, v; 5 with m^phiC for the local gradient scheme).
+inline Layout make_layout(int nx, int ny, size_t esz, size_t diag_blocks, int nh = 3) {
     Layout L;
     L.n = (long long)nx * ny;
     L.plane = (L.n + 63) / 64 * 64;
     L.esz = esz;
-    L.buf_bytes = (size_t)8 * L.plane + (size_t)20 * L.plane * esz;
+    L.buf_bytes = (size_t)8 * L.plane + (size_t)(17 + nh) * L.plane * esz;
     L.off_buf[0] = HDR_BYTES;
     L.off_buf[1] = L.off_buf[0] + L.buf_bytes;
     L.off_stamp = L.off_buf[1] + L.buf_bytes;

@@ -98,12 +98,48 @@ __device__ __forceinline__ void mass_flux(const KParams<T>& P, T phi, T gx, T gy
     T lam = P.lamc * (P.phiA - phi) * (phi - P.phiB);
     lnx = lam * gx * inv;
     lny = lam * gy * inv;
-    if (P.model == 1) {
+    if (P.model != 0) {
         mx = T(0);
         my = T(0);
     } else {
         mx = -P.drhoM * (gx - lnx);
         my = -P.drhoM * (gy - lny);
+    }
+}
+
+// grad phi of one node by the local scheme of Eq. local (Allen-Cahn, levels >= 1):
+// C = sum_i c_i f_i - phi u + d_t(phi u)/2 = A grad phi + B n with A = -M - cs^2/2,
+// B = M lambda.  u = u0 + mu_phi grad phi / (2 rho) (Eq. comU, u0 without F_s) and
+// d_t(phi u) = phi u - (phi u)^{n-1}, so C0 = sum_i c_i f_i - phi u0/2 - (phi u)^{n-1}/2
+// = A' grad phi + B n with A' = A + phi mu_phi/(4 rho): |grad phi| = (|C0| + B)/(-A')
+// (clamped at 0) along -C0, the direction regularised as n is: C0 / sqrt(|C0|^2 +
+// (A' eps_n)^2).  lap: Eq. central2 of phi; (phu_prev, phv_prev) = (phi u)^{n-1}.
+template <typename T>
+__device__ __forceinline__ void local_grad(const KParams<T>& P, const T* f, const T* g, T phi, T lap, T phu_prev,
+                                           T phv_prev, T& gx, T& gy) {
+    const T t = phi - P.phiB;
+    const T rho = P.drho * t + P.rhoB;
+    const T mu = P.beta4 * (phi - P.phiA) * t * (phi - P.phim) - P.kap * lap;
+    const T lam = P.lamc * (P.phiA - phi) * t;
+    const T irho = rcp(rho);
+    const T jgx = (g[1] - g[3]) + (g[5] - g[6]) + (g[8] - g[7]);
+    const T jgy = (g[2] - g[4]) + (g[5] + g[6]) - (g[7] + g[8]);
+    const T u0 = (jgx + T(0.5) * (P.Gx + (rho - P.rho_ref) * P.gx)) * irho;
+    const T v0 = (jgy + T(0.5) * (P.Gy + (rho - P.rho_ref) * P.gy)) * irho;
+    const T jfx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
+    const T jfy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
+    const T cx = jfx - T(0.5) * phi * u0 - T(0.5) * phu_prev;
+    const T cy = jfy - T(0.5) * phi * v0 - T(0.5) * phv_prev;
+    const T ap = P.Aloc + T(0.25) * phi * mu * irho;
+    const T cn2 = cx * cx + cy * cy;
+    const T mag = div_(sqrt(cn2) + P.Mphi * lam, -ap);
+    if (mag > T(0)) {
+        const T s = mag * rsqrt_(cn2 + ap * ap * P.eps2);
+        gx = -s * cx;
+        gy = -s * cy;
+    } else {
+        gx = T(0);
+        gy = T(0);
     }
 }
 
@@ -139,7 +175,9 @@ __device__ __forceinline__ void mass_flux_ch(const KParams<T>& P, T gmx, T gmy, 
 // up, vp): phi, grad phi and u of the previous level.  CH: the Cahn-Hilliard
 // flux from grad mu (gmx, gmy) and grad mu of the previous level (gmxp, gmyp);
 // lmu = lap mu for the corrected model's F_a.
-template <typename T, bool CH = false>
+// LOC (local gradient scheme): (gx, gy) come from local_grad and (gmxp, gmyp)
+// carry the stored m^phiC of the previous level.
+template <typename T, bool CH = false, bool LOC = false>
 __device__ __forceinline__ Macro<T> macro(const KParams<T>& P, const T* g, T phi, T gx, T gy, T lap,
                                           bool first, T php, T gxp, T gyp, T up, T vp, T gmx = T(0),
                                           T gmy = T(0), T gmxp = T(0), T gmyp = T(0), T lmu = T(0)) {
@@ -192,8 +230,14 @@ __device__ __forceinline__ Macro<T> macro(const KParams<T>& P, const T* g, T phi
         m.d0 = m.d1 = m.d2 = m.d3 = m.d4 = T(0);
     } else {
         T lpx, lpy, mpx, mpy;
-        if (CH) mass_flux_ch(P, gmxp, gmyp, mpx, mpy);
-        else mass_flux(P, php, gxp, gyp, lpx, lpy, mpx, mpy);
+        if (CH) {
+            mass_flux_ch(P, gmxp, gmyp, mpx, mpy);
+        } else if (LOC) {
+            mpx = gmxp;
+            mpy = gmyp;
+        } else {
+            mass_flux(P, php, gxp, gyp, lpx, lpy, mpx, mpy);
+        }
         m.d0 = phi * m.u - php * up;
         m.d1 = phi * m.v - php * vp;
         m.d2 = m.u * m.mx - up * mpx;

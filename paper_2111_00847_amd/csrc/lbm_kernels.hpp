@@ -20,6 +20,9 @@ hipError_t launch_import(const KParams<T>& P, char* state, const Layout& L, cons
 template <typename T>
 hipError_t launch_export(const KParams<T>& P, const char* state, const Layout& L, T* f, T* g, T* hist,
                          hipStream_t s);
+// the Allen-Cahn step / moments with the local gradient scheme (lbm_local.hip)
+template <typename T, int MODE>
+void launch_local(const KParams<T>& P, char* state, const Layout& L, hipStream_t s, T* phi, T* u, T* p);
 template <typename T>
 hipError_t launch_diagnostics(const KParams<T>& P, const char* state, const Layout& L, double* host_out,
                               hipStream_t s);

@@ -303,6 +303,7 @@ hipError_t launch_step(const KParams<T>& P, char* state, const Layout& L, int64_
     constexpr int T16 = sizeof(T) == 8 ? 8 : 16;   // FP64 tiles stop at 8 rows
     for (int64_t t = 0; t < nsteps; t++) {
         if (P.pf == 1) launch_ch<T, 0>(P, state, L, s, nullptr, nullptr, nullptr);
+        else if (P.grad == 1) launch_local<T, 0>(P, state, L, s, nullptr, nullptr, nullptr);
         else if (ty == 4) launch_tile<T, 4, 0>(P, state, L, s, nullptr, nullptr, nullptr);
         else if (ty == 8 || sizeof(T) == 8) {
             if (by == 8) launch_tile<T, 8, 0, 8>(P, state, L, s, nullptr, nullptr, nullptr);
@@ -319,6 +320,7 @@ template <typename T>
 hipError_t launch_moments(const KParams<T>& P, const char* state, const Layout& L, T* phi, T* u, T* p,
                           hipStream_t s) {
     if (P.pf == 1) launch_ch<T, 1>(P, const_cast<char*>(state), L, s, phi, u, p);
+    else if (P.grad == 1) launch_local<T, 1>(P, const_cast<char*>(state), L, s, phi, u, p);
     else launch_tile<T, 8, 1>(P, const_cast<char*>(state), L, s, phi, u, p);
     return hipGetLastError();
 }

@@ -27,10 +27,28 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(L, name), name
 
 
-def test_struct_size_matches_header():
-    """The ctypes mirror of lbm_params has the C layout (8 int32 + 45 doubles)."""
+def test_struct_layout_matches_header(tmp_path):
+    """The ctypes mirror of lbm_params has the layout the C compiler gives the
+    header's struct (size and the offset of every field)."""
+    import shutil
+    import subprocess
     from paper_2111_00847_amd._lib import LbmParams
-    assert ctypes.sizeof(LbmParams) == 8 * 4 + (10 + 18 + 2 + 2 + 1 + 4 + 2) * 8
+    assert ctypes.sizeof(LbmParams) == 10 * 4 + (10 + 18 + 2 + 2 + 1 + 4 + 2) * 8
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    names = [n for n, _ in LbmParams._fields_]
+    src = tmp_path / "layout.c"
+    src.write_text("#include <stdio.h>\n#include <stddef.h>\n#include \"lbm.h\"\nint main(void) {\n"
+                   + f'printf("%zu\\n", sizeof(lbm_params));\n'
+                   + "".join(f'printf("%zu\\n", offsetof(lbm_params, {n}));\n' for n in names)
+                   + "return 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", inc, str(src), "-o", str(exe)], check=True)
+    out = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    assert out[0] == ctypes.sizeof(LbmParams)
+    for n, off in zip(names, out[1:]):
+        assert getattr(LbmParams, n).offset == off, n
 
 
 def _params(**kw):
@@ -131,3 +149,31 @@ def test_corrected_model_is_cahn_hilliard_only():
     assert L.lbm_state_size(ctypes.byref(p), ctypes.byref(n)) == 0
     p = _params(dtype="f32", model="corrected")
     assert L.lbm_state_size(ctypes.byref(p), ctypes.byref(n)) == -8
+
+
+def test_local_gradient_scheme_options():
+    """The local gradient scheme (Eq. local) is an Allen-Cahn option with two more
+    history planes per copy; the calls it does not cover refuse it on the host."""
+    from paper_2111_00847_amd._lib import LbmParams, lib
+    L = lib()
+    n0, n1 = ctypes.c_size_t(), ctypes.c_size_t()
+    p0 = _params(dtype="f32")
+    p1 = _params(dtype="f32", grad_scheme="local")
+    assert L.lbm_state_size(ctypes.byref(p0), ctypes.byref(n0)) == 0
+    assert L.lbm_state_size(ctypes.byref(p1), ctypes.byref(n1)) == 0
+    plane = (p0.nx * p0.ny + 63) // 64 * 64
+    assert n1.value - n0.value == 2 * 2 * plane * 4          # two copies, two FP32 planes each
+    bad = _params(dtype="f32", grad_scheme="other")
+    assert L.lbm_state_size(ctypes.byref(bad), ctypes.byref(n0)) == -4
+    bad = _params(dtype="f32")
+    bad.reserved = 1
+    assert L.lbm_state_size(ctypes.byref(bad), ctypes.byref(n0)) == -4
+    ch = _params(dtype="f32", grad_scheme="local", phase_eq="cahn_hilliard", phiB=-1.0)
+    assert L.lbm_state_size(ctypes.byref(ch), ctypes.byref(n0)) == -8
+    out = (ctypes.c_double * 6)()
+    assert L.lbm_diagnostics(ctypes.byref(p1), None, out, None) == -8
+    assert L.lbm_export_state(ctypes.byref(p1), None, None, None, None, None, None) == -8
+    assert L.lbm_import_state(ctypes.byref(p1), None, None, None, None, 0, None) == -8
+    h = ctypes.c_void_p()
+    assert L.lbm_batch_create((LbmParams * 1)(p1), 1, 0, ctypes.byref(h)) == -8
+    assert L.lbm_tape_record(ctypes.byref(p1), ctypes.c_void_p(256), ctypes.c_void_p(256), 1, None) == -8
