@@ -320,7 +320,7 @@ def main():
                          "(a plain copy kernel of known size, to scale HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
+        print(f"bench.py: this benchmark runs on one GPU only (asked for --gpus {args.gpus}); "
               "a lattice is not sharded across GPUs here.", file=sys.stderr)
         sys.exit(2)
 
