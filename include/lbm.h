@@ -89,8 +89,8 @@ typedef enum {
                                  + B n with A' = -M_phi - cs^2/2 + phi mu_phi/(4 rho), B = M_phi lambda,
                                  u0 the velocity without F_s; |grad phi| = (|C0| + B)/(-A') clamped at 0.
                                  The history then holds m^phiC of the previous level too (22 planes per
-                                 copy instead of 20).  lbm_init, lbm_step and lbm_moments only: the other
-                                 calls return LBM_E_UNSUPPORTED */
+                                 copy instead of 20).  lbm_init, lbm_step, lbm_moments and lbm_diagnostics
+                                 only: the other calls return LBM_E_UNSUPPORTED */
 } lbm_grad;
 
 /* Problem statement in the paper's notation (Sec. 2; Sec. 4 preamble). */

@@ -322,7 +322,6 @@ int lbm_moments(const lbm_params* p, const void* state, void* phi, void* u, void
 int lbm_diagnostics(const lbm_params* p, const void* state, double* out, void* stream) {
     int rc = validate(p);
     if (rc) return rc;
-    if (p->grad_scheme == LBM_GRAD_LOCAL) return LBM_E_UNSUPPORTED;
     if (!state || !out) return LBM_E_NULL;
     Layout L = layout_of(p);
     hipStream_t s = (hipStream_t)stream;

@@ -107,12 +107,21 @@ __global__ __launch_bounds__(TX* BY) void k_diag1(KParams<T> P, const char* stat
         for (int i = 0; i < Q; i++) g[i] = pull(S.g, P, i, x, y);
         T gx, gy, lap, gxp = T(0), gyp = T(0), lp, php = sphp[ly + 1][lx + 1], up = T(0), vp = T(0);
         win_stencil<T, DTY>(sphi, lx + 1, ly + 1, gx, gy, lap);
+        const T phi = sphi[ly + 1][lx + 1];
         if (!first) {
-            win_stencil<T, DTY>(sphp, lx + 1, ly + 1, gxp, gyp, lp);
             up = S.h[P.plane + k];
             vp = S.h[2 * P.plane + k];
         }
-        Macro<T> M = macro(P, g, sphi[ly + 1][lx + 1], gx, gy, lap, first, php, gxp, gyp, up, vp);
+        if (P.grad == 1 && !first) {
+            // local gradient scheme: grad phi by Eq. local, m^phiC of the previous level stored
+            local_grad(P, f, g, phi, lap, php * up, php * vp, gx, gy);
+            const Macro<T> M = macro<T, false, true>(P, g, phi, gx, gy, lap, first, php, T(0), T(0), up, vp, T(0),
+                                                     T(0), S.h[3 * P.plane + k], S.h[4 * P.plane + k]);
+            diag_node(P, M, f, g, phid, first, php, k, scr, acc);
+            continue;
+        }
+        if (!first) win_stencil<T, DTY>(sphp, lx + 1, ly + 1, gxp, gyp, lp);
+        const Macro<T> M = macro(P, g, phi, gx, gy, lap, first, php, gxp, gyp, up, vp);
         diag_node(P, M, f, g, phid, first, php, k, scr, acc);
     }
     diag_finish<T>(acc, red, partials);

@@ -170,8 +170,6 @@ def test_local_gradient_scheme_options():
     assert L.lbm_state_size(ctypes.byref(bad), ctypes.byref(n0)) == -4
     ch = _params(dtype="f32", grad_scheme="local", phase_eq="cahn_hilliard", phiB=-1.0)
     assert L.lbm_state_size(ctypes.byref(ch), ctypes.byref(n0)) == -8
-    out = (ctypes.c_double * 6)()
-    assert L.lbm_diagnostics(ctypes.byref(p1), None, out, None) == -8
     assert L.lbm_export_state(ctypes.byref(p1), None, None, None, None, None, None) == -8
     assert L.lbm_import_state(ctypes.byref(p1), None, None, None, None, 0, None) == -8
     h = ctypes.c_void_p()

@@ -70,3 +70,31 @@ def test_local_scheme_full_size_rti_fp32_prefix():
     print(f"local rti 1024^2 fp32 100 steps: max|dphi|={dphi:.2e} max|du|/Umax={du:.2e} (Umax {umax:.2e})",
           flush=True)
     assert dphi <= 1e-5 and du <= 1e-4
+
+
+def test_local_scheme_diagnostics_fp64():
+    from paper_2111_00847_amd.sim import Sim
+    mk, phi_of, steps = CASES["square_droplet_70x37"]
+    case = mk("f64").replace(grad_scheme="local")
+    phi0 = phi_of(case)
+    dg = Sim(case).init(phi0).step(steps).diagnostics()
+    do = oracle.OracleSim(case).init(phi0).step(steps).diagnostics()
+    for key in ("sum_phi", "max_div", "Du_rms", "Sm_rms", "umax"):
+        print(f"local diagnostics {key}: GPU {dg[key]:.12e} oracle {do[key]:.12e}", flush=True)
+        assert abs(dg[key] - do[key]) <= 1e-8 * abs(do[key]) + 1e-16, key
+
+
+def test_local_scheme_graph_replay_equals_eager():
+    """lbm_step on a side stream replays captured graphs of 32 steps of the
+    local-scheme kernel; the moments equal those of eager launches bitwise."""
+    from paper_2111_00847_amd.sim import Sim
+    case, phi0 = W.rti(nx=128, ny=256)
+    case = case.replace(grad_scheme="local")
+    p0 = W.hydrostatic_pressure(case, phi0)
+    a = Sim(case).init(phi0, None, p0).step(101)
+    b = Sim(case, stream=torch.cuda.Stream()).init(phi0, None, p0)
+    b.step(70)
+    b.step(31)
+    torch.cuda.synchronize()
+    for x, y in zip(a.moments(), b.moments()):
+        assert torch.equal(x, y)
