@@ -88,20 +88,32 @@ def measured_traffic(nodes):
     return rec.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(budget_s=15.0):
+def cpu_baseline(budget_s=15.0, budget_1t_s=6.0):
+    """The FP64 oracle on the host's cores (all threads, then one thread), on a
+    bounded sample of the headline workload."""
     import oracle
     import workloads as W
     case, phi0 = W.rti()
-    s = oracle.OracleSim(case.replace(dtype="f64")).init(phi0, None, W.hydrostatic_pressure(case, phi0))
-    s.step(2)                       # first-touch of the oracle's fields
-    steps, t0 = 0, time.perf_counter()
-    while time.perf_counter() - t0 < budget_s:
-        s.step(5)
-        steps += 5
-    dt = time.perf_counter() - t0
-    mlups = case.nodes * steps / dt / 1e6
-    return {"value": round(mlups, 3), "unit": "MLUPS", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"FP64 oracle, rti 256x1024, {steps} steps after 2 untimed ({dt:.1f} s)"}
+    cores = oracle.num_threads()
+
+    def run(budget):
+        s = oracle.OracleSim(case.replace(dtype="f64")).init(phi0, None, W.hydrostatic_pressure(case, phi0))
+        s.step(2)                   # first-touch of the oracle's fields
+        steps, t0 = 0, time.perf_counter()
+        while time.perf_counter() - t0 < budget:
+            s.step(1)
+            steps += 1
+        dt = time.perf_counter() - t0
+        return case.nodes * steps / dt / 1e6, steps, dt
+
+    mlups, steps, dt = run(budget_s)
+    oracle.set_threads(1)
+    mlups1, steps1, dt1 = run(budget_1t_s)
+    oracle.set_threads(cores)
+    return {"value": round(mlups, 3), "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "single_thread_value": round(mlups1, 3),
+            "sample": f"FP64 oracle, rti 256x1024: {steps} steps on {cores} threads ({dt:.1f} s), "
+                      f"{steps1} steps on 1 thread ({dt1:.1f} s), each after 2 untimed"}
 
 
 def measure_main(args, torch, W, Sim):

@@ -75,6 +75,8 @@ def lib():
         L.orc_rates.argtypes = [ctypes.c_void_p, d, d]
         L.orc_stencils.argtypes = [ctypes.c_void_p, d, d, d, d]
         L.orc_grad.argtypes = [ctypes.c_void_p, d, d]
+        L.orc_set_threads.argtypes = [ctypes.c_int]
+        L.orc_set_threads.restype = None
         L.orc_lattice.argtypes = [P(ctypes.c_int), P(ctypes.c_int), d, d, d]
         L.orc_wetting.argtypes = [P(OrcParams), ctypes.c_double, ctypes.c_double,
                                   ctypes.c_double, d, d]
@@ -216,6 +218,11 @@ class OracleSim:
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads of the following oracle calls."""
+    lib().orc_set_threads(int(n))
 
 
 def lattice():

@@ -105,6 +105,10 @@ static int invert9(const double A[9][9], double R[9][9]) {
 
 int orc_num_threads(void) { return omp_get_max_threads(); }
 
+void orc_set_threads(int n) {
+    if (n > 0) omp_set_num_threads(n);
+}
+
 void orc_lattice(int cx[9], int cy[9], double w[9], double M[81], double Minv[81]) {
     double R[9][9];
     invert9(M1, R);

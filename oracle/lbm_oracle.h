@@ -71,6 +71,7 @@ int orc_rates(const orc_sim *s, double sf[9], double sg[9]);
 
 /* OpenMP threads the oracle's loops use. */
 int orc_num_threads(void);
+void orc_set_threads(int n);   /* OpenMP threads of the following calls (n > 0) */
 
 /* ---- building blocks exposed for the pins ---- */
 /* grad phi and lap phi of an arbitrary field with this lattice's ghost rule. */
