@@ -287,7 +287,7 @@ __global__ __launch_bounds__(TX* BY) void k_adj_local(KParams<T> P, const char* 
     }
 }
 
-// ---------------------------------------------------------------- adjoint step, kernel E
+// ---------------------------------------------------------------- wall-ghost helpers (kernel G)
 // Stencil weights of window offset (ex, ey): phi(x + e) enters grad_x phi,
 // grad_y phi and lap phi at x with these coefficients (App. C).
 template <typename T>
@@ -365,8 +365,8 @@ __device__ T xghost_adjoint(const KParams<T>& P, const AdjView<T>& V, int lev, c
 // One 64 x 4 tile per workgroup.  The stencil adjoints of the tile and its
 // one-node ring are staged in LDS (periodic axes wrap; positions beyond a wall
 // hold no node and contribute nothing); every node gathers the nine
-// transposed stencil terms.  The ghost routing of wall nodes follows in
-// kernel W.
+// transposed stencil terms, and wall nodes add what kernel G routed to them
+// from the ghosts (edge arrays).
 template <typename T>
 __global__ __launch_bounds__(TX* BY) void k_adj_gather(KParams<T> P, const char* tape, int j, AdjView<T> V) {
     constexpr int WX = TX + 2, WY = ATY + 2;
