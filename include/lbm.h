@@ -69,9 +69,12 @@ typedef enum {
     LBM_MODEL_PRESENT = 0,    /* consistent mass flux m^CC (the paper's model) */
     LBM_MODEL_ORIGINAL = 1,   /* mass flux rho u only (m^phiC = 0 in the flow model; Sec. 4 preamble) */
     LBM_MODEL_CORRECTED = 2   /* mass flux rho u plus the interface force F_a = (drho/dphi) u div(M_phi D)
-                                 (Sec. 4 preamble; App. A, Eq. NS2-add); Cahn-Hilliard only, where
-                                 div(M_phi D) = M_phi lap mu_phi (Eq. central2); u solves Eq. comU with
-                                 F = F_0 + F_a exactly.  Allen-Cahn params: LBM_E_UNSUPPORTED */
+                                 (Sec. 4 preamble; App. A, Eq. NS2-add); u solves Eq. comU with
+                                 F = F_0 + F_a exactly.  Cahn-Hilliard: div(M_phi D) = M_phi lap mu_phi
+                                 (Eq. central2).  Allen-Cahn: div D of D = grad phi - lambda n by Eq.
+                                 central1, a wall mirroring D with its normal component reversed.
+                                 Not with the local gradient scheme, batches or the reverse mode
+                                 (LBM_E_UNSUPPORTED) */
 } lbm_model;
 
 typedef enum {

@@ -69,7 +69,9 @@ struct orc_sim {
     double *rho, *mu, *lam, *nxv, *nyv, *mx, *my, *Fx, *Fy, *snu;
     double *ux, *uy, *pr, *P5, *dP5;
     double *muext;      /* (nx+2) x (ny+2) mu with its ghost layer (Cahn-Hilliard) */
-    double *fa;         /* [n] corrected model: F_a = fa u (Cahn-Hilliard) */
+    double *fa;         /* [n] corrected model: F_a = fa u */
+    double *dxv, *dyv;  /* [n] corrected AC model: D = grad phi - lambda n */
+    double *dext;       /* (nx+2) x (ny+2) second extended field (corrected AC model) */
 };
 
 /* ------------------------------------------------------------------ */
@@ -139,9 +141,9 @@ static int check_params(const orc_params *p) {
     if (!(p->W > 0 && p->sigma >= 0 && p->M >= 0)) return -4;
     if (p->eta != 1.0) return -4;
     if (p->pf != 0 && p->pf != 1) return -4;
-    if (p->model != 0 && p->model != 1 && !(p->model == 2 && p->pf == 1)) return -8;
+    if (p->model != 0 && p->model != 1 && p->model != 2) return -8;
     if (p->grad != 0 && p->grad != 1) return -4;
-    if (p->grad == 1 && p->pf != 0) return -8;
+    if (p->grad == 1 && (p->pf != 0 || p->model == 2)) return -8;
     if (p->visc_law != 0 && p->visc_law != 1) return -4;
     for (int i = 0; i < 9; i++)
         if (p->sf[i] >= 2.0 || p->sg[i] >= 2.0) return -5;
@@ -196,6 +198,9 @@ orc_sim *orc_create(const orc_params *p) {
     s->dP5 = calloc(5 * n, dz);
     s->muext = calloc((size_t)(p->nx + 2) * (p->ny + 2), dz);
     s->fa = calloc(n, dz);
+    s->dxv = calloc(n, dz);
+    s->dyv = calloc(n, dz);
+    s->dext = calloc((size_t)(p->nx + 2) * (p->ny + 2), dz);
     return s;
 }
 
@@ -203,7 +208,8 @@ void orc_destroy(orc_sim *s) {
     if (!s) return;
     double *bufs[] = {s->f, s->g, s->fs, s->gs, s->H, s->phi_prev, s->phi, s->ext, s->gx, s->gy,
                       s->lap, s->rho, s->mu, s->lam, s->nxv, s->nyv, s->mx, s->my, s->Fx, s->Fy,
-                      s->snu, s->ux, s->uy, s->pr, s->P5, s->dP5, s->muext, s->fa};
+                      s->snu, s->ux, s->uy, s->pr, s->P5, s->dP5, s->muext, s->fa,
+                      s->dxv, s->dyv, s->dext};
     for (size_t i = 0; i < sizeof(bufs) / sizeof(bufs[0]); i++) free(bufs[i]);
     free(s);
 }
@@ -299,11 +305,11 @@ int orc_stencils(const orc_sim *cs, const double *phi, double *gx, double *gy, d
     return 0;
 }
 
-/* Ghost layer of the chemical potential for the Cahn-Hilliard flux: periodic
- * axes wrap; at a wall the no-flux condition d mu / dn = 0 is imposed by
- * mirroring the first fluid node (x-walls first, then y-walls over the
- * extended rows, as for phi). */
-static void fill_ghosts_mirror(const orc_sim *s, const double *v, double *ext) {
+/* Ghost layer of a field mirrored at walls: periodic axes wrap; an x-wall
+ * ghost is sx times the first fluid node of its row, then a y-wall ghost is sy
+ * times the first fluid row over the extended columns (x-walls first, as for
+ * phi). */
+static void fill_ghosts_signed(const orc_sim *s, const double *v, double *ext, double sx, double sy) {
     int nx = s->nx, ny = s->ny, ex = nx + 2;
     for (int y = 0; y < ny; y++)
         for (int x = 0; x < nx; x++) ext[(y + 1) * ex + (x + 1)] = v[y * nx + x];
@@ -313,8 +319,8 @@ static void fill_ghosts_mirror(const orc_sim *s, const double *v, double *ext) {
             row[0] = row[nx];
             row[nx + 1] = row[1];
         } else {
-            row[0] = row[1];
-            row[nx + 1] = row[nx];
+            row[0] = sx * row[1];
+            row[nx + 1] = sx * row[nx];
         }
     }
     for (int X = 0; X < ex; X++) {
@@ -322,10 +328,18 @@ static void fill_ghosts_mirror(const orc_sim *s, const double *v, double *ext) {
             ext[X] = ext[ny * ex + X];
             ext[(ny + 1) * ex + X] = ext[1 * ex + X];
         } else {
-            ext[X] = ext[1 * ex + X];
-            ext[(ny + 1) * ex + X] = ext[ny * ex + X];
+            ext[X] = sy * ext[1 * ex + X];
+            ext[(ny + 1) * ex + X] = sy * ext[ny * ex + X];
         }
     }
+}
+
+/* Ghost layer of the chemical potential for the Cahn-Hilliard flux: periodic
+ * axes wrap; at a wall the no-flux condition d mu / dn = 0 is imposed by
+ * mirroring the first fluid node (x-walls first, then y-walls over the
+ * extended rows, as for phi). */
+static void fill_ghosts_mirror(const orc_sim *s, const double *v, double *ext) {
+    fill_ghosts_signed(s, v, ext, 1.0, 1.0);
 }
 
 /* Sec. 2 closure for one node (AC form of D(phi)). */
@@ -352,7 +366,7 @@ static closure_t closure(const orc_sim *s, double phi, double gx, double gy, dou
     /* m^phiC = -(drho/dphi) M D(phi), D = grad phi - lambda n */
     c.mx = -drho * p->M * (gx - c.lam * c.nx);
     c.my = -drho * p->M * (gy - c.lam * c.ny);
-    if (p->model == 1) c.mx = c.my = 0.0; /* original model: mass flux rho u only */
+    if (p->model != 0) c.mx = c.my = 0.0; /* original and corrected models: mass flux rho u only */
     /* F = F_s + external: F_s = mu_phi grad phi */
     c.Fx = c.mu_phi * gx + p->Gx + (c.rho - p->rho_ref) * p->gx;
     c.Fy = c.mu_phi * gy + p->Gy + (c.rho - p->rho_ref) * p->gy;
@@ -509,6 +523,27 @@ static void ch_flux(orc_sim *s, const double *mu, double *mx, double *my) {
     }
 }
 
+/* The corrected model's interface force with the AC phase field (App. A,
+ * Eq. NS2-add; Sec. 4 preamble): F_a = (drho/dphi) u div(M D), D = grad phi -
+ * lambda n with the closure's grad phi and n.  div D by Eq. central1 applied to
+ * each component, on a ghost layer in which a wall mirrors D of the first fluid
+ * node with its normal component reversed (no diffusive flux through the wall).
+ * Keeps the coefficient fa = (drho/dphi) M div D of u. */
+static void ac_corrected_force(orc_sim *s) {
+    const orc_params *p = &s->P;
+    long n = s->n;
+    for (long k = 0; k < n; k++) {
+        s->dxv[k] = s->gx[k] - s->lam[k] * s->nxv[k];
+        s->dyv[k] = s->gy[k] - s->lam[k] * s->nyv[k];
+    }
+    fill_ghosts_signed(s, s->dxv, s->muext, -1.0, 1.0);
+    fill_ghosts_signed(s, s->dyv, s->dext, 1.0, -1.0);
+    stencils(s, s->muext, s->dxv, NULL, NULL); /* d Dx / dx */
+    stencils(s, s->dext, NULL, s->dyv, NULL);  /* d Dy / dy */
+    double drho = (p->rhoA - p->rhoB) / (p->phiA - p->phiB);
+    for (long k = 0; k < n; k++) s->fa[k] = drho * p->M * (s->dxv[k] + s->dyv[k]);
+}
+
 /* The local scheme for grad phi of the AC model (Eq. local), levels >= 1:
  * with A = -M - cs^2/2, B = M lambda and C = sum_i c_i f_i - phi u + d_t(phi u)/2,
  * C = A grad phi + B n.  u depends on grad phi through F_s = mu_phi grad phi
@@ -586,6 +621,7 @@ static void macroscopic(orc_sim *s) {
             s->snu[k] = c.snu;
         }
     if (p->pf == 1) ch_flux(s, s->mu, s->mx, s->my);
+    else if (p->model == 2) ac_corrected_force(s);
     double drho = (p->rhoA - p->rhoB) / (p->phiA - p->phiB);
 #pragma omp parallel for
     for (int y = 0; y < ny; y++)

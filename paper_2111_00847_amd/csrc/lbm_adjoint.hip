@@ -48,11 +48,14 @@ void step_shape(const lbm_params* p, int* ty, int* by);
 template <typename T>
 KParams<T> resolve(const lbm_params* p, const Layout& L);
 
-// The reverse mode covers the Allen-Cahn step with the stencil gradient only.
+// The reverse mode covers the Allen-Cahn step with the stencil gradient (present and
+// original models) only.
 static int validate_ac(const lbm_params* p) {
     const int rc = validate(p);
     if (rc) return rc;
-    return p->phase_eq == LBM_ALLEN_CAHN && p->grad_scheme == LBM_GRAD_STENCIL ? LBM_OK : LBM_E_UNSUPPORTED;
+    return p->phase_eq == LBM_ALLEN_CAHN && p->grad_scheme == LBM_GRAD_STENCIL && p->model != LBM_MODEL_CORRECTED
+               ? LBM_OK
+               : LBM_E_UNSUPPORTED;
 }
 
 constexpr size_t ADJ_HDR = 256;

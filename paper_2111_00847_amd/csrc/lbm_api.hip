@@ -35,9 +35,9 @@ int validate(const lbm_params* p) {
     if (p->reserved != 0) return LBM_E_PARAM;
     if (p->grad_scheme != LBM_GRAD_STENCIL && p->grad_scheme != LBM_GRAD_LOCAL) return LBM_E_PARAM;
     if (p->grad_scheme == LBM_GRAD_LOCAL && p->phase_eq != LBM_ALLEN_CAHN) return LBM_E_UNSUPPORTED;
-    if (p->model != LBM_MODEL_PRESENT && p->model != LBM_MODEL_ORIGINAL &&
-        !(p->model == LBM_MODEL_CORRECTED && p->phase_eq == LBM_CAHN_HILLIARD))
+    if (p->model != LBM_MODEL_PRESENT && p->model != LBM_MODEL_ORIGINAL && p->model != LBM_MODEL_CORRECTED)
         return LBM_E_UNSUPPORTED;
+    if (p->model == LBM_MODEL_CORRECTED && p->grad_scheme == LBM_GRAD_LOCAL) return LBM_E_UNSUPPORTED;
     const double vals[] = {p->phi_A, p->phi_B, p->rho_A, p->rho_B, p->nu_A, p->nu_B, p->sigma, p->W,
                            p->M_phi, p->eta, p->body_force[0], p->body_force[1], p->gravity[0],
                            p->gravity[1], p->rho_ref, p->rho0, p->eps_n};

@@ -246,7 +246,9 @@ int lbm_batch_create(const lbm_params* cases, int32_t ncases, int32_t autotune, 
         if (rc) return rc;
         if (cases[c].dtype != cases[0].dtype) return LBM_E_DTYPE;
         // batches run the Allen-Cahn step with the stencil gradient
-        if (cases[c].phase_eq != LBM_ALLEN_CAHN || cases[c].grad_scheme != LBM_GRAD_STENCIL) return LBM_E_UNSUPPORTED;
+        if (cases[c].phase_eq != LBM_ALLEN_CAHN || cases[c].grad_scheme != LBM_GRAD_STENCIL ||
+            cases[c].model == LBM_MODEL_CORRECTED)
+            return LBM_E_UNSUPPORTED;
         Layout L = layout_of(&cases[c]);
         if (L.buf_bytes >= (size_t(1) << 32)) return LBM_E_SIZE;   // 32-bit offsets within a case
     }

@@ -8,6 +8,12 @@
 // first), mu on the one-node window, the ghosts of mu at walls by mirroring
 // the first fluid node (zero normal derivative: no diffusive flux through the
 // wall; x-walls first), and then hands every node's Macro to a functor.
+//
+// The same body serves the corrected comparison model with the Allen-Cahn phase
+// field (ACC): its interface force F_a = (drho/dphi) u div(M D) (App. A, Eq.
+// NS2-add) needs D = grad phi - lambda n on the one-node ring, hence phi on the
+// two-node ring.  D takes the place of mu (x component in `mu`, y in `mup`);
+// a wall mirrors D of the first fluid node with its normal component reversed.
 #pragma once
 
 #include "lbm_tile.hpp"
@@ -58,7 +64,7 @@ __device__ __forceinline__ void ch_fill(const KParams<T>& P, const Copy<T>& S, b
 // Thread (lx, ly) owns nodes (x0 + lx, y0 + ly + BY r), r < TY / BY: their f, g
 // and history are pulled first and kept in registers to the collision; the
 // two-node ring of the phi window is pulled afterwards by all threads.
-template <typename T, int TY, typename F>
+template <typename T, int TY, bool ACC = false, typename F>
 __device__ __forceinline__ void ch_tile(const KParams<T>& P, const Copy<T>& S, int64_t step, int x0, int y0,
                                         ChWindow<T, TY>& W, F&& per_node) {
     using Win = ChWindow<T, TY>;
@@ -136,13 +142,20 @@ __device__ __forceinline__ void ch_tile(const KParams<T>& P, const Copy<T>& S, i
         }
         __syncthreads();
     }
-    // 3. mu on the one-node window (nodes only)
+    // 3. mu (ACC: D) on the one-node window (nodes only)
     for (int idx = tid; idx < Win::MX * Win::MY; idx += TX * BY) {
         const int wy = idx / Win::MX, wx = idx - wy * Win::MX;
         int gx = x0 - 1 + wx, gy = y0 - 1 + wy;
         if (!ch_node(P, gx, gy, P.nx, P.ny)) continue;
         T gxx, gyy, lap;
         win_stencil_at(W.phi, wx + 1, wy + 1, gxx, gyy, lap);
+        if (ACC) {
+            T lnx, lny, mx, my;
+            mass_flux(P, W.phi[wy + 1][wx + 1], gxx, gyy, lnx, lny, mx, my);
+            W.mu[wy][wx] = gxx - lnx;
+            W.mup[wy][wx] = gyy - lny;
+            continue;
+        }
         W.mu[wy][wx] = chem_pot(P, W.phi[wy + 1][wx + 1], lap);
         if (!first) {
             win_stencil_at(W.php, wx + 1, wy + 1, gxx, gyy, lap);
@@ -150,19 +163,23 @@ __device__ __forceinline__ void ch_tile(const KParams<T>& P, const Copy<T>& S, i
         }
     }
     __syncthreads();
-    // 4. mu ghosts: mirror of the first fluid node, x-walls first
+    // 4. ghosts: mirror of the first fluid node, x-walls first (ACC: D with its
+    //    wall-normal component reversed)
+    const T sxx = ACC ? T(-1) : T(1);   // x-walls: factor of mu (ACC: of D_x); D_y keeps its sign
+    const T syy = ACC ? T(-1) : T(1);   // y-walls: factor of mu (ACC: of D_y); D_x keeps its sign
+    const bool second = ACC || !first;  // mup holds D_y (ACC) or the previous mu
     if (P.wall_x) {
         const int wr = P.nx - x0 + 1;   // mu-window column of x = nx
         for (int wy = tid; wy < Win::MY; wy += TX * BY) {
             const int gy = y0 - 1 + wy;
             if (gy > P.ny || (P.wall_y && (gy < 0 || gy >= P.ny))) continue;
             if (x0 == 0) {
-                W.mu[wy][0] = W.mu[wy][1];
-                if (!first) W.mup[wy][0] = W.mup[wy][1];
+                W.mu[wy][0] = sxx * W.mu[wy][1];
+                if (second) W.mup[wy][0] = W.mup[wy][1];
             }
             if (wr <= Win::MX - 1) {
-                W.mu[wy][wr] = W.mu[wy][wr - 1];
-                if (!first) W.mup[wy][wr] = W.mup[wy][wr - 1];
+                W.mu[wy][wr] = sxx * W.mu[wy][wr - 1];
+                if (second) W.mup[wy][wr] = W.mup[wy][wr - 1];
             }
         }
         __syncthreads();
@@ -174,11 +191,11 @@ __device__ __forceinline__ void ch_tile(const KParams<T>& P, const Copy<T>& S, i
             if (gx > P.nx) continue;
             if (y0 == 0) {
                 W.mu[0][wx] = W.mu[1][wx];
-                if (!first) W.mup[0][wx] = W.mup[1][wx];
+                if (second) W.mup[0][wx] = syy * W.mup[1][wx];
             }
             if (wt <= Win::MY - 1) {
                 W.mu[wt][wx] = W.mu[wt - 1][wx];
-                if (!first) W.mup[wt][wx] = W.mup[wt - 1][wx];
+                if (second) W.mup[wt][wx] = syy * W.mup[wt - 1][wx];
             }
         }
         __syncthreads();
@@ -193,6 +210,21 @@ __device__ __forceinline__ void ch_tile(const KParams<T>& P, const Copy<T>& S, i
         T gx, gy, lap, gmx, gmy, lm, gxp = T(0), gyp = T(0), lp, php = T(0), upr = T(0), vpr = T(0);
         T gmxp = T(0), gmyp = T(0), lmp;
         win_stencil_at(W.phi, lx + 2, ly + 2, gx, gy, lap);
+        if (ACC) {
+            // div D by Eq. central1: d D_x / dx + d D_y / dy
+            T ddx, ddy, t0, t1;
+            win_stencil_at(W.mu, lx + 1, ly + 1, ddx, t0, t1);
+            win_stencil_at(W.mup, lx + 1, ly + 1, t0, ddy, t1);
+            if (!first) {
+                php = W.php[ly + 2][lx + 2];
+                upr = up[r];
+                vpr = vp[r];
+            }
+            const Macro<T> M = macro<T>(P, g[r], W.phi[ly + 2][lx + 2], gx, gy, lap, first, php, T(0), T(0), upr,
+                                        vpr, T(0), T(0), T(0), T(0), ddx + ddy);
+            per_node(M, f[r], g[r], phid[r], x, y, k);
+            continue;
+        }
         win_stencil_at(W.mu, lx + 1, ly + 1, gmx, gmy, lm);
         if (!first) {
             win_stencil_at(W.php, lx + 2, ly + 2, gxp, gyp, lp);

@@ -173,8 +173,8 @@ __device__ __forceinline__ void mass_flux_ch(const KParams<T>& P, T gmx, T gmy, 
 // second way of Remark 1) of one node.  g: pulled populations; (gx, gy, lap):
 // stencils of phi; first: level 0 (time derivatives zero); (php, gxp, gyp,
 // up, vp): phi, grad phi and u of the previous level.  CH: the Cahn-Hilliard
-// flux from grad mu (gmx, gmy) and grad mu of the previous level (gmxp, gmyp);
-// lmu = lap mu for the corrected model's F_a.
+// flux from grad mu (gmx, gmy) and grad mu of the previous level (gmxp, gmyp).
+// Corrected model (model 2): lmu = div D (lap mu for CH), F_a = (drho/dphi) M lmu u.
 // LOC (local gradient scheme): (gx, gy) come from local_grad and (gmxp, gmyp)
 // carry the stored m^phiC of the previous level.
 template <typename T, bool CH = false, bool LOC = false>
@@ -212,8 +212,8 @@ __device__ __forceinline__ Macro<T> macro(const KParams<T>& P, const T* g, T phi
     }
     T jx = (g[1] - g[3]) + (g[5] - g[6]) + (g[8] - g[7]);
     T jy = (g[2] - g[4]) + (g[5] + g[6]) - (g[7] + g[8]);
-    if (CH && P.model == 2) {
-        // corrected model: F = F_0 + a u with a = (drho/dphi) M lap mu (App. A, Eq. NS2-add);
+    if (P.model == 2) {
+        // corrected model: F = F_0 + a u with a = (drho/dphi) M div D (App. A, Eq. NS2-add);
         // Eq. comU solved for u exactly
         const T a = P.drhoM * lmu;
         const T irho = rcp(m.rho - T(0.5) * a);

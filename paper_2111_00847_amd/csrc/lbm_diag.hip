@@ -127,9 +127,10 @@ __global__ __launch_bounds__(TX* BY) void k_diag1(KParams<T> P, const char* stat
     diag_finish<T>(acc, red, partials);
 }
 
-// Pass 1 of the Cahn-Hilliard variant: the same per-node quantities from the CH
-// tile body (m^phiC from grad mu).
-template <typename T>
+// Pass 1 of the Cahn-Hilliard variant (m^phiC from grad mu) and of the corrected
+// Allen-Cahn model (ACC: F_a from div D): the same per-node quantities from the
+// two-node-window tile body.
+template <typename T, bool ACC>
 __global__ __launch_bounds__(TX* BY) void k_diag1_ch(KParams<T> P, const char* state, size_t off0,
                                                      size_t off1, size_t off_stamp, T* scr, double* partials) {
     __shared__ ChWindow<T, DTY> W;
@@ -139,7 +140,7 @@ __global__ __launch_bounds__(TX* BY) void k_diag1_ch(KParams<T> P, const char* s
     const int cur = (int)(step & 1);
     const Copy<T> S = copy_at<T>(const_cast<char*>(state) + (cur ? off1 : off0), P.plane);
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    ch_tile<T, DTY>(P, S, step, blockIdx.x * TX, blockIdx.y * DTY, W,
+    ch_tile<T, DTY, ACC>(P, S, step, blockIdx.x * TX, blockIdx.y * DTY, W,
                     [&](const Macro<T>& M, T* f, T* g, double phid, int, int, long long k) {
                         // the previous phi of the node (for d_t rho) is the history plane
                         const T php = first ? M.phi : S.h[k];
@@ -219,7 +220,10 @@ hipError_t launch_diagnostics(const KParams<T>& P, const char* state, const Layo
     T* scr = reinterpret_cast<T*>(const_cast<char*>(state) + L.off_diag);
     double* partials = reinterpret_cast<double*>(const_cast<char*>(state) + L.off_diag + 3 * L.plane * L.esz);
     double* out = partials + L.diag_partials;
-    if (P.pf == 1) k_diag1_ch<T><<<grd, blk, 0, s>>>(P, state, L.off_buf[0], L.off_buf[1], L.off_stamp, scr, partials);
+    if (P.pf == 1)
+        k_diag1_ch<T, false><<<grd, blk, 0, s>>>(P, state, L.off_buf[0], L.off_buf[1], L.off_stamp, scr, partials);
+    else if (P.model == 2)
+        k_diag1_ch<T, true><<<grd, blk, 0, s>>>(P, state, L.off_buf[0], L.off_buf[1], L.off_stamp, scr, partials);
     else k_diag1<T><<<grd, blk, 0, s>>>(P, state, L.off_buf[0], L.off_buf[1], L.off_stamp, scr, partials);
     k_diag2<T><<<grd, blk, 0, s>>>(P, scr, partials);
     k_diag3<<<1, 64, 0, s>>>(partials, (int)(grd.x * grd.y), L.n, out);

@@ -39,10 +39,11 @@ void k_step(KParams<T> P, char* state, size_t off0, size_t off1, size_t off_stam
     step_tile<T, TY, MODE, OFF, NBY>(P, state, off0, off1, off_stamp, xt, yt, out_phi, out_u, out_p, sphi, sphp);
 }
 
-// The Cahn-Hilliard variant (lbm_ch.hpp): one 64 x TY tile per workgroup of
-// 64 x 4 threads, tiles dealt to the XCDs as for the Allen-Cahn step, the same
-// state layout, level stamps and non-temporal stores.  MODE 0: one time step;
-// MODE 1: phi, u, p of the current level.
+// The Cahn-Hilliard variant and the corrected comparison model with the
+// Allen-Cahn phase field (ACC), both on the two-node phi window of lbm_ch.hpp:
+// one 64 x TY tile per workgroup of 64 x 4 threads, tiles dealt to the XCDs as
+// for the Allen-Cahn step, the same state layout, level stamps and non-temporal
+// stores.  MODE 0: one time step; MODE 1: phi, u, p of the current level.
 // Tile rows (measured on MI355X, square droplet): 8 when that still gives >= 1024
 // tiles (+9% over 4 rows at 4096^2 FP32, +3% at 1024^2, equal in FP64), else 4
 // (+57% over 8 rows at 200^2, where the step is latency-bound); 16 rows lose
@@ -52,7 +53,7 @@ void k_step(KParams<T> P, char* state, size_t off0, size_t off1, size_t off_stam
 #define LBM_CH_TY 0
 #endif
 
-template <typename T, int TY, int MODE>
+template <typename T, int TY, int MODE, bool ACC>
 __global__ __launch_bounds__(TX* BY) void k_step_ch(KParams<T> P, char* state, size_t off0, size_t off1,
                                                    size_t off_stamp, int ntx, int nty, T* out_phi, T* out_u,
                                                    T* out_p) {
@@ -70,7 +71,7 @@ __global__ __launch_bounds__(TX* BY) void k_step_ch(KParams<T> P, char* state, s
     const int cur = (int)(step & 1);
     const Copy<T> S = copy_at<T>(state + (cur ? off1 : off0), P.plane);
     const Copy<T> D = copy_at<T>(state + (cur ? off0 : off1), P.plane);
-    ch_tile<T, TY>(P, S, step, x0, y0, W, [&](const Macro<T>& M, T* f, T* g, double phid, int, int, long long k) {
+    ch_tile<T, TY, ACC>(P, S, step, x0, y0, W, [&](const Macro<T>& M, T* f, T* g, double phid, int, int, long long k) {
         if (MODE == 1) {
             if (out_phi) out_phi[k] = M.phi;
             if (out_u) {
@@ -80,7 +81,7 @@ __global__ __launch_bounds__(TX* BY) void k_step_ch(KParams<T> P, char* state, s
             if (out_p) out_p[k] = M.p;
             return;
         }
-        const double f0n = collide_f<T, true>(P, M, f, phid);
+        const double f0n = collide_f<T, !ACC>(P, M, f, phid);
         collide_g(P, M, g);
         const long long pl = P.plane;
         st<double, long long>(reinterpret_cast<char*>(D.f0), 8 * k, f0n);
@@ -101,20 +102,27 @@ static int ch_rows(int nx, int ny) {
     return ntx * ((ny + 7) / 8) >= 1024 ? 8 : 4;
 }
 
-template <typename T, int MODE>
-static void launch_ch(const KParams<T>& P, char* state, const Layout& L, hipStream_t s, T* phi, T* u, T* p) {
+template <typename T, int MODE, bool ACC>
+static void launch_ch_acc(const KParams<T>& P, char* state, const Layout& L, hipStream_t s, T* phi, T* u, T* p) {
     const int ty = ch_rows(P.nx, P.ny);
     const int ntx = (P.nx + TX - 1) / TX, nty = (P.ny + ty - 1) / ty;
     const dim3 grd(ntx * nty), blk(TX, BY);
     if (ty == 16)
-        k_step_ch<T, 16, MODE><<<grd, blk, 0, s>>>(P, state, L.off_buf[0], L.off_buf[1], L.off_stamp, ntx, nty, phi,
-                                                   u, p);
+        k_step_ch<T, 16, MODE, ACC><<<grd, blk, 0, s>>>(P, state, L.off_buf[0], L.off_buf[1], L.off_stamp, ntx, nty,
+                                                        phi, u, p);
     else if (ty == 8)
-        k_step_ch<T, 8, MODE><<<grd, blk, 0, s>>>(P, state, L.off_buf[0], L.off_buf[1], L.off_stamp, ntx, nty, phi,
-                                                  u, p);
+        k_step_ch<T, 8, MODE, ACC><<<grd, blk, 0, s>>>(P, state, L.off_buf[0], L.off_buf[1], L.off_stamp, ntx, nty,
+                                                       phi, u, p);
     else
-        k_step_ch<T, 4, MODE><<<grd, blk, 0, s>>>(P, state, L.off_buf[0], L.off_buf[1], L.off_stamp, ntx, nty, phi,
-                                                  u, p);
+        k_step_ch<T, 4, MODE, ACC><<<grd, blk, 0, s>>>(P, state, L.off_buf[0], L.off_buf[1], L.off_stamp, ntx, nty,
+                                                       phi, u, p);
+}
+
+// CH (any model) or the corrected AC model: the two-node-window kernels.
+template <typename T, int MODE>
+static void launch_ch(const KParams<T>& P, char* state, const Layout& L, hipStream_t s, T* phi, T* u, T* p) {
+    if (P.pf == 1) launch_ch_acc<T, MODE, false>(P, state, L, s, phi, u, p);
+    else launch_ch_acc<T, MODE, true>(P, state, L, s, phi, u, p);
 }
 
 // ---------------------------------------------------------------- init / import / export
@@ -302,7 +310,7 @@ hipError_t launch_step(const KParams<T>& P, char* state, const Layout& L, int64_
                        int ty, int by) {
     constexpr int T16 = sizeof(T) == 8 ? 8 : 16;   // FP64 tiles stop at 8 rows
     for (int64_t t = 0; t < nsteps; t++) {
-        if (P.pf == 1) launch_ch<T, 0>(P, state, L, s, nullptr, nullptr, nullptr);
+        if (P.pf == 1 || P.model == 2) launch_ch<T, 0>(P, state, L, s, nullptr, nullptr, nullptr);
         else if (P.grad == 1) launch_local<T, 0>(P, state, L, s, nullptr, nullptr, nullptr);
         else if (ty == 4) launch_tile<T, 4, 0>(P, state, L, s, nullptr, nullptr, nullptr);
         else if (ty == 8 || sizeof(T) == 8) {
@@ -319,7 +327,7 @@ hipError_t launch_step(const KParams<T>& P, char* state, const Layout& L, int64_
 template <typename T>
 hipError_t launch_moments(const KParams<T>& P, const char* state, const Layout& L, T* phi, T* u, T* p,
                           hipStream_t s) {
-    if (P.pf == 1) launch_ch<T, 1>(P, const_cast<char*>(state), L, s, phi, u, p);
+    if (P.pf == 1 || P.model == 2) launch_ch<T, 1>(P, const_cast<char*>(state), L, s, phi, u, p);
     else if (P.grad == 1) launch_local<T, 1>(P, const_cast<char*>(state), L, s, phi, u, p);
     else launch_tile<T, 8, 1>(P, const_cast<char*>(state), L, s, phi, u, p);
     return hipGetLastError();

@@ -80,7 +80,7 @@ def test_state_size_layout():
     (dict(rhoA=0.0), -4), (dict(nuB=-1.0), -4), (dict(W=0.0), -4), (dict(eta=0.5), -4),
     (dict(phiA=0.0, phiB=1.0), -4), (dict(theta=(0.0, 1.0, 1.0, 1.0)), -4),
     (dict(s_g=(2.0,) + (0.0,) * 8), -5), (dict(s_f=(0.0,) * 3 + (2.5,) + (0.0,) * 5), -5),
-    (dict(sigma=float("nan")), -4), (dict(model="corrected"), -8), (dict(phase_eq="other"), -4),
+    (dict(sigma=float("nan")), -4), (dict(model="other"), -8), (dict(phase_eq="other"), -4),
 ])
 def test_parameter_validation(kw, code):
     rc, _ = _size(_params(**kw))
@@ -141,14 +141,21 @@ def test_cahn_hilliard_rejected_by_batches_and_reverse_mode():
     assert L.lbm_adjoint_run(ctypes.byref(p), ctypes.c_void_p(256), 0, 1, ctypes.c_void_p(256), None) == -8
 
 
-def test_corrected_model_is_cahn_hilliard_only():
-    from paper_2111_00847_amd._lib import lib
+def test_corrected_model_options():
+    """The corrected model runs with either phase field; not with the local
+    gradient scheme, in batches or in reverse mode."""
+    from paper_2111_00847_amd._lib import LbmParams, lib
     L = lib()
     n = ctypes.c_size_t()
     p = _params(dtype="f32", phase_eq="cahn_hilliard", phiB=-1.0, model="corrected")
     assert L.lbm_state_size(ctypes.byref(p), ctypes.byref(n)) == 0
     p = _params(dtype="f32", model="corrected")
-    assert L.lbm_state_size(ctypes.byref(p), ctypes.byref(n)) == -8
+    assert L.lbm_state_size(ctypes.byref(p), ctypes.byref(n)) == 0
+    q = _params(dtype="f32", model="corrected", grad_scheme="local")
+    assert L.lbm_state_size(ctypes.byref(q), ctypes.byref(n)) == -8
+    h = ctypes.c_void_p()
+    assert L.lbm_batch_create((LbmParams * 1)(p), 1, 0, ctypes.byref(h)) == -8
+    assert L.lbm_tape_record(ctypes.byref(p), ctypes.c_void_p(256), ctypes.c_void_p(256), 1, None) == -8
 
 
 def test_local_gradient_scheme_options():

@@ -142,7 +142,37 @@ def test_corrected_model_mass_source_equals_original():
     assert abs(out["corrected"] - out["original"]) <= 1e-3 * out["original"], out
 
 
-def test_corrected_model_is_cahn_hilliard_only():
-    case, phi0 = W.square_droplet(n=8, side=4.0)
-    with pytest.raises(Exception):
-        oracle.OracleSim(case.replace(model="corrected")).init(phi0)
+def test_corrected_model_allen_cahn_interface_force_closed_form():
+    """Corrected model with the AC phase field: F_a = (drho/dphi) u div(M D),
+    D = grad phi - lambda n.  On phi = 1/2 + A sin(kx) with a uniform V along y,
+    v = rho V / (rho - a/2) with a = (drho/dphi) M div D; where |phi'| >> eps_n,
+    div D = phi'' - lambda'(phi) |phi'| (n = sign(phi') along x), lambda =
+    (4/W)(1 - phi) phi, taken from the continuum derivatives (checked away from
+    the extrema of phi, where n flips).  Relative error 7.2e-3, 1.6e-3, 2.7e-4 at
+    64, 128, 256 nodes per wave (second order)."""
+    n, A = 128, 0.4
+    res = {}
+    for model in ("original", "corrected"):
+        case, _ = W.square_droplet(n=8, side=4.0)
+        case = case.replace(nx=n, ny=4, rhoA=10.0, rhoB=1.0, sigma=0.01, W=4.0, M=0.1, model=model)
+        X, _ = W.grid(case)
+        k = 2 * np.pi / n
+        phi0 = 0.5 + A * np.sin(k * X)
+        u0 = np.zeros((2,) + phi0.shape)
+        u0[1] = 1e-3
+        _, u, _ = oracle.OracleSim(case).init(phi0, u0).moments()
+        res[model] = u[1]
+    ph = 0.5 + A * np.sin(k * X)
+    d1 = A * k * np.cos(k * X)
+    d2 = -k * k * A * np.sin(k * X)
+    lam_p = (4.0 / case.W) * (1.0 - 2.0 * ph)
+    div_d = d2 - lam_p * np.abs(d1)
+    drho = case.rhoA - case.rhoB
+    rho = drho * ph + case.rhoB
+    a = drho * case.M * div_d
+    expect = rho / (rho - 0.5 * a) - 1.0
+    got = res["corrected"] / res["original"] - 1.0
+    far = np.abs(d1) > 0.5 * np.abs(d1).max()
+    np.testing.assert_allclose(res["original"], 1e-3, rtol=1e-12)
+    assert np.abs(expect[far]).max() > 1e-3
+    np.testing.assert_allclose(got[far], expect[far], rtol=0, atol=1e-2 * np.abs(expect[far]).max())
