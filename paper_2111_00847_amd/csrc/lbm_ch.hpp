@@ -220,8 +220,8 @@ __device__ __forceinline__ void ch_tile(const KParams<T>& P, const Copy<T>& S, i
                 upr = up[r];
                 vpr = vp[r];
             }
-            const Macro<T> M = macro<T>(P, g[r], W.phi[ly + 2][lx + 2], gx, gy, lap, first, php, T(0), T(0), upr,
-                                        vpr, T(0), T(0), T(0), T(0), ddx + ddy);
+            const Macro<T> M = macro<T, false, false, true>(P, g[r], W.phi[ly + 2][lx + 2], gx, gy, lap, first, php,
+                                                            T(0), T(0), upr, vpr, T(0), T(0), T(0), T(0), ddx + ddy);
             per_node(M, f[r], g[r], phid[r], x, y, k);
             continue;
         }
@@ -233,7 +233,7 @@ __device__ __forceinline__ void ch_tile(const KParams<T>& P, const Copy<T>& S, i
             upr = up[r];
             vpr = vp[r];
         }
-        const Macro<T> M = macro<T, true>(P, g[r], W.phi[ly + 2][lx + 2], gx, gy, lap, first, php, gxp, gyp, upr,
+        const Macro<T> M = macro<T, true, false, true>(P, g[r], W.phi[ly + 2][lx + 2], gx, gy, lap, first, php, gxp, gyp, upr,
                                           vpr, gmx, gmy, gmxp, gmyp, lm);
         per_node(M, f[r], g[r], phid[r], x, y, k);
     }

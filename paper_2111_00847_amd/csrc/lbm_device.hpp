@@ -176,8 +176,10 @@ __device__ __forceinline__ void mass_flux_ch(const KParams<T>& P, T gmx, T gmy, 
 // flux from grad mu (gmx, gmy) and grad mu of the previous level (gmxp, gmyp).
 // Corrected model (model 2): lmu = div D (lap mu for CH), F_a = (drho/dphi) M lmu u.
 // LOC (local gradient scheme): (gx, gy) come from local_grad and (gmxp, gmyp)
-// carry the stored m^phiC of the previous level.
-template <typename T, bool CH = false, bool LOC = false>
+// carry the stored m^phiC of the previous level.  CORR: the kernel may run the
+// corrected model (compiled out of the plain step, whose code then stays that
+// of the present and original models).
+template <typename T, bool CH = false, bool LOC = false, bool CORR = false>
 __device__ __forceinline__ Macro<T> macro(const KParams<T>& P, const T* g, T phi, T gx, T gy, T lap,
                                           bool first, T php, T gxp, T gyp, T up, T vp, T gmx = T(0),
                                           T gmy = T(0), T gmxp = T(0), T gmyp = T(0), T lmu = T(0)) {
@@ -212,7 +214,7 @@ __device__ __forceinline__ Macro<T> macro(const KParams<T>& P, const T* g, T phi
     }
     T jx = (g[1] - g[3]) + (g[5] - g[6]) + (g[8] - g[7]);
     T jy = (g[2] - g[4]) + (g[5] + g[6]) - (g[7] + g[8]);
-    if (P.model == 2) {
+    if (CORR && P.model == 2) {
         // corrected model: F = F_0 + a u with a = (drho/dphi) M div D (App. A, Eq. NS2-add);
         // Eq. comU solved for u exactly
         const T a = P.drhoM * lmu;

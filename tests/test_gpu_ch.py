@@ -255,3 +255,19 @@ def test_corrected_allen_cahn_dam_break_fp32():
     g = _sim()(case).init(phi0, None, p0).step(600)
     o = oracle.OracleSim(case.replace(dtype="f64")).init(phi0, None, p0).step(600)
     _compare(g, o, 1e-5, 1e-4, "AC corrected dam break 64x32 fp32")
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_ch_rayleigh_taylor(dtype):
+    """Sec. 4.4 runs the RTI with the Cahn-Hilliard phase field (phi in [-1, 1]):
+    the 64 x 256 copy of the set-up (walls in y, gravity, hydrostatic start),
+    1000 steps, against the oracle."""
+    case, phi01 = W.rti(nx=64, ny=256, dtype=dtype)
+    case, phi0 = W.to_cahn_hilliard(case, phi01)
+    p0 = W.hydrostatic_pressure(case, phi0)
+    g = _sim()(case).init(phi0, None, p0).step(1000)
+    o = oracle.OracleSim(case.replace(dtype="f64")).init(phi0, None, p0).step(1000)
+    if dtype == "f64":
+        _compare(g, o, 1e-10, 1e-9, "CH RTI 64x256 fp64")
+    else:
+        _compare(g, o, 1e-5, 1e-4, "CH RTI 64x256 fp32")
