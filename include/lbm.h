@@ -14,6 +14,9 @@
  * central2), explicit-Euler time derivatives (App. C), the pressure of
  * Eq. computP in the second way of Remark 1, half-way bounce-back and the
  * wetting boundary condition of Eq. Dwetting (Sec. 4.3).
+ * Options (lbm_params): the Cahn-Hilliard phase field (phase_eq), the original
+ * and corrected comparison models (model) and the local gradient scheme of
+ * Eq. local (grad_scheme); each entry point states which it covers.
  *
  * Conventions (all entry points):
  *  - Lattice units: dx = dt = c = 1, cs^2 = 1/3.
@@ -130,18 +133,22 @@ const char *lbm_status_string(int status);
 int lbm_state_size(const lbm_params *p, size_t *nbytes /* host */);
 
 /* Initial state f = f^eq(phi0, u0), g = g^eq(phi0, u0, p0) (equilibria of
- * Eq. MfMRAC1 and Eq. MgMF1 at the given fields; the Euler time derivatives
- * of the first step are zero).  phi0: [ny][nx]; u0: [2][ny][nx] or NULL
- * (zero); p0: [ny][nx] or NULL (zero). */
+ * Eq. MfMRAC1 -- Eq. MfMRCH1 for Cahn-Hilliard -- and Eq. MgMF1 at the given
+ * fields; the Euler time derivatives of the first step are zero).  phi0:
+ * [ny][nx]; u0: [2][ny][nx] or NULL (zero); p0: [ny][nx] or NULL (zero).
+ * Every option. */
 int lbm_init(const lbm_params *p, void *state, const void *phi0, const void *u0, const void *p0,
              void *stream);
 
 /* Advance nsteps >= 0 time steps (Sec. 3): moments, closure, both MRT
- * collisions and streaming with bounce-back, fused in one kernel per step. */
+ * collisions and streaming with bounce-back, fused in one kernel per step.
+ * On a non-NULL stream, runs of >= 64 steps replay a captured graph of 32
+ * steps (cached per params, state and stream).  Every option. */
 int lbm_step(const lbm_params *p, void *state, int64_t nsteps, void *stream);
 
 /* Order parameter, velocity (Eq. comU) and pressure (Eq. computP) of the
- * current time level.  phi, p: [ny][nx] or NULL; u: [2][ny][nx] or NULL. */
+ * current time level.  phi, p: [ny][nx] or NULL; u: [2][ny][nx] or NULL.
+ * Every option. */
 int lbm_moments(const lbm_params *p, const void *state, void *phi, void *u, void *pr,
                 void *stream);
 
@@ -150,19 +157,22 @@ int lbm_moments(const lbm_params *p, const void *state, void *phi, void *u, void
  *   out[4] max |u|, out[5] 1 if any population is NaN/Inf else 0,
  * with div u = tr S of Eq. strainRate and S_m = d_t rho + div m^CC, where
  * div m^phiC uses Eq. central1 (rms over nodes whose eight neighbours are
- * fluid).  Synchronises the stream.  Returns LBM_E_NONFINITE when out[5] = 1. */
+ * fluid).  Synchronises the stream.  Returns LBM_E_NONFINITE when out[5] = 1.
+ * Every option. */
 int lbm_diagnostics(const lbm_params *p, const void *state, double *out /* host [6] */,
                     void *stream);
 
 /* Post-streaming populations f^n, g^n ([9][ny][nx] each, either may be NULL),
  * phi and u of level n-1 (hist: [3][ny][nx] = phi, u, v; NULL to skip), and the
  * step index n (host int64, NULL to skip).  Synchronises the stream when step
- * is requested. */
+ * is requested.  Not with the local gradient scheme, whose history has five
+ * planes (LBM_E_UNSUPPORTED). */
 int lbm_export_state(const lbm_params *p, const void *state, void *f, void *g, void *hist,
                      int64_t *step, void *stream);
 
 /* Inverse of lbm_export_state: load post-streaming f^n, g^n and the level
- * n-1 history (ignored when n == 0) as the state of step n. */
+ * n-1 history (ignored when n == 0) as the state of step n.  Not with the local
+ * gradient scheme (LBM_E_UNSUPPORTED). */
 int lbm_import_state(const lbm_params *p, void *state, const void *f, const void *g,
                      const void *hist, int64_t step, void *stream);
 
@@ -182,8 +192,9 @@ int lbm_import_state(const lbm_params *p, void *state, const void *f, const void
  * are detected on the device; the step is skipped and lbm_adjoint_params then
  * returns LBM_E_PARAM.  Adjoint and tape buffers are caller-owned device
  * memory, 256-byte aligned, in the dtype of the params.  The reverse mode is
- * that of the Allen-Cahn step: every call below returns LBM_E_UNSUPPORTED for
- * Cahn-Hilliard params. */
+ * that of the Allen-Cahn step with the stencil gradient and the present or
+ * original model: every call below returns LBM_E_UNSUPPORTED for other
+ * params (Cahn-Hilliard, the local gradient scheme, the corrected model). */
 
 /* Bytes of a tape of `nlevels` consecutive levels. */
 int lbm_tape_size(const lbm_params *p, int32_t nlevels, size_t *nbytes /* host */);
@@ -224,8 +235,9 @@ int lbm_adjoint_import(const lbm_params *p, void *adj, const void *fbar, const v
 /* ---- batches: many independent lattices, one launch per time step ---------
  * (the per-step update above applied to every case; a case advanced in a
  * batch is bitwise identical to the same case advanced alone with lbm_step).
- * All cases share one dtype and use the Allen-Cahn phase field (Cahn-Hilliard
- * cases: LBM_E_UNSUPPORTED).  The plan is
+ * All cases share one dtype and use the Allen-Cahn phase field with the
+ * stencil gradient and the present or original model (other cases:
+ * LBM_E_UNSUPPORTED).  The plan is
  * library-owned (a small device table of the cases and, once lbm_batch_step
  * runs on a non-NULL stream with nsteps >= 32, a captured hipGraph of 32
  * steps for that state and stream). */
