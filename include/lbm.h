@@ -235,9 +235,11 @@ int lbm_adjoint_import(const lbm_params *p, void *adj, const void *fbar, const v
 /* ---- batches: many independent lattices, one launch per time step ---------
  * (the per-step update above applied to every case; a case advanced in a
  * batch is bitwise identical to the same case advanced alone with lbm_step).
- * All cases share one dtype and use the Allen-Cahn phase field with the
- * stencil gradient and the present or original model (other cases:
- * LBM_E_UNSUPPORTED).  The plan is
+ * All cases share one dtype; any phase field and model, the stencil gradient
+ * only (local-gradient cases: LBM_E_UNSUPPORTED).  Batches holding
+ * Cahn-Hilliard or corrected Allen-Cahn cases run 64 x 4-thread tiles of 4 or
+ * 8 rows; their two-node-window cases equal the lone runs to rounding (the
+ * tile height may differ), the others bitwise.  The plan is
  * library-owned (a small device table of the cases and, once lbm_batch_step
  * runs on a non-NULL stream with nsteps >= 32, a captured hipGraph of 32
  * steps for that state and stream). */

@@ -10,12 +10,16 @@
 // bitwise identical to the same case advanced alone.  The tile height and G
 // are picked per batch by timing the candidates on the batch itself (the
 // autotuner), and K steps are captured once into a hipGraph and replayed.
+// Batches that hold Cahn-Hilliard or corrected Allen-Cahn cases (the
+// two-node-window body of lbm_ch_step.hpp) run a second kernel whose LDS holds
+// either window; each item runs its case's body.
 #include <hip/hip_runtime.h>
 
 #include <cstring>
 #include <vector>
 
 #include "../../include/lbm.h"
+#include "lbm_ch_step.hpp"
 #include "lbm_fused.hpp"
 #include "lbm_kernels.hpp"
 
@@ -34,7 +38,7 @@ struct BatchCase {
     size_t off0, off1, off_stamp;
     int ntx, nty;
     int item_begin;              // first work item of this case
-    int pad;
+    int body;                    // 0: Allen-Cahn step; 1: Cahn-Hilliard; 2: corrected Allen-Cahn (ACC)
 };
 
 template <typename T, int TY, int NBY>
@@ -57,6 +61,41 @@ void k_step_batch(const BatchCase<T>* __restrict__ cases, int ncases, int nitems
     }
 }
 
+// Batches with two-node-window cases: 64 x 4 threads, the LDS holds either
+// window, each item runs its case's body.
+template <typename T, int TY>
+__global__ __launch_bounds__(TX* BY) void k_step_batch_wide(const BatchCase<T>* __restrict__ cases, int ncases,
+                                                            int nitems, char* batch_state) {
+    __shared__ union {
+        struct {
+            T sphi[TY + 2][TX + 3];
+            T sphp[TY + 2][TX + 3];
+        } ac;
+        ChWindow<T, TY> ch;
+    } lds;
+    for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
+        int lo = 0, hi = ncases - 1;   // last case with item_begin <= w
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (cases[mid].item_begin <= w) lo = mid;
+            else hi = mid - 1;
+        }
+        const BatchCase<T>& C = cases[lo];
+        const int local = w - C.item_begin;
+        char* st0 = batch_state + C.base;
+        if (C.body == 0)
+            step_tile<T, TY, 0, uint32_t, BY>(C.P, st0, C.off0, C.off1, C.off_stamp, local % C.ntx, local / C.ntx,
+                                              nullptr, nullptr, nullptr, lds.ac.sphi, lds.ac.sphp);
+        else if (C.body == 1)
+            ch_step_tile<T, TY, 0, false>(C.P, st0, C.off0, C.off1, C.off_stamp, local % C.ntx, local / C.ntx,
+                                          nullptr, nullptr, nullptr, lds.ch);
+        else
+            ch_step_tile<T, TY, 0, true>(C.P, st0, C.off0, C.off1, C.off_stamp, local % C.ntx, local / C.ntx, nullptr,
+                                         nullptr, nullptr, lds.ch);
+        __syncthreads();   // the next item reuses the LDS
+    }
+}
+
 }  // namespace lbm
 
 using namespace lbm;
@@ -73,6 +112,7 @@ struct lbm_batch {
     size_t total = 0;
     int autotune = 0;
     bool tuned = false;
+    bool wide = false;    // some case runs the two-node-window body (64 x 4 threads only)
     int ty = 8;
     int by = 4;           // thread rows per workgroup
     int grid = 0;
@@ -107,6 +147,7 @@ hipError_t upload_cases(lbm_batch* B, int ty) {
         C.off1 = B->layouts[c].off_buf[1];
         C.off_stamp = B->layouts[c].off_stamp;
         C.item_begin = items;
+        C.body = B->params[c].phase_eq == LBM_CAHN_HILLIARD ? 1 : (B->params[c].model == LBM_MODEL_CORRECTED ? 2 : 0);
         items += tiles_for(B->params[c], ty, &C.ntx, &C.nty);
     }
     B->nitems = items;
@@ -124,9 +165,21 @@ void batch_launch(lbm_batch* B, char* state, hipStream_t s) {
     k_step_batch<T, TY, NBY><<<g, dim3(TX, NBY), 0, s>>>(cases, B->ncases, B->nitems, state);
 }
 
+template <typename T, int TY>
+void batch_launch_wide(lbm_batch* B, char* state, hipStream_t s) {
+    const int g = B->grid > 0 ? B->grid : B->nitems;
+    const BatchCase<T>* cases = reinterpret_cast<const BatchCase<T>*>(B->d_cases);
+    k_step_batch_wide<T, TY><<<g, dim3(TX, BY), 0, s>>>(cases, B->ncases, B->nitems, state);
+}
+
 template <typename T>
 void launch_batch_once(lbm_batch* B, char* state, hipStream_t s) {
     constexpr int T16 = sizeof(T) == 8 ? 8 : 16;
+    if (B->wide) {
+        if (B->ty == 4) batch_launch_wide<T, 4>(B, state, s);
+        else batch_launch_wide<T, 8>(B, state, s);
+        return;
+    }
     if (B->ty == 4) batch_launch<T, 4, 4>(B, state, s);
     else if (B->ty == 8 || sizeof(T) == 8) {
         if (B->by == 8) batch_launch<T, 8, 8>(B, state, s);
@@ -197,6 +250,7 @@ int autotune_t(lbm_batch* B, char* state, const void* const* phi0, const void* c
     for (const auto& sh : shapes) {
         const int ty = sh[0];
         if (ty == 16 && sizeof(T) == 8) continue;
+        if (B->wide && (sh[1] != 4 || ty > 8)) continue;   // the two-node-window body: 64 x 4 threads
         B->ty = ty;
         B->by = sh[1];
         hipError_t e = upload_cases<T>(B, ty);
@@ -245,10 +299,8 @@ int lbm_batch_create(const lbm_params* cases, int32_t ncases, int32_t autotune, 
         int rc = validate(&cases[c]);
         if (rc) return rc;
         if (cases[c].dtype != cases[0].dtype) return LBM_E_DTYPE;
-        // batches run the Allen-Cahn step with the stencil gradient
-        if (cases[c].phase_eq != LBM_ALLEN_CAHN || cases[c].grad_scheme != LBM_GRAD_STENCIL ||
-            cases[c].model == LBM_MODEL_CORRECTED)
-            return LBM_E_UNSUPPORTED;
+        // the local gradient scheme has its own kernel and history layout
+        if (cases[c].grad_scheme != LBM_GRAD_STENCIL) return LBM_E_UNSUPPORTED;
         Layout L = layout_of(&cases[c]);
         if (L.buf_bytes >= (size_t(1) << 32)) return LBM_E_SIZE;   // 32-bit offsets within a case
     }
@@ -257,6 +309,8 @@ int lbm_batch_create(const lbm_params* cases, int32_t ncases, int32_t autotune, 
     B->dtype = cases[0].dtype;
     B->autotune = autotune;
     B->params.assign(cases, cases + ncases);
+    for (int c = 0; c < ncases; c++)
+        B->wide = B->wide || cases[c].phase_eq == LBM_CAHN_HILLIARD || cases[c].model == LBM_MODEL_CORRECTED;
     size_t off = 0;
     for (int c = 0; c < ncases; c++) {
         Layout L = layout_of(&cases[c]);

@@ -17,7 +17,7 @@
 // sums them into phi in LDS (the ring's pulls hit L2: those lines are the
 // neighbour tiles' own reads), fills wall ghosts, and then each thread runs
 // the per-node update for its nodes (lbm_fused.hpp).
-#include "lbm_ch.hpp"
+#include "lbm_ch_step.hpp"
 #include "lbm_fused.hpp"
 #include "lbm_kernels.hpp"
 
@@ -65,35 +65,7 @@ __global__ __launch_bounds__(TX* BY) void k_step_ch(KParams<T> P, char* state, s
         xt = blockIdx.x % ntx;
         yt = blockIdx.x / ntx;
     }
-    const int x0 = xt * TX, y0 = yt * TY;
-    int64_t* stamp = reinterpret_cast<int64_t*>(state + off_stamp) + (size_t)xt * P.ny + y0;
-    const int64_t step = stamp[0];
-    const int cur = (int)(step & 1);
-    const Copy<T> S = copy_at<T>(state + (cur ? off1 : off0), P.plane);
-    const Copy<T> D = copy_at<T>(state + (cur ? off0 : off1), P.plane);
-    ch_tile<T, TY, ACC>(P, S, step, x0, y0, W, [&](const Macro<T>& M, T* f, T* g, double phid, int, int, long long k) {
-        if (MODE == 1) {
-            if (out_phi) out_phi[k] = M.phi;
-            if (out_u) {
-                out_u[k] = M.u;
-                out_u[(long long)P.nx * P.ny + k] = M.v;
-            }
-            if (out_p) out_p[k] = M.p;
-            return;
-        }
-        const double f0n = collide_f<T, !ACC>(P, M, f, phid);
-        collide_g(P, M, g);
-        const long long pl = P.plane;
-        st<double, long long>(reinterpret_cast<char*>(D.f0), 8 * k, f0n);
-        for (int i = 1; i < Q; i++) st<T, long long>(reinterpret_cast<char*>(D.f), (long long)sizeof(T) * (i * pl + k), f[i]);
-        for (int i = 0; i < Q; i++) st<T, long long>(reinterpret_cast<char*>(D.g), (long long)sizeof(T) * (i * pl + k), g[i]);
-        st<T, long long>(reinterpret_cast<char*>(D.h), (long long)sizeof(T) * k, M.phi);
-        st<T, long long>(reinterpret_cast<char*>(D.h), (long long)sizeof(T) * (pl + k), M.u);
-        st<T, long long>(reinterpret_cast<char*>(D.h), (long long)sizeof(T) * (2 * pl + k), M.v);
-    });
-    // every wave read stamp[0] before the barriers of the tile body
-    const int tid = threadIdx.y * TX + threadIdx.x;
-    if (MODE == 0 && tid < TY && y0 + tid < P.ny) stamp[tid] = step + 1;
+    ch_step_tile<T, TY, MODE, ACC>(P, state, off0, off1, off_stamp, xt, yt, out_phi, out_u, out_p, W);
 }
 
 static int ch_rows(int nx, int ny) {

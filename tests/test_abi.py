@@ -127,23 +127,21 @@ def test_batch_create_validation():
     assert L.lbm_batch_destroy(None) == -1
 
 
-def test_cahn_hilliard_rejected_by_batches_and_reverse_mode():
-    """Batches and the adjoint run the Allen-Cahn step only: CH parameters are
-    refused on the host (before any HIP call)."""
+def test_cahn_hilliard_rejected_by_reverse_mode():
+    """The adjoint runs the Allen-Cahn step only: CH parameters are refused on
+    the host (before any HIP call)."""
     from paper_2111_00847_amd._lib import LbmParams, lib
     L = lib()
     p = _params(dtype="f32", phase_eq="cahn_hilliard", phiB=-1.0)
     n = ctypes.c_size_t()
     assert L.lbm_state_size(ctypes.byref(p), ctypes.byref(n)) == 0
-    h = ctypes.c_void_p()
-    assert L.lbm_batch_create((LbmParams * 1)(p), 1, 0, ctypes.byref(h)) == -8
     assert L.lbm_tape_record(ctypes.byref(p), ctypes.c_void_p(256), ctypes.c_void_p(256), 1, None) == -8
     assert L.lbm_adjoint_run(ctypes.byref(p), ctypes.c_void_p(256), 0, 1, ctypes.c_void_p(256), None) == -8
 
 
 def test_corrected_model_options():
     """The corrected model runs with either phase field; not with the local
-    gradient scheme, in batches or in reverse mode."""
+    gradient scheme or in reverse mode."""
     from paper_2111_00847_amd._lib import LbmParams, lib
     L = lib()
     n = ctypes.c_size_t()
@@ -153,8 +151,6 @@ def test_corrected_model_options():
     assert L.lbm_state_size(ctypes.byref(p), ctypes.byref(n)) == 0
     q = _params(dtype="f32", model="corrected", grad_scheme="local")
     assert L.lbm_state_size(ctypes.byref(q), ctypes.byref(n)) == -8
-    h = ctypes.c_void_p()
-    assert L.lbm_batch_create((LbmParams * 1)(p), 1, 0, ctypes.byref(h)) == -8
     assert L.lbm_tape_record(ctypes.byref(p), ctypes.c_void_p(256), ctypes.c_void_p(256), 1, None) == -8
 
 

@@ -112,3 +112,57 @@ def test_batch_case_view_rejects_bad_index():
     B = BatchSim([c for c, _ in cases])
     with pytest.raises(LbmError):
         B.case(2)
+
+
+def _wide_cases(dtype):
+    """A mix with two-node-window cases: Cahn-Hilliard droplets (one ragged, one
+    with walls) and a corrected Allen-Cahn dam break, beside plain Allen-Cahn cases."""
+    out = []
+    case, phi0 = W.spreading_case(128, 64, 40.0, dtype=dtype, R0=20.0)
+    out.append((case, phi0))
+    case, phi0 = W.square_droplet_ch(n=64, R=16.0, sigma=1e-3, rho_ratio=100.0, dtype=dtype)
+    out.append((case, phi0))
+    case = case.replace(nx=70, ny=37, wall_y=True, theta=(1.5708, 1.5708, 1.2, 2.0), name="ch_droplet_70x37_walls")
+    X, Y = W.grid(case)
+    out.append((case, W.tanh_profile(12.0 - np.hypot(X - 35.0, Y - 18.5), 4.0, 1.0, -1.0)))
+    case, phi0 = W.dam_break(nx=96, ny=40, column=24, dtype=dtype, theta_deg=70.0)
+    out.append((case.replace(model="corrected"), phi0))
+    out.append((case, phi0))
+    return out
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("mode", ["eager_default_stream", "autotuned_graph"])
+def test_wide_batch_bitwise_equals_single(dtype, mode):
+    """Cahn-Hilliard and corrected Allen-Cahn cases run the two-node-window body
+    inside the batch: Allen-Cahn cases equal the case advanced alone bitwise; the
+    two-node-window cases to a few units of rounding (the batch may run the body
+    at another tile height than the lone lattice, and the compiler contracts
+    the arithmetic of the two instantiations into FMAs differently: 1 ulp in
+    FP64 measured)."""
+    Sim, BatchSim = _mods()
+    cases = _wide_cases(dtype)
+    p0s = [W.hydrostatic_pressure(c, p) for c, p in cases]
+    stream = None if mode == "eager_default_stream" else torch.cuda.Stream()
+    B = BatchSim([c for c, _ in cases], autotune=(mode == "autotuned_graph"), stream=stream)
+    B.init([p for _, p in cases], p0s)
+    t = B.tuning()
+    print(f"wide batch {dtype} {mode}: tuning {t}", flush=True)
+    assert t["thread_rows"] == 4 and t["tile_rows"] in (4, 8)
+    steps = 75
+    B.step(steps)
+    for c, ((case, phi0), p0) in enumerate(zip(cases, p0s)):
+        alone = Sim(case).init(phi0, None, p0).step(steps)
+        torch.cuda.synchronize()
+        what = f"case {c} {case.name} {case.phase_eq} {case.model}"
+        if case.phase_eq == "allen_cahn" and case.model != "corrected":
+            _assert_same_state(B.case(c), alone, what)
+            continue
+        sa, sb = B.case(c).export_state(), alone.export_state()
+        assert sa["step"] == sb["step"], what
+        eps = np.finfo(np.float64 if dtype == "f64" else np.float32).eps
+        for key in ("f", "g", "hist"):
+            ta, tb = sa[key].cpu().numpy(), sb[key].cpu().numpy()
+            err = float(np.abs(ta - tb).max())
+            print(f"{what} {key}: max|diff| {err:.2e}", flush=True)
+            assert err <= 16 * eps * max(1.0, float(np.abs(tb).max())), (what, key, err)
