@@ -95,8 +95,8 @@ typedef enum {
                                  + B n with A' = -M_phi - cs^2/2 + phi mu_phi/(4 rho), B = M_phi lambda,
                                  u0 the velocity without F_s; |grad phi| = (|C0| + B)/(-A') clamped at 0.
                                  The history then holds m^phiC of the previous level too (22 planes per
-                                 copy instead of 20).  lbm_init, lbm_step, lbm_moments and lbm_diagnostics
-                                 only: the other calls return LBM_E_UNSUPPORTED */
+                                 copy instead of 20).  lbm_init, lbm_step, lbm_moments, lbm_diagnostics and
+                                 batches; export, import and the reverse mode return LBM_E_UNSUPPORTED */
 } lbm_grad;
 
 /* Problem statement in the paper's notation (Sec. 2; Sec. 4 preamble). */
@@ -235,11 +235,10 @@ int lbm_adjoint_import(const lbm_params *p, void *adj, const void *fbar, const v
 /* ---- batches: many independent lattices, one launch per time step ---------
  * (the per-step update above applied to every case; a case advanced in a
  * batch is bitwise identical to the same case advanced alone with lbm_step).
- * All cases share one dtype; any phase field and model, the stencil gradient
- * only (local-gradient cases: LBM_E_UNSUPPORTED).  Batches holding
- * Cahn-Hilliard or corrected Allen-Cahn cases run 64 x 4-thread tiles of 4 or
- * 8 rows; their two-node-window cases equal the lone runs to rounding (the
- * tile height may differ), the others bitwise.  The plan is
+ * All cases share one dtype; any option.  Batches holding Cahn-Hilliard,
+ * corrected Allen-Cahn or local-gradient cases run 64 x 4-thread tiles of 4
+ * or 8 rows; those cases equal the lone runs to rounding (the tile height may
+ * differ), the plain Allen-Cahn cases bitwise.  The plan is
  * library-owned (a small device table of the cases and, once lbm_batch_step
  * runs on a non-NULL stream with nsteps >= 32, a captured hipGraph of 32
  * steps for that state and stream). */

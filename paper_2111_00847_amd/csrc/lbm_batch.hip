@@ -11,8 +11,9 @@
 // are picked per batch by timing the candidates on the batch itself (the
 // autotuner), and K steps are captured once into a hipGraph and replayed.
 // Batches that hold Cahn-Hilliard or corrected Allen-Cahn cases (the
-// two-node-window body of lbm_ch_step.hpp) run a second kernel whose LDS holds
-// either window; each item runs its case's body.
+// two-node-window body of lbm_ch_step.hpp) or local-gradient cases
+// (lbm_local_step.hpp) run a second kernel whose LDS holds any of the windows;
+// each item runs its case's body.
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -22,6 +23,7 @@
 #include "lbm_ch_step.hpp"
 #include "lbm_fused.hpp"
 #include "lbm_kernels.hpp"
+#include "lbm_local_step.hpp"
 
 namespace lbm {
 
@@ -38,7 +40,8 @@ struct BatchCase {
     size_t off0, off1, off_stamp;
     int ntx, nty;
     int item_begin;              // first work item of this case
-    int body;                    // 0: Allen-Cahn step; 1: Cahn-Hilliard; 2: corrected Allen-Cahn (ACC)
+    int body;                    // 0: Allen-Cahn step; 1: Cahn-Hilliard; 2: corrected Allen-Cahn (ACC);
+                                 // 3: Allen-Cahn with the local gradient scheme
 };
 
 template <typename T, int TY, int NBY>
@@ -61,8 +64,8 @@ void k_step_batch(const BatchCase<T>* __restrict__ cases, int ncases, int nitems
     }
 }
 
-// Batches with two-node-window cases: 64 x 4 threads, the LDS holds either
-// window, each item runs its case's body.
+// Batches with two-node-window or local-gradient cases: 64 x 4 threads, the
+// LDS holds any of the windows, each item runs its case's body.
 template <typename T, int TY>
 __global__ __launch_bounds__(TX* BY) void k_step_batch_wide(const BatchCase<T>* __restrict__ cases, int ncases,
                                                             int nitems, char* batch_state) {
@@ -89,6 +92,9 @@ __global__ __launch_bounds__(TX* BY) void k_step_batch_wide(const BatchCase<T>* 
         else if (C.body == 1)
             ch_step_tile<T, TY, 0, false>(C.P, st0, C.off0, C.off1, C.off_stamp, local % C.ntx, local / C.ntx,
                                           nullptr, nullptr, nullptr, lds.ch);
+        else if (C.body == 3)
+            local_step_tile<T, TY, 0>(C.P, st0, C.off0, C.off1, C.off_stamp, local % C.ntx, local / C.ntx, nullptr,
+                                      nullptr, nullptr, lds.ac.sphi);
         else
             ch_step_tile<T, TY, 0, true>(C.P, st0, C.off0, C.off1, C.off_stamp, local % C.ntx, local / C.ntx, nullptr,
                                          nullptr, nullptr, lds.ch);
@@ -112,7 +118,7 @@ struct lbm_batch {
     size_t total = 0;
     int autotune = 0;
     bool tuned = false;
-    bool wide = false;    // some case runs the two-node-window body (64 x 4 threads only)
+    bool wide = false;    // some case runs the two-node-window or local body (64 x 4 threads only)
     int ty = 8;
     int by = 4;           // thread rows per workgroup
     int grid = 0;
@@ -147,7 +153,11 @@ hipError_t upload_cases(lbm_batch* B, int ty) {
         C.off1 = B->layouts[c].off_buf[1];
         C.off_stamp = B->layouts[c].off_stamp;
         C.item_begin = items;
-        C.body = B->params[c].phase_eq == LBM_CAHN_HILLIARD ? 1 : (B->params[c].model == LBM_MODEL_CORRECTED ? 2 : 0);
+        const lbm_params& q = B->params[c];
+        C.body = q.phase_eq == LBM_CAHN_HILLIARD ? 1
+                 : q.model == LBM_MODEL_CORRECTED ? 2
+                 : q.grad_scheme == LBM_GRAD_LOCAL ? 3
+                                                   : 0;
         items += tiles_for(B->params[c], ty, &C.ntx, &C.nty);
     }
     B->nitems = items;
@@ -250,7 +260,7 @@ int autotune_t(lbm_batch* B, char* state, const void* const* phi0, const void* c
     for (const auto& sh : shapes) {
         const int ty = sh[0];
         if (ty == 16 && sizeof(T) == 8) continue;
-        if (B->wide && (sh[1] != 4 || ty > 8)) continue;   // the two-node-window body: 64 x 4 threads
+        if (B->wide && (sh[1] != 4 || ty > 8)) continue;   // the wide bodies: 64 x 4 threads
         B->ty = ty;
         B->by = sh[1];
         hipError_t e = upload_cases<T>(B, ty);
@@ -299,8 +309,6 @@ int lbm_batch_create(const lbm_params* cases, int32_t ncases, int32_t autotune, 
         int rc = validate(&cases[c]);
         if (rc) return rc;
         if (cases[c].dtype != cases[0].dtype) return LBM_E_DTYPE;
-        // the local gradient scheme has its own kernel and history layout
-        if (cases[c].grad_scheme != LBM_GRAD_STENCIL) return LBM_E_UNSUPPORTED;
         Layout L = layout_of(&cases[c]);
         if (L.buf_bytes >= (size_t(1) << 32)) return LBM_E_SIZE;   // 32-bit offsets within a case
     }
@@ -310,7 +318,8 @@ int lbm_batch_create(const lbm_params* cases, int32_t ncases, int32_t autotune, 
     B->autotune = autotune;
     B->params.assign(cases, cases + ncases);
     for (int c = 0; c < ncases; c++)
-        B->wide = B->wide || cases[c].phase_eq == LBM_CAHN_HILLIARD || cases[c].model == LBM_MODEL_CORRECTED;
+        B->wide = B->wide || cases[c].phase_eq == LBM_CAHN_HILLIARD || cases[c].model == LBM_MODEL_CORRECTED ||
+                  cases[c].grad_scheme == LBM_GRAD_LOCAL;
     size_t off = 0;
     for (int c = 0; c < ncases; c++) {
         Layout L = layout_of(&cases[c]);
