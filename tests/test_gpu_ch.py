@@ -26,6 +26,21 @@ GEOMS = {
 }
 
 
+def _contour_radii(phi, X, Y, cx, cy, level, nang=32):
+    """Radius of the phi = level contour along nang rays from (cx, cy)."""
+    r = np.hypot(X - cx, Y - cy)
+    ang = np.arctan2(Y - cy, X - cx)
+    out = []
+    for a in np.linspace(-np.pi, np.pi, nang, endpoint=False):
+        m = np.abs(np.angle(np.exp(1j * (ang - a)))) < 0.05
+        rr, pp = r[m], phi[m]
+        o = np.argsort(rr)
+        rr, pp = rr[o], pp[o]
+        j = np.where(pp < level)[0][0]
+        out.append(rr[j - 1] + (pp[j - 1] - level) / (pp[j - 1] - pp[j]) * (rr[j] - rr[j - 1]))
+    return np.array(out)
+
+
 def _sim():
     from paper_2111_00847_amd.sim import Sim
     return Sim
@@ -146,6 +161,7 @@ def test_ch_table1_present_vs_original():
     corrected model is not reproduced: F_a as defined moves it by < 0.1% here.)"""
     marks = (100000, 300000, 1000000)
     out = {}
+    radius = {}
     for model in ("present", "original", "corrected"):
         case, phi0 = W.square_droplet_ch(model=model)
         s = _sim()(case, stream=torch.cuda.Stream()).init(phi0)
@@ -157,6 +173,15 @@ def test_ch_table1_present_vs_original():
             out[model, m] = (d["Sm_rms"], d["Du_rms"])
             print(f"Table 1 set-up, {model}, {m} steps: S_m^rms {d['Sm_rms']:.4e} D_u^rms {d['Du_rms']:.4e}",
                   flush=True)
+        phi, _, _ = s.moments_np()
+        X, Y = W.grid(case)
+        radius[model] = _contour_radii(phi, X, Y, 100.0, 100.0, 0.0)
+        print(f"Table 1 set-up, {model}: final radius {radius[model].mean():.3f} +- {radius[model].std():.3f}",
+              flush=True)
+    # The radius is printed, not asserted: the heavy droplet's viscous relaxation
+    # time (mu R / sigma ~ 5e8 steps here) is far beyond the 1e6 steps run (measured
+    # 49.26 +- 5.04, still square-ish); the circle of Sec. 4.1 is pinned on a CH
+    # droplet that relaxes in reach (tests/test_oracle_ch.py).
     ratios = [out["present", m][0] / out["original", m][0] for m in marks]
     print("S_m^rms present / original:", ", ".join(f"{r:.3f}" for r in ratios), flush=True)
     assert ratios[0] < 0.55 and ratios[1] < ratios[0] and ratios[2] < ratios[1] and ratios[2] < 0.33

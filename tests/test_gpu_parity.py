@@ -105,6 +105,28 @@ def test_one_step_map_fp64(geom, shape, step):
     np.testing.assert_allclose(h[1:], u_o, atol=1e-15)
 
 
+def test_checkpoint_restore_and_run_to_run_are_bitwise():
+    """A device-to-device copy of the state is a checkpoint: continuing from it
+    reproduces the original run bitwise; a second run from lbm_init reproduces it
+    bitwise too, diagnostics included (fixed-order reductions)."""
+    case, phi0 = W.rti(nx=128, ny=256)
+    p0 = W.hydrostatic_pressure(case, phi0)
+    Sim = _gpu()
+    a = Sim(case).init(phi0, None, p0).step(60)
+    torch.cuda.synchronize()
+    ck = a.state.clone()
+    a.step(60)
+    b = Sim(case, state=ck).step(60)
+    c = Sim(case).init(phi0, None, p0).step(120)
+    torch.cuda.synchronize()
+    sa, sb, sc = a.export_state(), b.export_state(), c.export_state()
+    for key in ("f", "g", "hist"):
+        assert torch.equal(sa[key], sb[key]), ("restore", key)
+        assert torch.equal(sa[key], sc[key]), ("rerun", key)
+    assert sa["step"] == sb["step"] == sc["step"] == 120
+    assert a.diagnostics() == c.diagnostics()
+
+
 def test_moments_fp64_equal_oracle():
     case = W.Case(nx=45, ny=33, wall_y=True, rhoA=5.0, rhoB=1.0, sigma=0.02, W=4.0, M=0.05,
                   gravity=(0, -1e-5), theta=(1.5708, 1.5708, 0.9, 2.1), dtype="f64")

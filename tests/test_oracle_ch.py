@@ -176,3 +176,19 @@ def test_corrected_model_allen_cahn_interface_force_closed_form():
     np.testing.assert_allclose(res["original"], 1e-3, rtol=1e-12)
     assert np.abs(expect[far]).max() > 1e-3
     np.testing.assert_allclose(got[far], expect[far], rtol=0, atol=1e-2 * np.abs(expect[far]).max())
+
+
+def test_ch_square_droplet_relaxes_to_a_circle_of_the_same_area():
+    """Sec. 4.1 with a droplet that relaxes within reach (64^2, R = 16, density
+    ratio 10, sigma 1e-2): the square of side D = sqrt(pi R^2 + (4 - pi) W^2 / 4)
+    becomes a circle (contour radii spread < 0.01) of radius R to 1%; the CH
+    equation then shrinks it slowly as the bulk phi shifts (15.94, 15.91, 15.87
+    at 5000, 10000, 20000 steps)."""
+    from test_oracle_physics import _contour_radii
+    case, phi0 = W.square_droplet_ch(n=64, R=16.0, sigma=1e-2, rho_ratio=10.0)
+    s = oracle.OracleSim(case).init(phi0).step(10000)
+    phi, _, _ = s.moments()
+    X, Y = W.grid(case)
+    rs = _contour_radii(phi, X, Y, 32.0, 32.0, 0.0)
+    assert rs.std() < 0.01, rs.std()
+    assert abs(rs.mean() - 16.0) < 0.16, rs.mean()

@@ -165,3 +165,33 @@ def test_equilibrium_contact_angle(theta_deg):
     R = R0 * math.sqrt((math.pi / 2) / (th - math.sin(th) * math.cos(th)))
     assert abs(H - R * (1 - math.cos(th))) < 0.6
     assert abs(L - 2 * R * math.sin(th)) < 1.2
+
+
+def _contour_radii(phi, X, Y, cx, cy, level, nang=32):
+    """Radius of the phi = level contour along nang rays from (cx, cy) (linear
+    interpolation on the nodes within 0.05 rad of each ray)."""
+    r = np.hypot(X - cx, Y - cy)
+    ang = np.arctan2(Y - cy, X - cx)
+    out = []
+    for a in np.linspace(-np.pi, np.pi, nang, endpoint=False):
+        m = np.abs(np.angle(np.exp(1j * (ang - a)))) < 0.05
+        rr, pp = r[m], phi[m]
+        o = np.argsort(rr)
+        rr, pp = rr[o], pp[o]
+        j = np.where(pp < level)[0][0]
+        out.append(rr[j - 1] + (pp[j - 1] - level) / (pp[j - 1] - pp[j]) * (rr[j] - rr[j - 1]))
+    return np.array(out)
+
+
+def test_square_droplet_relaxes_to_the_area_preserving_circle():
+    """Sec. 4.1: the square of side D relaxes to the circle of radius R with
+    pi R^2 + (4 - pi) W^2 / 4 = D^2 (the area of the square with corners rounded
+    by W/2).  64^2, D = 32, W = 4: R = 18.024; measured 18.025, round to 0.002."""
+    case, phi0 = W.square_droplet(n=64, side=32.0, dtype="f64")
+    s = oracle.OracleSim(case).init(phi0).step(10000)
+    phi, u, _ = s.moments()
+    X, Y = W.grid(case)
+    rs = _contour_radii(phi, X, Y, 32.0, 32.0, 0.5)
+    R = math.sqrt((32.0 ** 2 - (4 - math.pi) * case.W ** 2 / 4) / math.pi)
+    assert abs(rs.mean() - R) < 0.02, (rs.mean(), R)
+    assert rs.std() < 0.01
