@@ -24,32 +24,72 @@ __device__ __forceinline__ void local_step_tile(const KParams<T>& P, char* state
     const int cur = (int)(step & 1);
     const Copy<T> S = copy_at<T>(state + (cur ? off1 : off0), P.plane);
     const Copy<T> D = copy_at<T>(state + (cur ? off0 : off1), P.plane);
-    fill_window<T, TY>(P, S, false, x0, y0, sphi, sphi);   // no previous-level window is needed
     const long long pl = P.plane;
+    const int tid = threadIdx.y * TX + threadIdx.x;
+    const int lx = threadIdx.x;
+    // phi of window position (wx, wy) = node (x0 - 1 + wx, y0 - 1 + wy): periodic
+    // axes wrap; positions beyond a wall are left for wall_ghosts
+    auto fill = [&](int wx, int wy) {
+        int gx = x0 - 1 + wx, gy = y0 - 1 + wy;
+        if (gx > P.nx || gy > P.ny) return;
+        if (gx < 0 || gx >= P.nx) {
+            if (P.wall_x) return;
+            gx = gx < 0 ? gx + P.nx : gx - P.nx;
+        }
+        if (gy < 0 || gy >= P.ny) {
+            if (P.wall_y) return;
+            gy = gy < 0 ? gy + P.ny : gy - P.ny;
+        }
+        T fw[9];
+        sphi[wy][wx] = (T)node_phi(P, S, gx, gy, fw);
+    };
+    // 1. own nodes first (f, g and the history kept in registers), then the ring
+    T f[R][9], g[R][9], hv[R][5];
+    double phid[R];
 #pragma unroll
     for (int r = 0; r < R; r++) {
-        const int lx = threadIdx.x, ly = threadIdx.y + r * BY;
+        const int ly = threadIdx.y + r * BY;
+        const int x = x0 + lx, y = y0 + ly;
+        if (x < P.nx && y < P.ny) {
+            const long long k = (long long)y * P.nx + x;
+            phid[r] = node_phi(P, S, x, y, f[r]);
+#pragma unroll
+            for (int i = 0; i < Q; i++) g[r][i] = pull(S.g, P, i, x, y);
+            if (!first)
+#pragma unroll
+                for (int j = 0; j < 5; j++) hv[r][j] = S.h[j * pl + k];
+            sphi[ly + 1][lx + 1] = (T)phid[r];
+        } else {
+            fill(lx + 1, ly + 1);   // ragged tile: the position serves as ring
+        }
+    }
+    constexpr int WX = TX + 2;
+    for (int idx = tid; idx < 2 * WX + 2 * TY; idx += TX * BY) {
+        if (idx < 2 * WX) fill(idx % WX, idx < WX ? 0 : TY + 1);
+        else fill(idx < 2 * WX + TY ? 0 : WX - 1, 1 + (idx - 2 * WX) % TY);
+    }
+    __syncthreads();
+    wall_ghosts<T, TY>(P, false, x0, y0, sphi, sphi);
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const int ly = threadIdx.y + r * BY;
         const int x = x0 + lx, y = y0 + ly;
         if (x >= P.nx || y >= P.ny) continue;
         const long long k = (long long)y * P.nx + x;
-        T f[9], g[9];
-        const double phid = node_phi(P, S, x, y, f);
-#pragma unroll
-        for (int i = 0; i < Q; i++) g[i] = pull(S.g, P, i, x, y);
         T gx, gy, lap;
         win_stencil_at(sphi, lx + 1, ly + 1, gx, gy, lap);
         const T phi = sphi[ly + 1][lx + 1];
         T php = T(0), up = T(0), vp = T(0), mpx = T(0), mpy = T(0);
         if (!first) {
-            php = S.h[k];
-            up = S.h[pl + k];
-            vp = S.h[2 * pl + k];
-            mpx = S.h[3 * pl + k];
-            mpy = S.h[4 * pl + k];
-            local_grad(P, f, g, phi, lap, php * up, php * vp, gx, gy);
+            php = hv[r][0];
+            up = hv[r][1];
+            vp = hv[r][2];
+            mpx = hv[r][3];
+            mpy = hv[r][4];
+            local_grad(P, f[r], g[r], phi, lap, php * up, php * vp, gx, gy);
         }
         const Macro<T> M =
-            macro<T, false, true>(P, g, phi, gx, gy, lap, first, php, T(0), T(0), up, vp, T(0), T(0), mpx, mpy);
+            macro<T, false, true>(P, g[r], phi, gx, gy, lap, first, php, T(0), T(0), up, vp, T(0), T(0), mpx, mpy);
         if (MODE == 1) {
             if (out_phi) out_phi[k] = M.phi;
             if (out_u) {
@@ -59,16 +99,15 @@ __device__ __forceinline__ void local_step_tile(const KParams<T>& P, char* state
             if (out_p) out_p[k] = M.p;
             continue;
         }
-        const double f0n = collide_f(P, M, f, phid);
-        collide_g(P, M, g);
+        const double f0n = collide_f(P, M, f[r], phid[r]);
+        collide_g(P, M, g[r]);
         st<double, long long>(reinterpret_cast<char*>(D.f0), 8 * k, f0n);
-        for (int i = 1; i < Q; i++) st<T, long long>(reinterpret_cast<char*>(D.f), (long long)sizeof(T) * (i * pl + k), f[i]);
-        for (int i = 0; i < Q; i++) st<T, long long>(reinterpret_cast<char*>(D.g), (long long)sizeof(T) * (i * pl + k), g[i]);
-        const T hv[5] = {M.phi, M.u, M.v, M.mx, M.my};
-        for (int j = 0; j < 5; j++) st<T, long long>(reinterpret_cast<char*>(D.h), (long long)sizeof(T) * (j * pl + k), hv[j]);
+        for (int i = 1; i < Q; i++) st<T, long long>(reinterpret_cast<char*>(D.f), (long long)sizeof(T) * (i * pl + k), f[r][i]);
+        for (int i = 0; i < Q; i++) st<T, long long>(reinterpret_cast<char*>(D.g), (long long)sizeof(T) * (i * pl + k), g[r][i]);
+        const T hout[5] = {M.phi, M.u, M.v, M.mx, M.my};
+        for (int j = 0; j < 5; j++) st<T, long long>(reinterpret_cast<char*>(D.h), (long long)sizeof(T) * (j * pl + k), hout[j]);
     }
     // every wave read stamp[0] before the window barrier
-    const int tid = threadIdx.y * TX + threadIdx.x;
     if (MODE == 0 && tid < TY && y0 + tid < P.ny) stamp[tid] = step + 1;
 }
 
