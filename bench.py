@@ -24,6 +24,8 @@ The JSON line also carries:
                   FP32): one autotuned persistent launch per step replayed from a
                   captured graph, against the same cases advanced one after
                   another with the plain step (graph-captured, and eager);
+  square_droplet -- total-phi drift and max |div u| of the 64 x 64 square
+                  droplet after 2000 FP64 steps;
   cahn_hilliard -- the Cahn-Hilliard variant's step kernel on a 4096 x 4096
                   square droplet (Sec. 4.1 set-up scaled up, FP32);
   local_gradient -- the Allen-Cahn step with the local gradient scheme (Eq.
@@ -214,6 +216,18 @@ def measure_local(args, torch, W, Sim):
             "avg_launch_ms": round(ms_launch, 4)}
 
 
+def measure_square_droplet(torch, W, Sim):
+    """The 64 x 64 square droplet (Sec. 4.1 set-up of the AC model, FP64, 2000
+    steps): the total-phi drift and max |div u| it is reported by."""
+    case, phi0 = W.square_droplet()
+    sim = Sim(case, "cuda:0").init(phi0).step(2000)
+    d = sim.diagnostics()
+    s0 = float(phi0.sum())
+    return {"workload": "square_droplet_64x64", "dtype": "f64", "steps": 2000,
+            "sum_phi_rel_drift": abs(d["sum_phi"] - s0) / s0, "max_div_u": d["max_div"], "Du_rms": d["Du_rms"],
+            "Sm_rms": d["Sm_rms"]}
+
+
 def measure_copy(torch, mib=1024, reps=20):
     """Bandwidth of torch's device-to-device copy of a `mib` MiB buffer (read + write
     bytes per second): a measured ceiling next to the nominal HBM peak."""
@@ -366,6 +380,8 @@ def main():
         out["large_grid"]["frac_of_copy"] = round(out["large_grid"]["achieved_GBs"] / copy_gbs, 4)
         if not args.only_large:
             out["large_grid_fp64"] = measure_large(args, torch, W, Sim, "f64")
+    if not args.only_large:
+        out["square_droplet"] = measure_square_droplet(torch, W, Sim)
     if not args.no_ch and not args.only_large:
         out["cahn_hilliard"] = measure_ch(args, torch, W, Sim)
     if not args.no_local and not args.only_large:

@@ -147,6 +147,8 @@ def test_square_droplet_fp64_2000_steps():
     _compare_macro(g, o, 1e-10, 1e-10, "square droplet fp64")
     dg = g.diagnostics()
     do = o.diagnostics()
+    print(f"square droplet fp64 2000 steps: sum phi drift {abs(dg['sum_phi'] - phi0.sum()) / phi0.sum():.2e}, "
+          f"max|div u| {dg['max_div']:.3e} (oracle {do['max_div']:.3e})", flush=True)
     assert abs(dg["sum_phi"] - phi0.sum()) / phi0.sum() < 1e-12
     for key in ("max_div", "Du_rms", "Sm_rms", "umax"):
         assert abs(dg[key] - do[key]) <= 1e-8 * abs(do[key]) + 1e-18, (key, dg[key], do[key])
