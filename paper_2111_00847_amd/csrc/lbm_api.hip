@@ -107,6 +107,8 @@ KParams<T> resolve(const lbm_params* p, const Layout& L) {
         K.sf[i] = (T)sf[i];
         K.sg[i] = (T)sg[i];
     }
+    K.rates_std = sf[0] == 1.0 && sf[1] == 1.0 && sf[2] == 1.0 && sf[4] == 1.0 && sf[6] == 1.0 && sf[7] == 1.0 &&
+                  sf[8] == 1.0 && sg[0] == 1.0 && sg[1] == 1.0 && sg[2] == 1.0 && sg[3] == 1.0 && sg[5] == 1.0;
     K.Gx = (T)p->body_force[0];
     K.Gy = (T)p->body_force[1];
     K.gx = (T)p->gravity[0];

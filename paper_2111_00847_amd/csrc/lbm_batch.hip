@@ -58,8 +58,13 @@ void k_step_batch(const BatchCase<T>* __restrict__ cases, int ncases, int nitems
         }
         const BatchCase<T>& C = cases[lo];
         const int local = w - C.item_begin;
-        step_tile<T, TY, 0, uint32_t, NBY>(C.P, batch_state + C.base, C.off0, C.off1, C.off_stamp, local % C.ntx,
-                                           local / C.ntx, nullptr, nullptr, nullptr, sphi, sphp);
+        // the collision specialisation the case runs alone (lbm_step), so that it stays bitwise
+        if (C.P.rates_std)
+            step_tile<T, TY, 0, uint32_t, NBY, true>(C.P, batch_state + C.base, C.off0, C.off1, C.off_stamp,
+                                                     local % C.ntx, local / C.ntx, nullptr, nullptr, nullptr, sphi, sphp);
+        else
+            step_tile<T, TY, 0, uint32_t, NBY, false>(C.P, batch_state + C.base, C.off0, C.off1, C.off_stamp,
+                                                      local % C.ntx, local / C.ntx, nullptr, nullptr, nullptr, sphi, sphp);
         __syncthreads();   // the next item reuses the LDS window
     }
 }
@@ -86,9 +91,12 @@ __global__ __launch_bounds__(TX* BY) void k_step_batch_wide(const BatchCase<T>* 
         const BatchCase<T>& C = cases[lo];
         const int local = w - C.item_begin;
         char* st0 = batch_state + C.base;
-        if (C.body == 0)
-            step_tile<T, TY, 0, uint32_t, BY>(C.P, st0, C.off0, C.off1, C.off_stamp, local % C.ntx, local / C.ntx,
-                                              nullptr, nullptr, nullptr, lds.ac.sphi, lds.ac.sphp);
+        if (C.body == 0 && C.P.rates_std)
+            step_tile<T, TY, 0, uint32_t, BY, true>(C.P, st0, C.off0, C.off1, C.off_stamp, local % C.ntx,
+                                                    local / C.ntx, nullptr, nullptr, nullptr, lds.ac.sphi, lds.ac.sphp);
+        else if (C.body == 0)
+            step_tile<T, TY, 0, uint32_t, BY, false>(C.P, st0, C.off0, C.off1, C.off_stamp, local % C.ntx,
+                                                     local / C.ntx, nullptr, nullptr, nullptr, lds.ac.sphi, lds.ac.sphp);
         else if (C.body == 1)
             ch_step_tile<T, TY, 0, false>(C.P, st0, C.off0, C.off1, C.off_stamp, local % C.ntx, local / C.ntx,
                                           nullptr, nullptr, nullptr, lds.ch);

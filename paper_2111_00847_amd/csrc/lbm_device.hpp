@@ -338,7 +338,9 @@ __device__ __forceinline__ void from_moments(const T* m, T* f) {
 // collision-invariant: m_0^eq = phi and m_R has no zeroth moment).
 // CH: the Cahn-Hilliard moments of Eq. MfMRCH1 (eta mu_phi in rows 1 and 2;
 // lambda n is zero in M).
-template <typename T, bool CH = false>
+// STD: the rates other than s_f^3, s_f^5 (s_g^4, s_g^6, s_g^7, s_g^8) are 1 (the
+// paper's default, P.rates_std) and are compiled in as constants.
+template <typename T, bool CH = false, bool STD = false>
 __device__ __forceinline__ double collide_f(const KParams<T>& P, const Macro<T>& M, T* f, double phid) {
     T m[9];
     to_moments(f, m);
@@ -350,7 +352,10 @@ __device__ __forceinline__ double collide_f(const KParams<T>& P, const Macro<T>&
     T dm[9], d[9];
     dm[0] = T(0);
 #pragma unroll
-    for (int k = 1; k < 9; k++) dm[k] = -P.sf[k] * (m[k] - meq[k]) + (T(1) - T(0.5) * P.sf[k]) * mR[k];
+    for (int k = 1; k < 9; k++) {
+        const T sk = (STD && k != 3 && k != 5) ? T(1) : P.sf[k];
+        dm[k] = -sk * (m[k] - meq[k]) + (T(1) - T(0.5) * sk) * mR[k];
+    }
     if (CH) {
         // Rows 1, 2 of Eq. MfMRCH1 (eta = 1): m^eq = -4 phi + 2 mu, 4 phi - 3 mu.  With
         // f_0 = phi - S (S = axis sum a + diagonal sum d) the phi terms cancel exactly:
@@ -360,8 +365,8 @@ __device__ __forceinline__ double collide_f(const KParams<T>& P, const Macro<T>&
         // the rounding of f_0 and phi in FP32).
         const T a = (f[1] + f[2]) + (f[3] + f[4]);
         const T dd = (f[5] + f[6]) + (f[7] + f[8]);
-        dm[1] = -P.sf[1] * ((T(3) * a + T(6) * dd) - T(2) * M.mu);
-        dm[2] = -P.sf[2] * ((T(-6) * a - T(3) * dd) + T(3) * M.mu);
+        dm[1] = -(STD ? T(1) : P.sf[1]) * ((T(3) * a + T(6) * dd) - T(2) * M.mu);
+        dm[2] = -(STD ? T(1) : P.sf[2]) * ((T(-6) * a - T(3) * dd) + T(3) * M.mu);
     }
     from_moments(dm, d);
 #pragma unroll
@@ -370,7 +375,7 @@ __device__ __forceinline__ double collide_f(const KParams<T>& P, const Macro<T>&
 }
 
 // Hydrodynamic collision (Remark 2, moment form; Eq. MgMF1).
-template <typename T>
+template <typename T, bool STD = false>
 __device__ __forceinline__ void collide_g(const KParams<T>& P, const Macro<T>& M, T* g) {
     T m[9];
     to_moments(g, m);
@@ -402,7 +407,7 @@ __device__ __forceinline__ void collide_g(const KParams<T>& P, const Macro<T>& M
                (T(1) / T(3)) * (u * M.dry + v * M.drx) + (u * M.Fy + v * M.Fx) + T(0.5) * M.d4};
     T s[9];
 #pragma unroll
-    for (int k = 0; k < 9; k++) s[k] = P.sg[k];
+    for (int k = 0; k < 9; k++) s[k] = (STD && (k <= 3 || k == 5)) ? T(1) : P.sg[k];
     if (P.snu_local) {
         s[7] = M.snu;
         s[8] = M.snu;

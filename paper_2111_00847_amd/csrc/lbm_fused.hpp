@@ -117,7 +117,7 @@ struct StepWaves {
 // The tile body between explicit buffers: `src` holds level `step` (one copy:
 // post-collision populations of the previous step and the history), `dst`
 // receives level step + 1.
-template <typename T, int TY, int MODE, typename OFF, int NBY = BY>
+template <typename T, int TY, int MODE, typename OFF, int NBY = BY, bool STD = false>
 __device__ __forceinline__ void step_core(const KParams<T>& P, const char* src, char* dst, int64_t step, int xt,
                                           int yt, T* out_phi, T* out_u, T* out_p, T (*sphi)[TX + 3],
                                           T (*sphp)[TX + 3]) {
@@ -357,8 +357,8 @@ __device__ __forceinline__ void step_core(const KParams<T>& P, const char* src, 
             if (out_p) out_p[k] = M.p;
             continue;
         }
-        const double f0n = collide_f(P, M, f[r], phid[r]);
-        collide_g(P, M, g);
+        const double f0n = collide_f<T, false, STD>(P, M, f[r], phid[r]);
+        collide_g<T, STD>(P, M, g);
         st<double>(dst, (OFF)8 * k, f0n);
 #pragma unroll
         for (int i = 1; i < Q; i++) st<T>(dst, bF + ((OFF)(i - 1) * pl + k) * ES, f[r][i]);
@@ -372,7 +372,7 @@ __device__ __forceinline__ void step_core(const KParams<T>& P, const char* src, 
 
 // The tile body on a ping-pong state: the level stamp of the tile's first row
 // selects the source copy, and the tile's rows move to the next level.
-template <typename T, int TY, int MODE, typename OFF, int NBY = BY>
+template <typename T, int TY, int MODE, typename OFF, int NBY = BY, bool STD = false>
 __device__ __forceinline__ void step_tile(const KParams<T>& P, char* state, size_t off0, size_t off1,
                                           size_t off_stamp, int xt, int yt, T* out_phi, T* out_u, T* out_p,
                                           T (*sphi)[TX + 3], T (*sphp)[TX + 3]) {
@@ -380,7 +380,7 @@ __device__ __forceinline__ void step_tile(const KParams<T>& P, char* state, size
     int64_t* stamp = reinterpret_cast<int64_t*>(state + off_stamp) + (size_t)xt * P.ny + y0;
     const int64_t step = stamp[0];
     const int cur = (int)(step & 1);
-    step_core<T, TY, MODE, OFF, NBY>(P, state + (cur ? off1 : off0), state + (cur ? off0 : off1), step, xt, yt, out_phi,
+    step_core<T, TY, MODE, OFF, NBY, STD>(P, state + (cur ? off1 : off0), state + (cur ? off0 : off1), step, xt, yt, out_phi,
                                 out_u, out_p, sphi, sphp);
     // Own rows move to level n + 1.  Every wave of the workgroup consumed its
     // load of stamp[0] (it addresses all loads above) before the barriers of

@@ -23,7 +23,7 @@
 
 namespace lbm {
 
-template <typename T, int TY, int MODE, typename OFF, int NBY>
+template <typename T, int TY, int MODE, typename OFF, int NBY, bool STD>
 __global__ __launch_bounds__(TX* NBY) __attribute__((amdgpu_waves_per_eu(StepWaves<T, TY, NBY>::value)))
 void k_step(KParams<T> P, char* state, size_t off0, size_t off1, size_t off_stamp, int ntx, int nty, T* out_phi,
             T* out_u, T* out_p) {
@@ -36,7 +36,7 @@ void k_step(KParams<T> P, char* state, size_t off0, size_t off1, size_t off_stam
         xt = blockIdx.x % ntx;
         yt = blockIdx.x / ntx;
     }
-    step_tile<T, TY, MODE, OFF, NBY>(P, state, off0, off1, off_stamp, xt, yt, out_phi, out_u, out_p, sphi, sphp);
+    step_tile<T, TY, MODE, OFF, NBY, STD>(P, state, off0, off1, off_stamp, xt, yt, out_phi, out_u, out_p, sphi, sphp);
 }
 
 // The Cahn-Hilliard variant and the corrected comparison model with the
@@ -269,12 +269,23 @@ template <typename T, int TY, int MODE, int NBY = BY>
 static void launch_tile(const KParams<T>& P, char* state, const Layout& L, hipStream_t s, T* phi, T* u, T* p) {
     const int ntx = (P.nx + TX - 1) / TX, nty = (P.ny + TY - 1) / TY;
     dim3 blk(TX, NBY);
-    if (small_copy(L))
-        k_step<T, TY, MODE, uint32_t, NBY><<<ntx * nty, blk, 0, s>>>(P, state, L.off_buf[0], L.off_buf[1],
-                                                                      L.off_stamp, ntx, nty, phi, u, p);
-    else
-        k_step<T, TY, MODE, uint64_t, NBY><<<ntx * nty, blk, 0, s>>>(P, state, L.off_buf[0], L.off_buf[1],
-                                                                      L.off_stamp, ntx, nty, phi, u, p);
+    // the standard rates compiled in for steps (moments do not collide)
+    const bool std_rates = MODE == 0 && P.rates_std;
+    if (small_copy(L)) {
+        if (std_rates)
+            k_step<T, TY, MODE, uint32_t, NBY, true><<<ntx * nty, blk, 0, s>>>(P, state, L.off_buf[0], L.off_buf[1],
+                                                                                L.off_stamp, ntx, nty, phi, u, p);
+        else
+            k_step<T, TY, MODE, uint32_t, NBY, false><<<ntx * nty, blk, 0, s>>>(P, state, L.off_buf[0], L.off_buf[1],
+                                                                                 L.off_stamp, ntx, nty, phi, u, p);
+    } else {
+        if (std_rates)
+            k_step<T, TY, MODE, uint64_t, NBY, true><<<ntx * nty, blk, 0, s>>>(P, state, L.off_buf[0], L.off_buf[1],
+                                                                                L.off_stamp, ntx, nty, phi, u, p);
+        else
+            k_step<T, TY, MODE, uint64_t, NBY, false><<<ntx * nty, blk, 0, s>>>(P, state, L.off_buf[0], L.off_buf[1],
+                                                                                 L.off_stamp, ntx, nty, phi, u, p);
+    }
 }
 
 template <typename T>

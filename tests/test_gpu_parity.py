@@ -105,6 +105,27 @@ def test_one_step_map_fp64(geom, shape, step):
     np.testing.assert_allclose(h[1:], u_o, atol=1e-15)
 
 
+@pytest.mark.parametrize("rates", ["paper_default", "all_free"])
+def test_one_step_map_relaxation_rates(rates):
+    """The step compiles the paper's default rates (1 except the mobility and
+    viscosity ones, and s_g^4 = s_g^6) in as constants; any other set runs the
+    general collision.  Both against the oracle, FP64, walls on all faces."""
+    sf = (0.0,) * 9 if rates == "paper_default" else (1.0, 1.3, 1.15, 0.0, 1.2, 0.0, 1.1, 1.25, 0.95)
+    sg = (0.0,) * 9 if rates == "paper_default" else (1.05, 1.3, 1.2, 1.0, 1.6, 1.0, 1.6, 0.0, 0.0)
+    case = W.Case(nx=37, ny=23, rhoA=20.0, rhoB=1.0, nuA=0.05, nuB=0.2, sigma=0.01, W=4.0, M=0.05,
+                  body_force=(1e-6, -2e-6), gravity=(0.0, -1e-5), rho_ref=3.0, dtype="f64", s_f=sf, s_g=sg,
+                  **GEOMS["walls_xy"])
+    f, g, php, upr = _random_state(case, seed=11)
+    hist = np.concatenate([php[None], upr], 0)
+    gs = _gpu()(case).import_state(f, g, hist, 4).step(1)
+    so = oracle.OracleSim(case).set_state(f, g, 4, php, upr).step(1).get_state()
+    sg_ = gs.export_state()
+    df = np.abs(sg_["f"].cpu().numpy() - so["f"]).max()
+    dg = np.abs(sg_["g"].cpu().numpy() - so["g"]).max()
+    print(f"rates {rates}: max|df|={df:.3e} max|dg|={dg:.3e}", flush=True)
+    assert df < 1e-14 and dg < 1e-14
+
+
 def test_checkpoint_restore_and_run_to_run_are_bitwise():
     """A device-to-device copy of the state is a checkpoint: continuing from it
     reproduces the original run bitwise; a second run from lbm_init reproduces it
