@@ -97,15 +97,21 @@ __global__ __launch_bounds__(TX* BY) void k_step_batch_wide(const BatchCase<T>* 
         else if (C.body == 0)
             step_tile<T, TY, 0, uint32_t, BY, false>(C.P, st0, C.off0, C.off1, C.off_stamp, local % C.ntx,
                                                      local / C.ntx, nullptr, nullptr, nullptr, lds.ac.sphi, lds.ac.sphp);
+        else if (C.body == 1 && C.P.rates_std)
+            ch_step_tile<T, TY, 0, false, true>(C.P, st0, C.off0, C.off1, C.off_stamp, local % C.ntx, local / C.ntx,
+                                                nullptr, nullptr, nullptr, lds.ch);
         else if (C.body == 1)
-            ch_step_tile<T, TY, 0, false>(C.P, st0, C.off0, C.off1, C.off_stamp, local % C.ntx, local / C.ntx,
-                                          nullptr, nullptr, nullptr, lds.ch);
+            ch_step_tile<T, TY, 0, false, false>(C.P, st0, C.off0, C.off1, C.off_stamp, local % C.ntx, local / C.ntx,
+                                                 nullptr, nullptr, nullptr, lds.ch);
         else if (C.body == 3)
             local_step_tile<T, TY, 0>(C.P, st0, C.off0, C.off1, C.off_stamp, local % C.ntx, local / C.ntx, nullptr,
                                       nullptr, nullptr, lds.ac.sphi);
+        else if (C.P.rates_std)
+            ch_step_tile<T, TY, 0, true, true>(C.P, st0, C.off0, C.off1, C.off_stamp, local % C.ntx, local / C.ntx,
+                                               nullptr, nullptr, nullptr, lds.ch);
         else
-            ch_step_tile<T, TY, 0, true>(C.P, st0, C.off0, C.off1, C.off_stamp, local % C.ntx, local / C.ntx, nullptr,
-                                         nullptr, nullptr, lds.ch);
+            ch_step_tile<T, TY, 0, true, false>(C.P, st0, C.off0, C.off1, C.off_stamp, local % C.ntx, local / C.ntx,
+                                                nullptr, nullptr, nullptr, lds.ch);
         __syncthreads();   // the next item reuses the LDS
     }
 }

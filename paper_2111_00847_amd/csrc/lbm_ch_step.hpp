@@ -12,7 +12,8 @@ namespace lbm {
 
 // MODE 0: one time step, the tile's rows move to the next level; MODE 1:
 // phi, u, p of the current level into out_*.  W: the tile's LDS windows.
-template <typename T, int TY, int MODE, bool ACC>
+// STD: the paper's default rates compiled in (P.rates_std).
+template <typename T, int TY, int MODE, bool ACC, bool STD = false>
 __device__ __forceinline__ void ch_step_tile(const KParams<T>& P, char* state, size_t off0, size_t off1,
                                              size_t off_stamp, int xt, int yt, T* out_phi, T* out_u, T* out_p,
                                              ChWindow<T, TY>& W) {
@@ -32,8 +33,8 @@ __device__ __forceinline__ void ch_step_tile(const KParams<T>& P, char* state, s
             if (out_p) out_p[k] = M.p;
             return;
         }
-        const double f0n = collide_f<T, !ACC>(P, M, f, phid);
-        collide_g(P, M, g);
+        const double f0n = collide_f<T, !ACC, STD>(P, M, f, phid);
+        collide_g<T, STD>(P, M, g);
         const long long pl = P.plane;
         st<double, long long>(reinterpret_cast<char*>(D.f0), 8 * k, f0n);
         for (int i = 1; i < Q; i++) st<T, long long>(reinterpret_cast<char*>(D.f), (long long)sizeof(T) * (i * pl + k), f[i]);

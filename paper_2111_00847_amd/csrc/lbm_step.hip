@@ -53,7 +53,7 @@ void k_step(KParams<T> P, char* state, size_t off0, size_t off1, size_t off_stam
 #define LBM_CH_TY 0
 #endif
 
-template <typename T, int TY, int MODE, bool ACC>
+template <typename T, int TY, int MODE, bool ACC, bool STD>
 __global__ __launch_bounds__(TX* BY) void k_step_ch(KParams<T> P, char* state, size_t off0, size_t off1,
                                                    size_t off_stamp, int ntx, int nty, T* out_phi, T* out_u,
                                                    T* out_p) {
@@ -65,7 +65,7 @@ __global__ __launch_bounds__(TX* BY) void k_step_ch(KParams<T> P, char* state, s
         xt = blockIdx.x % ntx;
         yt = blockIdx.x / ntx;
     }
-    ch_step_tile<T, TY, MODE, ACC>(P, state, off0, off1, off_stamp, xt, yt, out_phi, out_u, out_p, W);
+    ch_step_tile<T, TY, MODE, ACC, STD>(P, state, off0, off1, off_stamp, xt, yt, out_phi, out_u, out_p, W);
 }
 
 static int ch_rows(int nx, int ny) {
@@ -74,20 +74,27 @@ static int ch_rows(int nx, int ny) {
     return ntx * ((ny + 7) / 8) >= 1024 ? 8 : 4;
 }
 
-template <typename T, int MODE, bool ACC>
-static void launch_ch_acc(const KParams<T>& P, char* state, const Layout& L, hipStream_t s, T* phi, T* u, T* p) {
+template <typename T, int MODE, bool ACC, bool STD>
+static void launch_ch_acc_std(const KParams<T>& P, char* state, const Layout& L, hipStream_t s, T* phi, T* u, T* p) {
     const int ty = ch_rows(P.nx, P.ny);
     const int ntx = (P.nx + TX - 1) / TX, nty = (P.ny + ty - 1) / ty;
     const dim3 grd(ntx * nty), blk(TX, BY);
     if (ty == 16)
-        k_step_ch<T, 16, MODE, ACC><<<grd, blk, 0, s>>>(P, state, L.off_buf[0], L.off_buf[1], L.off_stamp, ntx, nty,
-                                                        phi, u, p);
+        k_step_ch<T, 16, MODE, ACC, STD><<<grd, blk, 0, s>>>(P, state, L.off_buf[0], L.off_buf[1], L.off_stamp, ntx,
+                                                             nty, phi, u, p);
     else if (ty == 8)
-        k_step_ch<T, 8, MODE, ACC><<<grd, blk, 0, s>>>(P, state, L.off_buf[0], L.off_buf[1], L.off_stamp, ntx, nty,
-                                                       phi, u, p);
+        k_step_ch<T, 8, MODE, ACC, STD><<<grd, blk, 0, s>>>(P, state, L.off_buf[0], L.off_buf[1], L.off_stamp, ntx,
+                                                            nty, phi, u, p);
     else
-        k_step_ch<T, 4, MODE, ACC><<<grd, blk, 0, s>>>(P, state, L.off_buf[0], L.off_buf[1], L.off_stamp, ntx, nty,
-                                                       phi, u, p);
+        k_step_ch<T, 4, MODE, ACC, STD><<<grd, blk, 0, s>>>(P, state, L.off_buf[0], L.off_buf[1], L.off_stamp, ntx,
+                                                            nty, phi, u, p);
+}
+
+// the standard rates compiled in for steps (moments do not collide)
+template <typename T, int MODE, bool ACC>
+static void launch_ch_acc(const KParams<T>& P, char* state, const Layout& L, hipStream_t s, T* phi, T* u, T* p) {
+    if (MODE == 0 && P.rates_std) launch_ch_acc_std<T, MODE, ACC, true>(P, state, L, s, phi, u, p);
+    else launch_ch_acc_std<T, MODE, ACC, false>(P, state, L, s, phi, u, p);
 }
 
 // CH (any model) or the corrected AC model: the two-node-window kernels.
