@@ -234,3 +234,37 @@ def test_fp32_adjoint_tracks_fp64():
         res[dt] = (phi0_t.grad.double().cpu().numpy(), grav.grad.numpy(), theta.grad.numpy())
     for k, name in enumerate(("dL/dphi0", "dL/dgravity", "dL/dtheta")):
         _close(res["f32"][k], res["f64"][k], 1e-3, f"fp32 vs fp64 {name}")
+
+
+def test_contact_angle_recovered_by_gradient_descent():
+    """An inverse problem through the autograd function: the bottom-wall contact
+    angle of a spreading droplet (Sec. 4.3 set-up, 96 x 48, density ratio 10,
+    FP64, 1500 steps) is recovered from the target shape phi_T (made at 70 deg)
+    by secant iterations on dL/dtheta, L = sum (phi - phi_T)^2, from 90 deg."""
+    from paper_2111_00847_amd.autograd import trajectory_phi
+    case, phi0 = W.spreading_case(96, 48, 70.0, dtype="f64", R0=16.0, rho_ratio=10.0, mu_ratio=10.0,
+                                  sigma=5e-3, W=4.0, M=0.1)
+    dev = "cuda:0"
+    phi0_t = torch.tensor(phi0, dtype=torch.float64, device=dev)
+    grav = torch.zeros(2, dtype=torch.float64)
+    base = torch.tensor(case.theta, dtype=torch.float64)
+    target = trajectory_phi(phi0_t, grav, base, case, 1500, chk=300).detach()
+
+    def loss_grad(theta_bottom):
+        th = base.clone()
+        th[2] = theta_bottom
+        th.requires_grad_(True)
+        phi = trajectory_phi(phi0_t, grav, th, case, 1500, chk=300)
+        loss = ((phi - target) ** 2).sum()
+        loss.backward()
+        return float(loss), float(th.grad[2])
+
+    t_prev, t = math.radians(90.0), math.radians(85.0)
+    _, g_prev = loss_grad(t_prev)
+    for it in range(8):
+        L, g = loss_grad(t)
+        print(f"iteration {it}: theta {math.degrees(t):.4f} deg, L {L:.3e}, dL/dtheta {g:.3e}", flush=True)
+        if abs(math.degrees(t) - 70.0) < 1e-3:
+            break
+        t_prev, t, g_prev = t, t - g * (t - t_prev) / (g - g_prev), g
+    assert abs(math.degrees(t) - 70.0) < 0.01, math.degrees(t)
