@@ -58,6 +58,13 @@ int validate(const lbm_params* p) {
     return LBM_OK;
 }
 
+// The collision with the default rates compiled in (KParams::rates_std):
+// LBM_STD_RATES = 1 for FP32 and FP64, 2 for FP32 only, 0 never.
+#ifndef LBM_STD_RATES
+#define LBM_STD_RATES 1
+#endif
+static bool std_rates_enabled(size_t esz) { return LBM_STD_RATES == 1 || (LBM_STD_RATES == 2 && esz == 4); }
+
 template <typename T>
 KParams<T> resolve(const lbm_params* p, const Layout& L) {
     KParams<T> K;
@@ -107,7 +114,7 @@ KParams<T> resolve(const lbm_params* p, const Layout& L) {
         K.sf[i] = (T)sf[i];
         K.sg[i] = (T)sg[i];
     }
-    K.rates_std = sf[0] == 1.0 && sf[1] == 1.0 && sf[2] == 1.0 && sf[4] == 1.0 && sf[6] == 1.0 && sf[7] == 1.0 &&
+    K.rates_std = std_rates_enabled(sizeof(T)) && sf[0] == 1.0 && sf[1] == 1.0 && sf[2] == 1.0 && sf[4] == 1.0 && sf[6] == 1.0 && sf[7] == 1.0 &&
                   sf[8] == 1.0 && sg[0] == 1.0 && sg[1] == 1.0 && sg[2] == 1.0 && sg[3] == 1.0 && sg[5] == 1.0;
     K.Gx = (T)p->body_force[0];
     K.Gy = (T)p->body_force[1];

@@ -50,6 +50,7 @@ struct KParams {
     int pf;               // phase-field equation: 0 Allen-Cahn, 1 Cahn-Hilliard
     int grad;             // grad phi: 0 stencil (Eq. central1), 1 local scheme (Eq. local)
     int rates_std;        // every MRT rate is 1 but s_f^3, s_f^5, s_g^4, s_g^6, s_g^7, s_g^8
+                          // (and LBM_STD_RATES allows the compiled-in collision for this dtype)
     long long plane;      // elements between two population planes
     T phiA, phiB, phim;   // phim = (phiA + phiB) / 2
     T beta4, kap;         // 4 beta, k (Sec. 2)
