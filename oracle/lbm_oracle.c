@@ -22,6 +22,19 @@
  *   9. g collision in moment space (Remark 2, Eq. MgMF1)
  *  10. history <- current products
  *  11. streaming with half-way bounce-back (Sec. 4 preamble)
+ * Options: the Cahn-Hilliard phase field replaces the AC flux by the one of
+ * Eq. CHE and the f moments by Eq. MfMRCH1 (after step 4, ch_flux); the
+ * corrected comparison model adds F_a = a u and solves step 5 with it
+ * (ch_flux / ac_corrected_force); the local gradient scheme replaces step 3's
+ * grad phi of levels >= 1 by Eq. local (local_gradient).
+ *
+ * Pins (tests/test_oracle_*.py): every stage above against a closed form, a
+ * textbook identity or the paper's printed values, including the CH moments,
+ * the corrected model's F_a (periodic closed forms) and the local gradient
+ * (tanh derivative).  Parity unpinned, checked only against the GPU path:
+ * the values of the diagnostics S_m^rms, D_u^rms; the wall rules that the
+ * paper leaves open -- the mirror of mu_phi at walls (Cahn-Hilliard) and the
+ * mirror of D with reversed normal component (corrected AC model).
  */
 #include "lbm_oracle.h"
 
