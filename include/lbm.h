@@ -95,8 +95,8 @@ typedef enum {
                                  + B n with A' = -M_phi - cs^2/2 + phi mu_phi/(4 rho), B = M_phi lambda,
                                  u0 the velocity without F_s; |grad phi| = (|C0| + B)/(-A') clamped at 0.
                                  The history then holds m^phiC of the previous level too (22 planes per
-                                 copy instead of 20).  lbm_init, lbm_step, lbm_moments, lbm_diagnostics and
-                                 batches; export, import and the reverse mode return LBM_E_UNSUPPORTED */
+                                 copy instead of 20).  Every call but the reverse mode (LBM_E_UNSUPPORTED);
+                                 export and import carry the five history planes */
 } lbm_grad;
 
 /* Problem statement in the paper's notation (Sec. 2; Sec. 4 preamble). */
@@ -163,16 +163,16 @@ int lbm_diagnostics(const lbm_params *p, const void *state, double *out /* host 
                     void *stream);
 
 /* Post-streaming populations f^n, g^n ([9][ny][nx] each, either may be NULL),
- * phi and u of level n-1 (hist: [3][ny][nx] = phi, u, v; NULL to skip), and the
- * step index n (host int64, NULL to skip).  Synchronises the stream when step
- * is requested.  Not with the local gradient scheme, whose history has five
- * planes (LBM_E_UNSUPPORTED). */
+ * phi and u of level n-1 (hist: [3][ny][nx] = phi, u, v; [5][ny][nx] with
+ * m^phiC_x, m^phiC_y of level n-1 appended for the local gradient scheme; NULL
+ * to skip), and the step index n (host int64, NULL to skip).  Synchronises the
+ * stream when step is requested. */
 int lbm_export_state(const lbm_params *p, const void *state, void *f, void *g, void *hist,
                      int64_t *step, void *stream);
 
 /* Inverse of lbm_export_state: load post-streaming f^n, g^n and the level
- * n-1 history (ignored when n == 0) as the state of step n.  Not with the local
- * gradient scheme (LBM_E_UNSUPPORTED). */
+ * n-1 history (same planes as lbm_export_state; ignored when n == 0) as the
+ * state of step n. */
 int lbm_import_state(const lbm_params *p, void *state, const void *f, const void *g,
                      const void *hist, int64_t step, void *stream);
 

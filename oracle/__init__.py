@@ -75,6 +75,8 @@ def lib():
         L.orc_rates.argtypes = [ctypes.c_void_p, d, d]
         L.orc_stencils.argtypes = [ctypes.c_void_p, d, d, d, d]
         L.orc_grad.argtypes = [ctypes.c_void_p, d, d]
+        L.orc_set_state_m.argtypes = [ctypes.c_void_p, d, d, d, d, d, ctypes.c_long]
+        L.orc_flux.argtypes = [ctypes.c_void_p, d, d]
         L.orc_set_threads.argtypes = [ctypes.c_int]
         L.orc_set_threads.restype = None
         L.orc_lattice.argtypes = [P(ctypes.c_int), P(ctypes.c_int), d, d, d]
@@ -85,7 +87,8 @@ def lib():
         L.orc_moments_g.argtypes = [P(OrcParams)] + [ctypes.c_double] * 13 + [d, d]
         L.orc_direct_g.argtypes = [P(OrcParams)] + [ctypes.c_double] * 13 + [d, d]
         for name in ("orc_init", "orc_step", "orc_moments", "orc_diagnostics",
-                     "orc_get_state", "orc_set_state", "orc_rates", "orc_grad"):
+                     "orc_get_state", "orc_set_state", "orc_rates", "orc_grad", "orc_set_state_m",
+                     "orc_flux"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -193,14 +196,26 @@ class OracleSim:
         assert rc == 0, rc
         return gx, gy
 
-    def set_state(self, f, g, step, phi_prev=None, u_prev=None):
+    def set_state(self, f, g, step, phi_prev=None, u_prev=None, m_prev=None):
+        """Load post-streaming f, g of level `step` and the level step-1 history:
+        phi, u and, for the local gradient scheme, m^phiC (m_prev, [2][ny][nx])."""
         f = _f64(f).reshape((9,) + self.shape)
         g = _f64(g).reshape((9,) + self.shape)
         pp = None if phi_prev is None else _f64(phi_prev).reshape(self.shape)
         up = None if u_prev is None else _f64(u_prev).reshape((2,) + self.shape)
-        rc = lib().orc_set_state(self.h, _dp(f), _dp(g), _dp(pp), _dp(up), int(step))
+        if m_prev is None:
+            rc = lib().orc_set_state(self.h, _dp(f), _dp(g), _dp(pp), _dp(up), int(step))
+        else:
+            mp = _f64(m_prev).reshape((2,) + self.shape)
+            rc = lib().orc_set_state_m(self.h, _dp(f), _dp(g), _dp(pp), _dp(up), _dp(mp), int(step))
         assert rc == 0, rc
         return self
+
+    def flux(self):
+        """m^phiC of the current level, [2][ny][nx]."""
+        m = np.empty((2,) + self.shape)
+        assert lib().orc_flux(self.h, _dp(m[0]), _dp(m[1])) == 0
+        return m
 
     def stencils(self, phi):
         phi = _f64(phi).reshape(self.shape)

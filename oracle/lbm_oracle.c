@@ -816,6 +816,18 @@ int orc_grad(const orc_sim *cs, double *gx, double *gy) {
     return 0;
 }
 
+/* m^phiC of the current level (Eq. mPhiC for the Allen-Cahn model, the
+ * Cahn-Hilliard flux of Eq. CHE otherwise; zero for the original and
+ * corrected models). */
+int orc_flux(const orc_sim *cs, double *mx, double *my) {
+    orc_sim *s = (orc_sim *)cs;
+    if (!s || !mx || !my) return -1;
+    macroscopic(s);
+    memcpy(mx, s->mx, sizeof(double) * s->n);
+    memcpy(my, s->my, sizeof(double) * s->n);
+    return 0;
+}
+
 int orc_moments(const orc_sim *cs, double *phi, double *u, double *p) {
     orc_sim *s = (orc_sim *)cs;
     if (!s) return -1;
@@ -845,8 +857,17 @@ int orc_get_state(const orc_sim *s, double *f, double *g, double *H, double *phi
 
 int orc_set_state(orc_sim *s, const double *f, const double *g, const double *phi_prev,
                   const double *u_prev, long step) {
+    if (s && s->P.grad == 1 && step > 0) return -8; /* the local scheme's history needs m^phiC */
+    return orc_set_state_m(s, f, g, phi_prev, u_prev, NULL, step);
+}
+
+/* As orc_set_state; m_prev ([2][n], m^phiC of level n-1), when given, replaces
+ * the one the closure would compute from phi_prev (the local gradient scheme
+ * keeps it as history). */
+int orc_set_state_m(orc_sim *s, const double *f, const double *g, const double *phi_prev,
+                    const double *u_prev, const double *m_prev, long step) {
     if (!s || !f || !g || step < 0) return -1;
-    if (s->P.grad == 1 && step > 0) return -8; /* the history of m^phiC would need the local gradient */
+    if (s->P.grad == 1 && step > 0 && !m_prev) return -1;
     long n = s->n;
     memcpy(s->f, f, sizeof(double) * 9 * n);
     memcpy(s->g, g, sizeof(double) * 9 * n);
@@ -866,7 +887,7 @@ int orc_set_state(orc_sim *s, const double *f, const double *g, const double *ph
         if (s->P.pf == 1) ch_flux(s, s->mu, s->mx, s->my);
         for (long k = 0; k < n; k++) {
             double u = u_prev[k], v = u_prev[n + k], ph = phi_prev[k];
-            double mx = s->mx[k], my = s->my[k];
+            double mx = m_prev ? m_prev[k] : s->mx[k], my = m_prev ? m_prev[n + k] : s->my[k];
             double P[5] = {ph * u, ph * v, u * mx, v * my, u * my + v * mx};
             for (int j = 0; j < 5; j++) s->H[j * n + k] = P[j];
         }

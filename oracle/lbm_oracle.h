@@ -76,6 +76,9 @@ void orc_set_threads(int n);   /* OpenMP threads of the following calls (n > 0) 
 /* ---- building blocks exposed for the pins ---- */
 /* grad phi and lap phi of an arbitrary field with this lattice's ghost rule. */
 int orc_grad(const orc_sim *s, double *gx, double *gy);
+int orc_flux(const orc_sim *s, double *mx, double *my);
+int orc_set_state_m(orc_sim *s, const double *f, const double *g, const double *phi_prev,
+                    const double *u_prev, const double *m_prev, long step);
 int orc_stencils(const orc_sim *s, const double *phi, double *gx, double *gy, double *lap);
 void orc_lattice(int cx[9], int cy[9], double w[9], double M[81], double Minv[81]);
 /* Wetting wall value and ghost value for one wall-normal line (Eq. Dwetting). */

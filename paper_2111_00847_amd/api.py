@@ -117,11 +117,17 @@ def lbm_diagnostics(p, state, stream=None, raise_nonfinite=False):
     return dict(zip(DIAG_NAMES, list(out)))
 
 
+def hist_planes(p):
+    """History planes per node: phi, u, v of the previous level, plus m^phiC for
+    the local gradient scheme."""
+    return 5 if p.grad_scheme == 1 else 3
+
+
 def lbm_export_state(p, state, f=None, g=None, hist=None, stream=None):
     shp = (p.ny, p.nx)
     st = ctypes.c_int64()
     call("lbm_export_state", ctypes.byref(p), _state_ptr(state), _ptr(f, p, (9,) + shp, "f"),
-         _ptr(g, p, (9,) + shp, "g"), _ptr(hist, p, (3,) + shp, "hist"), ctypes.byref(st),
+         _ptr(g, p, (9,) + shp, "g"), _ptr(hist, p, (hist_planes(p),) + shp, "hist"), ctypes.byref(st),
          _stream(stream))
     return st.value
 
@@ -129,7 +135,7 @@ def lbm_export_state(p, state, f=None, g=None, hist=None, stream=None):
 def lbm_import_state(p, state, f, g, hist, step, stream=None):
     shp = (p.ny, p.nx)
     call("lbm_import_state", ctypes.byref(p), _state_ptr(state), _ptr(f, p, (9,) + shp, "f"),
-         _ptr(g, p, (9,) + shp, "g"), _ptr(hist, p, (3,) + shp, "hist"), int(step),
+         _ptr(g, p, (9,) + shp, "g"), _ptr(hist, p, (hist_planes(p),) + shp, "hist"), int(step),
          _stream(stream))
 
 

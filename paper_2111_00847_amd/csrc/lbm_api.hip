@@ -347,7 +347,6 @@ int lbm_export_state(const lbm_params* p, const void* state, void* f, void* g, v
                      void* stream) {
     int rc = validate(p);
     if (rc) return rc;
-    if (p->grad_scheme == LBM_GRAD_LOCAL) return LBM_E_UNSUPPORTED;
     if (!state) return LBM_E_NULL;
     Layout L = layout_of(p);
     hipStream_t s = (hipStream_t)stream;
@@ -373,7 +372,6 @@ int lbm_import_state(const lbm_params* p, void* state, const void* f, const void
                      int64_t step, void* stream) {
     int rc = validate(p);
     if (rc) return rc;
-    if (p->grad_scheme == LBM_GRAD_LOCAL) return LBM_E_UNSUPPORTED;
     if (!state || !f || !g) return LBM_E_NULL;
     if (step < 0) return LBM_E_SIZE;
     if (step > 0 && !hist) return LBM_E_NULL;

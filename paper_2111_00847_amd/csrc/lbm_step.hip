@@ -237,8 +237,8 @@ __global__ void k_export(KParams<T> P, char* state, size_t off0, size_t off1, si
         }
         if (g)
             for (int i = 0; i < Q; i++) g[i * n + k] = pull(S.g, P, i, x, y);
-        if (hist)
-            for (int j = 0; j < 3; j++) hist[j * n + k] = S.h[j * P.plane + k];
+        if (hist)   // phi, u, v of level n-1 (and m^phiC of level n-1 for the local gradient scheme)
+            for (int j = 0; j < (P.grad == 1 ? 5 : 3); j++) hist[j * n + k] = S.h[j * P.plane + k];
     }
 }
 
@@ -248,7 +248,7 @@ __global__ void k_copy_hist(KParams<T> P, const T* hist, char* dst_base) {
     const long long n = (long long)P.nx * P.ny;
     for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n;
          k += (long long)gridDim.x * blockDim.x)
-        for (int j = 0; j < 3; j++) D.h[j * P.plane + k] = hist ? hist[j * n + k] : T(0);
+        for (int j = 0; j < (P.grad == 1 ? 5 : 3); j++) D.h[j * P.plane + k] = hist ? hist[j * n + k] : T(0);
 }
 
 __global__ void k_set_header(StateHeader* H, int nx, int ny, int dtype) {

@@ -67,7 +67,7 @@ class Sim:
     def export_state(self):
         f = torch.empty((9,) + self.shape, dtype=self.dtype, device=self.device)
         g = torch.empty_like(f)
-        h = torch.empty((3,) + self.shape, dtype=self.dtype, device=self.device)
+        h = torch.empty((api.hist_planes(self.p),) + self.shape, dtype=self.dtype, device=self.device)
         self._enter()
         step = api.lbm_export_state(self.p, self.state, f, g, h, self.stream)
         self._leave()

@@ -1,7 +1,10 @@
 """The Allen-Cahn step with the local gradient scheme (Eq. local) on the GPU
-against the oracle, through the C ABI.  Trajectories from lbm_init (the scheme's
-history of m^phiC cannot be imported): FP64 within 1e-10, FP32 within
-max|dphi| <= 1e-5 and max|du|/Umax <= 1e-4; ragged tiles, all boundary kinds."""
+against the oracle, through the C ABI.  One-step maps from an imported state
+whose history carries m^phiC of the previous level (FP64 within 1e-14), and
+trajectories from lbm_init: FP64 within 1e-10, FP32 within max|dphi| <= 1e-5 and
+max|du|/Umax <= 1e-4; ragged tiles, all boundary kinds."""
+import math
+
 import numpy as np
 import pytest
 
@@ -40,6 +43,89 @@ CASES = {
     "spreading_128x64": (lambda dt: W.spreading_case(128, 64, 60.0, dtype=dt)[0],
                          lambda case: W.spreading_case(128, 64, 60.0)[1], 1000),
 }
+
+
+GEOMS = {
+    "periodic": dict(),
+    "walls_y": dict(wall_y=True, theta=(math.pi / 2, math.pi / 2, math.radians(50), math.radians(120))),
+    "walls_x": dict(wall_x=True, theta=(math.radians(60), math.radians(130), math.pi / 2, math.pi / 2)),
+    "walls_xy": dict(wall_x=True, wall_y=True,
+                     theta=(math.radians(70), math.radians(110), math.radians(40), math.radians(140))),
+}
+
+
+def _random_local_state(case, seed):
+    """A smooth random level-n state near equilibrium plus noise, and a level
+    n-1 history phi, u, m^phiC (the stencil closure's flux of phi_prev plus
+    noise, so that the imported flux is not one the step could recompute)."""
+    phi0, u0, p0 = W.random_state_fields(case, seed=seed)
+    o = oracle.OracleSim(case.replace(dtype="f64", grad_scheme="stencil")).init(phi0, u0, p0)
+    st = o.get_state()
+    rng = np.random.default_rng(seed + 1)
+    f = st["f"] + 1e-4 * rng.standard_normal(st["f"].shape)
+    g = st["g"] + 1e-5 * rng.standard_normal(st["g"].shape)
+    phi_prev = phi0 + 1e-3 * rng.standard_normal(phi0.shape)
+    u_prev = u0 + 1e-4 * rng.standard_normal(u0.shape)
+    m_prev = o.flux() + 1e-4 * rng.standard_normal((2,) + phi0.shape)
+    return f, g, phi_prev, u_prev, m_prev
+
+
+@pytest.mark.parametrize("geom", list(GEOMS))
+@pytest.mark.parametrize("shape", [(37, 23), (130, 19), (5, 70)])
+@pytest.mark.parametrize("step", [0, 5])
+def test_local_one_step_map_fp64(geom, shape, step):
+    """One GPU step of the local scheme from an imported state (five history
+    planes) equals one oracle step from the same state; the exported level-n
+    history is phi, u and the scheme's m^phiC of level n."""
+    from paper_2111_00847_amd.sim import Sim
+    nx, ny = shape
+    case = W.Case(nx=nx, ny=ny, rhoA=20.0, rhoB=1.0, nuA=0.05, nuB=0.2, sigma=0.01, W=4.0, M=0.05,
+                  body_force=(1e-6, -2e-6), gravity=(0.0, -1e-5), rho_ref=3.0, dtype="f64",
+                  grad_scheme="local", **GEOMS[geom])
+    f, g, php, upr, mpr = _random_local_state(case, seed=nx * 5 + ny)
+    hist = np.concatenate([php[None], upr, mpr], 0)
+    gs = Sim(case).import_state(f, g, hist if step > 0 else None, step)
+    exp = gs.export_state()
+    assert exp["step"] == step and exp["hist"].shape[0] == 5
+    np.testing.assert_array_equal(exp["f"].cpu().numpy(), f)
+    if step > 0:
+        np.testing.assert_array_equal(exp["hist"].cpu().numpy(), hist)
+    gs.step(1)
+    args = (php, upr, mpr) if step > 0 else ()
+    o = oracle.OracleSim(case).set_state(f, g, step, *args).step(1)
+    so, sg = o.get_state(), gs.export_state()
+    assert sg["step"] == step + 1
+    df = np.abs(sg["f"].cpu().numpy() - so["f"]).max()
+    dg = np.abs(sg["g"].cpu().numpy() - so["g"]).max()
+    print(f"local {geom} {shape} step {step}: max|df|={df:.3e} max|dg|={dg:.3e}", flush=True)
+    assert df < 1e-14 and dg < 1e-14
+    lvl = oracle.OracleSim(case).set_state(f, g, step, *args)
+    phi_o, u_o, _ = lvl.moments()
+    m_o = lvl.flux()
+    h = sg["hist"].cpu().numpy()
+    np.testing.assert_allclose(h[0], phi_o, atol=1e-14)
+    np.testing.assert_allclose(h[1:3], u_o, atol=1e-15)
+    np.testing.assert_allclose(h[3:], m_o, atol=1e-15)
+
+
+def test_local_export_continues_in_the_oracle():
+    """The GPU's own state after 300 steps of the dam break (FP64), exported with
+    its five history planes, continues in the oracle as on the GPU for 20 steps."""
+    from paper_2111_00847_amd.sim import Sim
+    case, phi0 = W.dam_break(nx=64, ny=32, column=16, dtype="f64", theta_deg=70.0)
+    case = case.replace(grad_scheme="local")
+    p0 = W.hydrostatic_pressure(case, phi0)
+    gs = Sim(case).init(phi0, None, p0).step(300)
+    st = gs.export_state()
+    h = st["hist"].cpu().numpy()
+    o = oracle.OracleSim(case).set_state(st["f"].cpu().numpy(), st["g"].cpu().numpy(), 300,
+                                         h[0], h[1:3], h[3:]).step(20)
+    gs.step(20)
+    so, sg = o.get_state(), gs.export_state()
+    df = np.abs(sg["f"].cpu().numpy() - so["f"]).max()
+    dg = np.abs(sg["g"].cpu().numpy() - so["g"]).max()
+    print(f"local dam break 300 -> 320 from the export: max|df|={df:.3e} max|dg|={dg:.3e}", flush=True)
+    assert df < 1e-13 and dg < 1e-13
 
 
 @pytest.mark.parametrize("name", list(CASES))
