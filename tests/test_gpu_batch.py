@@ -161,12 +161,9 @@ def test_wide_batch_bitwise_equals_single(dtype, mode):
             _assert_same_state(B.case(c), alone, what)
             continue
         eps = np.finfo(np.float64 if dtype == "f64" else np.float32).eps
-        if case.grad_scheme == "local":   # no export of its five-plane history: compare the moments
-            pairs = zip(("phi", "u", "p"), B.case(c).moments(), alone.moments())
-        else:
-            sa, sb = B.case(c).export_state(), alone.export_state()
-            assert sa["step"] == sb["step"], what
-            pairs = ((key, sa[key], sb[key]) for key in ("f", "g", "hist"))
+        sa, sb = B.case(c).export_state(), alone.export_state()
+        assert sa["step"] == sb["step"], what
+        pairs = ((key, sa[key], sb[key]) for key in ("f", "g", "hist"))
         for key, xa, xb in pairs:
             ta, tb = xa.cpu().numpy(), xb.cpu().numpy()
             err = float(np.abs(ta - tb).max())
