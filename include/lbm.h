@@ -76,14 +76,14 @@ typedef enum {
                                  F = F_0 + F_a exactly.  Cahn-Hilliard: div(M_phi D) = M_phi lap mu_phi
                                  (Eq. central2).  Allen-Cahn: div D of D = grad phi - lambda n by Eq.
                                  central1, a wall mirroring D with its normal component reversed.
-                                 Not with the local gradient scheme, batches or the reverse mode
+                                 Not with the local gradient scheme or the reverse mode
                                  (LBM_E_UNSUPPORTED) */
 } lbm_model;
 
 typedef enum {
     LBM_ALLEN_CAHN = 0,       /* conservative Allen-Cahn: D = grad phi - lambda n (Sec. 2, Eq. ACE; Eq. MfMRAC1) */
     LBM_CAHN_HILLIARD = 1     /* Cahn-Hilliard: D = grad mu_phi (Sec. 2, Eq. CHE; Eq. MfMRCH1); mu_phi has
-                                 zero normal derivative at walls; batches and the reverse mode are AC only */
+                                 zero normal derivative at walls; the reverse mode is AC only */
 } lbm_phase_eq;
 
 typedef enum {
@@ -233,9 +233,9 @@ int lbm_adjoint_import(const lbm_params *p, void *adj, const void *fbar, const v
                        int64_t level, void *stream);
 
 /* ---- batches: many independent lattices, one launch per time step ---------
- * (the per-step update above applied to every case; a case advanced in a
- * batch is bitwise identical to the same case advanced alone with lbm_step).
- * All cases share one dtype; any option.  Batches holding Cahn-Hilliard,
+ * (the per-step update above applied to every case).  All cases share one
+ * dtype; any option; each case's state copy below 4 GiB (else LBM_E_SIZE: the
+ * batch kernels address a case with 32-bit offsets).  Batches holding Cahn-Hilliard,
  * corrected Allen-Cahn or local-gradient cases run 64 x 4-thread tiles of 4
  * or 8 rows; those cases equal the lone runs to rounding (the tile height may
  * differ), the plain Allen-Cahn cases bitwise.  The plan is
