@@ -89,3 +89,30 @@ def test_degenerate_lattices_in_one_batch(dtype, mix):
             else:
                 err = float(np.abs(ta - tb).max())
                 assert err <= 16 * eps * max(1.0, float(np.abs(tb).max())), (case.name, key, err)
+
+
+def test_zero_steps_is_a_no_op_and_negative_counts_are_refused():
+    """lbm_step / lbm_batch_step with nsteps = 0 leave the state untouched; a
+    negative count is LBM_E_SIZE and also leaves it untouched."""
+    from paper_2111_00847_amd import api
+    from paper_2111_00847_amd._lib import LbmError
+    from paper_2111_00847_amd.sim import BatchSim, Sim
+    case, phi0, u0, p0 = _case("5x2_walls_y", "present")
+    s = Sim(case).init(phi0, u0, p0).step(3)
+    torch.cuda.synchronize()
+    before = s.state.clone()
+    s.step(0)
+    with pytest.raises(LbmError) as e:
+        api.lbm_step(s.p, s.state, -1)
+    assert e.value.code == -2
+    torch.cuda.synchronize()
+    assert torch.equal(before, s.state)
+    assert s.export_state()["step"] == 3
+    B = BatchSim([case, case.replace(nx=7)])
+    B.init([phi0, np.tile(phi0, (1, 2))[:, :7]], [p0, np.tile(p0, (1, 2))[:, :7]])
+    B.step(2)
+    torch.cuda.synchronize()
+    before = B.state.clone()
+    B.step(0)
+    torch.cuda.synchronize()
+    assert torch.equal(before, B.state)
