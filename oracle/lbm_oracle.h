@@ -65,6 +65,11 @@ int orc_get_state(const orc_sim *s, double *f, double *g, double *H, double *phi
  * from phi_prev with this file's own stencil and closure. */
 int orc_set_state(orc_sim *s, const double *f, const double *g, const double *phi_prev,
                   const double *u_prev, long step);
+/* As orc_set_state, with m^phiC of level step-1 (m_prev, [2][n]) given rather
+ * than recomputed: the local gradient scheme's history (required for it when
+ * step > 0; orc_set_state refuses that case with -8). */
+int orc_set_state_m(orc_sim *s, const double *f, const double *g, const double *phi_prev,
+                    const double *u_prev, const double *m_prev, long step);
 /* Resolved relaxation rates: s_f (9) and constant part of s_g (9; entries 7, 8
  * are -1 when they follow the local viscosity). */
 int orc_rates(const orc_sim *s, double sf[9], double sg[9]);
@@ -74,11 +79,12 @@ int orc_num_threads(void);
 void orc_set_threads(int n);   /* OpenMP threads of the following calls (n > 0) */
 
 /* ---- building blocks exposed for the pins ---- */
-/* grad phi and lap phi of an arbitrary field with this lattice's ghost rule. */
+/* grad phi of the current level as the step uses it (the stencil, or Eq.
+ * local for the local gradient scheme at levels >= 1). */
 int orc_grad(const orc_sim *s, double *gx, double *gy);
+/* m^phiC of the current level (zero for the original and corrected models). */
 int orc_flux(const orc_sim *s, double *mx, double *my);
-int orc_set_state_m(orc_sim *s, const double *f, const double *g, const double *phi_prev,
-                    const double *u_prev, const double *m_prev, long step);
+/* grad phi and lap phi of an arbitrary field with this lattice's ghost rule. */
 int orc_stencils(const orc_sim *s, const double *phi, double *gx, double *gy, double *lap);
 void orc_lattice(int cx[9], int cy[9], double w[9], double M[81], double Minv[81]);
 /* Wetting wall value and ghost value for one wall-normal line (Eq. Dwetting). */
