@@ -143,7 +143,9 @@ int lbm_init(const lbm_params *p, void *state, const void *phi0, const void *u0,
 /* Advance nsteps >= 0 time steps (Sec. 3): moments, closure, both MRT
  * collisions and streaming with bounce-back, fused in one kernel per step.
  * On a non-NULL stream, runs of >= 64 steps replay a captured graph of 32
- * steps (cached per params, state and stream).  Every option. */
+ * steps (cached per params, state and stream); while the caller captures the
+ * stream itself, the kernels are launched into the caller's graph instead.
+ * Every option. */
 int lbm_step(const lbm_params *p, void *state, int64_t nsteps, void *stream);
 
 /* Order parameter, velocity (Eq. comU) and pressure (Eq. computP) of the
@@ -240,8 +242,8 @@ int lbm_adjoint_import(const lbm_params *p, void *adj, const void *fbar, const v
  * or 8 rows; those cases equal the lone runs to rounding (the tile height may
  * differ), the plain Allen-Cahn cases bitwise.  The plan is
  * library-owned (a small device table of the cases and, once lbm_batch_step
- * runs on a non-NULL stream with nsteps >= 32, a captured hipGraph of 32
- * steps for that state and stream). */
+ * runs on a non-NULL stream with nsteps >= 32 that the caller is not
+ * capturing, a captured hipGraph of 32 steps for that state and stream). */
 typedef struct lbm_batch lbm_batch;
 
 /* Plan a batch of `ncases` lattices (cases: host array of ncases lbm_params).

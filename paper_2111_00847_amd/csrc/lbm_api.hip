@@ -140,11 +140,12 @@ template KParams<double> resolve<double>(const lbm_params*, const Layout&);
 
 // Shape of the step launch: 64 x TY tiles on workgroups of 64 x BY threads.
 // Taller tiles amortise the one-node halo ring; more waves hide latency.
-// Measured on MI355X (FP32): lattices of >= 4096 16-row tiles run best at
-// (8, 8) (30.4 GLUPS on 4096^2, within 3.5% of every other shape); below that
-// the step is latency bound and the tallest tile that still gives >= 4096
-// waves wins: (16, 8) for 1024 x 512 (27.1 vs 22.4 at (8, 8)), (8, 8) for
-// 256 x 1024 (24.8 vs 22.9 at (16, 8)), else (4, 4).  FP64 tiles stop at 8 rows
+// Measured on MI355X (FP32): lattices of >= 2048 16-row tiles run best at
+// (8, 8) (30.9 GLUPS on 4096^2, within 3.5% of every other shape; 26.1 vs 25.1
+// at (16, 8) on 2048 x 1024); below that the step is latency bound and the
+// tallest tile that still gives >= 4096 waves wins: (16, 8) for 1024 x 512
+// (27.2 vs 21.8 at (8, 8)), (8, 8) for 256 x 1024 (27.4 vs 25.5 at (16, 8)),
+// else (4, 4).  FP64 tiles stop at 8 rows
 // (taller ones spill); (8, 4) measured best for FP64.
 #ifndef LBM_STEP_TY
 #define LBM_STEP_TY 0   // force a tile height (4, 8, 16); 0 = by lattice size
@@ -159,7 +160,7 @@ void step_shape(const lbm_params* p, int* ty, int* by) {
     if (p->dtype == LBM_F64) {
         t = 8;
         b = 4;
-    } else if (t16 >= 4096) {
+    } else if (t16 >= 2048) {
         t = 8;
         b = 8;
     } else if (t16 * 8 >= 4096) {
@@ -268,8 +269,15 @@ int lbm_step(const lbm_params* p, void* state, int64_t nsteps, void* stream) {
         return launch_step<double>(resolve<double>(p, L), (char*)state, L, n, s, ty, by);
     };
     hipError_t e;
-    // Long runs on a capturable (non-NULL) stream replay a graph of GRAPH_K steps.
+    // Long runs on a non-NULL stream replay a graph of GRAPH_K steps, unless the
+    // caller is capturing that stream itself (the plain launches then go into
+    // the caller's graph).
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (s != nullptr && nsteps >= 2 * GRAPH_K) {
+        e = hipStreamIsCapturing(s, &cs);
+        if (e != hipSuccess) return hip_fail(e);
+    }
+    if (s != nullptr && nsteps >= 2 * GRAPH_K && cs == hipStreamCaptureStatusNone) {
         std::lock_guard<std::mutex> lock(g_graph_mu);
         size_t hit = g_graphs.size();
         for (size_t i = 0; i < g_graphs.size(); i++)

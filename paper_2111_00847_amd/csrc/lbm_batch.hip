@@ -226,7 +226,13 @@ template <typename T>
 int batch_step_t(lbm_batch* B, char* state, int64_t nsteps, hipStream_t s) {
     constexpr int K = 32;   // steps per captured graph
     hipError_t e;
+    // not while the caller captures the stream: the launches go into its graph
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (s != nullptr && nsteps >= K) {
+        e = hipStreamIsCapturing(s, &cs);
+        if (e != hipSuccess) return hip_fail(e);
+    }
+    if (s != nullptr && nsteps >= K && cs == hipStreamCaptureStatusNone) {
         if (!B->graph || B->graph_state != state || B->graph_stream != s) {
             drop_graph(B);
             hipGraph_t g;

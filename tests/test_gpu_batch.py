@@ -105,6 +105,40 @@ def test_plain_step_graph_equals_eager():
     _assert_same_state(a, b, "rti 128x256 graph vs eager")
 
 
+def test_steps_captured_by_the_caller_replay_like_eager_launches():
+    """lbm_step and lbm_batch_step called while the caller captures the stream
+    (long enough runs that would otherwise use the library's own graphs) go into
+    the caller's graph; each of three replays, with eager work and
+    synchronisations between them, advances the state as eager launches do."""
+    Sim, BatchSim = _mods()
+    case, phi0 = W.rti(nx=128, ny=256)
+    p0 = W.hydrostatic_pressure(case, phi0)
+    cases = _mixed_cases("f32")[:3]
+    p0s = [W.hydrostatic_pressure(c, p) for c, p in cases]
+    s = torch.cuda.Stream()
+    a = Sim(case, stream=s).init(phi0, None, p0)
+    B = BatchSim([c for c, _ in cases], stream=s)
+    B.init([p for _, p in cases], p0s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        a.step(100)
+        B.step(40)
+    ref = Sim(case).init(phi0, None, p0)
+    ref_b = [Sim(c).init(p, None, q) for (c, p), q in zip(cases, p0s)]
+    for rep in range(1, 4):
+        g.replay()
+        torch.cuda.synchronize()
+        ref.step(100)
+        for r in ref_b:
+            r.step(40)
+        _ = torch.ones(1000, device="cuda").sum().item()     # eager work between replays
+        torch.cuda.synchronize()
+        _assert_same_state(a, ref, f"captured lbm_step, replay {rep}")
+        for c, r in enumerate(ref_b):
+            _assert_same_state(B.case(c), r, f"captured lbm_batch_step case {c}, replay {rep}")
+
+
 def test_batch_case_view_rejects_bad_index():
     from paper_2111_00847_amd._lib import LbmError
     _, BatchSim = _mods()
