@@ -34,13 +34,8 @@ template <typename T, typename OFF>
 __device__ __forceinline__ T ld(const char* base, OFF byteoff) {
     return *reinterpret_cast<const T*>(base + byteoff);
 }
-// Tuning knobs (compile time, measured on MI355X): non-temporal stores for
-// the streamed state (+3% on a 4096^2 lattice); g loaded after the window
-// barrier (prefetching it with f gained nothing and costs registers); tiles
-// dealt to XCDs in bands (+11% on 256 x 1024, neutral on 4096^2).
-#ifndef LBM_NT_STORES
-#define LBM_NT_STORES 1
-#endif
+// Tuning knob (compile time, measured on MI355X): tiles dealt to XCDs in
+// bands (+11% on 256 x 1024, neutral on 4096^2).
 #ifndef LBM_XCD_REMAP
 #define LBM_XCD_REMAP 1
 #endif
@@ -62,9 +57,12 @@ __device__ __forceinline__ T ld(const char* base, OFF byteoff) {
 #define LBM_RING_EARLY -1
 #endif
 
-template <typename T, typename OFF>
+// Store of the streamed state: non-temporal (NT) unless the caller knows the
+// state stays in the last-level cache between steps.  Non-temporal stores gain
+// 4-5% on 2.9-5.9 GB states; ordinary ones gain 1-4.5% on 46-92 MB states.
+template <typename T, typename OFF, bool NT = true>
 __device__ __forceinline__ void st(char* base, OFF byteoff, T v) {
-    if (LBM_NT_STORES) __builtin_nontemporal_store(v, reinterpret_cast<T*>(base + byteoff));
+    if (NT) __builtin_nontemporal_store(v, reinterpret_cast<T*>(base + byteoff));
     else *reinterpret_cast<T*>(base + byteoff) = v;
 }
 
@@ -117,7 +115,7 @@ struct StepWaves {
 // The tile body between explicit buffers: `src` holds level `step` (one copy:
 // post-collision populations of the previous step and the history), `dst`
 // receives level step + 1.
-template <typename T, int TY, int MODE, typename OFF, int NBY = BY, bool STD = false>
+template <typename T, int TY, int MODE, typename OFF, int NBY = BY, bool STD = false, bool NT = true>
 __device__ __forceinline__ void step_core(const KParams<T>& P, const char* src, char* dst, int64_t step, int xt,
                                           int yt, T* out_phi, T* out_u, T* out_p, T (*sphi)[TX + 3],
                                           T (*sphp)[TX + 3]) {
@@ -359,20 +357,20 @@ __device__ __forceinline__ void step_core(const KParams<T>& P, const char* src, 
         }
         const double f0n = collide_f<T, false, STD>(P, M, f[r], phid[r]);
         collide_g<T, STD>(P, M, g);
-        st<double>(dst, (OFF)8 * k, f0n);
+        st<double, OFF, NT>(dst, (OFF)8 * k, f0n);
 #pragma unroll
-        for (int i = 1; i < Q; i++) st<T>(dst, bF + ((OFF)(i - 1) * pl + k) * ES, f[r][i]);
+        for (int i = 1; i < Q; i++) st<T, OFF, NT>(dst, bF + ((OFF)(i - 1) * pl + k) * ES, f[r][i]);
 #pragma unroll
-        for (int i = 0; i < Q; i++) st<T>(dst, bG + ((OFF)i * pl + k) * ES, g[i]);
-        st<T>(dst, bH + k * ES, M.phi);
-        st<T>(dst, bH + (pl + k) * ES, M.u);
-        st<T>(dst, bH + (2 * pl + k) * ES, M.v);
+        for (int i = 0; i < Q; i++) st<T, OFF, NT>(dst, bG + ((OFF)i * pl + k) * ES, g[i]);
+        st<T, OFF, NT>(dst, bH + k * ES, M.phi);
+        st<T, OFF, NT>(dst, bH + (pl + k) * ES, M.u);
+        st<T, OFF, NT>(dst, bH + (2 * pl + k) * ES, M.v);
     }
 }
 
 // The tile body on a ping-pong state: the level stamp of the tile's first row
 // selects the source copy, and the tile's rows move to the next level.
-template <typename T, int TY, int MODE, typename OFF, int NBY = BY, bool STD = false>
+template <typename T, int TY, int MODE, typename OFF, int NBY = BY, bool STD = false, bool NT = true>
 __device__ __forceinline__ void step_tile(const KParams<T>& P, char* state, size_t off0, size_t off1,
                                           size_t off_stamp, int xt, int yt, T* out_phi, T* out_u, T* out_p,
                                           T (*sphi)[TX + 3], T (*sphp)[TX + 3]) {
@@ -380,7 +378,7 @@ __device__ __forceinline__ void step_tile(const KParams<T>& P, char* state, size
     int64_t* stamp = reinterpret_cast<int64_t*>(state + off_stamp) + (size_t)xt * P.ny + y0;
     const int64_t step = stamp[0];
     const int cur = (int)(step & 1);
-    step_core<T, TY, MODE, OFF, NBY, STD>(P, state + (cur ? off1 : off0), state + (cur ? off0 : off1), step, xt, yt, out_phi,
+    step_core<T, TY, MODE, OFF, NBY, STD, NT>(P, state + (cur ? off1 : off0), state + (cur ? off0 : off1), step, xt, yt, out_phi,
                                 out_u, out_p, sphi, sphp);
     // Own rows move to level n + 1.  Every wave of the workgroup consumed its
     // load of stamp[0] (it addresses all loads above) before the barriers of

@@ -23,7 +23,7 @@
 
 namespace lbm {
 
-template <typename T, int TY, int MODE, typename OFF, int NBY, bool STD>
+template <typename T, int TY, int MODE, typename OFF, int NBY, bool STD, bool NT = true>
 __global__ __launch_bounds__(TX* NBY) __attribute__((amdgpu_waves_per_eu(StepWaves<T, TY, NBY>::value)))
 void k_step(KParams<T> P, char* state, size_t off0, size_t off1, size_t off_stamp, int ntx, int nty, T* out_phi,
             T* out_u, T* out_p) {
@@ -36,7 +36,8 @@ void k_step(KParams<T> P, char* state, size_t off0, size_t off1, size_t off_stam
         xt = blockIdx.x % ntx;
         yt = blockIdx.x / ntx;
     }
-    step_tile<T, TY, MODE, OFF, NBY, STD>(P, state, off0, off1, off_stamp, xt, yt, out_phi, out_u, out_p, sphi, sphp);
+    step_tile<T, TY, MODE, OFF, NBY, STD, NT>(P, state, off0, off1, off_stamp, xt, yt, out_phi, out_u, out_p, sphi,
+                                              sphp);
 }
 
 // The Cahn-Hilliard variant and the corrected comparison model with the
@@ -272,13 +273,30 @@ static int grid1d(long long n) {
 // Byte size of one copy fits 32-bit offsets?
 static bool small_copy(const Layout& L) { return L.buf_bytes < (size_t(1) << 32); }
 
+// The plain step stores its state with ordinary stores while both copies fit
+// in this many bytes, so that the state stays in the 256 MB last-level cache
+// from one step to the next (measured on MI355X: +1% on 256 x 1024 FP32,
+// +2% in FP64, +4.5% on 1024 x 512), and non-temporally above (+4-5% on
+// 4096^2 FP32 and FP64).
+#ifndef LBM_NT_MIN_BYTES
+#define LBM_NT_MIN_BYTES (192ull << 20)
+#endif
+static bool cached_state(const Layout& L) { return 2 * L.buf_bytes <= (size_t)LBM_NT_MIN_BYTES; }
+
 template <typename T, int TY, int MODE, int NBY = BY>
 static void launch_tile(const KParams<T>& P, char* state, const Layout& L, hipStream_t s, T* phi, T* u, T* p) {
     const int ntx = (P.nx + TX - 1) / TX, nty = (P.ny + TY - 1) / TY;
     dim3 blk(TX, NBY);
     // the standard rates compiled in for steps (moments do not collide)
     const bool std_rates = MODE == 0 && P.rates_std;
-    if (small_copy(L)) {
+    if (MODE == 0 && cached_state(L)) {
+        if (std_rates)
+            k_step<T, TY, MODE, uint32_t, NBY, true, false><<<ntx * nty, blk, 0, s>>>(
+                P, state, L.off_buf[0], L.off_buf[1], L.off_stamp, ntx, nty, phi, u, p);
+        else
+            k_step<T, TY, MODE, uint32_t, NBY, false, false><<<ntx * nty, blk, 0, s>>>(
+                P, state, L.off_buf[0], L.off_buf[1], L.off_stamp, ntx, nty, phi, u, p);
+    } else if (small_copy(L)) {
         if (std_rates)
             k_step<T, TY, MODE, uint32_t, NBY, true><<<ntx * nty, blk, 0, s>>>(P, state, L.off_buf[0], L.off_buf[1],
                                                                                 L.off_stamp, ntx, nty, phi, u, p);
