@@ -59,7 +59,8 @@ __device__ __forceinline__ T ld(const char* base, OFF byteoff) {
 
 // Store of the streamed state: non-temporal (NT) unless the caller knows the
 // state stays in the last-level cache between steps.  Non-temporal stores gain
-// 4-5% on 2.9-5.9 GB states; ordinary ones gain 1-4.5% on 46-92 MB states.
+// 3-5% on states of 369 MB and more; ordinary ones 2-26% on states of up to
+// 277 MB.
 template <typename T, typename OFF, bool NT = true>
 __device__ __forceinline__ void st(char* base, OFF byteoff, T v) {
     if (NT) __builtin_nontemporal_store(v, reinterpret_cast<T*>(base + byteoff));

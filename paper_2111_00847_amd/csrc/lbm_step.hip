@@ -274,12 +274,14 @@ static int grid1d(long long n) {
 static bool small_copy(const Layout& L) { return L.buf_bytes < (size_t(1) << 32); }
 
 // The plain step stores its state with ordinary stores while both copies fit
-// in this many bytes, so that the state stays in the 256 MB last-level cache
-// from one step to the next (measured on MI355X: +1% on 256 x 1024 FP32,
-// +2% in FP64, +4.5% on 1024 x 512), and non-temporally above (+4-5% on
-// 4096^2 FP32 and FP64).
+// in this many bytes, so that the state (or most of it) stays in the 256 MB
+// last-level cache from one step to the next, and non-temporally above.
+// Measured on MI355X, FP32 (state of both copies): 256 x 1024 (46 MB) +2%,
+// 1024 x 512 (92 MB) +7%, 1024 x 1024 (184 MB) +26%, 1024 x 1536 (277 MB) +11%
+// with ordinary stores; 2048 x 1024 (369 MB) +3% and 4096^2 (2.9 GB) +5% with
+// non-temporal ones (FP64 4096^2 +5%).
 #ifndef LBM_NT_MIN_BYTES
-#define LBM_NT_MIN_BYTES (192ull << 20)
+#define LBM_NT_MIN_BYTES (320ull << 20)
 #endif
 static bool cached_state(const Layout& L) { return 2 * L.buf_bytes <= (size_t)LBM_NT_MIN_BYTES; }
 
