@@ -13,7 +13,7 @@ namespace lbm {
 // MODE 0: one time step, the tile's rows move to the next level; MODE 1:
 // phi, u, p of the current level into out_*.  W: the tile's LDS windows.
 // STD: the paper's default rates compiled in (P.rates_std).
-template <typename T, int TY, int MODE, bool ACC, bool STD = false>
+template <typename T, int TY, int MODE, bool ACC, bool STD = false, bool NT = true>
 __device__ __forceinline__ void ch_step_tile(const KParams<T>& P, char* state, size_t off0, size_t off1,
                                              size_t off_stamp, int xt, int yt, T* out_phi, T* out_u, T* out_p,
                                              ChWindow<T, TY>& W) {
@@ -36,12 +36,12 @@ __device__ __forceinline__ void ch_step_tile(const KParams<T>& P, char* state, s
         const double f0n = collide_f<T, !ACC, STD>(P, M, f, phid);
         collide_g<T, STD>(P, M, g);
         const long long pl = P.plane;
-        st<double, long long>(reinterpret_cast<char*>(D.f0), 8 * k, f0n);
-        for (int i = 1; i < Q; i++) st<T, long long>(reinterpret_cast<char*>(D.f), (long long)sizeof(T) * (i * pl + k), f[i]);
-        for (int i = 0; i < Q; i++) st<T, long long>(reinterpret_cast<char*>(D.g), (long long)sizeof(T) * (i * pl + k), g[i]);
-        st<T, long long>(reinterpret_cast<char*>(D.h), (long long)sizeof(T) * k, M.phi);
-        st<T, long long>(reinterpret_cast<char*>(D.h), (long long)sizeof(T) * (pl + k), M.u);
-        st<T, long long>(reinterpret_cast<char*>(D.h), (long long)sizeof(T) * (2 * pl + k), M.v);
+        st<double, long long, NT>(reinterpret_cast<char*>(D.f0), 8 * k, f0n);
+        for (int i = 1; i < Q; i++) st<T, long long, NT>(reinterpret_cast<char*>(D.f), (long long)sizeof(T) * (i * pl + k), f[i]);
+        for (int i = 0; i < Q; i++) st<T, long long, NT>(reinterpret_cast<char*>(D.g), (long long)sizeof(T) * (i * pl + k), g[i]);
+        st<T, long long, NT>(reinterpret_cast<char*>(D.h), (long long)sizeof(T) * k, M.phi);
+        st<T, long long, NT>(reinterpret_cast<char*>(D.h), (long long)sizeof(T) * (pl + k), M.u);
+        st<T, long long, NT>(reinterpret_cast<char*>(D.h), (long long)sizeof(T) * (2 * pl + k), M.v);
     });
     // every wave read stamp[0] before the barriers of the tile body
     const int tid = threadIdx.y * TX + threadIdx.x;

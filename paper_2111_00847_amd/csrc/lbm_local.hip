@@ -4,7 +4,8 @@
 // previous level (5 planes), since m^phiC of that level came from its own
 // local gradient.  One 64 x 8 tile per workgroup of 64 x 4 threads, the phi
 // window with a one-node ring in LDS (for lap phi), tiles dealt to the XCDs as
-// for the stencil step, non-temporal stores.
+// for the stencil step, the same store policy (non-temporal for states beyond
+// the last-level cache).
 #include "lbm_kernels.hpp"
 #include "lbm_local_step.hpp"
 
@@ -12,7 +13,7 @@ namespace lbm {
 
 constexpr int LOC_TY = 8;
 
-template <typename T, int MODE>
+template <typename T, int MODE, bool NT = true>
 __global__ __launch_bounds__(TX* BY) void k_step_local(KParams<T> P, char* state, size_t off0, size_t off1,
                                                       size_t off_stamp, int ntx, int nty, T* out_phi, T* out_u,
                                                       T* out_p) {
@@ -24,14 +25,18 @@ __global__ __launch_bounds__(TX* BY) void k_step_local(KParams<T> P, char* state
         xt = blockIdx.x % ntx;
         yt = blockIdx.x / ntx;
     }
-    local_step_tile<T, LOC_TY, MODE>(P, state, off0, off1, off_stamp, xt, yt, out_phi, out_u, out_p, sphi);
+    local_step_tile<T, LOC_TY, MODE, NT>(P, state, off0, off1, off_stamp, xt, yt, out_phi, out_u, out_p, sphi);
 }
 
 template <typename T, int MODE>
 void launch_local(const KParams<T>& P, char* state, const Layout& L, hipStream_t s, T* phi, T* u, T* p) {
     const int ntx = (P.nx + TX - 1) / TX, nty = (P.ny + LOC_TY - 1) / LOC_TY;
-    k_step_local<T, MODE><<<ntx * nty, dim3(TX, BY), 0, s>>>(P, state, L.off_buf[0], L.off_buf[1], L.off_stamp,
-                                                              ntx, nty, phi, u, p);
+    if (MODE == 0 && cached_state(L))
+        k_step_local<T, MODE, false><<<ntx * nty, dim3(TX, BY), 0, s>>>(P, state, L.off_buf[0], L.off_buf[1],
+                                                                         L.off_stamp, ntx, nty, phi, u, p);
+    else
+        k_step_local<T, MODE><<<ntx * nty, dim3(TX, BY), 0, s>>>(P, state, L.off_buf[0], L.off_buf[1], L.off_stamp,
+                                                                  ntx, nty, phi, u, p);
 }
 
 template void launch_local<float, 0>(const KParams<float>&, char*, const Layout&, hipStream_t, float*, float*, float*);

@@ -12,7 +12,7 @@ namespace lbm {
 
 // MODE 0: one time step, the tile's rows move to the next level; MODE 1:
 // phi, u, p of the current level into out_*.  sphi: the tile's phi window.
-template <typename T, int TY, int MODE>
+template <typename T, int TY, int MODE, bool NT = true>
 __device__ __forceinline__ void local_step_tile(const KParams<T>& P, char* state, size_t off0, size_t off1,
                                                 size_t off_stamp, int xt, int yt, T* out_phi, T* out_u, T* out_p,
                                                 T (*sphi)[TX + 3]) {
@@ -101,11 +101,11 @@ __device__ __forceinline__ void local_step_tile(const KParams<T>& P, char* state
         }
         const double f0n = collide_f(P, M, f[r], phid[r]);
         collide_g(P, M, g[r]);
-        st<double, long long>(reinterpret_cast<char*>(D.f0), 8 * k, f0n);
-        for (int i = 1; i < Q; i++) st<T, long long>(reinterpret_cast<char*>(D.f), (long long)sizeof(T) * (i * pl + k), f[r][i]);
-        for (int i = 0; i < Q; i++) st<T, long long>(reinterpret_cast<char*>(D.g), (long long)sizeof(T) * (i * pl + k), g[r][i]);
+        st<double, long long, NT>(reinterpret_cast<char*>(D.f0), 8 * k, f0n);
+        for (int i = 1; i < Q; i++) st<T, long long, NT>(reinterpret_cast<char*>(D.f), (long long)sizeof(T) * (i * pl + k), f[r][i]);
+        for (int i = 0; i < Q; i++) st<T, long long, NT>(reinterpret_cast<char*>(D.g), (long long)sizeof(T) * (i * pl + k), g[r][i]);
         const T hout[5] = {M.phi, M.u, M.v, M.mx, M.my};
-        for (int j = 0; j < 5; j++) st<T, long long>(reinterpret_cast<char*>(D.h), (long long)sizeof(T) * (j * pl + k), hout[j]);
+        for (int j = 0; j < 5; j++) st<T, long long, NT>(reinterpret_cast<char*>(D.h), (long long)sizeof(T) * (j * pl + k), hout[j]);
     }
     // every wave read stamp[0] before the window barrier
     if (MODE == 0 && tid < TY && y0 + tid < P.ny) stamp[tid] = step + 1;

@@ -43,8 +43,8 @@ void k_step(KParams<T> P, char* state, size_t off0, size_t off1, size_t off_stam
 // The Cahn-Hilliard variant and the corrected comparison model with the
 // Allen-Cahn phase field (ACC), both on the two-node phi window of lbm_ch.hpp:
 // one 64 x TY tile per workgroup of 64 x 4 threads, tiles dealt to the XCDs as
-// for the Allen-Cahn step, the same state layout, level stamps and non-temporal
-// stores.  MODE 0: one time step; MODE 1: phi, u, p of the current level.
+// for the Allen-Cahn step, the same state layout, level stamps and store
+// policy.  MODE 0: one time step; MODE 1: phi, u, p of the current level.
 // Tile rows (measured on MI355X, square droplet): 8 when that still gives >= 1024
 // tiles (+9% over 4 rows at 4096^2 FP32, +3% at 1024^2, equal in FP64), else 4
 // (+57% over 8 rows at 200^2, where the step is latency-bound); 16 rows lose
@@ -54,7 +54,7 @@ void k_step(KParams<T> P, char* state, size_t off0, size_t off1, size_t off_stam
 #define LBM_CH_TY 0
 #endif
 
-template <typename T, int TY, int MODE, bool ACC, bool STD>
+template <typename T, int TY, int MODE, bool ACC, bool STD, bool NT = true>
 __global__ __launch_bounds__(TX* BY) void k_step_ch(KParams<T> P, char* state, size_t off0, size_t off1,
                                                    size_t off_stamp, int ntx, int nty, T* out_phi, T* out_u,
                                                    T* out_p) {
@@ -66,7 +66,7 @@ __global__ __launch_bounds__(TX* BY) void k_step_ch(KParams<T> P, char* state, s
         xt = blockIdx.x % ntx;
         yt = blockIdx.x / ntx;
     }
-    ch_step_tile<T, TY, MODE, ACC, STD>(P, state, off0, off1, off_stamp, xt, yt, out_phi, out_u, out_p, W);
+    ch_step_tile<T, TY, MODE, ACC, STD, NT>(P, state, off0, off1, off_stamp, xt, yt, out_phi, out_u, out_p, W);
 }
 
 static int ch_rows(int nx, int ny) {
@@ -75,27 +75,38 @@ static int ch_rows(int nx, int ny) {
     return ntx * ((ny + 7) / 8) >= 1024 ? 8 : 4;
 }
 
-template <typename T, int MODE, bool ACC, bool STD>
+template <typename T, int MODE, bool ACC, bool STD, bool NT = true>
 static void launch_ch_acc_std(const KParams<T>& P, char* state, const Layout& L, hipStream_t s, T* phi, T* u, T* p) {
     const int ty = ch_rows(P.nx, P.ny);
     const int ntx = (P.nx + TX - 1) / TX, nty = (P.ny + ty - 1) / ty;
     const dim3 grd(ntx * nty), blk(TX, BY);
     if (ty == 16)
-        k_step_ch<T, 16, MODE, ACC, STD><<<grd, blk, 0, s>>>(P, state, L.off_buf[0], L.off_buf[1], L.off_stamp, ntx,
-                                                             nty, phi, u, p);
+        k_step_ch<T, 16, MODE, ACC, STD, NT><<<grd, blk, 0, s>>>(P, state, L.off_buf[0], L.off_buf[1], L.off_stamp,
+                                                                 ntx, nty, phi, u, p);
     else if (ty == 8)
-        k_step_ch<T, 8, MODE, ACC, STD><<<grd, blk, 0, s>>>(P, state, L.off_buf[0], L.off_buf[1], L.off_stamp, ntx,
-                                                            nty, phi, u, p);
+        k_step_ch<T, 8, MODE, ACC, STD, NT><<<grd, blk, 0, s>>>(P, state, L.off_buf[0], L.off_buf[1], L.off_stamp,
+                                                                ntx, nty, phi, u, p);
     else
-        k_step_ch<T, 4, MODE, ACC, STD><<<grd, blk, 0, s>>>(P, state, L.off_buf[0], L.off_buf[1], L.off_stamp, ntx,
-                                                            nty, phi, u, p);
+        k_step_ch<T, 4, MODE, ACC, STD, NT><<<grd, blk, 0, s>>>(P, state, L.off_buf[0], L.off_buf[1], L.off_stamp,
+                                                                ntx, nty, phi, u, p);
 }
 
-// the standard rates compiled in for steps (moments do not collide)
+// the standard rates compiled in for steps (moments do not collide); steps on
+// a state that the last-level cache holds store it with ordinary stores
 template <typename T, int MODE, bool ACC>
 static void launch_ch_acc(const KParams<T>& P, char* state, const Layout& L, hipStream_t s, T* phi, T* u, T* p) {
-    if (MODE == 0 && P.rates_std) launch_ch_acc_std<T, MODE, ACC, true>(P, state, L, s, phi, u, p);
-    else launch_ch_acc_std<T, MODE, ACC, false>(P, state, L, s, phi, u, p);
+    if constexpr (MODE == 0) {
+        const bool cached = cached_state(L);
+        if (P.rates_std) {
+            if (cached) launch_ch_acc_std<T, MODE, ACC, true, false>(P, state, L, s, phi, u, p);
+            else launch_ch_acc_std<T, MODE, ACC, true>(P, state, L, s, phi, u, p);
+        } else {
+            if (cached) launch_ch_acc_std<T, MODE, ACC, false, false>(P, state, L, s, phi, u, p);
+            else launch_ch_acc_std<T, MODE, ACC, false>(P, state, L, s, phi, u, p);
+        }
+    } else {
+        launch_ch_acc_std<T, MODE, ACC, false>(P, state, L, s, phi, u, p);
+    }
 }
 
 // CH (any model) or the corrected AC model: the two-node-window kernels.
@@ -273,17 +284,6 @@ static int grid1d(long long n) {
 // Byte size of one copy fits 32-bit offsets?
 static bool small_copy(const Layout& L) { return L.buf_bytes < (size_t(1) << 32); }
 
-// The plain step stores its state with ordinary stores while both copies fit
-// in this many bytes, so that the state (or most of it) stays in the 256 MB
-// last-level cache from one step to the next, and non-temporally above.
-// Measured on MI355X, FP32 (state of both copies): 256 x 1024 (46 MB) +2%,
-// 1024 x 512 (92 MB) +7%, 1024 x 1024 (184 MB) +26%, 1024 x 1536 (277 MB) +11%
-// with ordinary stores; 2048 x 1024 (369 MB) +3% and 4096^2 (2.9 GB) +5% with
-// non-temporal ones (FP64 4096^2 +5%).
-#ifndef LBM_NT_MIN_BYTES
-#define LBM_NT_MIN_BYTES (320ull << 20)
-#endif
-static bool cached_state(const Layout& L) { return 2 * L.buf_bytes <= (size_t)LBM_NT_MIN_BYTES; }
 
 template <typename T, int TY, int MODE, int NBY = BY>
 static void launch_tile(const KParams<T>& P, char* state, const Layout& L, hipStream_t s, T* phi, T* u, T* p) {
