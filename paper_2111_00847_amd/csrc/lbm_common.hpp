@@ -137,5 +137,8 @@ inline Layout make_layout(int nx, int ny, size_t esz, size_t diag_blocks, int nh
 #define LBM_NT_MIN_BYTES (320ull << 20)
 #endif
 inline bool cached_state(const Layout& L) { return 2 * L.buf_bytes <= (size_t)LBM_NT_MIN_BYTES; }
+// Both copies within the 256 MB last-level cache itself (the plain step then
+// loads g after its window barrier).
+inline bool resident_state(const Layout& L) { return 2 * L.buf_bytes <= (size_t(256) << 20); }
 
 }  // namespace lbm

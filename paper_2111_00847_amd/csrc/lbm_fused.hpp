@@ -41,9 +41,12 @@ __device__ __forceinline__ T ld(const char* base, OFF byteoff) {
 #endif
 // g and the history velocity are loaded together with f, before the window
 // barrier, when a thread holds at most two nodes (+10-30% on lattices of
-// 0.25-0.5 M nodes, where the step is latency bound); with four nodes per
-// thread the extra live registers cost more than the overlap gains (-17% on
-// 4096^2).  LBM_G_EARLY forces it on (1) or off (0).
+// 0.25-0.5 M nodes streamed from HBM, where the step is latency bound); with
+// four nodes per thread the extra live registers cost more than the overlap
+// gains (-17% on 4096^2).  A state that the last-level cache holds is read
+// with less latency, and there loading g after the barrier (LATE_G) wins:
+// +1.4% on 256 x 1024, +6% on 1024 x 512, +9-15% on 1-1.3 M nodes (FP32),
+// +5.6% on 256 x 1024 FP64.  LBM_G_EARLY forces early loads on (1) or off (0).
 #ifndef LBM_G_EARLY
 #define LBM_G_EARLY -1
 #endif
@@ -116,12 +119,13 @@ struct StepWaves {
 // The tile body between explicit buffers: `src` holds level `step` (one copy:
 // post-collision populations of the previous step and the history), `dst`
 // receives level step + 1.
-template <typename T, int TY, int MODE, typename OFF, int NBY = BY, bool STD = false, bool NT = true>
+template <typename T, int TY, int MODE, typename OFF, int NBY = BY, bool STD = false, bool NT = true,
+          bool LATE_G = false>
 __device__ __forceinline__ void step_core(const KParams<T>& P, const char* src, char* dst, int64_t step, int xt,
                                           int yt, T* out_phi, T* out_u, T* out_p, T (*sphi)[TX + 3],
                                           T (*sphp)[TX + 3]) {
     constexpr int R = TY / NBY;
-    constexpr bool GE = LBM_G_EARLY < 0 ? R <= 2 : LBM_G_EARLY != 0;
+    constexpr bool GE = LBM_G_EARLY < 0 ? (R <= 2 && !LATE_G) : LBM_G_EARLY != 0;
     constexpr bool RE = LBM_RING_EARLY < 0 ? sizeof(T) == 8 : LBM_RING_EARLY != 0;
     constexpr int WX = TX + 2, WY = TY + 2;
     constexpr OFF ES = sizeof(T);
@@ -371,7 +375,8 @@ __device__ __forceinline__ void step_core(const KParams<T>& P, const char* src, 
 
 // The tile body on a ping-pong state: the level stamp of the tile's first row
 // selects the source copy, and the tile's rows move to the next level.
-template <typename T, int TY, int MODE, typename OFF, int NBY = BY, bool STD = false, bool NT = true>
+template <typename T, int TY, int MODE, typename OFF, int NBY = BY, bool STD = false, bool NT = true,
+          bool LATE_G = false>
 __device__ __forceinline__ void step_tile(const KParams<T>& P, char* state, size_t off0, size_t off1,
                                           size_t off_stamp, int xt, int yt, T* out_phi, T* out_u, T* out_p,
                                           T (*sphi)[TX + 3], T (*sphp)[TX + 3]) {
@@ -379,7 +384,7 @@ __device__ __forceinline__ void step_tile(const KParams<T>& P, char* state, size
     int64_t* stamp = reinterpret_cast<int64_t*>(state + off_stamp) + (size_t)xt * P.ny + y0;
     const int64_t step = stamp[0];
     const int cur = (int)(step & 1);
-    step_core<T, TY, MODE, OFF, NBY, STD, NT>(P, state + (cur ? off1 : off0), state + (cur ? off0 : off1), step, xt, yt, out_phi,
+    step_core<T, TY, MODE, OFF, NBY, STD, NT, LATE_G>(P, state + (cur ? off1 : off0), state + (cur ? off0 : off1), step, xt, yt, out_phi,
                                 out_u, out_p, sphi, sphp);
     // Own rows move to level n + 1.  Every wave of the workgroup consumed its
     // load of stamp[0] (it addresses all loads above) before the barriers of

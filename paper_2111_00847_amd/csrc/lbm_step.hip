@@ -23,7 +23,7 @@
 
 namespace lbm {
 
-template <typename T, int TY, int MODE, typename OFF, int NBY, bool STD, bool NT = true>
+template <typename T, int TY, int MODE, typename OFF, int NBY, bool STD, bool NT = true, bool LATE_G = false>
 __global__ __launch_bounds__(TX* NBY) __attribute__((amdgpu_waves_per_eu(StepWaves<T, TY, NBY>::value)))
 void k_step(KParams<T> P, char* state, size_t off0, size_t off1, size_t off_stamp, int ntx, int nty, T* out_phi,
             T* out_u, T* out_p) {
@@ -36,8 +36,8 @@ void k_step(KParams<T> P, char* state, size_t off0, size_t off1, size_t off_stam
         xt = blockIdx.x % ntx;
         yt = blockIdx.x / ntx;
     }
-    step_tile<T, TY, MODE, OFF, NBY, STD, NT>(P, state, off0, off1, off_stamp, xt, yt, out_phi, out_u, out_p, sphi,
-                                              sphp);
+    step_tile<T, TY, MODE, OFF, NBY, STD, NT, LATE_G>(P, state, off0, off1, off_stamp, xt, yt, out_phi, out_u,
+                                                      out_p, sphi, sphp);
 }
 
 // The Cahn-Hilliard variant and the corrected comparison model with the
@@ -291,7 +291,14 @@ static void launch_tile(const KParams<T>& P, char* state, const Layout& L, hipSt
     dim3 blk(TX, NBY);
     // the standard rates compiled in for steps (moments do not collide)
     const bool std_rates = MODE == 0 && P.rates_std;
-    if (MODE == 0 && cached_state(L)) {
+    if (MODE == 0 && resident_state(L)) {   // the last-level cache holds both copies: g loaded late
+        if (std_rates)
+            k_step<T, TY, MODE, uint32_t, NBY, true, false, true><<<ntx * nty, blk, 0, s>>>(
+                P, state, L.off_buf[0], L.off_buf[1], L.off_stamp, ntx, nty, phi, u, p);
+        else
+            k_step<T, TY, MODE, uint32_t, NBY, false, false, true><<<ntx * nty, blk, 0, s>>>(
+                P, state, L.off_buf[0], L.off_buf[1], L.off_stamp, ntx, nty, phi, u, p);
+    } else if (MODE == 0 && cached_state(L)) {
         if (std_rates)
             k_step<T, TY, MODE, uint32_t, NBY, true, false><<<ntx * nty, blk, 0, s>>>(
                 P, state, L.off_buf[0], L.off_buf[1], L.off_stamp, ntx, nty, phi, u, p);
