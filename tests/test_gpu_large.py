@@ -1,9 +1,9 @@
-"""Lattices whose state copy exceeds 4 GiB: the plain step then addresses its
-buffers with 64-bit offsets (32-bit below that).  A lattice of k side-by-side
-copies of the 256 x 1024 Rayleigh-Taylor field (periodic in x) must stay k exact
-copies of the 256 x 1024 run, which itself matches the oracle; so the
-large-offset path is held to the small one bitwise, at a size the oracle could
-not follow step by step."""
+"""Large lattices against tiled small ones.  A periodic lattice made of copies
+of a small one must stay those copies bitwise, so a code path that only large
+states take is held to the small lattice's path, which the oracle checks:
+state copies beyond 4 GiB (the plain step's 64-bit offsets, 32-bit below), and
+states beyond the last-level cache (non-temporal stores, early g loads) against
+cached ones (ordinary stores; late g loads in the plain step)."""
 import numpy as np
 import pytest
 
@@ -60,3 +60,44 @@ def test_lattice_beyond_4gib_per_copy_is_the_tiled_small_lattice(dtype, k):
         assert dphi <= 1e-12 and du <= 1e-10
     else:
         assert dphi <= 1e-5 and du <= 1e-4
+
+
+def _tiled_pair(small_case, phi_s, p_s, kx, ky):
+    big = small_case.replace(nx=small_case.nx * kx, ny=small_case.ny * ky, name=small_case.name + "_tiled")
+    tile = lambda a: None if a is None else np.tile(a, (ky, kx))
+    return big, tile(phi_s), tile(p_s)
+
+
+@pytest.mark.parametrize("variant,dtype", [("plain", "f32"), ("plain", "f64"), ("cahn_hilliard", "f32"),
+                                           ("local_gradient", "f32")])
+def test_streamed_state_path_is_the_tiled_cached_one(variant, dtype):
+    """Lattices whose state exceeds the last-level cache take the non-temporal
+    store path with early g loads; small ones keep their state in the cache
+    (ordinary stores, and for the plain step g loaded late).  A periodic
+    lattice of copies of a small one (same tile shapes) must stay those copies
+    bitwise: 30 steps, phi, u and p compared."""
+    from paper_2111_00847_amd import api
+    from paper_2111_00847_amd.sim import Sim
+    if variant == "cahn_hilliard":
+        case_s, phi_s = W.square_droplet_ch(n=512, R=128.0, sigma=1e-3, rho_ratio=100.0, dtype=dtype)
+        case_s, phi_s = case_s.replace(nx=1024, ny=512), np.tile(phi_s, (1, 2))
+        p_s, kx, ky = None, 2, 2
+    else:
+        case_s, phi_s = W.rti(nx=256, ny=1024, dtype=dtype)
+        if variant == "local_gradient":
+            case_s = case_s.replace(grad_scheme="local")
+        p_s, kx, ky = W.hydrostatic_pressure(case_s, phi_s), 8, 1
+    case_b, phi_b, p_b = _tiled_pair(case_s, phi_s, p_s, kx, ky)
+    nb = api.lbm_state_size(api.make_params(case_b))
+    ns = api.lbm_state_size(api.make_params(case_s))
+    assert ns < (192 << 20) and (340 << 20) < nb < (8 << 30), (ns, nb)   # small: cached; big: streamed
+    small = Sim(case_s).init(phi_s, None, p_s).step(30)
+    big = Sim(case_b).init(phi_b, None, p_b).step(30)
+    torch.cuda.synchronize()
+    for name, a, b in zip(("phi", "u", "p"), small.moments(), big.moments()):
+        ny, nx = a.shape[-2:]
+        lead = a.shape[:-2]
+        tiled = a.reshape(lead + (1, ny, 1, nx)).expand(lead + (ky, ny, kx, nx)).reshape(b.shape)
+        d = (b - tiled).abs().max().item()
+        print(f"{variant} {dtype} {name}: max |big - tiled small| = {d:.3e}", flush=True)
+        assert torch.equal(b, tiled), (variant, dtype, name)
