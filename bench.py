@@ -15,7 +15,10 @@ The JSON line also carries:
                   (HIP events over the timed region on the launch stream);
                   `traffic` is the measured HBM bytes per launch from the
                   committed rocprofv3 counter summary when it matches the
-                  current kernel source, else null;
+                  current kernel source, else null; `copy_GBs` is torch's
+                  device copy of the same bytes (half read, half written),
+                  which stays in the 256 MB cache as the step's 46 MB state
+                  does, and `frac_of_copy` the step's rate against it;
   large_grid   -- the same kernel at 4096 x 4096 (state 2.9 GB, far beyond the
                   256 MB Infinity Cache), where HBM is the real bound, next to
                   the bandwidth of torch's own device copy; large_grid_fp64 the
@@ -373,6 +376,10 @@ def main():
         return
     if not args.only_large:
         out.update(measure_main(args, torch, W, Sim))
+        half = out["roofline"]["alg_bytes_per_launch"] // 2
+        copy_gbs = measure_copy(torch, mib=max(1, round(half / (1 << 20))), reps=200)
+        out["roofline"]["copy_GBs"] = copy_gbs
+        out["roofline"]["frac_of_copy"] = round(out["roofline"]["achieved"] / copy_gbs, 4)
     if not args.no_large:
         out["large_grid"] = measure_large(args, torch, W, Sim)
         copy_gbs = measure_copy(torch)
