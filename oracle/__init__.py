@@ -77,6 +77,7 @@ def lib():
         L.orc_grad.argtypes = [ctypes.c_void_p, d, d]
         L.orc_set_state_m.argtypes = [ctypes.c_void_p, d, d, d, d, d, ctypes.c_long]
         L.orc_flux.argtypes = [ctypes.c_void_p, d, d]
+        L.orc_fa.argtypes = [ctypes.c_void_p, d]
         L.orc_set_threads.argtypes = [ctypes.c_int]
         L.orc_set_threads.restype = None
         L.orc_lattice.argtypes = [P(ctypes.c_int), P(ctypes.c_int), d, d, d]
@@ -88,7 +89,7 @@ def lib():
         L.orc_direct_g.argtypes = [P(OrcParams)] + [ctypes.c_double] * 13 + [d, d]
         for name in ("orc_init", "orc_step", "orc_moments", "orc_diagnostics",
                      "orc_get_state", "orc_set_state", "orc_rates", "orc_grad", "orc_set_state_m",
-                     "orc_flux"):
+                     "orc_flux", "orc_fa"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -210,6 +211,12 @@ class OracleSim:
             rc = lib().orc_set_state_m(self.h, _dp(f), _dp(g), _dp(pp), _dp(up), _dp(mp), int(step))
         assert rc == 0, rc
         return self
+
+    def fa(self):
+        """a of the corrected model's F_a = a u at the current level, [ny][nx]."""
+        a = np.empty(self.shape)
+        assert lib().orc_fa(self.h, _dp(a)) == 0
+        return a
 
     def flux(self):
         """m^phiC of the current level, [2][ny][nx]."""

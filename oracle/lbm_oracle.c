@@ -31,10 +31,12 @@
  * Pins (tests/test_oracle_*.py): every stage above against a closed form, a
  * textbook identity or the paper's printed values, including the CH moments,
  * the corrected model's F_a (periodic closed forms) and the local gradient
- * (tanh derivative).  Parity unpinned, checked only against the GPU path:
- * the values of the diagnostics S_m^rms, D_u^rms; the wall rules that the
- * paper leaves open -- the mirror of mu_phi at walls (Cahn-Hilliard) and the
- * mirror of D with reversed normal component (corrected AC model).
+ * (tanh derivative); the wall rules that the paper leaves open -- the mirror
+ * of mu_phi at walls (Cahn-Hilliard) and the mirror of D with reversed normal
+ * component (corrected AC model) -- by the no-flux property they stand for
+ * (sum of F_a's coefficient over a walled lattice is zero).  Parity unpinned,
+ * checked only against the GPU path: the values of the diagnostics S_m^rms,
+ * D_u^rms.
  */
 #include "lbm_oracle.h"
 
@@ -825,6 +827,16 @@ int orc_flux(const orc_sim *cs, double *mx, double *my) {
     macroscopic(s);
     memcpy(mx, s->mx, sizeof(double) * s->n);
     memcpy(my, s->my, sizeof(double) * s->n);
+    return 0;
+}
+
+/* The corrected model's coefficient a of F_a = a u at the current level
+ * (zero for the other models). */
+int orc_fa(const orc_sim *cs, double *a) {
+    orc_sim *s = (orc_sim *)cs;
+    if (!s || !a) return -1;
+    macroscopic(s);
+    memcpy(a, s->fa, sizeof(double) * s->n);
     return 0;
 }
 

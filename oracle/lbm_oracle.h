@@ -84,6 +84,9 @@ void orc_set_threads(int n);   /* OpenMP threads of the following calls (n > 0) 
 int orc_grad(const orc_sim *s, double *gx, double *gy);
 /* m^phiC of the current level (zero for the original and corrected models). */
 int orc_flux(const orc_sim *s, double *mx, double *my);
+/* a of the corrected model's interface force F_a = a u, current level (zero
+ * for the other models). */
+int orc_fa(const orc_sim *s, double *a);
 /* grad phi and lap phi of an arbitrary field with this lattice's ghost rule. */
 int orc_stencils(const orc_sim *s, const double *phi, double *gx, double *gy, double *lap);
 void orc_lattice(int cx[9], int cy[9], double w[9], double M[81], double Minv[81]);

@@ -192,3 +192,28 @@ def test_ch_square_droplet_relaxes_to_a_circle_of_the_same_area():
     rs = _contour_radii(phi, X, Y, 32.0, 32.0, 0.0)
     assert rs.std() < 0.01, rs.std()
     assert abs(rs.mean() - 16.0) < 0.16, rs.mean()
+
+
+@pytest.mark.parametrize("pf", ["allen_cahn", "cahn_hilliard"])
+@pytest.mark.parametrize("geom", ["periodic", "walls_x", "walls_y", "walls_xy"])
+def test_corrected_force_has_no_net_flux_through_walls(pf, geom):
+    """The corrected model's F_a = a u with a = (drho/dphi) div(M D): summed over
+    the lattice, the discrete divergence telescopes to its boundary terms, which
+    the wall ghosts must cancel -- D mirrored with its normal component reversed
+    (Allen-Cahn), mu_phi mirrored (Cahn-Hilliard: D = grad mu_phi), the no-flux
+    conditions of R23 and R25.  A ghost rule without that property (a plain
+    mirror of D, say) leaves sum(a) of the order of sum|a|."""
+    import math
+    th = (math.radians(70), math.radians(110), math.radians(40), math.radians(140))
+    walls = {"periodic": {}, "walls_x": dict(wall_x=True), "walls_y": dict(wall_y=True),
+             "walls_xy": dict(wall_x=True, wall_y=True)}[geom]
+    case = W.Case(nx=37, ny=23, rhoA=20.0, rhoB=1.0, nuA=0.05, nuB=0.2, sigma=0.01, W=4.0, M=0.05,
+                  dtype="f64", theta=th, model="corrected", **walls)
+    phi0, u0, p0 = W.random_state_fields(case, seed=5)
+    if pf == "cahn_hilliard":
+        case, phi0 = W.to_cahn_hilliard(case, phi0)
+    a = oracle.OracleSim(case).init(phi0, u0, p0).step(3).fa()
+    assert np.abs(a).sum() > 0.1
+    assert abs(a.sum()) <= 1e-13 * np.abs(a).sum(), (a.sum(), np.abs(a).sum())
+    # the present model has no F_a
+    assert np.all(oracle.OracleSim(case.replace(model="present")).init(phi0, u0, p0).fa() == 0.0)
