@@ -175,7 +175,7 @@ __global__ void k_tape_copy(const char* state, size_t off0, size_t off1, size_t 
     }
 }
 
-template <typename T, int TY, typename OFF, int NBY, bool STD>
+template <typename T, int TY, typename OFF, int NBY, bool STD, bool NT = true>
 __global__ __launch_bounds__(TX* NBY) __attribute__((amdgpu_waves_per_eu(StepWaves<T, TY, NBY>::value)))
 void k_tape_step(KParams<T> P, char* tape, size_t slot, int j, int ntx, int nty) {
     __shared__ T sphi[TY + 2][TX + 3];
@@ -184,7 +184,7 @@ void k_tape_step(KParams<T> P, char* tape, size_t slot, int j, int ntx, int nty)
     char* src = tape + TAPE_HDR + (size_t)j * slot;
     int xt, yt;
     xcd_tile(blockIdx.x, ntx, nty, xt, yt);
-    step_core<T, TY, 0, OFF, NBY, STD>(P, src, src + slot, n, xt, yt, nullptr, nullptr, nullptr, sphi, sphp);
+    step_core<T, TY, 0, OFF, NBY, STD, NT>(P, src, src + slot, n, xt, yt, nullptr, nullptr, nullptr, sphi, sphp);
 }
 
 // ---------------------------------------------------------------- adjoint step, kernel A
@@ -644,8 +644,17 @@ static int grid1d(long long n) {
 template <typename T, int TY, int NBY>
 static void tape_step_launch(const KParams<T>& P, char* tape, size_t slot, int j, hipStream_t s) {
     const int ntx = (P.nx + TX - 1) / TX, nty = (P.ny + TY - 1) / TY;
-    // the same specialisation as lbm_step, so that the tape holds the forward levels bitwise
-    if (slot < (size_t(1) << 32)) {
+    // the same specialisation as lbm_step, so that the tape holds the forward levels bitwise;
+    // ordinary stores while a level and the next fit the last-level cache (the
+    // next tape step reads the level just written)
+    if (2 * slot <= (size_t)LBM_NT_MIN_BYTES) {
+        if (P.rates_std)
+            k_tape_step<T, TY, uint32_t, NBY, true, false><<<ntx * nty, dim3(TX, NBY), 0, s>>>(P, tape, slot, j, ntx,
+                                                                                               nty);
+        else
+            k_tape_step<T, TY, uint32_t, NBY, false, false><<<ntx * nty, dim3(TX, NBY), 0, s>>>(P, tape, slot, j, ntx,
+                                                                                                nty);
+    } else if (slot < (size_t(1) << 32)) {
         if (P.rates_std)
             k_tape_step<T, TY, uint32_t, NBY, true><<<ntx * nty, dim3(TX, NBY), 0, s>>>(P, tape, slot, j, ntx, nty);
         else
