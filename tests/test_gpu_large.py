@@ -101,3 +101,40 @@ def test_streamed_state_path_is_the_tiled_cached_one(variant, dtype):
         d = (b - tiled).abs().max().item()
         print(f"{variant} {dtype} {name}: max |big - tiled small| = {d:.3e}", flush=True)
         assert torch.equal(b, tiled), (variant, dtype, name)
+
+
+def test_reverse_mode_on_a_streamed_state_is_the_tiled_cached_one():
+    """The reverse mode's tape recompute stores a level non-temporally when a
+    level and the next exceed the last-level cache, with ordinary stores
+    otherwise.  On a periodic lattice of 8 copies of the 256 x 1024 RTI field
+    (tape levels of 185 MB, streamed) the gradient in phi0 is the tiled gradient
+    of the small lattice (cached tape) bitwise, and the gradients in gravity and
+    the contact angles are 8 times the small ones (FP64 sums in another order)."""
+    import math
+    from paper_2111_00847_amd import api
+    from paper_2111_00847_amd.autograd import trajectory_phi
+    case_s, phi_s = W.rti(nx=256, ny=1024, dtype="f32")
+    case_b, phi_b, _ = _tiled_pair(case_s, phi_s, None, 8, 1)
+    ps, pb = api.make_params(case_s), api.make_params(case_b)
+    slot_s = api.lbm_state_size(ps) / 2
+    slot_b = api.lbm_state_size(pb) / 2
+    assert 2 * slot_s < (320 << 20) < 2 * slot_b, (slot_s, slot_b)
+    X, Y = W.grid(case_s)
+    w_s = np.cos(2 * np.pi * X / 256.0) * np.exp(-((Y - 512.0) / 40.0) ** 2)
+    res = {}
+    for name, case, phi0, w in (("small", case_s, phi_s, w_s), ("big", case_b, phi_b, np.tile(w_s, (1, 8)))):
+        phi0_t = torch.tensor(phi0, dtype=torch.float32, device="cuda", requires_grad=True)
+        grav = torch.tensor(list(case.gravity), dtype=torch.float64, requires_grad=True)
+        theta = torch.tensor([math.pi / 2] * 4, dtype=torch.float64, requires_grad=True)
+        phiN = trajectory_phi(phi0_t, grav, theta, case, 8, None, 4)
+        L = (phiN.double() * torch.tensor(w, device="cuda")).sum()
+        L.backward()
+        res[name] = (phi0_t.grad.detach().clone(), grav.grad.numpy().copy(), theta.grad.numpy().copy())
+    gs, gb = res["small"][0], res["big"][0]
+    tiled = gs.unsqueeze(1).expand(1024, 8, 256).reshape(1024, 2048)
+    print(f"dL/dphi0: max |big - tiled small| = {(gb - tiled).abs().max().item():.3e}", flush=True)
+    assert torch.equal(gb, tiled)
+    for k, what in ((1, "gravity"), (2, "theta")):
+        a, b = res["small"][k], res["big"][k]
+        print(f"dL/d{what}: small {a}, big {b}", flush=True)
+        np.testing.assert_allclose(b, 8 * a, rtol=1e-10, atol=1e-30)
