@@ -44,7 +44,9 @@ struct BatchCase {
                                  // 3: Allen-Cahn with the local gradient scheme
 };
 
-template <typename T, int TY, int NBY>
+// NT: non-temporal state stores (the batch's state exceeds the last-level
+// cache); ordinary ones otherwise, as for a single lattice.
+template <typename T, int TY, int NBY, bool NT>
 __global__ __launch_bounds__(TX* NBY) __attribute__((amdgpu_waves_per_eu(StepWaves<T, TY, NBY>::value)))
 void k_step_batch(const BatchCase<T>* __restrict__ cases, int ncases, int nitems, char* batch_state) {
     __shared__ T sphi[TY + 2][TX + 3];
@@ -60,10 +62,10 @@ void k_step_batch(const BatchCase<T>* __restrict__ cases, int ncases, int nitems
         const int local = w - C.item_begin;
         // the collision specialisation the case runs alone (lbm_step), so that it stays bitwise
         if (C.P.rates_std)
-            step_tile<T, TY, 0, uint32_t, NBY, true>(C.P, batch_state + C.base, C.off0, C.off1, C.off_stamp,
+            step_tile<T, TY, 0, uint32_t, NBY, true, NT>(C.P, batch_state + C.base, C.off0, C.off1, C.off_stamp,
                                                      local % C.ntx, local / C.ntx, nullptr, nullptr, nullptr, sphi, sphp);
         else
-            step_tile<T, TY, 0, uint32_t, NBY, false>(C.P, batch_state + C.base, C.off0, C.off1, C.off_stamp,
+            step_tile<T, TY, 0, uint32_t, NBY, false, NT>(C.P, batch_state + C.base, C.off0, C.off1, C.off_stamp,
                                                       local % C.ntx, local / C.ntx, nullptr, nullptr, nullptr, sphi, sphp);
         __syncthreads();   // the next item reuses the LDS window
     }
@@ -71,7 +73,7 @@ void k_step_batch(const BatchCase<T>* __restrict__ cases, int ncases, int nitems
 
 // Batches with two-node-window or local-gradient cases: 64 x 4 threads, the
 // LDS holds any of the windows, each item runs its case's body.
-template <typename T, int TY>
+template <typename T, int TY, bool NT>
 __global__ __launch_bounds__(TX* BY) void k_step_batch_wide(const BatchCase<T>* __restrict__ cases, int ncases,
                                                             int nitems, char* batch_state) {
     __shared__ union {
@@ -92,25 +94,25 @@ __global__ __launch_bounds__(TX* BY) void k_step_batch_wide(const BatchCase<T>* 
         const int local = w - C.item_begin;
         char* st0 = batch_state + C.base;
         if (C.body == 0 && C.P.rates_std)
-            step_tile<T, TY, 0, uint32_t, BY, true>(C.P, st0, C.off0, C.off1, C.off_stamp, local % C.ntx,
+            step_tile<T, TY, 0, uint32_t, BY, true, NT>(C.P, st0, C.off0, C.off1, C.off_stamp, local % C.ntx,
                                                     local / C.ntx, nullptr, nullptr, nullptr, lds.ac.sphi, lds.ac.sphp);
         else if (C.body == 0)
-            step_tile<T, TY, 0, uint32_t, BY, false>(C.P, st0, C.off0, C.off1, C.off_stamp, local % C.ntx,
+            step_tile<T, TY, 0, uint32_t, BY, false, NT>(C.P, st0, C.off0, C.off1, C.off_stamp, local % C.ntx,
                                                      local / C.ntx, nullptr, nullptr, nullptr, lds.ac.sphi, lds.ac.sphp);
         else if (C.body == 1 && C.P.rates_std)
-            ch_step_tile<T, TY, 0, false, true>(C.P, st0, C.off0, C.off1, C.off_stamp, local % C.ntx, local / C.ntx,
+            ch_step_tile<T, TY, 0, false, true, NT>(C.P, st0, C.off0, C.off1, C.off_stamp, local % C.ntx, local / C.ntx,
                                                 nullptr, nullptr, nullptr, lds.ch);
         else if (C.body == 1)
-            ch_step_tile<T, TY, 0, false, false>(C.P, st0, C.off0, C.off1, C.off_stamp, local % C.ntx, local / C.ntx,
+            ch_step_tile<T, TY, 0, false, false, NT>(C.P, st0, C.off0, C.off1, C.off_stamp, local % C.ntx, local / C.ntx,
                                                  nullptr, nullptr, nullptr, lds.ch);
         else if (C.body == 3)
-            local_step_tile<T, TY, 0>(C.P, st0, C.off0, C.off1, C.off_stamp, local % C.ntx, local / C.ntx, nullptr,
+            local_step_tile<T, TY, 0, NT>(C.P, st0, C.off0, C.off1, C.off_stamp, local % C.ntx, local / C.ntx, nullptr,
                                       nullptr, nullptr, lds.ac.sphi);
         else if (C.P.rates_std)
-            ch_step_tile<T, TY, 0, true, true>(C.P, st0, C.off0, C.off1, C.off_stamp, local % C.ntx, local / C.ntx,
+            ch_step_tile<T, TY, 0, true, true, NT>(C.P, st0, C.off0, C.off1, C.off_stamp, local % C.ntx, local / C.ntx,
                                                nullptr, nullptr, nullptr, lds.ch);
         else
-            ch_step_tile<T, TY, 0, true, false>(C.P, st0, C.off0, C.off1, C.off_stamp, local % C.ntx, local / C.ntx,
+            ch_step_tile<T, TY, 0, true, false, NT>(C.P, st0, C.off0, C.off1, C.off_stamp, local % C.ntx, local / C.ntx,
                                                 nullptr, nullptr, nullptr, lds.ch);
         __syncthreads();   // the next item reuses the LDS
     }
@@ -186,14 +188,20 @@ template <typename T, int TY, int NBY>
 void batch_launch(lbm_batch* B, char* state, hipStream_t s) {
     const int g = B->grid > 0 ? B->grid : B->nitems;
     const BatchCase<T>* cases = reinterpret_cast<const BatchCase<T>*>(B->d_cases);
-    k_step_batch<T, TY, NBY><<<g, dim3(TX, NBY), 0, s>>>(cases, B->ncases, B->nitems, state);
+    if (B->total <= (size_t)LBM_NT_MIN_BYTES)
+        k_step_batch<T, TY, NBY, false><<<g, dim3(TX, NBY), 0, s>>>(cases, B->ncases, B->nitems, state);
+    else
+        k_step_batch<T, TY, NBY, true><<<g, dim3(TX, NBY), 0, s>>>(cases, B->ncases, B->nitems, state);
 }
 
 template <typename T, int TY>
 void batch_launch_wide(lbm_batch* B, char* state, hipStream_t s) {
     const int g = B->grid > 0 ? B->grid : B->nitems;
     const BatchCase<T>* cases = reinterpret_cast<const BatchCase<T>*>(B->d_cases);
-    k_step_batch_wide<T, TY><<<g, dim3(TX, BY), 0, s>>>(cases, B->ncases, B->nitems, state);
+    if (B->total <= (size_t)LBM_NT_MIN_BYTES)
+        k_step_batch_wide<T, TY, false><<<g, dim3(TX, BY), 0, s>>>(cases, B->ncases, B->nitems, state);
+    else
+        k_step_batch_wide<T, TY, true><<<g, dim3(TX, BY), 0, s>>>(cases, B->ncases, B->nitems, state);
 }
 
 template <typename T>

@@ -138,3 +138,37 @@ def test_reverse_mode_on_a_streamed_state_is_the_tiled_cached_one():
         a, b = res["small"][k], res["big"][k]
         print(f"dL/d{what}: small {a}, big {b}", flush=True)
         np.testing.assert_allclose(b, 8 * a, rtol=1e-10, atol=1e-30)
+
+
+@pytest.mark.parametrize("mix", ["plain", "with_cahn_hilliard"])
+def test_streamed_batch_equals_lone_runs(mix):
+    """A batch whose state exceeds the last-level cache stores it non-temporally
+    (the smaller batches of the other tests keep theirs in the cache): four
+    1024 x 512 FP32 lattices (dam breaks at four contact angles, or three and a
+    Cahn-Hilliard droplet), 20 steps, each equal to the lattice advanced alone --
+    the Allen-Cahn cases bitwise, the Cahn-Hilliard one within 16 ulp."""
+    from paper_2111_00847_amd import api
+    from paper_2111_00847_amd.sim import BatchSim, Sim
+    cases = [W.dam_break(nx=1024, ny=512, theta_deg=th) for th in (50.0, 80.0, 110.0, 140.0)]
+    if mix == "with_cahn_hilliard":
+        case, phi0 = W.square_droplet_ch(n=512, R=128.0, sigma=1e-3, rho_ratio=100.0, dtype="f32")
+        cases[3] = (case.replace(nx=1024, ny=512), np.tile(phi0, (1, 2)))
+    total = sum(api.lbm_state_size(api.make_params(c)) for c, _ in cases)
+    assert total > (340 << 20), total
+    p0s = [W.hydrostatic_pressure(c, p) if any(c.gravity) else None for c, p in cases]
+    B = BatchSim([c for c, _ in cases], stream=torch.cuda.Stream())
+    B.init([p for _, p in cases], p0s)
+    B.step(20)
+    eps = np.finfo(np.float32).eps
+    for c, ((case, phi0), p0) in enumerate(zip(cases, p0s)):
+        alone = Sim(case).init(phi0, None, p0).step(20)
+        torch.cuda.synchronize()
+        sa, sb = B.case(c).export_state(), alone.export_state()
+        assert sa["step"] == sb["step"] == 20
+        for key in ("f", "g", "hist"):
+            ta, tb = sa[key], sb[key]
+            if case.phase_eq == "allen_cahn":
+                assert torch.equal(ta, tb), (c, key)
+            else:
+                err = (ta - tb).abs().max().item()
+                assert err <= 16 * eps * max(1.0, tb.abs().max().item()), (c, key, err)
