@@ -1,0 +1,47 @@
+"""The shared set-up module holds inputs only.  Its one physical input beyond
+the initial order parameter, the hydrostatic initial pressure, is pinned here
+by what it is for: with it a stably stratified two-phase column starts close
+to rest, where p = 0 launches a pressure transient through the whole lattice."""
+import math
+
+import numpy as np
+
+import oracle
+import workloads as W
+
+
+def _stratified(ny=96, rho_ratio=3.0, g=1e-5):
+    case = W.Case(nx=4, ny=ny, wall_y=True, rhoA=rho_ratio, rhoB=1.0, nuA=0.05, nuB=0.05, sigma=1e-3, W=4.0,
+                  M=0.05, gravity=(0.0, -g), rho_ref=0.0, dtype="f64")
+    X, Y = W.grid(case)
+    return case, W.tanh_profile(ny / 2.0 - Y, case.W)     # heavy phase A below
+
+
+def test_hydrostatic_pressure_balances_each_bulk_column():
+    case, phi0 = _stratified()
+    p0 = W.hydrostatic_pressure(case, phi0)
+    assert abs(p0.mean()) < 1e-15
+    dp = np.diff(p0, axis=0)                      # p[j+1] - p[j]
+    g = case.gravity[1]
+    np.testing.assert_allclose(dp[:40], case.rhoA * g, rtol=1e-12)    # heavy bulk: dp/dy = rho_A g_y
+    np.testing.assert_allclose(dp[-40:], case.rhoB * g, rtol=1e-12)   # light bulk
+    assert np.all(W.hydrostatic_pressure(case.replace(gravity=(0.0, 0.0)), phi0) == 0)
+
+
+def test_hydrostatic_start_is_close_to_rest():
+    case, phi0 = _stratified()
+    p0 = W.hydrostatic_pressure(case, phi0)
+    u_h = np.abs(oracle.OracleSim(case).init(phi0, None, p0).step(400).moments()[1]).max()
+    u_0 = np.abs(oracle.OracleSim(case).init(phi0, None, None).step(400).moments()[1]).max()
+    print(f"max|u| after 400 steps: hydrostatic start {u_h:.2e}, p = 0 start {u_0:.2e}")
+    assert u_h < 0.05 * u_0
+
+
+def test_seeded_spreading_mix_is_reproducible():
+    a = W.spreading_batch()
+    b = W.spreading_batch()
+    assert [(c.nx, c.ny, c.theta) for c, _ in a] == [(c.nx, c.ny, c.theta) for c, _ in b]
+    sizes = {(c.nx, c.ny) for c, _ in a}
+    assert sizes == set(W.SPREAD_SIZES)
+    th = [math.degrees(c.theta[2]) for c, _ in a]
+    assert 30.0 <= min(th) and max(th) <= 150.0
