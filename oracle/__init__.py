@@ -78,6 +78,9 @@ def lib():
         L.orc_set_state_m.argtypes = [ctypes.c_void_p, d, d, d, d, d, ctypes.c_long]
         L.orc_flux.argtypes = [ctypes.c_void_p, d, d]
         L.orc_fa.argtypes = [ctypes.c_void_p, d]
+        L.orc_div_fields.argtypes = [ctypes.c_void_p, d, d]
+        L.orc_collide_node.argtypes = [d, d, d, d, d]
+        L.orc_collide_node.restype = None
         L.orc_set_threads.argtypes = [ctypes.c_int]
         L.orc_set_threads.restype = None
         L.orc_lattice.argtypes = [P(ctypes.c_int), P(ctypes.c_int), d, d, d]
@@ -89,7 +92,7 @@ def lib():
         L.orc_direct_g.argtypes = [P(OrcParams)] + [ctypes.c_double] * 13 + [d, d]
         for name in ("orc_init", "orc_step", "orc_moments", "orc_diagnostics",
                      "orc_get_state", "orc_set_state", "orc_rates", "orc_grad", "orc_set_state_m",
-                     "orc_flux", "orc_fa"):
+                     "orc_flux", "orc_fa", "orc_div_fields"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -212,6 +215,14 @@ class OracleSim:
         assert rc == 0, rc
         return self
 
+    def div_fields(self):
+        """div u = tr S (Eq. strainRate) and S_m (Sec. 4.1) of every node of the
+        current level; S_m is NaN at nodes with a neighbour beyond a wall."""
+        div = np.empty(self.shape)
+        sm = np.empty(self.shape)
+        assert lib().orc_div_fields(self.h, _dp(div), _dp(sm)) == 0
+        return div, sm
+
     def fa(self):
         """a of the corrected model's F_a = a u at the current level, [ny][nx]."""
         a = np.empty(self.shape)
@@ -288,6 +299,14 @@ def moments_g(case, rho, pr, u, v, mx, my, Fx, Fy, drx, dry, d_umx, d_vmy, d_cro
     lib().orc_moments_g(ctypes.byref(p), rho, pr, u, v, mx, my, Fx, Fy, drx, dry, d_umx, d_vmy,
                         d_cross, _dp(meq), _dp(mF))
     return meq, mF
+
+
+def collide_node(S, fv, meq, mR):
+    """The oracle's moment-form collision of one node (Eq. evoPF / Remark 2)."""
+    S, fv, meq, mR = (_f64(a).reshape(9) for a in (S, fv, meq, mR))
+    out = np.empty(9)
+    lib().orc_collide_node(_dp(S), _dp(fv), _dp(meq), _dp(mR), _dp(out))
+    return out
 
 
 def direct_g(case, rho, pr, u, v, mx, my, Fx, Fy, drx, dry, d_umx, d_vmy, d_cross):

@@ -683,6 +683,23 @@ static void macroscopic(orc_sim *s) {
         }
 }
 
+/* One node of Eq. (evoPF) -- and of Remark 2 for g -- in moment form:
+ * m = M1 f; m* = m - S (m - m^eq) + (I - S/2) m_R; f* = M1^-1 m*. */
+static void collide_node(const double Minv[9][9], const double S[9], const double fv[9], const double meq[9],
+                         const double mR[9], double out[9]) {
+    double m[9], ms[9];
+    matvec(M1, fv, m);
+    for (int j = 0; j < 9; j++) ms[j] = m[j] - S[j] * (m[j] - meq[j]) + (1.0 - S[j] / 2.0) * mR[j];
+    matvec(Minv, ms, out);
+}
+
+void orc_collide_node(const double S[9], const double fv[9], const double meq[9], const double mR[9],
+                      double out[9]) {
+    double R[9][9];
+    invert9(M1, R);
+    collide_node(R, S, fv, meq, mR, out);
+}
+
 static void collide(orc_sim *s) {
     long n = s->n;
     int nx = s->nx, ny = s->ny;
@@ -691,7 +708,7 @@ static void collide(orc_sim *s) {
     for (int y = 0; y < ny; y++)
         for (int x = 0; x < nx; x++) {
             long k = (long)y * nx + x;
-            double fv[9], gv[9], m[9], meq[9], mR[9], ms[9], out[9];
+            double fv[9], gv[9], meq[9], mR[9], out[9];
             for (int i = 0; i < 9; i++) {
                 fv[i] = s->f[i * n + k];
                 gv[i] = s->g[i * n + k];
@@ -703,10 +720,7 @@ static void collide(orc_sim *s) {
             else
                 orc_moments_f(p, s->phi[k], u, v, s->lam[k] * s->nxv[k], s->lam[k] * s->nyv[k],
                               s->dP5[0 * n + k], s->dP5[1 * n + k], meq, mR);
-            matvec(M1, fv, m);
-            for (int j = 0; j < 9; j++)
-                ms[j] = m[j] - s->sf[j] * (m[j] - meq[j]) + (1.0 - s->sf[j] / 2.0) * mR[j];
-            matvec(s->Minv, ms, out);
+            collide_node(s->Minv, s->sf, fv, meq, mR, out);
             for (int i = 0; i < 9; i++) s->fs[i * n + k] = out[i];
             /* Remark 2, moment form of Eq. (evoNS) */
             orc_moments_g(p, s->rho[k], s->pr[k], u, v, s->mx[k], s->my[k], s->Fx[k], s->Fy[k],
@@ -716,10 +730,7 @@ static void collide(orc_sim *s) {
             double sg[9];
             for (int j = 0; j < 9; j++) sg[j] = s->sg[j];
             sg[7] = sg[8] = s->snu[k];
-            matvec(M1, gv, m);
-            for (int j = 0; j < 9; j++)
-                ms[j] = m[j] - sg[j] * (m[j] - meq[j]) + (1.0 - sg[j] / 2.0) * mR[j];
-            matvec(s->Minv, ms, out);
+            collide_node(s->Minv, sg, gv, meq, mR, out);
             for (int i = 0; i < 9; i++) s->gs[i * n + k] = out[i];
         }
 }
@@ -915,31 +926,26 @@ int orc_set_state_m(orc_sim *s, const double *f, const double *g, const double *
 }
 
 /* ------------------------------------------------------------------ */
-/* Diagnostics of the current level (Sec. 4.1):
+/* Per-node diagnostics of the current level (Sec. 4.1), after macroscopic():
  *  div u = tr S with S from Eq. (strainRate):
  *     S = -s_2/(2 rho cs^2) [sum_i c_i c_i (g_i - g_i^eq) + M_2F/2],
+ *     s_2 the node's s_nu, tr M_2F = 2 u.F + d_t(u.m) + 4 cs^2 u.grad rho
+ *     (way 2 of Remark 1: d_t(rho uu + p I) -> uF + Fu),
  *  S_m = d_t rho + div(m^CC) = (rho^n - rho^{n-1}) + rho div u + u.grad rho + div m^phiC,
- *  where div m^phiC uses Eq. (central1).  The rms of S_m runs over the
- *  nodes whose eight neighbours are all fluid nodes (all nodes when both
- *  axes are periodic); D_u^rms runs over all nodes. */
-int orc_diagnostics(const orc_sim *cs, double out[6]) {
-    orc_sim *s = (orc_sim *)cs;
-    if (!s || !out) return -1;
+ *  where div m^phiC uses Eq. (central1); interior[k] = 0 (and S_m 0) at nodes
+ *  that have a neighbour beyond a wall. */
+static void div_fields(orc_sim *s, double *div, double *sm, unsigned char *interior) {
     const orc_params *p = &s->P;
-    macroscopic(s);
     long n = s->n;
     int nx = s->nx, ny = s->ny;
     double drho = (p->rhoA - p->rhoB) / (p->phiA - p->phiB);
-    double *div = calloc(n, sizeof(double));
-    double sum_phi = 0, maxdiv = 0, sdu = 0, umax = 0, nonfinite = 0;
     for (long k = 0; k < n; k++) {
-        double geq[9], Fi[9], meq[9], mF[9];
+        double geq[9], meq[9], mF[9];
         double u = s->ux[k], v = s->uy[k];
         orc_moments_g(p, s->rho[k], s->pr[k], u, v, s->mx[k], s->my[k], s->Fx[k], s->Fy[k],
                       drho * s->gx[k], drho * s->gy[k], s->dP5[2 * n + k], s->dP5[3 * n + k],
                       s->dP5[4 * n + k], meq, mF);
         matvec(s->Minv, meq, geq);
-        (void)Fi;
         double acc = 0;
         for (int i = 0; i < 9; i++) {
             double c2 = CX[i] * CX[i] + CY[i] * CY[i];
@@ -949,18 +955,10 @@ int orc_diagnostics(const orc_sim *cs, double out[6]) {
         double trM2F = 2.0 * (u * s->Fx[k] + v * s->Fy[k]) + (s->dP5[2 * n + k] + s->dP5[3 * n + k]) +
                        2.0 * CS2 * ugr + 2.0 * CS2 * ugr;
         div[k] = -s->snu[k] / (2.0 * s->rho[k] * CS2) * (acc + 0.5 * trM2F);
-        sum_phi += s->phi[k];
-        if (fabs(div[k]) > maxdiv) maxdiv = fabs(div[k]);
-        sdu += div[k] * div[k];
-        double um = sqrt(u * u + v * v);
-        if (um > umax) umax = um;
-        for (int i = 0; i < 9; i++)
-            if (!isfinite(s->f[i * n + k]) || !isfinite(s->g[i * n + k])) nonfinite = 1;
     }
-    double ssm = 0;
-    long cnt = 0;
     for (int y = 0; y < ny; y++)
         for (int x = 0; x < nx; x++) {
+            long k = (long)y * nx + x;
             int ok = 1;
             double dmx = 0, dmy = 0;
             for (int i = 1; i < 9; i++) {
@@ -977,16 +975,68 @@ int orc_diagnostics(const orc_sim *cs, double out[6]) {
                 dmx += WT[i] * CX[i] * s->mx[t];
                 dmy += WT[i] * CY[i] * s->my[t];
             }
-            if (!ok) continue;
-            long k = (long)y * nx + x;
+            interior[k] = (unsigned char)ok;
+            if (!ok) {
+                sm[k] = 0.0;
+                continue;
+            }
             double divm = (dmx + dmy) / CS2;
             double rho_prev = drho * (s->phi_prev[k] - p->phiB) + p->rhoB;
             double dtr = s->step > 0 ? s->rho[k] - rho_prev : 0.0;
             double ugr = s->ux[k] * drho * s->gx[k] + s->uy[k] * drho * s->gy[k];
-            double Sm = dtr + s->rho[k] * div[k] + ugr + divm;
-            ssm += Sm * Sm;
-            cnt++;
+            sm[k] = dtr + s->rho[k] * div[k] + ugr + divm;
         }
+}
+
+/* div u (tr S) and S_m of every node of the current level, [ny][nx] each; S_m
+ * is NaN at nodes with a neighbour beyond a wall.  Either pointer may be NULL. */
+int orc_div_fields(const orc_sim *cs, double *div, double *sm) {
+    orc_sim *s = (orc_sim *)cs;
+    if (!s) return -1;
+    macroscopic(s);
+    long n = s->n;
+    double *d = calloc(n, sizeof(double)), *m = calloc(n, sizeof(double));
+    unsigned char *in = calloc(n, 1);
+    div_fields(s, d, m, in);
+    for (long k = 0; k < n; k++)
+        if (!in[k]) m[k] = NAN;
+    if (div) memcpy(div, d, sizeof(double) * n);
+    if (sm) memcpy(sm, m, sizeof(double) * n);
+    free(d);
+    free(m);
+    free(in);
+    return 0;
+}
+
+/* Diagnostics of the current level (Sec. 4.1) from the per-node fields above:
+ * the rms of S_m runs over the nodes whose eight neighbours are all fluid
+ * nodes (all nodes when both axes are periodic); D_u^rms runs over all nodes. */
+int orc_diagnostics(const orc_sim *cs, double out[6]) {
+    orc_sim *s = (orc_sim *)cs;
+    if (!s || !out) return -1;
+    macroscopic(s);
+    long n = s->n;
+    double *div = calloc(n, sizeof(double)), *sm = calloc(n, sizeof(double));
+    unsigned char *interior = calloc(n, 1);
+    div_fields(s, div, sm, interior);
+    double sum_phi = 0, maxdiv = 0, sdu = 0, umax = 0, nonfinite = 0;
+    for (long k = 0; k < n; k++) {
+        double u = s->ux[k], v = s->uy[k];
+        sum_phi += s->phi[k];
+        if (fabs(div[k]) > maxdiv) maxdiv = fabs(div[k]);
+        sdu += div[k] * div[k];
+        double um = sqrt(u * u + v * v);
+        if (um > umax) umax = um;
+        for (int i = 0; i < 9; i++)
+            if (!isfinite(s->f[i * n + k]) || !isfinite(s->g[i * n + k])) nonfinite = 1;
+    }
+    double ssm = 0;
+    long cnt = 0;
+    for (long k = 0; k < n; k++) {
+        if (!interior[k]) continue;
+        ssm += sm[k] * sm[k];
+        cnt++;
+    }
     out[0] = sum_phi;
     out[1] = maxdiv;
     out[2] = sqrt(sdu / (double)n);
@@ -994,5 +1044,7 @@ int orc_diagnostics(const orc_sim *cs, double out[6]) {
     out[4] = umax;
     out[5] = nonfinite;
     free(div);
+    free(sm);
+    free(interior);
     return 0;
 }

@@ -56,6 +56,10 @@ int orc_step(orc_sim *s, long nsteps);
 int orc_moments(const orc_sim *s, double *phi, double *u, double *p);
 /* out: sum phi, max|div u|, D_u^rms, S_m^rms, max|u|, non-finite flag. */
 int orc_diagnostics(const orc_sim *s, double out[6]);
+/* The per-node fields behind them: div u = tr S (Eq. strainRate) and S_m
+ * (Sec. 4.1), [ny][nx] each; S_m is NaN at nodes with a neighbour beyond a
+ * wall.  Either pointer may be NULL. */
+int orc_div_fields(const orc_sim *s, double *div, double *sm);
 /* Post-streaming distributions at the current level, the five Euler-history
  * products H = (phi u, phi v, u m_x, v m_y, u m_y + v m_x) of the previous
  * level, and phi at the previous level; any pointer may be NULL. */
@@ -101,6 +105,10 @@ void orc_moments_f_ch(const orc_params *p, double phi, double mu, double u, doub
 void orc_moments_g(const orc_params *p, double rho, double pr, double u, double v, double mx, double my,
                    double Fx, double Fy, double drx, double dry, double dP_um_x, double dP_vm_y,
                    double dP_cross, double meq[9], double mF[9]);
+/* One node of the collision in moment form (Eq. evoPF; Remark 2 for g):
+ * out = M1^-1 [(I - S) M1 fv + S meq + (I - S/2) mR]. */
+void orc_collide_node(const double S[9], const double fv[9], const double meq[9], const double mR[9],
+                      double out[9]);
 /* Direct (Sec. 3) forms: g^eq_i (Eq. geq) and F_i with M_2F in the second way of Remark 1. */
 void orc_direct_g(const orc_params *p, double rho, double pr, double u, double v, double mx, double my,
                   double Fx, double Fy, double drx, double dry, double dP_um_x, double dP_vm_y,
