@@ -190,10 +190,12 @@ int lbm_import_state(const lbm_params *p, void *state, const void *f, const void
  *   for each segment, newest first: lbm_tape_record from the segment's first
  *   level, then lbm_adjoint_step(tape, j) for j = L-1 .. 0 (or one lbm_adjoint_run)
  *   lbm_adjoint_init -> dL/dphi0; lbm_adjoint_params -> dL/dgravity, dL/dtheta.
- * Level mismatches (a step whose tape level is not one below the adjoint's)
- * are detected on the device; the step is skipped and lbm_adjoint_params then
- * returns LBM_E_PARAM.  Adjoint and tape buffers are caller-owned device
- * memory, 256-byte aligned, in the dtype of the params.  The reverse mode is
+ * Level mismatches (a step whose tape level is not one below the adjoint's),
+ * a slot j the tape does not hold and a tape recorded for another lattice or
+ * dtype are detected on the device from the tape's header before any slot is
+ * read; the step is skipped and lbm_adjoint_params then returns LBM_E_PARAM.
+ * Adjoint and tape buffers are caller-owned device memory, 256-byte aligned,
+ * in the dtype of the params.  The reverse mode is
  * that of the Allen-Cahn step with the stencil gradient and the present or
  * original model: every call below returns LBM_E_UNSUPPORTED for other
  * params (Cahn-Hilliard, the local gradient scheme, the corrected model). */

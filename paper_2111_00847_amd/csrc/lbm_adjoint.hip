@@ -69,7 +69,8 @@ struct TapeHeader {
 
 struct AdjHeader {
     int64_t level;     // level of the adjoint currently held
-    int32_t status;    // 0 ok; 1 an adjoint step met an adjoint of the wrong level; 2 init not at level 0
+    int32_t status;    // 0 ok; 1 an adjoint step met an adjoint of the wrong level; 2 init not at level 0;
+                       // 3 a tape without slot j, or recorded for another lattice or dtype
     int32_t nx, ny, dtype;
     double result[6];  // lbm_adjoint_params output
 };
@@ -216,11 +217,18 @@ __global__ __launch_bounds__(TX* BY) void k_adj_local(KParams<T> P, const char* 
     __shared__ T sphi[ATY + 2][TX + 3];
     __shared__ T sphp[ATY + 2][TX + 3];
     __shared__ double red[2][BY];
-    const int64_t n = reinterpret_cast<const TapeHeader*>(tape)->n0 + j;
+    // The tape must hold slot j and have been recorded for this lattice and
+    // dtype; otherwise nothing of the tape beyond its header is read, the
+    // status records why, and the later kernels of the step (which exit on a
+    // non-zero status) and lbm_adjoint_params report it.
+    const TapeHeader* TH = reinterpret_cast<const TapeHeader*>(tape);
+    const bool tape_ok = j >= 0 && j < TH->nlevels && TH->nx == P.nx && TH->ny == P.ny &&
+                         TH->dtype == (sizeof(T) == 8 ? LBM_F64 : LBM_F32);
+    const int64_t n = TH->n0 + j;
     AdjHeader* H = V.hdr();
     const int tid = threadIdx.y * TX + threadIdx.x;
-    if (H->status != 0 || H->level != n + 1) {
-        if (blockIdx.x == 0 && tid == 0 && H->level != n + 1) H->status = 1;
+    if (!tape_ok || H->status != 0 || H->level != n + 1) {
+        if (blockIdx.x == 0 && tid == 0 && H->status == 0) H->status = tape_ok ? 1 : 3;
         return;
     }
     const bool first = n == 0;
