@@ -125,7 +125,7 @@ def cpu_baseline(budget_s=15.0, budget_1t_s=6.0):
     cores = oracle.num_threads()
 
     def run(budget):
-        s = oracle.OracleSim(case.replace(dtype="f64")).init(phi0, None, W.hydrostatic_pressure(case, phi0))
+        s = oracle.OracleSim(case.replace(dtype="f64")).init(phi0, None, "hydrostatic")
         s.step(2)                   # first-touch of the oracle's fields
         steps, t0 = 0, time.perf_counter()
         while time.perf_counter() - t0 < budget:
@@ -148,7 +148,7 @@ def measure_main(args, torch, W, Sim):
     """The headline: RTI 256 x 1024, FP32, K steps after W warm-up steps, timed
     as the median of `reps` replays of a captured graph of the K steps."""
     case, phi0 = W.rti()
-    sim = Sim(case, "cuda:0").init(phi0, None, W.hydrostatic_pressure(case, phi0))
+    sim = Sim(case, "cuda:0").init(phi0, None, "hydrostatic")
     sim.step(args.warmup)
     torch.cuda.synchronize()
     reps = time_graph(sim, args.steps, args.reps, torch)
@@ -192,7 +192,7 @@ def measure_large(args, torch, W, Sim, dtype="f32"):
     """The same kernel on a 4096 x 4096 lattice (state 2.9 GB in FP32, 5.6 GB in
     FP64: far beyond the 256 MB cache), where HBM is the bound."""
     caseL, phiL = W.rti(nx=4096, ny=4096, dtype=dtype)
-    simL = Sim(caseL, "cuda:0").init(phiL, None, W.hydrostatic_pressure(caseL, phiL))
+    simL = Sim(caseL, "cuda:0").init(phiL, None, "hydrostatic")
     simL.step(10)
     steps = args.large_steps if dtype == "f32" else max(args.large_steps // 2, 1)
     msL = _median(time_graph(simL, steps, 3, torch))
@@ -235,7 +235,7 @@ def measure_local(args, torch, W, Sim):
     of the previous level: 184 B of algorithmic traffic per update."""
     case, phi0 = W.rti(nx=4096, ny=4096)
     case = case.replace(grad_scheme="local")
-    sim = Sim(case, "cuda:0").init(phi0, None, W.hydrostatic_pressure(case, phi0))
+    sim = Sim(case, "cuda:0").init(phi0, None, "hydrostatic")
     sim.step(10)
     steps = args.large_steps
     ms = _median(time_graph(sim, steps, 3, torch))

@@ -140,6 +140,15 @@ int lbm_state_size(const lbm_params *p, size_t *nbytes /* host */);
 int lbm_init(const lbm_params *p, void *state, const void *phi0, const void *u0, const void *p0,
              void *stream);
 
+/* Initial pressure of the two fluids at rest under gravity (the gravity-driven
+ * set-ups of Secs. 4.4 and 4.5 leave it unstated; read as hydrostatic): with
+ * rho from the density law of Sec. 2 at phi0, p0 integrates
+ * dp/dy = (rho - rho_ref) gravity[1] down every column by the trapezoid rule
+ * from the top row, in FP64, then takes the mean out.  phi0, p0: [ny][nx];
+ * zero gravity gives p0 = 0.  gravity[0] != 0: LBM_E_UNSUPPORTED.  Runs as one
+ * workgroup (an initialisation call, not a per-step one). */
+int lbm_hydrostatic_pressure(const lbm_params *p, const void *phi0, void *p0, void *stream);
+
 /* Advance nsteps >= 0 time steps (Sec. 3): moments, closure, both MRT
  * collisions and streaming with bounce-back, fused in one kernel per step.
  * On a non-NULL stream, runs of >= 64 steps replay a captured graph of 32

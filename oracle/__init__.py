@@ -81,6 +81,8 @@ def lib():
         L.orc_div_fields.argtypes = [ctypes.c_void_p, d, d]
         L.orc_collide_node.argtypes = [d, d, d, d, d]
         L.orc_collide_node.restype = None
+        L.orc_hydrostatic_pressure.argtypes = [P(OrcParams), d, d]
+        L.orc_hydrostatic_pressure.restype = ctypes.c_int
         L.orc_set_threads.argtypes = [ctypes.c_int]
         L.orc_set_threads.restype = None
         L.orc_lattice.argtypes = [P(ctypes.c_int), P(ctypes.c_int), d, d, d]
@@ -156,6 +158,10 @@ class OracleSim:
         return (self.ny, self.nx)
 
     def init(self, phi0, u0=None, p0=None):
+        """p0: a field, None (zero) or "hydrostatic" (hydrostatic_pressure)."""
+        if isinstance(p0, str):
+            assert p0 == "hydrostatic", p0
+            p0 = hydrostatic_pressure(self.case, phi0)
         phi0 = _f64(phi0).reshape(self.shape)
         u0 = None if u0 is None else _f64(u0).reshape((2,) + self.shape)
         p0 = None if p0 is None else _f64(p0).reshape(self.shape)
@@ -247,6 +253,19 @@ class OracleSim:
         sg = np.empty(9)
         lib().orc_rates(self.h, _dp(sf), _dp(sg))
         return sf, sg
+
+
+def hydrostatic_pressure(case, phi0):
+    """The oracle's hydrostatic initial pressure for a case with gravity along y
+    (zero without gravity), [ny][nx]."""
+    phi0 = _f64(phi0).reshape((case.ny, case.nx))
+    if case.gravity[0] == 0.0 and case.gravity[1] == 0.0:
+        return np.zeros_like(phi0)
+    p = make_params(case)
+    out = np.empty_like(phi0)
+    rc = lib().orc_hydrostatic_pressure(ctypes.byref(p), _dp(phi0), _dp(out))
+    assert rc == 0, rc
+    return out
 
 
 def num_threads() -> int:

@@ -818,6 +818,32 @@ int orc_init(orc_sim *s, const double *phi0, const double *u0, const double *p0)
     return 0;
 }
 
+/* Initial pressure of the two fluids at rest under gravity along y (the
+ * gravity-driven set-ups of Secs. 4.4 and 4.5 do not state it; read as
+ * hydrostatic): the density law of Sec. 2 at phi0 gives rho, and p follows
+ * dp/dy = (rho - rho_ref) g_y down every column by the trapezoid rule from
+ * p = 0 at the top row; the mean over the lattice is then subtracted. */
+int orc_hydrostatic_pressure(const orc_params *p, const double *phi0, double *p0) {
+    if (!p || !phi0 || !p0) return -1;
+    if (p->gx != 0.0) return -8;
+    int nx = p->nx, ny = p->ny;
+    long n = (long)nx * ny;
+    double drho = (p->rhoA - p->rhoB) / (p->phiA - p->phiB);
+    double total = 0.0;
+    for (int x = 0; x < nx; x++) {
+        p0[(long)(ny - 1) * nx + x] = 0.0;
+        for (int y = ny - 2; y >= 0; y--) {
+            double rho_lo = p->rhoB + drho * (phi0[(long)y * nx + x] - p->phiB);
+            double rho_hi = p->rhoB + drho * (phi0[(long)(y + 1) * nx + x] - p->phiB);
+            double f_lo = (rho_lo - p->rho_ref) * p->gy, f_hi = (rho_hi - p->rho_ref) * p->gy;
+            p0[(long)y * nx + x] = p0[(long)(y + 1) * nx + x] - 0.5 * (f_lo + f_hi);
+        }
+    }
+    for (long k = 0; k < n; k++) total += p0[k];
+    for (long k = 0; k < n; k++) p0[k] -= total / (double)n;
+    return 0;
+}
+
 /* grad phi of the current level as the closure uses it (Eq. central1, or
  * Eq. local when selected). */
 int orc_grad(const orc_sim *cs, double *gx, double *gy) {

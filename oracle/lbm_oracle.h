@@ -52,6 +52,10 @@ void orc_destroy(orc_sim *s);
 /* f = f^eq(phi0,u0), g = g^eq(phi0,u0,p0); u0 is [2][ny][nx] or NULL, p0 [ny][nx] or NULL. */
 int orc_init(orc_sim *s, const double *phi0, const double *u0, const double *p0);
 int orc_step(orc_sim *s, long nsteps);
+/* Hydrostatic initial pressure for gravity along y: rho from the density law
+ * of Sec. 2 at phi0, dp/dy = (rho - rho_ref) g_y down every column (trapezoid
+ * rule from the top row), zero mean.  phi0, p0: [ny][nx].  -8 if gx != 0. */
+int orc_hydrostatic_pressure(const orc_params *p, const double *phi0, double *p0);
 /* phi, p: [ny][nx]; u: [2][ny][nx]; values at the current time level (pre-collision). */
 int orc_moments(const orc_sim *s, double *phi, double *u, double *p);
 /* out: sum phi, max|div u|, D_u^rms, S_m^rms, max|u|, non-finite flag. */

@@ -56,6 +56,7 @@ _SIGS = {
     "lbm_state_size": [P(LbmParams), P(ctypes.c_size_t)],
     "lbm_init": [P(LbmParams), vp, vp, vp, vp, vp],
     "lbm_step": [P(LbmParams), vp, ctypes.c_int64, vp],
+    "lbm_hydrostatic_pressure": [P(LbmParams), vp, vp, vp],
     "lbm_moments": [P(LbmParams), vp, vp, vp, vp, vp],
     "lbm_diagnostics": [P(LbmParams), vp, P(ctypes.c_double), vp],
     "lbm_export_state": [P(LbmParams), vp, vp, vp, vp, P(ctypes.c_int64), vp],

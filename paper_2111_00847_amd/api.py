@@ -96,6 +96,13 @@ def lbm_init(p, state, phi0, u0=None, p0=None, stream=None):
          _ptr(u0, p, (2,) + shp, "u0"), _ptr(p0, p, shp, "p0"), _stream(stream))
 
 
+def lbm_hydrostatic_pressure(p, phi0, p0, stream=None):
+    """Hydrostatic initial pressure of phi0 into p0 (both [ny][nx] GPU tensors)."""
+    shp = (p.ny, p.nx)
+    call("lbm_hydrostatic_pressure", ctypes.byref(p), _ptr(phi0, p, shp, "phi0"), _ptr(p0, p, shp, "p0"),
+         _stream(stream))
+
+
 def lbm_step(p, state, nsteps=1, stream=None):
     call("lbm_step", ctypes.byref(p), _state_ptr(state), int(nsteps), _stream(stream))
 

@@ -255,6 +255,21 @@ int lbm_init(const lbm_params* p, void* state, const void* phi0, const void* u0,
     return e == hipSuccess ? LBM_OK : hip_fail(e);
 }
 
+int lbm_hydrostatic_pressure(const lbm_params* p, const void* phi0, void* p0, void* stream) {
+    int rc = validate(p);
+    if (rc) return rc;
+    if (!phi0 || !p0) return LBM_E_NULL;
+    if (p->gravity[0] != 0.0) return LBM_E_UNSUPPORTED;
+    Layout L = layout_of(p);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e;
+    if (p->dtype == LBM_F32)
+        e = launch_hydrostatic<float>(resolve<float>(p, L), (const float*)phi0, (float*)p0, s);
+    else
+        e = launch_hydrostatic<double>(resolve<double>(p, L), (const double*)phi0, (double*)p0, s);
+    return e == hipSuccess ? LBM_OK : hip_fail(e);
+}
+
 int lbm_step(const lbm_params* p, void* state, int64_t nsteps, void* stream) {
     int rc = validate(p);
     if (rc) return rc;

@@ -15,6 +15,8 @@ template <typename T>
 hipError_t launch_init(const KParams<T>& P, char* state, const Layout& L, const T* phi0, const T* u0,
                        const T* p0, int dtype, hipStream_t s);
 template <typename T>
+hipError_t launch_hydrostatic(const KParams<T>& P, const T* phi0, T* p0, hipStream_t s);
+template <typename T>
 hipError_t launch_import(const KParams<T>& P, char* state, const Layout& L, const T* f, const T* g,
                          const T* hist, int64_t step, int dtype, hipStream_t s);
 template <typename T>

@@ -275,6 +275,48 @@ __global__ void k_set_stamps(int64_t* stamp, long long n, int64_t level) {
         stamp[i] = level;
 }
 
+// Hydrostatic pressure of the two fluids at rest (the initial pressure of the
+// gravity-driven set-ups): rho from the density law of Sec. 2 at phi0,
+// dp/dy = (rho - rho_ref) g_y integrated down every column by the trapezoid
+// rule from p = 0 at the top row, then the mean taken out.  One workgroup:
+// every thread walks its columns twice (FP64 sums; the second walk subtracts
+// the mean that the block reduction of the first one gives).
+constexpr int HYDRO_THREADS = 1024;
+
+template <typename T>
+__global__ __launch_bounds__(HYDRO_THREADS) void k_hydrostatic(KParams<T> P, const T* phi0, T* p0) {
+    __shared__ double red[HYDRO_THREADS / 64];
+    const int nx = P.nx, ny = P.ny;
+    const double gy = (double)P.gy, drho = (double)P.drho, rhoB = (double)P.rhoB, rref = (double)P.rho_ref,
+                 phiB = (double)P.phiB;
+    auto force = [&](int j, int x) { return (drho * ((double)phi0[(long long)j * nx + x] - phiB) + rhoB - rref) * gy; };
+    double total = 0.0;
+    for (int pass = 0; pass < 2; pass++) {
+        const double mean = pass == 0 ? 0.0 : total / ((double)nx * (double)ny);
+        double acc = 0.0;
+        for (int x = threadIdx.x; x < nx; x += HYDRO_THREADS) {
+            double p = 0.0, fu = force(ny - 1, x);
+            acc += p;
+            if (pass == 1) p0[(long long)(ny - 1) * nx + x] = (T)(p - mean);
+            for (int j = ny - 2; j >= 0; j--) {
+                const double f = force(j, x);
+                p -= 0.5 * (f + fu);
+                fu = f;
+                acc += p;
+                if (pass == 1) p0[(long long)j * nx + x] = (T)(p - mean);
+            }
+        }
+        if (pass == 0) {
+            for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+            if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+            __syncthreads();
+            double t = 0.0;
+            for (int w = 0; w < HYDRO_THREADS / 64; w++) t += red[w];
+            total = t;
+        }
+    }
+}
+
 // ---------------------------------------------------------------- launchers
 static int grid1d(long long n) {
     long long b = (n + 255) / 256;
@@ -366,6 +408,12 @@ hipError_t launch_init(const KParams<T>& P, char* state, const Layout& L, const 
 }
 
 template <typename T>
+hipError_t launch_hydrostatic(const KParams<T>& P, const T* phi0, T* p0, hipStream_t s) {
+    k_hydrostatic<T><<<1, HYDRO_THREADS, 0, s>>>(P, phi0, p0);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_import(const KParams<T>& P, char* state, const Layout& L, const T* f, const T* g,
                          const T* hist, int64_t step, int dtype, hipStream_t s) {
     // f and g are separate caller arrays of [9][n]; stage them contiguously in
@@ -407,7 +455,8 @@ hipError_t launch_export(const KParams<T>& P, const char* state, const Layout& L
     template hipError_t launch_import<T>(const KParams<T>&, char*, const Layout&, const T*, const T*,   \
                                          const T*, int64_t, int, hipStream_t);                          \
     template hipError_t launch_export<T>(const KParams<T>&, const char*, const Layout&, T*, T*, T*,     \
-                                         hipStream_t);
+                                         hipStream_t);                                                  \
+    template hipError_t launch_hydrostatic<T>(const KParams<T>&, const T*, T*, hipStream_t);
 
 LBM_INSTANTIATE(float)
 LBM_INSTANTIATE(double)

@@ -38,7 +38,20 @@ class Sim:
                 self.stream.synchronize()
             torch.cuda.current_stream(self.device).wait_stream(self.stream)
 
+    def hydrostatic_pressure(self, phi0):
+        """The library's hydrostatic initial pressure of phi0 (lbm_hydrostatic_pressure)."""
+        phi = self._t(phi0)
+        p0 = torch.empty(self.shape, dtype=self.dtype, device=self.device)
+        self._enter()
+        api.lbm_hydrostatic_pressure(self.p, phi, p0, self.stream)
+        self._leave(sync=True)
+        return p0
+
     def init(self, phi0, u0=None, p0=None):
+        """p0: a field, None (zero) or "hydrostatic" (lbm_hydrostatic_pressure of phi0)."""
+        if isinstance(p0, str):
+            assert p0 == "hydrostatic", p0
+            p0 = self.hydrostatic_pressure(phi0)
         args = (self._t(phi0), self._t(u0), self._t(p0))
         self._enter()
         api.lbm_init(self.p, self.state, *args, self.stream)
@@ -108,8 +121,21 @@ class BatchSim:
         return torch.as_tensor(np.ascontiguousarray(a), dtype=self.dtype, device=self.device)
 
     def init(self, phi0s, p0s=None):
+        """p0s: None, "hydrostatic" (every case), or one entry per case (a field,
+        None or "hydrostatic")."""
         phis = [self._t(a) for a in phi0s]
-        ps = None if p0s is None else [self._t(a) for a in p0s]
+        if isinstance(p0s, str):
+            p0s = [p0s] * len(phis)
+        ps = None
+        if p0s is not None:
+            ps = []
+            for c, a in enumerate(p0s):
+                if isinstance(a, str):
+                    assert a == "hydrostatic", a
+                    ps.append(Sim(self.cases[c], self.device, state=self.state[:0], stream=self.stream)
+                              .hydrostatic_pressure(phis[c]))
+                else:
+                    ps.append(self._t(a))
         if self.stream is not None:
             self.stream.wait_stream(torch.cuda.current_stream(self.device))
         api.lbm_batch_init(self.handle, self.params, self.state, phis, ps, self.stream)

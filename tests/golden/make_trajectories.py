@@ -64,9 +64,8 @@ def path_of(name: str) -> str:
 def make(name: str) -> str:
     spec = WORKLOADS[name]
     case, phi0 = spec["make"]()
-    p0 = W.hydrostatic_pressure(case, phi0)
     idx = sample_index(case.nx, case.ny)
-    o = oracle.OracleSim(case).init(phi0, None, p0)
+    o = oracle.OracleSim(case).init(phi0, None, "hydrostatic")
     snaps, vel = spec["snaps"], spec["vel"]
     phi_s = np.empty((len(snaps), idx.size))
     u_s = np.empty((len(vel), 2, idx.size))

@@ -1,0 +1,115 @@
+"""GPU trajectories at the stated step counts of the Rayleigh-Taylor
+instability (Sec. 4.4, 256 x 1024, 20000 steps), the dam break (Sec. 4.5,
+1024 x 512, 4000 steps) and a droplet spreading on a wetting wall (Sec. 4.3
+set-up, 512 x 256, 10000 steps), against FP64 oracle trajectories stored by
+tests/golden/make_trajectories.py (phi on a fixed 1/32 sample of the nodes at
+a list of levels, u and v at some of them, the full-lattice total of phi and
+max |u| at every level).  Both runs use the launch configuration the
+benchmark times for their size; total phi is conserved to 1e-12 (FP64) and
+1e-7 (FP32) relative at every level.
+
+FP64: max|dphi| and max|du| / Umax within 1e-10 at every stored level up to
+FP64_HORIZON (measured on MI355X: the droplet spreading over its whole 10000
+steps, 1.1e-14; the Rayleigh-Taylor run through 18000 steps, 9.9e-11, then
+1.0e-9 at 20000 as the instability's roll-ups amplify the rounding-order
+differences; the dam break through 100 steps, 5.1e-12, then 8.4e-10 at 150 and
+3e-3 by 500 -- the collapse pushes the bulk water off phi_A, where the
+direction of n is set by rounding, test_oracle_conditioning.py), and within
+FP64_BOUND beyond.
+
+FP32: max|dphi| <= 1e-5 and max|du| / Umax <= 1e-4 up to FP32_HORIZON
+(measured: spreading over all 10000 steps, 1.9e-7; Rayleigh-Taylor through 6000
+steps, 6.6e-6, first past at 8000 with 3.3e-5; dam break through 50 steps,
+2.5e-6, first past at 100 with 3.8e-4), and phi within FP32_BOUND of the oracle
+over the whole run.  The first stored level past each bound is printed.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+MAKE = {
+    "rti_256x1024": lambda dt: W.rti(dtype=dt),
+    "dam_break_1024x512": lambda dt: W.dam_break(dtype=dt),
+    "spreading_512x256": lambda dt: W.spreading_case(512, 256, 47.0, dtype=dt),
+}
+# last stored level up to which the FP64 GPU run stays within 1e-10 of the oracle, and the
+# bound on max|dphi| and max|du|/Umax beyond it
+FP64_HORIZON = {"rti_256x1024": 18000, "dam_break_1024x512": 100, "spreading_512x256": 10000}
+FP64_BOUND = {"rti_256x1024": 1e-8, "dam_break_1024x512": 1e-2, "spreading_512x256": 1e-10}
+# last stored level up to which the FP32 GPU run stays within 1e-5 / 1e-4 Umax
+FP32_HORIZON = {"rti_256x1024": 6000, "dam_break_1024x512": 50, "spreading_512x256": 10000}
+# bound on max|dphi| of the FP32 run over the whole stated horizon
+FP32_BOUND = {"rti_256x1024": 0.5, "dam_break_1024x512": 2e-2, "spreading_512x256": 1e-5}
+
+
+def _golden(name):
+    path = os.path.join(GOLDEN, f"trajectory_{name}.npz")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated (python tests/golden/make_trajectories.py {name})")
+    return np.load(path)
+
+
+def _trajectory(name, dtype):
+    from paper_2111_00847_amd.sim import Sim
+    d = _golden(name)
+    case, phi0 = MAKE[name](dtype)
+    idx = d["index"]
+    sim = Sim(case).init(phi0, None, "hydrostatic")
+    vel = list(d["vel_steps"])
+    rows, done = [], 0
+    for j, n in enumerate(d["steps"]):
+        sim.step(int(n) - done)
+        done = int(n)
+        phi, u, _ = sim.moments_np()
+        dphi = float(np.abs(phi.ravel()[idx] - d["phi"][j]).max())
+        du = None
+        if n in vel:
+            du = float(np.abs(u.reshape(2, -1)[:, idx] - d["u"][vel.index(n)]).max() / d["umax"][j])
+        diag = sim.diagnostics()
+        drift = abs(diag["sum_phi"] - float(d["sum_phi0"])) / float(d["sum_phi0"])
+        rows.append((int(n), dphi, du, drift))
+        print(f"{name} {dtype} level {int(n)}: max|dphi|={dphi:.3e}"
+              + (f" max|du|/Umax={du:.3e}" if du is not None else "") + f" sum-phi drift {drift:.2e}",
+              flush=True)
+    return rows
+
+
+def _first_past(rows, tol_phi, tol_u):
+    for n, dphi, du, _ in rows:
+        if dphi > tol_phi or (du is not None and du > tol_u):
+            return n
+    return None
+
+
+@pytest.mark.parametrize("name", list(MAKE))
+def test_fp64_trajectory_at_the_stated_horizon(name):
+    rows = _trajectory(name, "f64")
+    first = _first_past(rows, 1e-10, 1e-10)
+    print(f"{name} fp64: first stored level past 1e-10: {first}", flush=True)
+    for n, dphi, du, drift in rows:
+        assert drift < 1e-12, (n, drift)
+        tol = 1e-10 if n <= FP64_HORIZON[name] else FP64_BOUND[name]
+        assert dphi <= tol, (n, dphi)
+        assert du is None or du <= tol, (n, du)
+
+
+@pytest.mark.parametrize("name", list(MAKE))
+def test_fp32_trajectory_at_the_stated_horizon(name):
+    rows = _trajectory(name, "f32")
+    first = _first_past(rows, 1e-5, 1e-4)
+    print(f"{name} fp32: first stored level past max|dphi| 1e-5 / max|du| 1e-4 Umax: {first}", flush=True)
+    for n, dphi, du, drift in rows:
+        assert drift < 1e-7, (n, drift)
+        assert dphi <= FP32_BOUND[name], (n, dphi)
+        if n <= FP32_HORIZON[name]:
+            assert dphi <= 1e-5, (n, dphi)
+            assert du is None or du <= 1e-4, (n, du)

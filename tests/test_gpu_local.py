@@ -20,7 +20,7 @@ def _pair(case, phi0, steps, p0=None):
     from paper_2111_00847_amd.sim import Sim
     case = case.replace(grad_scheme="local")
     if p0 is None and any(case.gravity):
-        p0 = W.hydrostatic_pressure(case, phi0)
+        p0 = "hydrostatic"
     g = Sim(case).init(phi0, None, p0).step(steps)
     o = oracle.OracleSim(case.replace(dtype="f64")).init(phi0, None, p0).step(steps)
     torch.cuda.synchronize()
@@ -114,7 +114,7 @@ def test_local_export_continues_in_the_oracle():
     from paper_2111_00847_amd.sim import Sim
     case, phi0 = W.dam_break(nx=64, ny=32, column=16, dtype="f64", theta_deg=70.0)
     case = case.replace(grad_scheme="local")
-    p0 = W.hydrostatic_pressure(case, phi0)
+    p0 = "hydrostatic"
     gs = Sim(case).init(phi0, None, p0).step(300)
     st = gs.export_state()
     h = st["hist"].cpu().numpy()
@@ -176,7 +176,7 @@ def test_local_scheme_graph_replay_equals_eager():
     from paper_2111_00847_amd.sim import Sim
     case, phi0 = W.rti(nx=128, ny=256)
     case = case.replace(grad_scheme="local")
-    p0 = W.hydrostatic_pressure(case, phi0)
+    p0 = "hydrostatic"
     a = Sim(case).init(phi0, None, p0).step(101)
     b = Sim(case, stream=torch.cuda.Stream()).init(phi0, None, p0)
     b.step(70)

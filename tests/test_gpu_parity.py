@@ -39,7 +39,7 @@ def _compare_macro(gs, os_, tol_phi, tol_u, what=""):
 
 def _run_pair(case, phi0, steps, u0=None, p0=None):
     if p0 is None:
-        p0 = W.hydrostatic_pressure(case, phi0)
+        p0 = "hydrostatic"
     Sim = _gpu()
     g = Sim(case).init(phi0, u0, p0).step(steps)
     o = oracle.OracleSim(case.replace(dtype="f64")).init(phi0, u0, p0).step(steps)
@@ -131,7 +131,7 @@ def test_checkpoint_restore_and_run_to_run_are_bitwise():
     reproduces the original run bitwise; a second run from lbm_init reproduces it
     bitwise too, diagnostics included (fixed-order reductions)."""
     case, phi0 = W.rti(nx=128, ny=256)
-    p0 = W.hydrostatic_pressure(case, phi0)
+    p0 = "hydrostatic"
     Sim = _gpu()
     a = Sim(case).init(phi0, None, p0).step(60)
     torch.cuda.synchronize()
@@ -146,6 +146,26 @@ def test_checkpoint_restore_and_run_to_run_are_bitwise():
         assert torch.equal(sa[key], sc[key]), ("rerun", key)
     assert sa["step"] == sb["step"] == sc["step"] == 120
     assert a.diagnostics() == c.diagnostics()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_hydrostatic_pressure_equals_oracle(dtype):
+    """lbm_hydrostatic_pressure against the oracle's own integration of the same
+    reading (RTI with rho_ref, a dam break wider than the kernel's 1024 threads,
+    zero gravity): FP64 to 1e-12, FP32 to 2e-6 of the largest |p| (the two sum the
+    columns in different orders)."""
+    Sim = _gpu()
+    for case, phi0 in (W.rti(nx=256, ny=1024, dtype=dtype), W.dam_break(nx=1030, ny=70, column=100, dtype=dtype),
+                       W.square_droplet(n=40, side=16, dtype=dtype)):
+        pg = Sim(case).hydrostatic_pressure(phi0).double().cpu().numpy()
+        po = oracle.hydrostatic_pressure(case, phi0)
+        scale = max(np.abs(po).max(), 1e-300)
+        err = np.abs(pg - po).max()
+        print(f"hydrostatic p0 {case.name} {dtype}: max|dp| = {err:.3e} of max|p| {scale:.3e}", flush=True)
+        if not any(case.gravity):
+            assert np.all(pg == 0)
+        else:
+            assert err <= (1e-12 if dtype == "f64" else 2e-6) * scale
 
 
 def test_moments_fp64_equal_oracle():
@@ -244,7 +264,7 @@ def test_one_step_at_horizon(name, dtype):
     1e-6 and u within 1e-5 Umax after the step); total phi is conserved."""
     make, steps = HORIZON[name]
     case, phi0 = make(dtype)
-    p0 = W.hydrostatic_pressure(case, phi0)
+    p0 = "hydrostatic"
     gs = _gpu()(case).init(phi0, None, p0).step(steps)
     st = gs.export_state()
     assert st["step"] == steps

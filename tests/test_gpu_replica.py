@@ -5,13 +5,18 @@ through the C ABI and compared with the printed numbers (tests/golden/).
 Table 3 is matched within max(1.5 deg, twice the paper's own deviation).
 Table 2 runs with the paper's unregularised normal (eps_n = 1e-9 in FP64; the
 default 1e-4 is chosen for FP32 conditioning and, at density ratio 1000, its
-residual flux in the tanh tails dominates the error at fine resolution).  Our
-Err_u is 1.1e-2 .. 1.3e-2 where the paper prints 1.5e-3 .. 8.4e-3; the
-difference converges away at second order in dx/W, i.e. it is discretisation
-(the paper samples U_x at y = j dx with an unstated wall placement, we use
-half-way walls and nodes at half-integers) -- checked here by doubling the
-resolution at fixed W/h.  The GPU value equals the oracle's at the paper's
-set-up.
+residual flux in the tanh tails dominates the error at fine resolution).
+Table 2 is not reproduced: our Err_u is 1.1e-2 .. 1.3e-2 where the paper
+prints 1.5e-3 .. 8.4e-3.  No reading of the node and wall placement closes the
+gap (test_table2_placement_readings: nodes at half-integers or on integers,
+the interface between nodes or on one, 99, 100 or 101 rows -- every placement
+consistent with half-way walls gives the same 1.06e-2 .. 1.07e-2 at 10:1, and
+sampling U_e with walls at +-h where the lattice puts them elsewhere gives
+3e-2).  The residual sits at the interface: a velocity-gradient mismatch
+across the layer of strong viscosity contrast, linear in each phase, which
+falls at second order in dx/W (test_table2_error_is_second_order_
+discretisation).  Our values are pinned to 5%; the GPU value equals the
+oracle's at the paper's set-up.
 """
 import json
 import math
@@ -64,13 +69,64 @@ def _gpu_err(ratio, ny, Wd, steps):
     return _err(u, ue)
 
 
+# Err_u of this library at the Sec. 4.2 set-up after 160000 steps (FP64), per density ratio
+TABLE2_OURS = {10: 1.061e-2, 100: 1.26e-2, 150: 8.91e-3, 1000: 1.10e-2}
+
+
 @pytest.mark.parametrize("ratio", [10, 100, 150, 1000])
 def test_table2_layered_poiseuille(ratio):
     ref = _golden("paper_table2_layered_poiseuille.json")
     paper = ref["Err_u"][ref["density_ratio"].index(ratio)]
     err = _gpu_err(float(ratio), 100, 4.0, 160000)
-    print(f"Table 2, density ratio {ratio}: Err_u {err:.3e} (paper {paper:.3e})", flush=True)
-    assert err < 1.5e-2 and err < 8.0 * paper
+    print(f"Table 2, density ratio {ratio}: Err_u {err:.3e} (paper {paper:.3e}; recorded {TABLE2_OURS[ratio]:.3e})",
+          flush=True)
+    assert abs(err - TABLE2_OURS[ratio]) <= 0.05 * TABLE2_OURS[ratio]
+    assert err < 8.0 * paper
+
+
+def _ue_between(case, y, lo, hi):
+    """The closed form of Sec. 4.2 (forcing G, smooth mu of the tanh layer) for
+    walls at y = lo and y = hi and the interface at y = 0."""
+    from scipy.integrate import quad
+    muA, muB = case.rhoA * case.nuA, case.rhoB * case.nuB
+    mu = lambda t: 0.5 * (muA + muB) + 0.5 * (muA - muB) * math.tanh(-2 * t / case.W)
+    G = case.body_force[0]
+    A = quad(lambda t: t / mu(t), lo, hi, limit=200)[0]
+    B = quad(lambda t: 1 / mu(t), lo, hi, limit=200)[0]
+    return np.array([G * (-quad(lambda t: t / mu(t), lo, v, limit=200)[0] + (A / B) * quad(lambda t: 1 / mu(t), lo, v,
+                                                                                          limit=200)[0]) for v in y])
+
+
+def test_table2_placement_readings():
+    """Density ratio 10, the Sec. 4.2 set-up with four placements of the nodes
+    relative to the walls and the interface: every placement consistent with
+    half-way walls gives Err_u within 1.0e-2 .. 1.1e-2 (the paper prints
+    1.54e-3), and U_e sampled with walls at +-h where the lattice has them half
+    a node off gives more, not less."""
+    errs = {}
+    for ny, shift in ((100, 0.0), (100, 0.5), (101, 0.0), (99, 0.0)):
+        case, _ = W.layered_poiseuille(nx=10, ny=ny, density_ratio=10.0, visc_ratio=10.0, umax=1e-6, M=0.1,
+                                       sigma=1e-3, W=4.0, muB=0.1, dtype="f64")
+        case = case.replace(eps_n=1e-9)
+        X, Y = W.grid(case)
+        yc = Y - ny / 2.0 - shift                 # node positions relative to the interface
+        s = _sim()(case, stream=torch.cuda.Stream()).init(W.tanh_profile(-yc, 4.0)).step(160000)
+        ux = s.moments_np()[1][0, :, 0]
+        y = yc[:, 0]
+        ue = _ue_between(case, y, y[0] - 0.5, y[-1] + 0.5)
+        errs[(ny, shift, "lattice walls")] = float(np.abs(ux - ue).sum() / np.abs(ue).sum())
+        if shift != 0.0 or ny == 99:
+            lo, hi = (-50.0, 50.0)
+            m = (y > lo) & (y < hi)
+            ue2 = _ue_between(case, y[m], lo, hi)
+            errs[(ny, shift, "walls at +-h")] = float(np.abs(ux[m] - ue2).sum() / np.abs(ue2).sum())
+    for k, v in errs.items():
+        print(f"Table 2 placement {k}: Err_u {v:.3e}", flush=True)
+    for k, v in errs.items():
+        if k[2] == "lattice walls":
+            assert 1.0e-2 < v < 1.1e-2, (k, v)
+        else:
+            assert v > 1.1e-2, (k, v)
 
 
 def test_table2_gpu_equals_oracle():

@@ -30,7 +30,7 @@ import workloads as W
 
 
 def _sensitivity(case, phi0, levels):
-    p0 = W.hydrostatic_pressure(case, phi0)
+    p0 = "hydrostatic"
     a = oracle.OracleSim(case).init(phi0, None, p0)
     b = oracle.OracleSim(case).init(phi0.astype(np.float32).astype(np.float64), None, p0)
     out, done = [], 0

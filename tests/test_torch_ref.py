@@ -68,7 +68,7 @@ def test_step_equals_oracle(geom, n, visc):
 
 def test_trajectory_from_init_equals_oracle():
     case, phi0 = W.dam_break(nx=32, ny=16, column=8, dtype="f64", theta_deg=70.0)
-    p0 = W.hydrostatic_pressure(case, phi0)
+    p0 = oracle.hydrostatic_pressure(case, phi0)
     ref = TorchRef(case)
     grav, theta = as_params(case)
     with torch.no_grad():

@@ -271,31 +271,6 @@ def flat_interface(nx: int = 4, ny: int = 128, W: float = 4.0, rho_ratio: float 
     return case, phi0
 
 
-def hydrostatic_pressure(case: Case, phi0):
-    """Initial pressure of the two fluids at rest, taken with a sharp interface:
-    every node carries the bulk density of the phase its initial order parameter
-    lies nearer to (rho_A where phi0 > (phi_A + phi_B)/2, else rho_B), and p
-    integrates dp/dy = (rho - rho_ref) g_y down every column (trapezoid rule from
-    the top row), with zero mean.  Zero for cases without gravity.  A set-up input
-    like phi0 itself: it holds only the two bulk densities, not the diffuse
-    interface's density law, and it leaves an imbalance only inside the interface
-    layer.  Starting from p = 0 instead launches a pressure transient across the
-    whole lattice that pushes the bulk phi off phi_A, where the sharpening term of
-    the Allen-Cahn flux is ill-conditioned."""
-    if case.gravity[0] != 0.0:
-        raise NotImplementedError("hydrostatic start for gravity along y only")
-    phi0 = np.asarray(phi0, dtype=np.float64)
-    if case.gravity[1] == 0.0:
-        return np.zeros_like(phi0)
-    heavy = phi0 > 0.5 * (case.phiA + case.phiB)
-    rho = np.where(heavy, case.rhoA, case.rhoB)
-    fy = (rho - case.rho_ref) * case.gravity[1]
-    p = np.zeros_like(phi0)
-    for j in range(case.ny - 2, -1, -1):
-        p[j] = p[j + 1] - 0.5 * (fy[j] + fy[j + 1])
-    return p - p.mean()
-
-
 def random_state_fields(case: Case, seed: int = 7, amp_u: float = 1e-3):
     """A smooth random phi0 in (0, 1) and small random u0, p0 for step-map tests."""
     rng = np.random.default_rng(seed)
