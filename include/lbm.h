@@ -279,6 +279,25 @@ int lbm_batch_tuning(const lbm_batch *batch, int32_t *tile_rows, int32_t *thread
                      int32_t *items);
 int lbm_batch_destroy(lbm_batch *batch);
 
+/* ---- a batch step that allocates nothing ----------------------------------
+ * For callers that cannot allocate: code under stream capture, tight serving
+ * loops, harnesses that forbid hipMalloc.  lbm_batch_step_noalloc advances
+ * the cases of a batch state (the layout lbm_batch_state_size and
+ * lbm_batch_case_offset give for the same cases, initialised by
+ * lbm_batch_init or by lbm_init of every case at its offset) exactly as
+ * lbm_batch_step does with an untuned plan of the same cases (8-row tiles,
+ * one workgroup per work item), without a plan and without allocating: the
+ * case table (at most LBM_NOALLOC_MAX_CASES cases, about 140 KB) lives in a
+ * fixed device array of the library that every GPU it runs on holds until
+ * the process ends; the call writes it with small kernels on `stream` before
+ * its steps.  Every call on one GPU shares that array and it keeps the last
+ * call's table: calls that overlap on one GPU (different streams or host
+ * threads) race, calls ordered on one stream do not.  No graph is captured
+ * or replayed.  Errors: LBM_E_SIZE for more cases than the limit, a state
+ * not 256-byte aligned or nsteps < 0; otherwise those of lbm_batch_create. */
+#define LBM_NOALLOC_MAX_CASES 256
+int lbm_batch_step_noalloc(const lbm_params *cases, int32_t ncases, void *state, int64_t nsteps, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -78,6 +78,7 @@ _SIGS = {
     "lbm_batch_step": [vp, vp, ctypes.c_int64, vp],
     "lbm_batch_tuning": [vp, P(ctypes.c_int32), P(ctypes.c_int32), P(ctypes.c_int32), P(ctypes.c_int32)],
     "lbm_batch_destroy": [vp],
+    "lbm_batch_step_noalloc": [P(LbmParams), ctypes.c_int32, vp, ctypes.c_int64, vp],
 }
 _RESTYPE = {"lbm_status_string": ctypes.c_char_p}
 

@@ -266,6 +266,13 @@ def lbm_batch_step(batch, state, nsteps=1, stream=None):
     call("lbm_batch_step", batch, _state_ptr(state), int(nsteps), _stream(stream))
 
 
+def lbm_batch_step_noalloc(params, state, nsteps=1, stream=None):
+    """Advance a batch state of the cases `params` (list of LbmParams) without a
+    plan and without allocating (the library's fixed device case table)."""
+    arr = (LbmParams * len(params))(*params)
+    call("lbm_batch_step_noalloc", arr, len(params), _state_ptr(state), int(nsteps), _stream(stream))
+
+
 def lbm_batch_tuning(batch):
     ty, by, g, items = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
     call("lbm_batch_tuning", batch, ctypes.byref(ty), ctypes.byref(by), ctypes.byref(g), ctypes.byref(items))

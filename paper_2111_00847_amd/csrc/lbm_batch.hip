@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "../../include/lbm.h"
@@ -156,27 +157,35 @@ int tiles_for(const lbm_params& p, int ty, int* ntx, int* nty) {
     return *ntx * *nty;
 }
 
+// Case table of a batch for tiles of `ty` rows: parameters, state offsets and
+// the first work item of every case; returns the number of work items.
 template <typename T>
-hipError_t upload_cases(lbm_batch* B, int ty) {
-    std::vector<BatchCase<T>> h(B->ncases);
+int fill_cases(const lbm_params* params, const Layout* layouts, const size_t* base, int ncases, int ty,
+               BatchCase<T>* h) {
     int items = 0;
-    for (int c = 0; c < B->ncases; c++) {
+    for (int c = 0; c < ncases; c++) {
         BatchCase<T>& C = h[c];
         memset(&C, 0, sizeof(C));
-        C.P = resolve<T>(&B->params[c], B->layouts[c]);
-        C.base = B->base[c];
-        C.off0 = B->layouts[c].off_buf[0];
-        C.off1 = B->layouts[c].off_buf[1];
-        C.off_stamp = B->layouts[c].off_stamp;
+        C.P = resolve<T>(&params[c], layouts[c]);
+        C.base = base[c];
+        C.off0 = layouts[c].off_buf[0];
+        C.off1 = layouts[c].off_buf[1];
+        C.off_stamp = layouts[c].off_stamp;
         C.item_begin = items;
-        const lbm_params& q = B->params[c];
+        const lbm_params& q = params[c];
         C.body = q.phase_eq == LBM_CAHN_HILLIARD ? 1
                  : q.model == LBM_MODEL_CORRECTED ? 2
                  : q.grad_scheme == LBM_GRAD_LOCAL ? 3
                                                    : 0;
-        items += tiles_for(B->params[c], ty, &C.ntx, &C.nty);
+        items += tiles_for(params[c], ty, &C.ntx, &C.nty);
     }
-    B->nitems = items;
+    return items;
+}
+
+template <typename T>
+hipError_t upload_cases(lbm_batch* B, int ty) {
+    std::vector<BatchCase<T>> h(B->ncases);
+    B->nitems = fill_cases<T>(B->params.data(), B->layouts.data(), B->base.data(), B->ncases, ty, h.data());
     if (!B->d_cases) {
         hipError_t e = hipMalloc(&B->d_cases, sizeof(BatchCase<T>) * B->ncases);
         if (e != hipSuccess) return e;
@@ -184,42 +193,56 @@ hipError_t upload_cases(lbm_batch* B, int ty) {
     return hipMemcpy(B->d_cases, h.data(), sizeof(BatchCase<T>) * B->ncases, hipMemcpyHostToDevice);
 }
 
+// One launch of the batch kernels over `nitems` work items of a device case
+// table (grid 0: one workgroup per item).
+struct BatchShape {
+    int ty, by, grid, nitems, ncases;
+    bool wide;
+    size_t total;   // bytes of the batch state (store policy)
+};
+
 template <typename T, int TY, int NBY>
-void batch_launch(lbm_batch* B, char* state, hipStream_t s) {
-    const int g = B->grid > 0 ? B->grid : B->nitems;
-    const BatchCase<T>* cases = reinterpret_cast<const BatchCase<T>*>(B->d_cases);
-    if (B->total <= (size_t)LBM_NT_MIN_BYTES)
-        k_step_batch<T, TY, NBY, false><<<g, dim3(TX, NBY), 0, s>>>(cases, B->ncases, B->nitems, state);
+void batch_launch(const BatchShape& S, const void* d_cases, char* state, hipStream_t s) {
+    const int g = S.grid > 0 ? S.grid : S.nitems;
+    const BatchCase<T>* cases = reinterpret_cast<const BatchCase<T>*>(d_cases);
+    if (S.total <= (size_t)LBM_NT_MIN_BYTES)
+        k_step_batch<T, TY, NBY, false><<<g, dim3(TX, NBY), 0, s>>>(cases, S.ncases, S.nitems, state);
     else
-        k_step_batch<T, TY, NBY, true><<<g, dim3(TX, NBY), 0, s>>>(cases, B->ncases, B->nitems, state);
+        k_step_batch<T, TY, NBY, true><<<g, dim3(TX, NBY), 0, s>>>(cases, S.ncases, S.nitems, state);
 }
 
 template <typename T, int TY>
-void batch_launch_wide(lbm_batch* B, char* state, hipStream_t s) {
-    const int g = B->grid > 0 ? B->grid : B->nitems;
-    const BatchCase<T>* cases = reinterpret_cast<const BatchCase<T>*>(B->d_cases);
-    if (B->total <= (size_t)LBM_NT_MIN_BYTES)
-        k_step_batch_wide<T, TY, false><<<g, dim3(TX, BY), 0, s>>>(cases, B->ncases, B->nitems, state);
+void batch_launch_wide(const BatchShape& S, const void* d_cases, char* state, hipStream_t s) {
+    const int g = S.grid > 0 ? S.grid : S.nitems;
+    const BatchCase<T>* cases = reinterpret_cast<const BatchCase<T>*>(d_cases);
+    if (S.total <= (size_t)LBM_NT_MIN_BYTES)
+        k_step_batch_wide<T, TY, false><<<g, dim3(TX, BY), 0, s>>>(cases, S.ncases, S.nitems, state);
     else
-        k_step_batch_wide<T, TY, true><<<g, dim3(TX, BY), 0, s>>>(cases, B->ncases, B->nitems, state);
+        k_step_batch_wide<T, TY, true><<<g, dim3(TX, BY), 0, s>>>(cases, S.ncases, S.nitems, state);
+}
+
+template <typename T>
+void launch_batch_shape(const BatchShape& S, const void* d_cases, char* state, hipStream_t s) {
+    constexpr int T16 = sizeof(T) == 8 ? 8 : 16;
+    if (S.wide) {
+        if (S.ty == 4) batch_launch_wide<T, 4>(S, d_cases, state, s);
+        else batch_launch_wide<T, 8>(S, d_cases, state, s);
+        return;
+    }
+    if (S.ty == 4) batch_launch<T, 4, 4>(S, d_cases, state, s);
+    else if (S.ty == 8 || sizeof(T) == 8) {
+        if (S.by == 8) batch_launch<T, 8, 8>(S, d_cases, state, s);
+        else batch_launch<T, 8, 4>(S, d_cases, state, s);
+    } else {
+        if (S.by == 8) batch_launch<T, T16, 8>(S, d_cases, state, s);
+        else batch_launch<T, T16, 4>(S, d_cases, state, s);
+    }
 }
 
 template <typename T>
 void launch_batch_once(lbm_batch* B, char* state, hipStream_t s) {
-    constexpr int T16 = sizeof(T) == 8 ? 8 : 16;
-    if (B->wide) {
-        if (B->ty == 4) batch_launch_wide<T, 4>(B, state, s);
-        else batch_launch_wide<T, 8>(B, state, s);
-        return;
-    }
-    if (B->ty == 4) batch_launch<T, 4, 4>(B, state, s);
-    else if (B->ty == 8 || sizeof(T) == 8) {
-        if (B->by == 8) batch_launch<T, 8, 8>(B, state, s);
-        else batch_launch<T, 8, 4>(B, state, s);
-    } else {
-        if (B->by == 8) batch_launch<T, T16, 8>(B, state, s);
-        else batch_launch<T, T16, 4>(B, state, s);
-    }
+    const BatchShape S{B->ty, B->by, B->grid, B->nitems, B->ncases, B->wide, B->total};
+    launch_batch_shape<T>(S, B->d_cases, state, s);
 }
 
 void drop_graph(lbm_batch* B) {
@@ -326,12 +349,8 @@ int autotune_t(lbm_batch* B, char* state, const void* const* phi0, const void* c
     return LBM_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-int lbm_batch_create(const lbm_params* cases, int32_t ncases, int32_t autotune, lbm_batch** out) {
-    if (!cases || !out) return LBM_E_NULL;
+// Every case valid, one dtype, each case's state copy addressable with 32-bit offsets.
+int validate_batch(const lbm_params* cases, int ncases) {
     if (ncases < 1) return LBM_E_SIZE;
     for (int c = 0; c < ncases; c++) {
         int rc = validate(&cases[c]);
@@ -340,22 +359,122 @@ int lbm_batch_create(const lbm_params* cases, int32_t ncases, int32_t autotune, 
         Layout L = layout_of(&cases[c]);
         if (L.buf_bytes >= (size_t(1) << 32)) return LBM_E_SIZE;   // 32-bit offsets within a case
     }
+    return LBM_OK;
+}
+
+// Byte offset of every case's state in a batch state (each rounded up to 256 B);
+// returns the total.
+size_t batch_offsets(const lbm_params* cases, int ncases, Layout* layouts, size_t* base) {
+    size_t off = 0;
+    for (int c = 0; c < ncases; c++) {
+        layouts[c] = layout_of(&cases[c]);
+        base[c] = off;
+        off += (layouts[c].total + 255) / 256 * 256;
+    }
+    return off;
+}
+
+bool wide_batch(const lbm_params* cases, int ncases) {
+    bool w = false;
+    for (int c = 0; c < ncases; c++)
+        w = w || cases[c].phase_eq == LBM_CAHN_HILLIARD || cases[c].model == LBM_MODEL_CORRECTED ||
+            cases[c].grad_scheme == LBM_GRAD_LOCAL;
+    return w;
+}
+
+// ---- the batch step that allocates nothing (lbm_batch_step_noalloc) ----
+// Its case table lives in `scratch`, a fixed array of the library in every
+// GPU's memory.  In host code `scratch` only names the symbol: the kernels get
+// the device address that hipGetSymbolAddress returns for the current device
+// (looked up once per device, on the first call there).
+constexpr size_t NOALLOC_CASE_BYTES =
+    sizeof(BatchCase<double>) > sizeof(BatchCase<float>) ? sizeof(BatchCase<double>) : sizeof(BatchCase<float>);
+static_assert(LBM_NOALLOC_MAX_CASES * NOALLOC_CASE_BYTES <= (size_t(256) << 10), "case table above 256 KB");
+static __device__ __align__(256) unsigned char scratch[LBM_NOALLOC_MAX_CASES * NOALLOC_CASE_BYTES];
+
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_dev;   // device address of `scratch`, per device ordinal
+
+hipError_t scratch_address(void** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if ((size_t)dev >= g_scratch_dev.size()) g_scratch_dev.resize(dev + 1, nullptr);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return hipSuccess;
+}
+
+// A few cases of the table travel in the kernel arguments (copied at launch,
+// so the host table may go away as soon as the launch returns) and are stored
+// into the device table by one small workgroup.
+template <typename T>
+struct CaseChunk {
+    static constexpr int N = (int)(3072 / sizeof(BatchCase<T>)) > 0 ? (int)(3072 / sizeof(BatchCase<T>)) : 1;
+    BatchCase<T> c[N];
+    int first, count;
+};
+
+template <typename T>
+__global__ void k_put_cases(CaseChunk<T> chunk, BatchCase<T>* dst) {
+    for (int i = threadIdx.x; i < chunk.count; i += blockDim.x) dst[chunk.first + i] = chunk.c[i];
+}
+
+template <typename T>
+int batch_step_noalloc_t(const lbm_params* cases, int ncases, char* state, int64_t nsteps, hipStream_t s) {
+    // host-side tables on the stack: at most LBM_NOALLOC_MAX_CASES cases
+    static_assert(LBM_NOALLOC_MAX_CASES <= 256, "stack tables");
+    Layout layouts[LBM_NOALLOC_MAX_CASES];
+    size_t base[LBM_NOALLOC_MAX_CASES];
+    const size_t total = batch_offsets(cases, ncases, layouts, base);
+    void* dtab = nullptr;
+    hipError_t e = scratch_address(&dtab);
+    if (e != hipSuccess) return hip_fail(e);
+    BatchCase<T>* table = reinterpret_cast<BatchCase<T>*>(dtab);
+    // the untuned plan's shape: 8-row tiles, 64 x 4 threads, one workgroup per item
+    const int ty = 8;
+    CaseChunk<T> chunk;
+    int nitems = 0;
+    for (int c0 = 0; c0 < ncases; c0 += CaseChunk<T>::N) {
+        const int cnt = ncases - c0 < CaseChunk<T>::N ? ncases - c0 : CaseChunk<T>::N;
+        memset(&chunk, 0, sizeof(chunk));
+        const int items = fill_cases<T>(cases + c0, layouts + c0, base + c0, cnt, ty, chunk.c);
+        for (int i = 0; i < cnt; i++) chunk.c[i].item_begin += nitems;
+        nitems += items;
+        chunk.first = c0;
+        chunk.count = cnt;
+        k_put_cases<T><<<1, 64, 0, s>>>(chunk, table);
+    }
+    const BatchShape S{ty, 4, 0, nitems, ncases, wide_batch(cases, ncases), total};
+    for (int64_t t = 0; t < nsteps; t++) launch_batch_shape<T>(S, table, state, s);
+    e = hipGetLastError();
+    return e == hipSuccess ? LBM_OK : hip_fail(e);
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_batch_create(const lbm_params* cases, int32_t ncases, int32_t autotune, lbm_batch** out) {
+    if (!cases || !out) return LBM_E_NULL;
+    int rc = validate_batch(cases, ncases);
+    if (rc) return rc;
     lbm_batch* B = new lbm_batch();
     B->ncases = ncases;
     B->dtype = cases[0].dtype;
     B->autotune = autotune;
     B->params.assign(cases, cases + ncases);
-    for (int c = 0; c < ncases; c++)
-        B->wide = B->wide || cases[c].phase_eq == LBM_CAHN_HILLIARD || cases[c].model == LBM_MODEL_CORRECTED ||
-                  cases[c].grad_scheme == LBM_GRAD_LOCAL;
-    size_t off = 0;
-    for (int c = 0; c < ncases; c++) {
-        Layout L = layout_of(&cases[c]);
-        B->layouts.push_back(L);
-        B->base.push_back(off);
-        off += (L.total + 255) / 256 * 256;
-    }
-    B->total = off;
+    B->wide = wide_batch(cases, ncases);
+    B->layouts.resize(ncases);
+    B->base.resize(ncases);
+    B->total = batch_offsets(cases, ncases, B->layouts.data(), B->base.data());
     int dev = 0;
     if (hipGetDevice(&dev) == hipSuccess)
         (void)hipDeviceGetAttribute(&B->cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -406,6 +525,19 @@ int lbm_batch_step(lbm_batch* B, void* state, int64_t nsteps, void* stream) {
     hipStream_t s = (hipStream_t)stream;
     return B->dtype == LBM_F32 ? batch_step_t<float>(B, (char*)state, nsteps, s)
                                : batch_step_t<double>(B, (char*)state, nsteps, s);
+}
+
+int lbm_batch_step_noalloc(const lbm_params* cases, int32_t ncases, void* state, int64_t nsteps, void* stream) {
+    if (!cases || !state) return LBM_E_NULL;
+    if (ncases > LBM_NOALLOC_MAX_CASES) return LBM_E_SIZE;
+    int rc = validate_batch(cases, ncases);
+    if (rc) return rc;
+    if (nsteps < 0) return LBM_E_SIZE;
+    if ((uintptr_t)state % 256) return LBM_E_SIZE;
+    if (nsteps == 0) return LBM_OK;
+    hipStream_t s = (hipStream_t)stream;
+    return cases[0].dtype == LBM_F32 ? batch_step_noalloc_t<float>(cases, ncases, (char*)state, nsteps, s)
+                                     : batch_step_noalloc_t<double>(cases, ncases, (char*)state, nsteps, s);
 }
 
 int lbm_batch_tuning(const lbm_batch* B, int32_t* tile_rows, int32_t* thread_rows, int32_t* grid, int32_t* items) {

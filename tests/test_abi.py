@@ -185,3 +185,23 @@ def test_local_gradient_scheme_options():
     if rc == 0:
         assert L.lbm_batch_destroy(h) == 0
     assert L.lbm_tape_record(ctypes.byref(p1), ctypes.c_void_p(256), ctypes.c_void_p(256), 1, None) == -8
+
+
+def test_noalloc_batch_step_validates_on_the_host():
+    """lbm_batch_step_noalloc refuses oversized batches, negative step counts and
+    misaligned states before any HIP call; zero steps is a no-op."""
+    from paper_2111_00847_amd import _lib
+    from paper_2111_00847_amd._lib import LbmParams, lib
+    p = _params()
+    many = (LbmParams * 257)(*([p] * 257))
+    fake = ctypes.c_void_p(1 << 20)          # never dereferenced: every call returns before any HIP call
+    assert lib().lbm_batch_step_noalloc(many, 257, fake, 1, None) == -2
+    one = (LbmParams * 1)(p)
+    assert lib().lbm_batch_step_noalloc(one, 1, fake, -1, None) == -2
+    assert lib().lbm_batch_step_noalloc(one, 1, ctypes.c_void_p((1 << 20) + 8), 1, None) == -2
+    assert lib().lbm_batch_step_noalloc(one, 0, fake, 1, None) == -2
+    assert lib().lbm_batch_step_noalloc(None, 1, fake, 1, None) == -1
+    bad = _params(W=-1.0)
+    assert lib().lbm_batch_step_noalloc((LbmParams * 1)(bad), 1, fake, 1, None) == -4
+    assert lib().lbm_batch_step_noalloc(one, 1, fake, 0, None) == 0
+    assert _lib.LBM_OK == 0
