@@ -243,7 +243,7 @@ __global__ __launch_bounds__(TX* BY) void k_adj_local(KParams<T> P, const char* 
     if (x < P.nx && y < P.ny) {
         const long long k = (long long)y * P.nx + x;
         T f[9], g[9];
-        f[0] = (T)S.f0[k];
+        f[0] = (T)rest_decode(S.f0[k], S.h[k], P.rest_w);
 #pragma unroll
         for (int i = 1; i < Q; i++) f[i] = pull(S.f, P, i, x, y);
 #pragma unroll

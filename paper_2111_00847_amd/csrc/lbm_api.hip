@@ -132,6 +132,7 @@ KParams<T> resolve(const lbm_params* p, const Layout& L) {
     K.rho0 = (T)p->rho0;
     K.eps2 = (T)(p->eps_n * p->eps_n);
     K.Hp = (T)((sg[2] - sg[0]) / (9.0 * sg[0] * sg[2]));
+    K.rest_w = p->phase_eq == LBM_CAHN_HILLIARD ? 1.0 : 4.0 / 9.0;
     return K;
 }
 
@@ -198,10 +199,39 @@ struct StepGraph {
     void* state;
     hipStream_t stream;
     int ty, by;
+    int parity;           // parity of the level the graph's first launch expects
     hipGraphExec_t exec;
 };
 static std::mutex g_graph_mu;
 static std::vector<StepGraph> g_graphs;   // front = most recent
+
+// The level each state was last left at by lbm_init, lbm_import_state and
+// lbm_step, as far as this library knows: the step kernel takes its parity as
+// the guess of which copy to start loading from.  A state the record does not
+// know (or knows wrongly: a device copy restored as a checkpoint, a state
+// stepped through a replayed graph an odd number of times) still steps
+// correctly, only without the head start.  A small most-recently-used list.
+constexpr size_t LEVEL_RECORDS = 1024;
+static std::mutex g_level_mu;
+static std::vector<std::pair<const void*, int64_t>> g_levels;   // front = most recent
+
+int64_t level_guess(const void* state) {
+    std::lock_guard<std::mutex> lock(g_level_mu);
+    for (const auto& e : g_levels)
+        if (e.first == state) return e.second;
+    return 0;
+}
+
+void level_record(const void* state, int64_t level) {
+    std::lock_guard<std::mutex> lock(g_level_mu);
+    for (size_t i = 0; i < g_levels.size(); i++)
+        if (g_levels[i].first == state) {
+            g_levels.erase(g_levels.begin() + i);
+            break;
+        }
+    if (g_levels.size() == LEVEL_RECORDS) g_levels.pop_back();
+    g_levels.insert(g_levels.begin(), std::make_pair(state, level));
+}
 
 int hip_fail(hipError_t e) {
     snprintf(g_last_error, sizeof g_last_error, "%s", hipGetErrorString(e));
@@ -252,6 +282,7 @@ int lbm_init(const lbm_params* p, void* state, const void* phi0, const void* u0,
     else
         e = launch_init<double>(resolve<double>(p, L), (char*)state, L, (const double*)phi0,
                                 (const double*)u0, (const double*)p0, p->dtype, s);
+    level_record(state, 0);
     return e == hipSuccess ? LBM_OK : hip_fail(e);
 }
 
@@ -279,9 +310,10 @@ int lbm_step(const lbm_params* p, void* state, int64_t nsteps, void* stream) {
     hipStream_t s = (hipStream_t)stream;
     int ty, by;
     step_shape(p, &ty, &by);
-    auto launch = [&](int64_t n) -> hipError_t {
-        if (p->dtype == LBM_F32) return launch_step<float>(resolve<float>(p, L), (char*)state, L, n, s, ty, by);
-        return launch_step<double>(resolve<double>(p, L), (char*)state, L, n, s, ty, by);
+    int64_t lev = level_guess(state);
+    auto launch = [&](int64_t n, int64_t l0) -> hipError_t {
+        if (p->dtype == LBM_F32) return launch_step<float>(resolve<float>(p, L), (char*)state, L, n, s, ty, by, l0);
+        return launch_step<double>(resolve<double>(p, L), (char*)state, L, n, s, ty, by, l0);
     };
     hipError_t e;
     // Long runs on a non-NULL stream replay a graph of GRAPH_K steps, unless the
@@ -297,7 +329,7 @@ int lbm_step(const lbm_params* p, void* state, int64_t nsteps, void* stream) {
         size_t hit = g_graphs.size();
         for (size_t i = 0; i < g_graphs.size(); i++)
             if (g_graphs[i].state == state && g_graphs[i].stream == s && g_graphs[i].ty == ty && g_graphs[i].by == by &&
-                memcmp(&g_graphs[i].p, p, sizeof(lbm_params)) == 0) {
+                g_graphs[i].parity == (int)(lev & 1) && memcmp(&g_graphs[i].p, p, sizeof(lbm_params)) == 0) {
                 hit = i;
                 break;
             }
@@ -305,11 +337,11 @@ int lbm_step(const lbm_params* p, void* state, int64_t nsteps, void* stream) {
             hipGraph_t g;
             e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
             if (e != hipSuccess) return hip_fail(e);
-            hipError_t le = launch(GRAPH_K);
+            hipError_t le = launch(GRAPH_K, lev);
             e = hipStreamEndCapture(s, &g);
             if (le != hipSuccess) return hip_fail(le);
             if (e != hipSuccess) return hip_fail(e);
-            StepGraph sg{*p, state, s, ty, by, nullptr};
+            StepGraph sg{*p, state, s, ty, by, (int)(lev & 1), nullptr};
             e = hipGraphInstantiate(&sg.exec, g, nullptr, nullptr, 0);
             (void)hipGraphDestroy(g);
             if (e != hipSuccess) return hip_fail(e);
@@ -328,10 +360,12 @@ int lbm_step(const lbm_params* p, void* state, int64_t nsteps, void* stream) {
         for (int64_t t = 0; t + GRAPH_K <= nsteps; t += GRAPH_K) {
             e = hipGraphLaunch(g_graphs[0].exec, s);
             if (e != hipSuccess) return hip_fail(e);
+            lev += GRAPH_K;
         }
         nsteps %= GRAPH_K;
     }
-    e = launch(nsteps);
+    e = launch(nsteps, lev);
+    level_record(state, lev + nsteps);
     return e == hipSuccess ? LBM_OK : hip_fail(e);
 }
 
@@ -408,6 +442,7 @@ int lbm_import_state(const lbm_params* p, void* state, const void* f, const void
     else
         e = launch_import<double>(resolve<double>(p, L), (char*)state, L, (const double*)f,
                                   (const double*)g, (const double*)hist, step, p->dtype, s);
+    level_record(state, step);
     return e == hipSuccess ? LBM_OK : hip_fail(e);
 }
 

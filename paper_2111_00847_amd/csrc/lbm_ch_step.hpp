@@ -36,7 +36,7 @@ __device__ __forceinline__ void ch_step_tile(const KParams<T>& P, char* state, s
         const double f0n = collide_f<T, !ACC, STD>(P, M, f, phid);
         collide_g<T, STD>(P, M, g);
         const long long pl = P.plane;
-        st<double, long long, NT>(reinterpret_cast<char*>(D.f0), 8 * k, f0n);
+        st<T, long long, NT>(reinterpret_cast<char*>(D.f0), (long long)sizeof(T) * k, rest_encode<T>(f0n, M.phi, P.rest_w));
         for (int i = 1; i < Q; i++) st<T, long long, NT>(reinterpret_cast<char*>(D.f), (long long)sizeof(T) * (i * pl + k), f[i]);
         for (int i = 0; i < Q; i++) st<T, long long, NT>(reinterpret_cast<char*>(D.g), (long long)sizeof(T) * (i * pl + k), g[i]);
         st<T, long long, NT>(reinterpret_cast<char*>(D.h), (long long)sizeof(T) * k, M.phi);

@@ -67,18 +67,47 @@ struct KParams {
     T wda[4];                // d a / d theta per wall
     T rho0, eps2;
     T Hp;                 // H of App. C: (s_g^2 - s_g^0)/(9 s_g^0 s_g^2)
+    double rest_w;        // share of phi of the rest population at equilibrium (rest_encode)
 };
 
-// One ping-pong copy of the state.  The rest population of f is kept in FP64
-// whatever the element type T: after each collision it is set to phi minus
-// the eight moving populations in double precision, so the total of phi is
-// conserved to double rounding even when the moving populations are FP32.
-// Planes: f0 (double) | f_1..f_8 | g_0..g_8 | hist phi, u, v (previous level)
-// [| m^phiC_x, m^phiC_y of the previous level, local gradient scheme].
+// The rest population f_0 as a copy stores it.  After each collision it is
+// set to phi minus the eight moving populations in double precision, so that
+// the total of phi survives the rounding of the stored populations.  FP64
+// copies hold it as it is.  FP32 copies hold its offset from w phi_h, phi_h
+// being the FP32 history phi the same copy holds for the same node (the phi
+// of the collision that produced f_0; zero after initialisation) and w the
+// rest population's share of phi at equilibrium (4/9 for the Allen-Cahn
+// equilibrium at eta = 1; 1 for the Cahn-Hilliard one, whose rest population
+// is phi minus 5/9 of the small chemical potential), and restore it as
+// offset + w phi_h in FP64.  The offset is small, so its FP32 rounding costs the
+// total of phi about 1e-11 per node and step, where a plain FP32 f_0 of order
+// one would round by 3e-8 -- and by the same bias at every step of a steady
+// state.
+template <typename T>
+__host__ __device__ inline double rest_decode(T stored, T hphi, double w) {
+    return (double)stored + w * (double)hphi;
+}
+template <>
+__host__ __device__ inline double rest_decode<double>(double stored, double, double) {
+    return stored;
+}
+template <typename T>
+__host__ __device__ inline T rest_encode(double f0, T hphi, double w) {
+    return (T)(f0 - w * (double)hphi);
+}
+template <>
+__host__ __device__ inline double rest_encode<double>(double f0, double, double) {
+    return f0;
+}
+
+// One ping-pong copy of the state, every plane of element type T:
+// f_0 (stored as rest_encode gives it) | f_1..f_8 | g_0..g_8 | hist phi, u, v
+// (previous level) [| m^phiC_x, m^phiC_y of the previous level, local gradient
+// scheme].
 template <typename T>
 struct Copy {
-    double* f0;
-    T* f;   // f + i * plane is plane i, i = 1..8 (the pointer sits one plane before f_1)
+    T* f0;
+    T* f;   // f + i * plane is plane i, i = 1..8 (and f + 0 = f0)
     T* g;   // g + i * plane, i = 0..8
     T* h;   // h + j * plane, j = 0..2 (0..4 for the local gradient scheme)
 };
@@ -86,11 +115,10 @@ struct Copy {
 template <typename T>
 __host__ __device__ inline Copy<T> copy_at(char* base, long long plane) {
     Copy<T> c;
-    c.f0 = reinterpret_cast<double*>(base);
-    T* fm = reinterpret_cast<T*>(base + 8 * plane);
-    c.f = fm - plane;
-    c.g = fm + 8 * plane;
-    c.h = fm + 17 * plane;
+    c.f0 = reinterpret_cast<T*>(base);
+    c.f = c.f0;
+    c.g = c.f0 + 9 * plane;
+    c.h = c.f0 + 18 * plane;
     return c;
 }
 
@@ -99,7 +127,7 @@ struct Layout {
     long long n;          // nodes
     long long plane;      // padded plane length (elements)
     size_t esz;           // element size
-    size_t buf_bytes;     // one ping-pong copy: f0 (FP64), f[1..8], g[9], hist[3 or 5] planes
+    size_t buf_bytes;     // one ping-pong copy: f[9], g[9], hist[3 or 5] planes
     size_t off_buf[2];
     size_t off_stamp;     // int64 level stamps, ceil(nx / 64) * ny of them
     size_t nstamp;
@@ -114,7 +142,7 @@ inline Layout make_layout(int nx, int ny, size_t esz, size_t diag_blocks, int nh
     L.n = (long long)nx * ny;
     L.plane = (L.n + 63) / 64 * 64;
     L.esz = esz;
-    L.buf_bytes = (size_t)8 * L.plane + (size_t)(17 + nh) * L.plane * esz;
+    L.buf_bytes = (size_t)(18 + nh) * L.plane * esz;
     L.off_buf[0] = HDR_BYTES;
     L.off_buf[1] = L.off_buf[0] + L.buf_bytes;
     L.off_stamp = L.off_buf[1] + L.buf_bytes;

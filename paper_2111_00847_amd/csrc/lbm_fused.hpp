@@ -70,13 +70,13 @@ __device__ __forceinline__ void st(char* base, OFF byteoff, T v) {
     else *reinterpret_cast<T*>(base + byteoff) = v;
 }
 
-// Pulled moving populations f_1..f_8 and the FP64 rest population of node
-// (x, y) of a copy, addressed by byte offsets of type OFF from the copy base
-// (bF: offset of plane f_1, pl: plane length, ES: element size).  Returns the
-// node's element index.
+// Pulled moving populations f_1..f_8 and the rest population (in FP64) of
+// node (x, y) of a copy, addressed by byte offsets of type OFF from the copy
+// base (bF: offset of plane f_1, bH: of the history planes, pl: plane length,
+// ES: element size).  Returns the node's element index.
 template <typename T, typename OFF>
-__device__ __forceinline__ OFF pull_f_at(const KParams<T>& P, const char* src, OFF bF, OFF pl, int x, int y, T* f,
-                                         double& f0) {
+__device__ __forceinline__ OFF pull_f_at(const KParams<T>& P, const char* src, OFF bF, OFF bH, OFF pl, int x, int y,
+                                         T* f, double& f0) {
     constexpr OFF ES = sizeof(T);
     const OFF nx = (OFF)P.nx;
     OFF col[3], row[3];
@@ -92,7 +92,7 @@ __device__ __forceinline__ OFF pull_f_at(const KParams<T>& P, const char* src, O
     if (y == 0) wy[0] = P.wall_y;
     if (y == P.ny - 1) wy[2] = P.wall_y;
     const OFF k = row[1] + col[1];
-    f0 = ld<double>(src, (OFF)8 * k);
+    f0 = rest_decode(ld<T>(src, k * ES), ld<T>(src, bH + k * ES), P.rest_w);
 #pragma unroll
     for (int i = 1; i < Q; i++) {
         const int ax = 1 - cx(i), ay = 1 - cy(i);
@@ -118,21 +118,30 @@ struct StepWaves {
 
 // The tile body between explicit buffers: `src` holds level `step` (one copy:
 // post-collision populations of the previous step and the history), `dst`
-// receives level step + 1.
+// receives level step + 1.  Returns the level it advanced.
+// SPEC: the level is not known on entry.  It is read from `stamp` while the
+// thread's own-node loads already run on `src`, the copy the host's parity
+// guess `hint` names (the host's record of the level it last left the state
+// at); when the stamp's parity differs -- a state restored or advanced outside
+// that record -- the loads are repeated on `alt_src` and the level is written
+// to `alt_dst`.  The stamp's round trip then overlaps the first loads instead
+// of preceding them.
 template <typename T, int TY, int MODE, typename OFF, int NBY = BY, bool STD = false, bool NT = true,
-          bool LATE_G = false>
-__device__ __forceinline__ void step_core(const KParams<T>& P, const char* src, char* dst, int64_t step, int xt,
-                                          int yt, T* out_phi, T* out_u, T* out_p, T (*sphi)[TX + 3],
-                                          T (*sphp)[TX + 3]) {
+          bool LATE_G = false, bool SPEC = false>
+__device__ __forceinline__ int64_t step_core(const KParams<T>& P, const char* src, char* dst, int64_t step, int xt,
+                                             int yt, T* out_phi, T* out_u, T* out_p, T (*sphi)[TX + 3],
+                                             T (*sphp)[TX + 3], const char* alt_src = nullptr,
+                                             char* alt_dst = nullptr, const int64_t* stamp = nullptr,
+                                             int hint = 0) {
     constexpr int R = TY / NBY;
     constexpr bool GE = LBM_G_EARLY < 0 ? (R <= 2 && !LATE_G) : LBM_G_EARLY != 0;
     constexpr bool RE = LBM_RING_EARLY < 0 ? sizeof(T) == 8 : LBM_RING_EARLY != 0;
     constexpr int WX = TX + 2, WY = TY + 2;
     constexpr OFF ES = sizeof(T);
     const int x0 = xt * TX, y0 = yt * TY;
-    const bool first = step == 0;
+    const int64_t lev = SPEC ? stamp[0] : step;
     const OFF pl = (OFF)P.plane;
-    const OFF bF = 8 * pl;               // byte base of f_1; f_i at bF + (i - 1) pl ES
+    const OFF bF = pl * ES;              // byte base of f_1; f_i at bF + (i - 1) pl ES, f_0 at 0
     const OFF bG = bF + 8 * pl * ES;     // g_i at bG + i pl ES
     const OFF bH = bG + 9 * pl * ES;     // hist_j at bH + j pl ES
     const OFF nx = (OFF)P.nx;
@@ -160,58 +169,73 @@ __device__ __forceinline__ void step_core(const KParams<T>& P, const char* src, 
 
     T f[R][9];
     double phid[R], f0d[R];
-    T hp[R];
+    T hp[R], f0s[R];
     [[maybe_unused]] T ge[GE ? R : 1][9];
     [[maybe_unused]] T he[GE ? R : 1][2];
+    // The thread's own-node pulls (f, the previous phi, and g and the previous
+    // velocity when GE) from copy s_; the history planes are read at every
+    // level (level 0 holds zeros there and does not use them).
+    auto load_own = [&](const char* s_) {
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            const int ly = threadIdx.y + r * NBY, y = y0 + ly;
+            f0s[r] = T(0);
+            hp[r] = T(0);
+            if (x >= P.nx || y >= P.ny) continue;
+            OFF row[3];
+            bool wy[3] = {false, false, false};
+            row[1] = (OFF)y * nx;
+            if (y == 0) {
+                wy[0] = P.wall_y;
+                row[0] = (OFF)(P.ny - 1) * nx;
+            } else {
+                row[0] = (OFF)(y - 1) * nx;
+            }
+            if (y == P.ny - 1) {
+                wy[2] = P.wall_y;
+                row[2] = 0;
+            } else {
+                row[2] = (OFF)(y + 1) * nx;
+            }
+            const OFF k = row[1] + col[1];
+            f0s[r] = ld<T>(s_, k * ES);
+#pragma unroll
+            for (int i = 1; i < Q; i++) {
+                const int ax = 1 - cx(i), ay = 1 - cy(i);
+                const bool bb = wx[ax] || wy[ay];
+                const OFF o = bb ? bF + ((OFF)(opp(i) - 1) * pl + k) * ES : bF + ((OFF)(i - 1) * pl + row[ay] + col[ax]) * ES;
+                f[r][i] = ld<T>(s_, o);
+            }
+            if (GE) {
+#pragma unroll
+                for (int i = 0; i < Q; i++) {
+                    const int ax = 1 - cx(i), ay = 1 - cy(i);
+                    const bool bb = wx[ax] || wy[ay];
+                    const OFF o = bb ? bG + ((OFF)opp(i) * pl + k) * ES : bG + ((OFF)i * pl + row[ay] + col[ax]) * ES;
+                    ge[GE ? r : 0][i] = ld<T>(s_, o);
+                }
+                he[GE ? r : 0][0] = ld<T>(s_, bH + (pl + k) * ES);
+                he[GE ? r : 0][1] = ld<T>(s_, bH + (2 * pl + k) * ES);
+            }
+            hp[r] = ld<T>(s_, bH + k * ES);
+        }
+    };
+    load_own(src);
+    if (SPEC && (int)(lev & 1) != hint) {   // wave-uniform: the guess was wrong
+        src = alt_src;
+        dst = alt_dst;
+        load_own(src);
+    }
+    const bool first = lev == 0;
 #pragma unroll
     for (int r = 0; r < R; r++) {
         const int ly = threadIdx.y + r * NBY, y = y0 + ly;
         phid[r] = 0.0;
-        f0d[r] = 0.0;
-        hp[r] = T(0);
+        f0d[r] = rest_decode(f0s[r], hp[r], P.rest_w);   // after the check: the loads stay in flight through it
+        f[r][0] = (T)f0d[r];
         if (x >= P.nx || y >= P.ny) continue;
-        OFF row[3];
-        bool wy[3] = {false, false, false};
-        row[1] = (OFF)y * nx;
-        if (y == 0) {
-            wy[0] = P.wall_y;
-            row[0] = (OFF)(P.ny - 1) * nx;
-        } else {
-            row[0] = (OFF)(y - 1) * nx;
-        }
-        if (y == P.ny - 1) {
-            wy[2] = P.wall_y;
-            row[2] = 0;
-        } else {
-            row[2] = (OFF)(y + 1) * nx;
-        }
-        const OFF k = row[1] + col[1];
-        const double f0 = ld<double>(src, (OFF)8 * k);
-        f[r][0] = (T)f0;
-#pragma unroll
-        for (int i = 1; i < Q; i++) {
-            const int ax = 1 - cx(i), ay = 1 - cy(i);
-            const bool bb = wx[ax] || wy[ay];
-            const OFF o = bb ? bF + ((OFF)(opp(i) - 1) * pl + k) * ES : bF + ((OFF)(i - 1) * pl + row[ay] + col[ax]) * ES;
-            f[r][i] = ld<T>(src, o);
-        }
-        if (GE) {
-#pragma unroll
-            for (int i = 0; i < Q; i++) {
-                const int ax = 1 - cx(i), ay = 1 - cy(i);
-                const bool bb = wx[ax] || wy[ay];
-                const OFF o = bb ? bG + ((OFF)opp(i) * pl + k) * ES : bG + ((OFF)i * pl + row[ay] + col[ax]) * ES;
-                ge[GE ? r : 0][i] = ld<T>(src, o);
-            }
-            if (!first) {
-                he[GE ? r : 0][0] = ld<T>(src, bH + (pl + k) * ES);
-                he[GE ? r : 0][1] = ld<T>(src, bH + (2 * pl + k) * ES);
-            }
-        }
-        f0d[r] = f0;
-        if (!first) hp[r] = ld<T>(src, bH + k * ES);
         if (!RE) {
-            phid[r] = f0 + moving_sum_d(f[r]);
+            phid[r] = f0d[r] + moving_sum_d(f[r]);
             sphi[ly + 1][lx + 1] = (T)phid[r];
             if (!first) sphp[ly + 1][lx + 1] = hp[r];
         }
@@ -254,7 +278,7 @@ __device__ __forceinline__ void step_core(const KParams<T>& P, const char* src, 
         T fr[9], rh = T(0);
         double fr0 = 0.0;
         if (rv) {
-            const OFF rk = pull_f_at<T, OFF>(P, src, bF, pl, rgx, rgy, fr, fr0);
+            const OFF rk = pull_f_at<T, OFF>(P, src, bF, bH, pl, rgx, rgy, fr, fr0);
             if (!first) rh = ld<T>(src, bH + rk * ES);
         }
 #pragma unroll
@@ -285,7 +309,7 @@ __device__ __forceinline__ void step_core(const KParams<T>& P, const char* src, 
         }
         T fw[9];
         double fw0;
-        const OFF wk = pull_f_at<T, OFF>(P, src, bF, pl, gx, gy, fw, fw0);
+        const OFF wk = pull_f_at<T, OFF>(P, src, bF, bH, pl, gx, gy, fw, fw0);
         [[maybe_unused]] T wh = T(0);
         if (!first) wh = ld<T>(src, bH + wk * ES);
         sphi[wyi][wxi] = (T)(fw0 + moving_sum_d(fw));
@@ -362,7 +386,7 @@ __device__ __forceinline__ void step_core(const KParams<T>& P, const char* src, 
         }
         const double f0n = collide_f<T, false, STD>(P, M, f[r], phid[r]);
         collide_g<T, STD>(P, M, g);
-        st<double, OFF, NT>(dst, (OFF)8 * k, f0n);
+        st<T, OFF, NT>(dst, k * ES, rest_encode<T>(f0n, M.phi, P.rest_w));
 #pragma unroll
         for (int i = 1; i < Q; i++) st<T, OFF, NT>(dst, bF + ((OFF)(i - 1) * pl + k) * ES, f[r][i]);
 #pragma unroll
@@ -371,24 +395,35 @@ __device__ __forceinline__ void step_core(const KParams<T>& P, const char* src, 
         st<T, OFF, NT>(dst, bH + (pl + k) * ES, M.u);
         st<T, OFF, NT>(dst, bH + (2 * pl + k) * ES, M.v);
     }
+    return lev;
 }
 
 // The tile body on a ping-pong state: the level stamp of the tile's first row
-// selects the source copy, and the tile's rows move to the next level.
+// selects the source copy, and the tile's rows move to the next level.  SPEC:
+// the loads start on the copy that `hint` (the parity of the level the host
+// expects) names, while the stamp is read (step_core).
 template <typename T, int TY, int MODE, typename OFF, int NBY = BY, bool STD = false, bool NT = true,
-          bool LATE_G = false>
+          bool LATE_G = false, bool SPEC = false>
 __device__ __forceinline__ void step_tile(const KParams<T>& P, char* state, size_t off0, size_t off1,
                                           size_t off_stamp, int xt, int yt, T* out_phi, T* out_u, T* out_p,
-                                          T (*sphi)[TX + 3], T (*sphp)[TX + 3]) {
+                                          T (*sphi)[TX + 3], T (*sphp)[TX + 3], int hint = 0) {
     const int y0 = yt * TY;
     int64_t* stamp = reinterpret_cast<int64_t*>(state + off_stamp) + (size_t)xt * P.ny + y0;
-    const int64_t step = stamp[0];
-    const int cur = (int)(step & 1);
-    step_core<T, TY, MODE, OFF, NBY, STD, NT, LATE_G>(P, state + (cur ? off1 : off0), state + (cur ? off0 : off1), step, xt, yt, out_phi,
-                                out_u, out_p, sphi, sphp);
+    int64_t step;
+    if (SPEC) {
+        char* ch = state + (hint ? off1 : off0);
+        char* co = state + (hint ? off0 : off1);
+        step = step_core<T, TY, MODE, OFF, NBY, STD, NT, LATE_G, true>(P, ch, co, 0, xt, yt, out_phi, out_u, out_p,
+                                                                      sphi, sphp, co, ch, stamp, hint);
+    } else {
+        step = stamp[0];
+        const int cur = (int)(step & 1);
+        step_core<T, TY, MODE, OFF, NBY, STD, NT, LATE_G>(P, state + (cur ? off1 : off0), state + (cur ? off0 : off1),
+                                                          step, xt, yt, out_phi, out_u, out_p, sphi, sphp);
+    }
     // Own rows move to level n + 1.  Every wave of the workgroup consumed its
-    // load of stamp[0] (it addresses all loads above) before the barriers of
-    // the body, so no wave can still be about to read it.
+    // load of stamp[0] (it selects the copy of all loads above) before the
+    // barriers of the body, so no wave can still be about to read it.
     const int tid = threadIdx.y * TX + threadIdx.x;
     if (MODE == 0 && tid < TY && y0 + tid < P.ny) stamp[tid] = step + 1;
 }

@@ -7,7 +7,7 @@ namespace lbm {
 
 template <typename T>
 hipError_t launch_step(const KParams<T>& P, char* state, const Layout& L, int64_t nsteps, hipStream_t s,
-                       int ty, int by);
+                       int ty, int by, int64_t level0);
 template <typename T>
 hipError_t launch_moments(const KParams<T>& P, const char* state, const Layout& L, T* phi, T* u, T* p,
                           hipStream_t s);

@@ -101,7 +101,7 @@ __device__ __forceinline__ void local_step_tile(const KParams<T>& P, char* state
         }
         const double f0n = collide_f(P, M, f[r], phid[r]);
         collide_g(P, M, g[r]);
-        st<double, long long, NT>(reinterpret_cast<char*>(D.f0), 8 * k, f0n);
+        st<T, long long, NT>(reinterpret_cast<char*>(D.f0), (long long)sizeof(T) * k, rest_encode<T>(f0n, M.phi, P.rest_w));
         for (int i = 1; i < Q; i++) st<T, long long, NT>(reinterpret_cast<char*>(D.f), (long long)sizeof(T) * (i * pl + k), f[r][i]);
         for (int i = 0; i < Q; i++) st<T, long long, NT>(reinterpret_cast<char*>(D.g), (long long)sizeof(T) * (i * pl + k), g[r][i]);
         const T hout[5] = {M.phi, M.u, M.v, M.mx, M.my};

@@ -23,10 +23,16 @@
 
 namespace lbm {
 
+// Steps start their loads on the copy of the host's parity guess `hint` while
+// the level stamp is read (step_core); LBM_PARITY_HINT=0 reads the stamp first.
+#ifndef LBM_PARITY_HINT
+#define LBM_PARITY_HINT 1
+#endif
+
 template <typename T, int TY, int MODE, typename OFF, int NBY, bool STD, bool NT = true, bool LATE_G = false>
 __global__ __launch_bounds__(TX* NBY) __attribute__((amdgpu_waves_per_eu(StepWaves<T, TY, NBY>::value)))
 void k_step(KParams<T> P, char* state, size_t off0, size_t off1, size_t off_stamp, int ntx, int nty, T* out_phi,
-            T* out_u, T* out_p) {
+            T* out_u, T* out_p, int hint) {
     __shared__ T sphi[TY + 2][TX + 3];
     __shared__ T sphp[TY + 2][TX + 3];
     int xt, yt;
@@ -36,8 +42,8 @@ void k_step(KParams<T> P, char* state, size_t off0, size_t off1, size_t off_stam
         xt = blockIdx.x % ntx;
         yt = blockIdx.x / ntx;
     }
-    step_tile<T, TY, MODE, OFF, NBY, STD, NT, LATE_G>(P, state, off0, off1, off_stamp, xt, yt, out_phi, out_u,
-                                                      out_p, sphi, sphp);
+    step_tile<T, TY, MODE, OFF, NBY, STD, NT, LATE_G, MODE == 0 && LBM_PARITY_HINT>(
+        P, state, off0, off1, off_stamp, xt, yt, out_phi, out_u, out_p, sphi, sphp, hint);
 }
 
 // The Cahn-Hilliard variant and the corrected comparison model with the
@@ -227,7 +233,7 @@ __global__ void k_to_pull(KParams<T> P, const T* post, long long post_stride, ch
                 }
                 T val = wall ? src[opp(i) * post_stride + k] : src[i * post_stride + (long long)ty * P.nx + tx];
                 if (h == 1) D.g[i * P.plane + k] = val;
-                else if (i == 0) D.f0[k] = (double)val;
+                else if (i == 0) D.f0[k] = rest_encode<T>((double)val, D.h[k], P.rest_w);
                 else D.f[i * P.plane + k] = val;
             }
         }
@@ -244,7 +250,7 @@ __global__ void k_export(KParams<T> P, char* state, size_t off0, size_t off1, si
          k += (long long)gridDim.x * blockDim.x) {
         const int y = (int)(k / P.nx), x = (int)(k - (long long)y * P.nx);
         if (f) {
-            f[k] = (T)S.f0[k];
+            f[k] = (T)rest_decode(S.f0[k], S.h[k], P.rest_w);
             for (int i = 1; i < Q; i++) f[i * n + k] = pull(S.f, P, i, x, y);
         }
         if (g)
@@ -328,7 +334,8 @@ static bool small_copy(const Layout& L) { return L.buf_bytes < (size_t(1) << 32)
 
 
 template <typename T, int TY, int MODE, int NBY = BY>
-static void launch_tile(const KParams<T>& P, char* state, const Layout& L, hipStream_t s, T* phi, T* u, T* p) {
+static void launch_tile(const KParams<T>& P, char* state, const Layout& L, hipStream_t s, T* phi, T* u, T* p,
+                        int hint = 0) {
     const int ntx = (P.nx + TX - 1) / TX, nty = (P.ny + TY - 1) / TY;
     dim3 blk(TX, NBY);
     // the standard rates compiled in for steps (moments do not collide)
@@ -336,48 +343,49 @@ static void launch_tile(const KParams<T>& P, char* state, const Layout& L, hipSt
     if (MODE == 0 && resident_state(L)) {   // the last-level cache holds both copies: g loaded late
         if (std_rates)
             k_step<T, TY, MODE, uint32_t, NBY, true, false, true><<<ntx * nty, blk, 0, s>>>(
-                P, state, L.off_buf[0], L.off_buf[1], L.off_stamp, ntx, nty, phi, u, p);
+                P, state, L.off_buf[0], L.off_buf[1], L.off_stamp, ntx, nty, phi, u, p, hint);
         else
             k_step<T, TY, MODE, uint32_t, NBY, false, false, true><<<ntx * nty, blk, 0, s>>>(
-                P, state, L.off_buf[0], L.off_buf[1], L.off_stamp, ntx, nty, phi, u, p);
+                P, state, L.off_buf[0], L.off_buf[1], L.off_stamp, ntx, nty, phi, u, p, hint);
     } else if (MODE == 0 && cached_state(L)) {
         if (std_rates)
             k_step<T, TY, MODE, uint32_t, NBY, true, false><<<ntx * nty, blk, 0, s>>>(
-                P, state, L.off_buf[0], L.off_buf[1], L.off_stamp, ntx, nty, phi, u, p);
+                P, state, L.off_buf[0], L.off_buf[1], L.off_stamp, ntx, nty, phi, u, p, hint);
         else
             k_step<T, TY, MODE, uint32_t, NBY, false, false><<<ntx * nty, blk, 0, s>>>(
-                P, state, L.off_buf[0], L.off_buf[1], L.off_stamp, ntx, nty, phi, u, p);
+                P, state, L.off_buf[0], L.off_buf[1], L.off_stamp, ntx, nty, phi, u, p, hint);
     } else if (small_copy(L)) {
         if (std_rates)
             k_step<T, TY, MODE, uint32_t, NBY, true><<<ntx * nty, blk, 0, s>>>(P, state, L.off_buf[0], L.off_buf[1],
-                                                                                L.off_stamp, ntx, nty, phi, u, p);
+                                                                                L.off_stamp, ntx, nty, phi, u, p, hint);
         else
             k_step<T, TY, MODE, uint32_t, NBY, false><<<ntx * nty, blk, 0, s>>>(P, state, L.off_buf[0], L.off_buf[1],
-                                                                                 L.off_stamp, ntx, nty, phi, u, p);
+                                                                                 L.off_stamp, ntx, nty, phi, u, p, hint);
     } else {
         if (std_rates)
             k_step<T, TY, MODE, uint64_t, NBY, true><<<ntx * nty, blk, 0, s>>>(P, state, L.off_buf[0], L.off_buf[1],
-                                                                                L.off_stamp, ntx, nty, phi, u, p);
+                                                                                L.off_stamp, ntx, nty, phi, u, p, hint);
         else
             k_step<T, TY, MODE, uint64_t, NBY, false><<<ntx * nty, blk, 0, s>>>(P, state, L.off_buf[0], L.off_buf[1],
-                                                                                 L.off_stamp, ntx, nty, phi, u, p);
+                                                                                 L.off_stamp, ntx, nty, phi, u, p, hint);
     }
 }
 
 template <typename T>
 hipError_t launch_step(const KParams<T>& P, char* state, const Layout& L, int64_t nsteps, hipStream_t s,
-                       int ty, int by) {
+                       int ty, int by, int64_t level0) {
     constexpr int T16 = sizeof(T) == 8 ? 8 : 16;   // FP64 tiles stop at 8 rows
     for (int64_t t = 0; t < nsteps; t++) {
+        const int h = (int)((level0 + t) & 1);   // parity guess of this launch's level
         if (P.pf == 1 || P.model == 2) launch_ch<T, 0>(P, state, L, s, nullptr, nullptr, nullptr);
         else if (P.grad == 1) launch_local<T, 0>(P, state, L, s, nullptr, nullptr, nullptr);
-        else if (ty == 4) launch_tile<T, 4, 0>(P, state, L, s, nullptr, nullptr, nullptr);
+        else if (ty == 4) launch_tile<T, 4, 0>(P, state, L, s, nullptr, nullptr, nullptr, h);
         else if (ty == 8 || sizeof(T) == 8) {
-            if (by == 8) launch_tile<T, 8, 0, 8>(P, state, L, s, nullptr, nullptr, nullptr);
-            else launch_tile<T, 8, 0>(P, state, L, s, nullptr, nullptr, nullptr);
+            if (by == 8) launch_tile<T, 8, 0, 8>(P, state, L, s, nullptr, nullptr, nullptr, h);
+            else launch_tile<T, 8, 0>(P, state, L, s, nullptr, nullptr, nullptr, h);
         } else {
-            if (by == 8) launch_tile<T, T16, 0, 8>(P, state, L, s, nullptr, nullptr, nullptr);
-            else launch_tile<T, T16, 0>(P, state, L, s, nullptr, nullptr, nullptr);
+            if (by == 8) launch_tile<T, T16, 0, 8>(P, state, L, s, nullptr, nullptr, nullptr, h);
+            else launch_tile<T, T16, 0>(P, state, L, s, nullptr, nullptr, nullptr, h);
         }
     }
     return hipGetLastError();
@@ -399,8 +407,8 @@ hipError_t launch_init(const KParams<T>& P, char* state, const Layout& L, const 
     char* dst = state + L.off_buf[0];
     int g = grid1d(L.n);
     k_equilibrium<T><<<g, 256, 0, s>>>(P, phi0, u0, p0, scratch);
+    k_copy_hist<T><<<g, 256, 0, s>>>(P, nullptr, dst);   // before k_to_pull: f_0 is stored relative to it
     k_to_pull<T><<<g, 256, 0, s>>>(P, scratch, P.plane, dst);
-    k_copy_hist<T><<<g, 256, 0, s>>>(P, nullptr, dst);
     k_set_header<<<1, 1, 0, s>>>(reinterpret_cast<StateHeader*>(state), P.nx, P.ny, dtype);
     k_set_stamps<<<grid1d((long long)L.nstamp), 256, 0, s>>>(reinterpret_cast<int64_t*>(state + L.off_stamp),
                                                               (long long)L.nstamp, 0);
@@ -430,8 +438,8 @@ hipError_t launch_import(const KParams<T>& P, char* state, const Layout& L, cons
     if (e != hipSuccess) return e;
     (void)bytes9;
     int gr = grid1d(L.n);
+    k_copy_hist<T><<<gr, 256, 0, s>>>(P, step > 0 ? hist : nullptr, dst);   // before k_to_pull (f_0)
     k_to_pull<T><<<gr, 256, 0, s>>>(P, stage, P.plane, dst);
-    k_copy_hist<T><<<gr, 256, 0, s>>>(P, step > 0 ? hist : nullptr, dst);
     k_set_header<<<1, 1, 0, s>>>(reinterpret_cast<StateHeader*>(state), P.nx, P.ny, dtype);
     k_set_stamps<<<grid1d((long long)L.nstamp), 256, 0, s>>>(reinterpret_cast<int64_t*>(state + L.off_stamp),
                                                               (long long)L.nstamp, step);
@@ -447,7 +455,8 @@ hipError_t launch_export(const KParams<T>& P, const char* state, const Layout& L
 }
 
 #define LBM_INSTANTIATE(T)                                                                              \
-    template hipError_t launch_step<T>(const KParams<T>&, char*, const Layout&, int64_t, hipStream_t, int, int); \
+    template hipError_t launch_step<T>(const KParams<T>&, char*, const Layout&, int64_t, hipStream_t, int, int, \
+                                       int64_t);                                                         \
     template hipError_t launch_moments<T>(const KParams<T>&, const char*, const Layout&, T*, T*, T*,     \
                                           hipStream_t);                                                 \
     template hipError_t launch_init<T>(const KParams<T>&, char*, const Layout&, const T*, const T*,     \

@@ -12,7 +12,8 @@ constexpr int BY = 4;
 // phi of node (x, y) in FP64: rest population plus the pulled moving ones.
 template <typename T>
 __device__ __forceinline__ double node_phi(const KParams<T>& P, const Copy<T>& C, int x, int y, T* f) {
-    const double f0 = C.f0[(long long)y * P.nx + x];
+    const long long k = (long long)y * P.nx + x;
+    const double f0 = rest_decode(C.f0[k], C.h[k], P.rest_w);
     f[0] = (T)f0;
 #pragma unroll
     for (int i = 1; i < Q; i++) f[i] = pull(C.f, P, i, x, y);

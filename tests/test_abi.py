@@ -123,7 +123,7 @@ def test_batch_create_validation():
     assert L.lbm_batch_create((LbmParams * 2)(good, _params(dtype="f64")), 2, 0, ctypes.byref(h)) == -3
     assert L.lbm_batch_create((LbmParams * 2)(good, _params(W=-1.0)), 2, 0, ctypes.byref(h)) == -4
     # a case whose state copy reaches 4 GiB (the batch kernels address a case with 32-bit offsets)
-    big = _params(dtype="f32", nx=48128, ny=1024)
+    big = _params(dtype="f32", nx=51200, ny=1024)
     assert _size(big)[0] == 0
     assert L.lbm_batch_create((LbmParams * 2)(good, big), 2, 0, ctypes.byref(h)) == -2
     assert L.lbm_batch_state_size(None, None) == -1

@@ -17,7 +17,7 @@ torch = pytest.importorskip("torch")
 STEPS = 40
 
 
-@pytest.mark.parametrize("dtype,k", [("f32", 188), ("f64", 100)])
+@pytest.mark.parametrize("dtype,k", [("f32", 200), ("f64", 100)])
 def test_lattice_beyond_4gib_per_copy_is_the_tiled_small_lattice(dtype, k):
     from paper_2111_00847_amd import api
     from paper_2111_00847_amd.sim import Sim
@@ -137,7 +137,9 @@ def test_reverse_mode_on_a_streamed_state_is_the_tiled_cached_one():
     for k, what in ((1, "gravity"), (2, "theta")):
         a, b = res["small"][k], res["big"][k]
         print(f"dL/d{what}: small {a}, big {b}", flush=True)
-        np.testing.assert_allclose(b, 8 * a, rtol=1e-10, atol=1e-30)
+        # a component that cancels to 1e-9 of the other (dL/dgravity_x) is held to
+        # the vector's size: its FP64 sums run in another order over 8x the nodes
+        np.testing.assert_allclose(b, 8 * a, rtol=1e-10, atol=1e-12 * np.abs(8 * a).max())
 
 
 @pytest.mark.parametrize("mix", ["plain", "with_cahn_hilliard"])
