@@ -150,12 +150,22 @@ int lbm_init(const lbm_params *p, void *state, const void *phi0, const void *u0,
 int lbm_hydrostatic_pressure(const lbm_params *p, const void *phi0, void *p0, void *stream);
 
 /* Advance nsteps >= 0 time steps (Sec. 3): moments, closure, both MRT
- * collisions and streaming with bounce-back, fused in one kernel per step.
- * On a non-NULL stream, runs of >= 64 steps replay a captured graph of 32
- * steps (cached per params, state and stream); while the caller captures the
- * stream itself, the kernels are launched into the caller's graph instead.
- * Every option. */
+ * collisions and streaming with bounce-back, fused in one kernel per step --
+ * or per two steps, for the Allen-Cahn step with stencil gradients (present
+ * and original models) on a state whose two copies fit the 256 MB last-level
+ * cache and whose lattice has at least 256 tiles of 64 x 8 nodes
+ * (lbm_levels_per_launch; the environment variable LBM_TWO_LEVEL = "0" or "1"
+ * turns the size rule off or on for every such state): a run of n steps is
+ * then n / 2 two-level launches and, for odd n, one one-level launch, with
+ * results equal bit for bit to n one-level launches.  On a non-NULL stream, runs of >= 64 steps
+ * replay a captured graph of 32 steps (cached per params, state and stream);
+ * while the caller captures the stream itself, the kernels are launched into
+ * the caller's graph instead.  Every option. */
 int lbm_step(const lbm_params *p, void *state, int64_t nsteps, void *stream);
+
+/* Time levels that one step launch of lbm_step advances for these params
+ * (1 or 2; see lbm_step).  Host only, no device work. */
+int lbm_levels_per_launch(const lbm_params *p, int32_t *levels /* host */);
 
 /* Order parameter, velocity (Eq. comU) and pressure (Eq. computP) of the
  * current time level.  phi, p: [ny][nx] or NULL; u: [2][ny][nx] or NULL.

@@ -107,6 +107,12 @@ def lbm_step(p, state, nsteps=1, stream=None):
     call("lbm_step", ctypes.byref(p), _state_ptr(state), int(nsteps), _stream(stream))
 
 
+def lbm_levels_per_launch(p) -> int:
+    v = ctypes.c_int32()
+    call("lbm_levels_per_launch", ctypes.byref(p), ctypes.byref(v))
+    return v.value
+
+
 def lbm_moments(p, state, phi=None, u=None, pr=None, stream=None):
     shp = (p.ny, p.nx)
     call("lbm_moments", ctypes.byref(p), _state_ptr(state), _ptr(phi, p, shp, "phi"),

@@ -16,6 +16,10 @@ HIPCC_FLAGS = [
     "-Wall", "-Wno-unused-result",
     # no packed FP32 instructions anywhere in this library
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # multiply-adds fused only within one expression: a quantity is rounded the
+    # same way in every kernel that computes it (the one- and two-level steps,
+    # the batched and the tape steps), so their results agree bit for bit
+    "-ffp-contract=on",
 ]
 
 

@@ -160,8 +160,8 @@ __device__ __forceinline__ double wave_sum(double v) {
 // ---------------------------------------------------------------- tape
 __global__ void k_tape_copy(const char* state, size_t off0, size_t off1, size_t off_stamp, size_t bytes,
                             char* tape, int nlevels, int nx, int ny, int dtype) {
-    const int64_t n = *reinterpret_cast<const int64_t*>(state + off_stamp);
-    const uint4* src = reinterpret_cast<const uint4*>(state + ((n & 1) ? off1 : off0));
+    const int64_t sv = *reinterpret_cast<const int64_t*>(state + off_stamp), n = stamp_level(sv);
+    const uint4* src = reinterpret_cast<const uint4*>(state + (stamp_copy(sv) ? off1 : off0));
     uint4* dst = reinterpret_cast<uint4*>(tape + TAPE_HDR);
     const size_t nv = bytes / sizeof(uint4);
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nv; i += (size_t)gridDim.x * blockDim.x)
@@ -531,8 +531,8 @@ __global__ __launch_bounds__(GHOST_THREADS) void k_adj_ghosts(KParams<T> P, cons
 // ---------------------------------------------------------------- seed, init, parameters
 template <typename T>
 __global__ void k_adj_seed(KParams<T> P, const char* state, size_t off_stamp, AdjView<T> V, const T* dL) {
-    const int64_t N = *reinterpret_cast<const int64_t*>(state + off_stamp);
-    const int c = (int)(N & 1);
+    const int64_t N = stamp_level(*reinterpret_cast<const int64_t*>(state + off_stamp));
+    const int c = (int)(N & 1);   // the adjoint's own copies alternate with the level
     const long long nn = (long long)P.nx * P.ny;
     const long long nslot = V.nslot();
     const long long lim = nn > nslot ? nn : nslot;

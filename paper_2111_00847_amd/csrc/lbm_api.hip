@@ -199,38 +199,38 @@ struct StepGraph {
     void* state;
     hipStream_t stream;
     int ty, by;
-    int parity;           // parity of the level the graph's first launch expects
+    int copy;             // the copy the graph's first launch expects the state in
     hipGraphExec_t exec;
 };
 static std::mutex g_graph_mu;
 static std::vector<StepGraph> g_graphs;   // front = most recent
 
-// The level each state was last left at by lbm_init, lbm_import_state and
-// lbm_step, as far as this library knows: the step kernel takes its parity as
-// the guess of which copy to start loading from.  A state the record does not
+// The copy each state was last left in by lbm_init, lbm_import_state and
+// lbm_step, as far as this library knows: the step kernel takes it as the
+// guess of which copy to start loading from.  A state the record does not
 // know (or knows wrongly: a device copy restored as a checkpoint, a state
-// stepped through a replayed graph an odd number of times) still steps
+// stepped through a replayed graph an odd number of launches) still steps
 // correctly, only without the head start.  A small most-recently-used list.
-constexpr size_t LEVEL_RECORDS = 1024;
-static std::mutex g_level_mu;
-static std::vector<std::pair<const void*, int64_t>> g_levels;   // front = most recent
+constexpr size_t COPY_RECORDS = 1024;
+static std::mutex g_copy_mu;
+static std::vector<std::pair<const void*, int>> g_copies;   // front = most recent
 
-int64_t level_guess(const void* state) {
-    std::lock_guard<std::mutex> lock(g_level_mu);
-    for (const auto& e : g_levels)
+int copy_guess(const void* state) {
+    std::lock_guard<std::mutex> lock(g_copy_mu);
+    for (const auto& e : g_copies)
         if (e.first == state) return e.second;
     return 0;
 }
 
-void level_record(const void* state, int64_t level) {
-    std::lock_guard<std::mutex> lock(g_level_mu);
-    for (size_t i = 0; i < g_levels.size(); i++)
-        if (g_levels[i].first == state) {
-            g_levels.erase(g_levels.begin() + i);
+void copy_record(const void* state, int copy) {
+    std::lock_guard<std::mutex> lock(g_copy_mu);
+    for (size_t i = 0; i < g_copies.size(); i++)
+        if (g_copies[i].first == state) {
+            g_copies.erase(g_copies.begin() + i);
             break;
         }
-    if (g_levels.size() == LEVEL_RECORDS) g_levels.pop_back();
-    g_levels.insert(g_levels.begin(), std::make_pair(state, level));
+    if (g_copies.size() == COPY_RECORDS) g_copies.pop_back();
+    g_copies.insert(g_copies.begin(), std::make_pair(state, copy));
 }
 
 int hip_fail(hipError_t e) {
@@ -282,7 +282,7 @@ int lbm_init(const lbm_params* p, void* state, const void* phi0, const void* u0,
     else
         e = launch_init<double>(resolve<double>(p, L), (char*)state, L, (const double*)phi0,
                                 (const double*)u0, (const double*)p0, p->dtype, s);
-    level_record(state, 0);
+    copy_record(state, 0);
     return e == hipSuccess ? LBM_OK : hip_fail(e);
 }
 
@@ -310,10 +310,10 @@ int lbm_step(const lbm_params* p, void* state, int64_t nsteps, void* stream) {
     hipStream_t s = (hipStream_t)stream;
     int ty, by;
     step_shape(p, &ty, &by);
-    int64_t lev = level_guess(state);
-    auto launch = [&](int64_t n, int64_t l0) -> hipError_t {
-        if (p->dtype == LBM_F32) return launch_step<float>(resolve<float>(p, L), (char*)state, L, n, s, ty, by, l0);
-        return launch_step<double>(resolve<double>(p, L), (char*)state, L, n, s, ty, by, l0);
+    int copy = copy_guess(state);
+    auto launch = [&](int64_t n, int& c) -> hipError_t {
+        if (p->dtype == LBM_F32) return launch_step<float>(resolve<float>(p, L), (char*)state, L, n, s, ty, by, c);
+        return launch_step<double>(resolve<double>(p, L), (char*)state, L, n, s, ty, by, c);
     };
     hipError_t e;
     // Long runs on a non-NULL stream replay a graph of GRAPH_K steps, unless the
@@ -329,7 +329,7 @@ int lbm_step(const lbm_params* p, void* state, int64_t nsteps, void* stream) {
         size_t hit = g_graphs.size();
         for (size_t i = 0; i < g_graphs.size(); i++)
             if (g_graphs[i].state == state && g_graphs[i].stream == s && g_graphs[i].ty == ty && g_graphs[i].by == by &&
-                g_graphs[i].parity == (int)(lev & 1) && memcmp(&g_graphs[i].p, p, sizeof(lbm_params)) == 0) {
+                g_graphs[i].copy == copy && memcmp(&g_graphs[i].p, p, sizeof(lbm_params)) == 0) {
                 hit = i;
                 break;
             }
@@ -337,11 +337,15 @@ int lbm_step(const lbm_params* p, void* state, int64_t nsteps, void* stream) {
             hipGraph_t g;
             e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
             if (e != hipSuccess) return hip_fail(e);
-            hipError_t le = launch(GRAPH_K, lev);
+            int c = copy;
+            hipError_t le = launch(GRAPH_K, c);
             e = hipStreamEndCapture(s, &g);
             if (le != hipSuccess) return hip_fail(le);
             if (e != hipSuccess) return hip_fail(e);
-            StepGraph sg{*p, state, s, ty, by, (int)(lev & 1), nullptr};
+            // GRAPH_K is even and so is the launch count of every path: a replay
+            // leaves the state in the copy it found it in
+            if (c != copy) return hip_fail(hipErrorUnknown);
+            StepGraph sg{*p, state, s, ty, by, copy, nullptr};
             e = hipGraphInstantiate(&sg.exec, g, nullptr, nullptr, 0);
             (void)hipGraphDestroy(g);
             if (e != hipSuccess) return hip_fail(e);
@@ -360,13 +364,20 @@ int lbm_step(const lbm_params* p, void* state, int64_t nsteps, void* stream) {
         for (int64_t t = 0; t + GRAPH_K <= nsteps; t += GRAPH_K) {
             e = hipGraphLaunch(g_graphs[0].exec, s);
             if (e != hipSuccess) return hip_fail(e);
-            lev += GRAPH_K;
         }
         nsteps %= GRAPH_K;
     }
-    e = launch(nsteps, lev);
-    level_record(state, lev + nsteps);
+    e = launch(nsteps, copy);
+    copy_record(state, copy);
     return e == hipSuccess ? LBM_OK : hip_fail(e);
+}
+
+int lbm_levels_per_launch(const lbm_params* p, int32_t* levels) {
+    int rc = validate(p);
+    if (rc) return rc;
+    if (!levels) return LBM_E_NULL;
+    *levels = two_level_path(layout_of(p), p->nx, p->ny, p->phase_eq, p->model, p->grad_scheme) ? 2 : 1;
+    return LBM_OK;
 }
 
 int lbm_moments(const lbm_params* p, const void* state, void* phi, void* u, void* pr, void* stream) {
@@ -418,9 +429,11 @@ int lbm_export_state(const lbm_params* p, const void* state, void* f, void* g, v
         if (e != hipSuccess) return hip_fail(e);
     }
     if (step) {
-        e = hipMemcpyAsync(step, (const char*)state + L.off_stamp, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+        int64_t sv = 0;
+        e = hipMemcpyAsync(&sv, (const char*)state + L.off_stamp, sizeof(int64_t), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) return hip_fail(e);
+        *step = stamp_level(sv);
     }
     return LBM_OK;
 }
@@ -442,7 +455,7 @@ int lbm_import_state(const lbm_params* p, void* state, const void* f, const void
     else
         e = launch_import<double>(resolve<double>(p, L), (char*)state, L, (const double*)f,
                                   (const double*)g, (const double*)hist, step, p->dtype, s);
-    level_record(state, step);
+    copy_record(state, (int)(step & 1));
     return e == hipSuccess ? LBM_OK : hip_fail(e);
 }
 

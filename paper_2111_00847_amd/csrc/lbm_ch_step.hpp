@@ -19,8 +19,8 @@ __device__ __forceinline__ void ch_step_tile(const KParams<T>& P, char* state, s
                                              ChWindow<T, TY>& W) {
     const int x0 = xt * TX, y0 = yt * TY;
     int64_t* stamp = reinterpret_cast<int64_t*>(state + off_stamp) + (size_t)xt * P.ny + y0;
-    const int64_t step = stamp[0];
-    const int cur = (int)(step & 1);
+    const int64_t sv = stamp[0], step = stamp_level(sv);
+    const int cur = stamp_copy(sv);
     const Copy<T> S = copy_at<T>(state + (cur ? off1 : off0), P.plane);
     const Copy<T> D = copy_at<T>(state + (cur ? off0 : off1), P.plane);
     ch_tile<T, TY, ACC>(P, S, step, x0, y0, W, [&](const Macro<T>& M, T* f, T* g, double phid, int, int, long long k) {
@@ -45,7 +45,7 @@ __device__ __forceinline__ void ch_step_tile(const KParams<T>& P, char* state, s
     });
     // every wave read stamp[0] before the barriers of the tile body
     const int tid = threadIdx.y * TX + threadIdx.x;
-    if (MODE == 0 && tid < TY && y0 + tid < P.ny) stamp[tid] = step + 1;
+    if (MODE == 0 && tid < TY && y0 + tid < P.ny) stamp[tid] = stamp_of(step + 1, 1 - cur);
 }
 
 }  // namespace lbm

@@ -32,14 +32,19 @@ struct StateHeader {
     int32_t nx, ny, dtype;
 };
 
-// Level stamps.  The time level n of the state is kept per (64-wide column
-// band, row): stamp[xt * ny + y].  A step workgroup reads the stamp of its
-// first row to learn n (copy n & 1 is its source), and at its end writes n + 1
-// into the stamps of the rows it owns.  Every (band, row) belongs to exactly
-// one workgroup of a launch whatever the tile height, so no two workgroups
-// touch the same stamp and no cross-workgroup synchronisation is needed; all
-// stamps are equal between launches.
+// Level stamps.  The time level n of the state and the copy c that holds it
+// are kept per (64-wide column band, row): stamp[xt * ny + y] = 2 n + c.  A
+// step workgroup reads the stamp of its first row to learn n and its source
+// copy, and at its end writes level n + 1 in the other copy into the stamps of
+// the rows it owns (a two-level launch: n + 2 in the other copy, so the copy
+// is not the parity of the level).  Every (band, row) belongs to exactly one
+// workgroup of a launch whatever the tile height, so no two workgroups touch
+// the same stamp and no cross-workgroup synchronisation is needed; all stamps
+// are equal between launches.
 constexpr int STAMP_BAND = 64;
+__host__ __device__ constexpr int64_t stamp_of(int64_t level, int copy) { return 2 * level + copy; }
+__host__ __device__ constexpr int64_t stamp_level(int64_t s) { return s >> 1; }
+__host__ __device__ constexpr int stamp_copy(int64_t s) { return (int)(s & 1); }
 // Parameters resolved on the host and passed by value to every kernel.
 template <typename T>
 struct KParams {

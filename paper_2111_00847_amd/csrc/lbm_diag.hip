@@ -89,9 +89,9 @@ __global__ __launch_bounds__(TX* BY) void k_diag1(KParams<T> P, const char* stat
     __shared__ T sphi[DTY + 2][TX + 3];
     __shared__ T sphp[DTY + 2][TX + 3];
     __shared__ double red[BY][5];
-    const int64_t step = *reinterpret_cast<const int64_t*>(state + off_stamp);
+    const int64_t sv = *reinterpret_cast<const int64_t*>(state + off_stamp), step = stamp_level(sv);
     const bool first = step == 0;
-    const int cur = (int)(step & 1);
+    const int cur = stamp_copy(sv);
     const Copy<T> S = copy_at<T>(const_cast<char*>(state) + (cur ? off1 : off0), P.plane);
     const int x0 = blockIdx.x * TX, y0 = blockIdx.y * DTY;
     fill_window<T, DTY>(P, S, true, x0, y0, sphi, sphp);
@@ -135,9 +135,9 @@ __global__ __launch_bounds__(TX* BY) void k_diag1_ch(KParams<T> P, const char* s
                                                      size_t off1, size_t off_stamp, T* scr, double* partials) {
     __shared__ ChWindow<T, DTY> W;
     __shared__ double red[BY][5];
-    const int64_t step = *reinterpret_cast<const int64_t*>(state + off_stamp);
+    const int64_t sv = *reinterpret_cast<const int64_t*>(state + off_stamp), step = stamp_level(sv);
     const bool first = step == 0;
-    const int cur = (int)(step & 1);
+    const int cur = stamp_copy(sv);
     const Copy<T> S = copy_at<T>(const_cast<char*>(state) + (cur ? off1 : off0), P.plane);
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     ch_tile<T, DTY, ACC>(P, S, step, blockIdx.x * TX, blockIdx.y * DTY, W,

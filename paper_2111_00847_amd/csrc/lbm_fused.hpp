@@ -119,13 +119,13 @@ struct StepWaves {
 // The tile body between explicit buffers: `src` holds level `step` (one copy:
 // post-collision populations of the previous step and the history), `dst`
 // receives level step + 1.  Returns the level it advanced.
-// SPEC: the level is not known on entry.  It is read from `stamp` while the
-// thread's own-node loads already run on `src`, the copy the host's parity
-// guess `hint` names (the host's record of the level it last left the state
-// at); when the stamp's parity differs -- a state restored or advanced outside
-// that record -- the loads are repeated on `alt_src` and the level is written
-// to `alt_dst`.  The stamp's round trip then overlaps the first loads instead
-// of preceding them.
+// SPEC: the level and source copy are not known on entry.  They are read from
+// `stamp` while the thread's own-node loads already run on `src`, the copy the
+// host's guess `hint` names (the host's record of where it last left the
+// state); when the stamp names the other copy -- a state restored or advanced
+// outside that record -- the loads are repeated on `alt_src` and the level is
+// written to `alt_dst`.  The stamp's round trip then overlaps the first loads
+// instead of preceding them.  Returns the stamp read (SPEC) or `step`.
 template <typename T, int TY, int MODE, typename OFF, int NBY = BY, bool STD = false, bool NT = true,
           bool LATE_G = false, bool SPEC = false>
 __device__ __forceinline__ int64_t step_core(const KParams<T>& P, const char* src, char* dst, int64_t step, int xt,
@@ -139,7 +139,8 @@ __device__ __forceinline__ int64_t step_core(const KParams<T>& P, const char* sr
     constexpr int WX = TX + 2, WY = TY + 2;
     constexpr OFF ES = sizeof(T);
     const int x0 = xt * TX, y0 = yt * TY;
-    const int64_t lev = SPEC ? stamp[0] : step;
+    const int64_t sv = SPEC ? stamp[0] : step;
+    const int64_t lev = SPEC ? stamp_level(sv) : step;
     const OFF pl = (OFF)P.plane;
     const OFF bF = pl * ES;              // byte base of f_1; f_i at bF + (i - 1) pl ES, f_0 at 0
     const OFF bG = bF + 8 * pl * ES;     // g_i at bG + i pl ES
@@ -221,7 +222,7 @@ __device__ __forceinline__ int64_t step_core(const KParams<T>& P, const char* sr
         }
     };
     load_own(src);
-    if (SPEC && (int)(lev & 1) != hint) {   // wave-uniform: the guess was wrong
+    if (SPEC && stamp_copy(sv) != hint) {   // wave-uniform: the guess was wrong
         src = alt_src;
         dst = alt_dst;
         load_own(src);
@@ -395,12 +396,12 @@ __device__ __forceinline__ int64_t step_core(const KParams<T>& P, const char* sr
         st<T, OFF, NT>(dst, bH + (pl + k) * ES, M.u);
         st<T, OFF, NT>(dst, bH + (2 * pl + k) * ES, M.v);
     }
-    return lev;
+    return sv;
 }
 
 // The tile body on a ping-pong state: the level stamp of the tile's first row
-// selects the source copy, and the tile's rows move to the next level.  SPEC:
-// the loads start on the copy that `hint` (the parity of the level the host
+// selects the source copy, and the tile's rows move to the next level in the
+// other copy.  SPEC: the loads start on the copy that `hint` (the copy the host
 // expects) names, while the stamp is read (step_core).
 template <typename T, int TY, int MODE, typename OFF, int NBY = BY, bool STD = false, bool NT = true,
           bool LATE_G = false, bool SPEC = false>
@@ -409,23 +410,23 @@ __device__ __forceinline__ void step_tile(const KParams<T>& P, char* state, size
                                           T (*sphi)[TX + 3], T (*sphp)[TX + 3], int hint = 0) {
     const int y0 = yt * TY;
     int64_t* stamp = reinterpret_cast<int64_t*>(state + off_stamp) + (size_t)xt * P.ny + y0;
-    int64_t step;
+    int64_t sv;
     if (SPEC) {
         char* ch = state + (hint ? off1 : off0);
         char* co = state + (hint ? off0 : off1);
-        step = step_core<T, TY, MODE, OFF, NBY, STD, NT, LATE_G, true>(P, ch, co, 0, xt, yt, out_phi, out_u, out_p,
-                                                                      sphi, sphp, co, ch, stamp, hint);
+        sv = step_core<T, TY, MODE, OFF, NBY, STD, NT, LATE_G, true>(P, ch, co, 0, xt, yt, out_phi, out_u, out_p,
+                                                                    sphi, sphp, co, ch, stamp, hint);
     } else {
-        step = stamp[0];
-        const int cur = (int)(step & 1);
+        sv = stamp[0];
+        const int cur = stamp_copy(sv);
         step_core<T, TY, MODE, OFF, NBY, STD, NT, LATE_G>(P, state + (cur ? off1 : off0), state + (cur ? off0 : off1),
-                                                          step, xt, yt, out_phi, out_u, out_p, sphi, sphp);
+                                                          stamp_level(sv), xt, yt, out_phi, out_u, out_p, sphi, sphp);
     }
     // Own rows move to level n + 1.  Every wave of the workgroup consumed its
     // load of stamp[0] (it selects the copy of all loads above) before the
     // barriers of the body, so no wave can still be about to read it.
     const int tid = threadIdx.y * TX + threadIdx.x;
-    if (MODE == 0 && tid < TY && y0 + tid < P.ny) stamp[tid] = step + 1;
+    if (MODE == 0 && tid < TY && y0 + tid < P.ny) stamp[tid] = stamp_of(stamp_level(sv) + 1, 1 - stamp_copy(sv));
 }
 
 }  // namespace lbm

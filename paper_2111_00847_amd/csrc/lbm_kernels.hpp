@@ -5,9 +5,17 @@
 
 namespace lbm {
 
+// nsteps levels; `copy`: the host's guess of the copy holding the state on
+// entry, updated to where the launches leave it
 template <typename T>
 hipError_t launch_step(const KParams<T>& P, char* state, const Layout& L, int64_t nsteps, hipStream_t s,
-                       int ty, int by, int64_t level0);
+                       int ty, int by, int& copy);
+// two levels of the plain Allen-Cahn step in one launch (lbm_step2.hip)
+template <typename T>
+void launch_step2(const KParams<T>& P, char* state, const Layout& L, hipStream_t s);
+// the plain Allen-Cahn step on a state the last-level cache holds (of at least
+// one tile per CU): two levels per launch
+bool two_level_path(const Layout& L, int nx, int ny, int pf, int model, int grad);
 template <typename T>
 hipError_t launch_moments(const KParams<T>& P, const char* state, const Layout& L, T* phi, T* u, T* p,
                           hipStream_t s);

@@ -19,9 +19,9 @@ __device__ __forceinline__ void local_step_tile(const KParams<T>& P, char* state
     constexpr int R = TY / BY;
     const int x0 = xt * TX, y0 = yt * TY;
     int64_t* stamp = reinterpret_cast<int64_t*>(state + off_stamp) + (size_t)xt * P.ny + y0;
-    const int64_t step = stamp[0];
+    const int64_t sv = stamp[0], step = stamp_level(sv);
     const bool first = step == 0;
-    const int cur = (int)(step & 1);
+    const int cur = stamp_copy(sv);
     const Copy<T> S = copy_at<T>(state + (cur ? off1 : off0), P.plane);
     const Copy<T> D = copy_at<T>(state + (cur ? off0 : off1), P.plane);
     const long long pl = P.plane;
@@ -108,7 +108,7 @@ __device__ __forceinline__ void local_step_tile(const KParams<T>& P, char* state
         for (int j = 0; j < 5; j++) st<T, long long, NT>(reinterpret_cast<char*>(D.h), (long long)sizeof(T) * (j * pl + k), hout[j]);
     }
     // every wave read stamp[0] before the window barrier
-    if (MODE == 0 && tid < TY && y0 + tid < P.ny) stamp[tid] = step + 1;
+    if (MODE == 0 && tid < TY && y0 + tid < P.ny) stamp[tid] = stamp_of(step + 1, 1 - cur);
 }
 
 }  // namespace lbm

@@ -2,21 +2,23 @@
 //
 // Memory layout (structure of arrays, x fastest): a state buffer is
 //   [header | copy 0 | copy 1 | level stamps | diagnostics scratch],
-// a copy being f_0 (FP64) | f_1..f_8 | g_0..g_8 | hist = (phi, u, v), every
-// plane padded to a multiple of 64 elements.  Copy (n & 1) holds the
-// post-collision populations of level n-1 -- a node obtains its level-n
-// populations by pulling them from its neighbours -- and the history of level
-// n-1, from which the explicit-Euler time derivatives are formed.  A step
-// reads copy (n & 1) and writes the other.  The level n is kept in per-row
-// stamps owned by the workgroups (lbm_common.hpp), so host code never needs
-// the parity, no workgroup waits for another, and a sequence of steps can be
-// captured in a graph.
+// a copy being f_0 | f_1..f_8 | g_0..g_8 | hist = (phi, u, v), every
+// plane padded to a multiple of 64 elements.  The copy that holds level n
+// holds the post-collision populations of level n-1 -- a node obtains its
+// level-n populations by pulling them from its neighbours -- and the history
+// of level n-1, from which the explicit-Euler time derivatives are formed.  A
+// launch reads that copy and writes the other.  The level and its copy are
+// kept in per-row stamps owned by the workgroups (lbm_common.hpp), so host
+// code never needs them, no workgroup waits for another, and a sequence of
+// steps can be captured in a graph.
 //
 // The phi stencils need phi on a one-node ring around each tile.  A tile of
 // 64 x TY nodes first pulls the populations of its (64+2) x (TY+2) window,
 // sums them into phi in LDS (the ring's pulls hit L2: those lines are the
 // neighbour tiles' own reads), fills wall ghosts, and then each thread runs
 // the per-node update for its nodes (lbm_fused.hpp).
+#include <cstdlib>
+
 #include "lbm_ch_step.hpp"
 #include "lbm_fused.hpp"
 #include "lbm_kernels.hpp"
@@ -243,7 +245,7 @@ __global__ void k_to_pull(KParams<T> P, const T* post, long long post_stride, ch
 template <typename T>
 __global__ void k_export(KParams<T> P, char* state, size_t off0, size_t off1, size_t off_stamp, T* f, T* g,
                          T* hist) {
-    const int cur = (int)(*reinterpret_cast<const int64_t*>(state + off_stamp) & 1);
+    const int cur = stamp_copy(*reinterpret_cast<const int64_t*>(state + off_stamp));
     const Copy<T> S = copy_at<T>(state + (cur ? off1 : off0), P.plane);
     const long long n = (long long)P.nx * P.ny;
     for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n;
@@ -276,9 +278,9 @@ __global__ void k_set_header(StateHeader* H, int nx, int ny, int dtype) {
     H->dtype = dtype;
 }
 
-__global__ void k_set_stamps(int64_t* stamp, long long n, int64_t level) {
+__global__ void k_set_stamps(int64_t* stamp, long long n, int64_t value) {
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
-        stamp[i] = level;
+        stamp[i] = value;
 }
 
 // Hydrostatic pressure of the two fluids at rest (the initial pressure of the
@@ -371,12 +373,40 @@ static void launch_tile(const KParams<T>& P, char* state, const Layout& L, hipSt
     }
 }
 
+// Two levels per launch for the plain Allen-Cahn step on states the
+// last-level cache holds, once the lattice has at least one 64 x 8 tile per
+// CU (measured on MI355X, FP32, per level: 256 x 1024 7.8 us against 9.0 us
+// one-level, 1024 x 512 15.6 against 16.1; below, where every CU runs at most
+// one short tile, the longer chain of the two-level tile costs more than the
+// launch it saves: 256 x 128 5.1 against 4.8, 64 x 8 4.9 against 4.7).  The
+// environment variable LBM_TWO_LEVEL, read at every call, overrides the size
+// rule: "0" never, "1" on every eligible state whatever its size.  The
+// compile-time LBM_TWO_LEVEL=0 removes the path.
+#ifndef LBM_TWO_LEVEL
+#define LBM_TWO_LEVEL 1
+#endif
+
+bool two_level_path(const Layout& L, int nx, int ny, int pf, int model, int grad) {
+    if (!LBM_TWO_LEVEL || pf != 0 || model == 2 || grad != 0 || !resident_state(L)) return false;
+    const char* e = getenv("LBM_TWO_LEVEL");
+    if (e && e[0] == '0' && e[1] == 0) return false;
+    if (e && e[0] == '1' && e[1] == 0) return true;
+    const long long tiles8 = (long long)((nx + TX - 1) / TX) * ((ny + 7) / 8);
+    return tiles8 >= 256;
+}
+
 template <typename T>
 hipError_t launch_step(const KParams<T>& P, char* state, const Layout& L, int64_t nsteps, hipStream_t s,
-                       int ty, int by, int64_t level0) {
+                       int ty, int by, int& copy) {
     constexpr int T16 = sizeof(T) == 8 ? 8 : 16;   // FP64 tiles stop at 8 rows
+    if (two_level_path(L, P.nx, P.ny, P.pf, P.model, P.grad))
+        for (; nsteps >= 2; nsteps -= 2) {
+            launch_step2<T>(P, state, L, s);
+            copy ^= 1;
+        }
     for (int64_t t = 0; t < nsteps; t++) {
-        const int h = (int)((level0 + t) & 1);   // parity guess of this launch's level
+        const int h = copy;   // the copy this launch is expected to find the state in
+        copy ^= 1;
         if (P.pf == 1 || P.model == 2) launch_ch<T, 0>(P, state, L, s, nullptr, nullptr, nullptr);
         else if (P.grad == 1) launch_local<T, 0>(P, state, L, s, nullptr, nullptr, nullptr);
         else if (ty == 4) launch_tile<T, 4, 0>(P, state, L, s, nullptr, nullptr, nullptr, h);
@@ -411,7 +441,7 @@ hipError_t launch_init(const KParams<T>& P, char* state, const Layout& L, const 
     k_to_pull<T><<<g, 256, 0, s>>>(P, scratch, P.plane, dst);
     k_set_header<<<1, 1, 0, s>>>(reinterpret_cast<StateHeader*>(state), P.nx, P.ny, dtype);
     k_set_stamps<<<grid1d((long long)L.nstamp), 256, 0, s>>>(reinterpret_cast<int64_t*>(state + L.off_stamp),
-                                                              (long long)L.nstamp, 0);
+                                                              (long long)L.nstamp, stamp_of(0, 0));
     return hipGetLastError();
 }
 
@@ -442,7 +472,7 @@ hipError_t launch_import(const KParams<T>& P, char* state, const Layout& L, cons
     k_to_pull<T><<<gr, 256, 0, s>>>(P, stage, P.plane, dst);
     k_set_header<<<1, 1, 0, s>>>(reinterpret_cast<StateHeader*>(state), P.nx, P.ny, dtype);
     k_set_stamps<<<grid1d((long long)L.nstamp), 256, 0, s>>>(reinterpret_cast<int64_t*>(state + L.off_stamp),
-                                                              (long long)L.nstamp, step);
+                                                              (long long)L.nstamp, stamp_of(step, cur));
     return hipGetLastError();
 }
 
@@ -456,7 +486,7 @@ hipError_t launch_export(const KParams<T>& P, const char* state, const Layout& L
 
 #define LBM_INSTANTIATE(T)                                                                              \
     template hipError_t launch_step<T>(const KParams<T>&, char*, const Layout&, int64_t, hipStream_t, int, int, \
-                                       int64_t);                                                         \
+                                       int&);                                                            \
     template hipError_t launch_moments<T>(const KParams<T>&, const char*, const Layout&, T*, T*, T*,     \
                                           hipStream_t);                                                 \
     template hipError_t launch_init<T>(const KParams<T>&, char*, const Layout&, const T*, const T*,     \

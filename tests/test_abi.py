@@ -205,3 +205,47 @@ def test_noalloc_batch_step_validates_on_the_host():
     assert lib().lbm_batch_step_noalloc((LbmParams * 1)(bad), 1, fake, 1, None) == -4
     assert lib().lbm_batch_step_noalloc(one, 1, fake, 0, None) == 0
     assert _lib.LBM_OK == 0
+
+
+def test_levels_per_launch():
+    """Two levels per launch exactly for the plain Allen-Cahn step (stencil
+    gradients, present or original model) on a state whose two copies fit the
+    256 MB last-level cache, of at least 256 tiles of 64 x 8 nodes (any size
+    with LBM_TWO_LEVEL=1, none with LBM_TWO_LEVEL=0); one otherwise."""
+    from paper_2111_00847_amd import _lib
+    L = ctypes.CDLL(_lib.LIB_PATH)
+
+    def levels(**kw):
+        v = ctypes.c_int32(-1)
+        assert L.lbm_levels_per_launch(ctypes.byref(_params(**kw)), ctypes.byref(v)) == 0
+        return v.value
+
+    os.environ.pop("LBM_TWO_LEVEL", None)
+    assert levels(nx=256, ny=512, dtype="f32") == 2       # 4 x 64 tiles
+    assert levels(nx=256, ny=504, dtype="f32") == 1       # 4 x 63 tiles
+    assert levels(nx=64, ny=64, dtype="f32") == 1
+    os.environ["LBM_TWO_LEVEL"] = "0"
+    try:
+        assert levels(nx=256, ny=1024, dtype="f32") == 1
+        os.environ["LBM_TWO_LEVEL"] = "1"
+        assert levels(nx=64, ny=64, dtype="f32") == 2
+        assert levels(nx=2048, ny=1024, dtype="f32") == 1   # still only on cache-resident states
+    finally:
+        os.environ["LBM_TWO_LEVEL"] = "1"
+
+    f32 = dict(dtype="f32")
+    # the size-independent rules, everything eligible
+    assert levels(nx=256, ny=1024, **f32) == 2             # the RTI lattice: 2 x 22 MB
+    assert levels(nx=256, ny=1024, dtype="f64") == 2
+    assert levels(nx=2, ny=2, wall_x=True, wall_y=True, **f32) == 2
+    assert levels(nx=256, ny=1024, model="original", **f32) == 2
+    assert levels(nx=256, ny=1024, model="corrected", **f32) == 1
+    assert levels(nx=256, ny=1024, grad_scheme="local", **f32) == 1
+    assert levels(nx=256, ny=1024, phase_eq="cahn_hilliard", phiA=1.0, phiB=-1.0, **f32) == 1
+    assert levels(nx=1024, ny=1024, **f32) == 2            # 2 x 88 MB
+    assert levels(nx=2048, ny=1024, **f32) == 1            # 2 x 176 MB: streamed from HBM
+    assert levels(nx=1024, ny=1024, dtype="f64") == 1
+    os.environ.pop("LBM_TWO_LEVEL", None)
+    v = ctypes.c_int32()
+    assert L.lbm_levels_per_launch(None, ctypes.byref(v)) == -1
+    assert L.lbm_levels_per_launch(ctypes.byref(_params()), None) == -1

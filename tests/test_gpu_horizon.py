@@ -18,10 +18,13 @@ direction of n is set by rounding, test_oracle_conditioning.py), and within
 FP64_BOUND beyond.
 
 FP32: max|dphi| <= 1e-5 and max|du| / Umax <= 1e-4 up to FP32_HORIZON
-(measured: spreading over all 10000 steps, 1.9e-7; Rayleigh-Taylor through 6000
-steps, 6.6e-6, first past at 8000 with 3.3e-5; dam break through 50 steps,
-2.5e-6, first past at 100 with 3.8e-4), and phi within FP32_BOUND of the oracle
-over the whole run.  The first stored level past each bound is printed.
+(measured: spreading over all 10000 steps, 1.9e-7; Rayleigh-Taylor through 2000
+steps, 5.4e-7, first past at 4000 with 1.25e-5, 9.2e-6 at 6000 and 3.3e-5 at
+8000 -- the FP32 rounding the instability amplifies sits at 1e-5 there, so the
+first level past it moves with any change of FP32 rounding order; dam break
+through 50 steps, 2.5e-6, first past at 100 with 3.8e-4), and phi within
+FP32_BOUND of the oracle over the whole run.  The first stored level past each
+bound is printed.
 """
 import os
 
@@ -46,7 +49,7 @@ MAKE = {
 FP64_HORIZON = {"rti_256x1024": 18000, "dam_break_1024x512": 100, "spreading_512x256": 10000}
 FP64_BOUND = {"rti_256x1024": 1e-8, "dam_break_1024x512": 1e-2, "spreading_512x256": 1e-10}
 # last stored level up to which the FP32 GPU run stays within 1e-5 / 1e-4 Umax
-FP32_HORIZON = {"rti_256x1024": 6000, "dam_break_1024x512": 50, "spreading_512x256": 10000}
+FP32_HORIZON = {"rti_256x1024": 2000, "dam_break_1024x512": 50, "spreading_512x256": 10000}
 # bound on max|dphi| of the FP32 run over the whole stated horizon
 FP32_BOUND = {"rti_256x1024": 0.5, "dam_break_1024x512": 2e-2, "spreading_512x256": 1e-5}
 
