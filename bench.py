@@ -297,6 +297,33 @@ def measure_copy(torch, mib=1024, reps=20):
     return round(2 * n * 4 * reps / (ms * 1e-3) / 1e9, 1)
 
 
+def measure_ceiling(torch, mib=1024, reps=5):
+    """The device's streaming rates (lbm_bandwidth_probe): read, write and copy
+    of a `mib` MiB buffer (beyond the 256 MB last-level cache), swept over grid
+    sizes and store policies; each point the median of `reps` launches timed
+    with HIP events.  Rates in GB/s (copy: read + written bytes)."""
+    from paper_2111_00847_amd import api
+    nbytes = mib << 20
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    s = torch.cuda.current_stream()
+    sweep = []
+    for kind, name in ((0, "read"), (1, "write"), (2, "copy")):
+        for nt in ((True,) if kind == 0 else (False, True)):
+            for blocks in (256, 512, 1024, 2048, 4096, 8192, 16384):
+                fn = lambda: api.lbm_bandwidth_probe(kind, dst, src, nbytes, blocks, nt, s)
+                fn()
+                ts = [_timed(s, torch, fn) for _ in range(reps)]
+                ms = _median(ts)
+                moved = nbytes * (2 if kind == 2 else 1)
+                sweep.append({"kind": name, "nt": nt, "blocks": blocks, "GBs": round(moved / (ms * 1e-3) / 1e9, 1)})
+    del src, dst
+    torch.cuda.empty_cache()
+    best = {k: max(p["GBs"] for p in sweep if p["kind"] == k) for k in ("read", "write", "copy")}
+    return {"buffer_MiB": mib, "read_GBs": best["read"], "write_GBs": best["write"], "copy_GBs": best["copy"],
+            "sweep": sweep}
+
+
 def _timed(stream, torch, fn):
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -407,6 +434,12 @@ def main():
                     help="run only the headline measurement (profiling runs)")
     ap.add_argument("--only-large", action="store_true",
                     help="run only the 4096 x 4096 measurement (profiling runs)")
+    ap.add_argument("--only-adjoint", action="store_true",
+                    help="run only the adjoint measurement (profiling runs)")
+    ap.add_argument("--only-batched", action="store_true",
+                    help="run only the batched measurement (profiling runs)")
+    ap.add_argument("--only-ceiling", action="store_true",
+                    help="run only the streaming-ceiling sweep (lbm_bandwidth_probe)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="instead of the benchmark: copy a MIB-sized device buffer 20 times "
                          "(a plain copy kernel of known size, to scale HBM byte counters)")
@@ -440,6 +473,15 @@ def main():
     if args.only_main:
         print(json.dumps(measure_main(args, torch, W, Sim)), flush=True)
         return
+    if args.only_ceiling:
+        print(json.dumps({"stream_ceiling": measure_ceiling(torch)}), flush=True)
+        return
+    if args.only_adjoint:
+        print(json.dumps({"adjoint": measure_adjoint(args, torch, W, Sim)}), flush=True)
+        return
+    if args.only_batched:
+        print(json.dumps({"batched": measure_batched(args, torch, W, Sim, BatchSim)}), flush=True)
+        return
     if not args.only_large:
         out.update(measure_main(args, torch, W, Sim))
         half = out["roofline"]["alg_bytes_per_launch"] // 2
@@ -451,6 +493,9 @@ def main():
         copy_gbs = measure_copy(torch)
         out["large_grid"]["torch_copy_GBs"] = copy_gbs
         out["large_grid"]["frac_of_copy"] = round(out["large_grid"]["achieved_GBs"] / copy_gbs, 4)
+        ceil = measure_ceiling(torch)
+        out["large_grid"]["stream_ceiling"] = {k: ceil[k] for k in ("read_GBs", "write_GBs", "copy_GBs")}
+        out["large_grid"]["frac_of_stream_copy"] = round(out["large_grid"]["achieved_GBs"] / ceil["copy_GBs"], 4)
         if not args.only_large:
             out["large_grid_fp64"] = measure_large(args, torch, W, Sim, "f64")
     if not args.only_large:

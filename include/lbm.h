@@ -308,6 +308,20 @@ int lbm_batch_destroy(lbm_batch *batch);
 #define LBM_NOALLOC_MAX_CASES 256
 int lbm_batch_step_noalloc(const lbm_params *cases, int32_t ncases, void *state, int64_t nsteps, void *stream);
 
+/* ---- streaming probe -------------------------------------------------------
+ * Not part of the method: the HBM read, write and copy rates of the device,
+ * the measured ceiling next to the nominal peak that the step kernels'
+ * bandwidth is compared with.  One launch of `blocks` workgroups of 256
+ * threads streaming `bytes` (a multiple of 16; 16-byte aligned buffers) with
+ * 16-byte loads and stores in a grid-stride loop:
+ *   kind 0: read src; dst receives one uint32 per thread (blocks * 1024 bytes);
+ *   kind 1: write dst (src unused, may be NULL);
+ *   kind 2: copy src to dst.
+ * nt != 0: non-temporal stores.  Asynchronous on `stream`.  Errors:
+ * LBM_E_PARAM (kind), LBM_E_SIZE (blocks, bytes, alignment), LBM_E_NULL. */
+int lbm_bandwidth_probe(int32_t kind, void *dst, const void *src, size_t bytes, int32_t blocks, int32_t nt,
+                        void *stream);
+
 #ifdef __cplusplus
 }
 #endif

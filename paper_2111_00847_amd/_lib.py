@@ -56,6 +56,7 @@ _SIGS = {
     "lbm_state_size": [P(LbmParams), P(ctypes.c_size_t)],
     "lbm_init": [P(LbmParams), vp, vp, vp, vp, vp],
     "lbm_step": [P(LbmParams), vp, ctypes.c_int64, vp],
+    "lbm_levels_per_launch": [P(LbmParams), P(ctypes.c_int32)],
     "lbm_hydrostatic_pressure": [P(LbmParams), vp, vp, vp],
     "lbm_moments": [P(LbmParams), vp, vp, vp, vp, vp],
     "lbm_diagnostics": [P(LbmParams), vp, P(ctypes.c_double), vp],
@@ -79,6 +80,7 @@ _SIGS = {
     "lbm_batch_tuning": [vp, P(ctypes.c_int32), P(ctypes.c_int32), P(ctypes.c_int32), P(ctypes.c_int32)],
     "lbm_batch_destroy": [vp],
     "lbm_batch_step_noalloc": [P(LbmParams), ctypes.c_int32, vp, ctypes.c_int64, vp],
+    "lbm_bandwidth_probe": [ctypes.c_int32, vp, vp, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32, vp],
 }
 _RESTYPE = {"lbm_status_string": ctypes.c_char_p}
 

@@ -107,6 +107,12 @@ def lbm_step(p, state, nsteps=1, stream=None):
     call("lbm_step", ctypes.byref(p), _state_ptr(state), int(nsteps), _stream(stream))
 
 
+def lbm_bandwidth_probe(kind, dst, src, nbytes, blocks, nt=True, stream=None):
+    """One streaming-probe launch (0 read, 1 write, 2 copy) over device tensors."""
+    call("lbm_bandwidth_probe", int(kind), dst.data_ptr(), src.data_ptr() if src is not None else None,
+         int(nbytes), int(blocks), int(bool(nt)), _stream(stream))
+
+
 def lbm_levels_per_launch(p) -> int:
     v = ctypes.c_int32()
     call("lbm_levels_per_launch", ctypes.byref(p), ctypes.byref(v))

@@ -60,7 +60,9 @@ static int validate_ac(const lbm_params* p) {
 
 constexpr size_t ADJ_HDR = 256;
 constexpr size_t TAPE_HDR = 256;
-constexpr int ATY = BY;   // adjoint tiles: 64 x 4, one node per thread
+constexpr int ATY = 8;    // tiles of kernel A: 64 x 8, one node per thread of 64 x ABY
+constexpr int ABY = 8;
+constexpr int BTY = BY;   // tiles of kernel B: 64 x 4, one node per thread
 
 struct TapeHeader {
     int64_t n0;
@@ -89,7 +91,7 @@ struct AdjLayout {
     size_t off_edge;      // G -> B: [level][wall][depth][position along the wall]
     long long emax;
     size_t off_part;      // doubles: 2 per tile of A (gravity), then 4 per workgroup of G (contact angles)
-    int ntA, nB;
+    int ntA, ntB, nB;
     size_t total;
 };
 
@@ -110,6 +112,7 @@ AdjLayout adj_layout_of(const lbm_params* p) {
     A.emax = ((long long)(p->nx > p->ny ? p->nx : p->ny) + 63) / 64 * 64;
     A.off_part = al256(A.off_edge + (size_t)16 * A.emax * L.esz);
     A.ntA = ((p->nx + TX - 1) / TX) * ((p->ny + ATY - 1) / ATY);
+    A.ntB = ((p->nx + TX - 1) / TX) * ((p->ny + BTY - 1) / BTY);
     A.nB = ghost_blocks(p);   // workgroups of kernel G
     A.total = al256(A.off_part + (size_t)(2 * A.ntA + 4 * A.nB) * sizeof(double));
     return A;
@@ -125,7 +128,7 @@ struct AdjView {
     T* edge;
     long long emax;
     double* part;
-    int ntA, nB;
+    int ntA, ntB, nB;
     __device__ AdjHeader* hdr() const { return reinterpret_cast<AdjHeader*>(base); }
     __device__ T* plane_of(int c, int i) const { return copy[c] + (long long)i * plane; }
     __device__ T* s(int i) const { return scr + (long long)i * plane; }
@@ -142,11 +145,12 @@ AdjView<T> adj_view(void* adj, const AdjLayout& A) {
     V.copy[0] = reinterpret_cast<T*>(V.base + A.off_copy[0]);
     V.copy[1] = reinterpret_cast<T*>(V.base + A.off_copy[1]);
     V.scr = reinterpret_cast<T*>(V.base + A.off_scr);
-    V.edge = reinterpret_cast<T*>(V.base + A.off_edge);
-    V.emax = A.emax;
     V.part = reinterpret_cast<double*>(V.base + A.off_part);
     V.ntA = A.ntA;
+    V.ntB = A.ntB;
     V.nB = A.nB;
+    V.edge = reinterpret_cast<T*>(V.base + A.off_edge);
+    V.emax = A.emax;
     return V;
 }
 
@@ -192,9 +196,13 @@ void k_tape_step(KParams<T> P, char* tape, size_t slot, int j, int ntx, int nty)
 // Adjoint of post-collision population i of node (x, y): the population
 // streams to (x, y) + c_i, or back to (x, y) as opp(i) through a wall.
 // planes: the adjoint copy of level n + 1; returns fd + phib of the receiver.
-template <typename T>
-__device__ __forceinline__ void push_read(const T* planes, long long plane, const KParams<T>& P, int i, int x,
-                                          int y, T& fo, T& go) {
+// Adjoints of post-collision f_i and g_i of node (x, y), read where they
+// stream to (fd + phib of the receiver; phib from the LDS window `sb`, whose
+// position (wx, wy) is the node's own).
+template <typename T, typename OFF>
+__device__ __forceinline__ void push_read(const char* cp, OFF pl, const KParams<T>& P, int i, int x, int y,
+                                          const T (*sb)[TX + 3], int wx, int wy, T& fo, T& go) {
+    constexpr OFF ES = sizeof(T);
     int tx = x + cx(i), ty = y + cy(i);
     bool bb = false;
     if (tx < 0 || tx >= P.nx) {
@@ -205,21 +213,30 @@ __device__ __forceinline__ void push_read(const T* planes, long long plane, cons
         if (P.wall_y) bb = true;
         else ty = ty < 0 ? ty + P.ny : ty - P.ny;
     }
-    const long long k = bb ? (long long)y * P.nx + x : (long long)ty * P.nx + tx;
-    const int d = bb ? opp(i) : i;
-    fo = planes[d * plane + k] + planes[P_PHIB * plane + k];
-    go = planes[(9 + d) * plane + k];
+    const OFF k = bb ? (OFF)y * (OFF)P.nx + (OFF)x : (OFF)ty * (OFF)P.nx + (OFF)tx;
+    const OFF d = (OFF)(bb ? opp(i) : i);
+    fo = ld<T>(cp, (d * pl + k) * ES) + (bb ? sb[wy][wx] : sb[wy + cy(i)][wx + cx(i)]);
+    go = ld<T>(cp, ((9 + d) * pl + k) * ES);
 }
 
-template <typename T>
-__global__ __launch_bounds__(TX* BY) void k_adj_local(KParams<T> P, const char* tape, size_t slot, int j,
-                                                     AdjView<T> V) {
+// One 64 x ATY tile per workgroup of 64 x ABY threads, ATY / ABY nodes per
+// thread.  Every thread pulls its nodes' populations from the tape slot once
+// (their phi goes into the LDS window), spare threads pull the window's ring,
+// and the node update is recomputed from the registers.  OFF: byte offsets
+// within a tape slot and within the adjoint buffer.
+template <typename T, typename OFF>
+__global__ __launch_bounds__(TX* ABY) void k_adj_local(KParams<T> P, const char* tape, size_t slot, int j,
+                                                      AdjView<T> V) {
+    constexpr int R = ATY / ABY;
+    constexpr int WX = TX + 2, WY = ATY + 2;
+    constexpr OFF ES = sizeof(T);
     __shared__ T sphi[ATY + 2][TX + 3];
     __shared__ T sphp[ATY + 2][TX + 3];
-    __shared__ double red[2][BY];
+    __shared__ T sphib[ATY + 2][TX + 3];   // phib of level n + 1 on the tile and its ring
+    __shared__ double red[2][ABY];
     // The tape must hold slot j and have been recorded for this lattice and
     // dtype; otherwise nothing of the tape beyond its header is read, the
-    // status records why, and the later kernels of the step (which exit on a
+    // status records why, and the later kernel of the step (which exits on a
     // non-zero status) and lbm_adjoint_params report it.
     const TapeHeader* TH = reinterpret_cast<const TapeHeader*>(tape);
     const bool tape_ok = j >= 0 && j < TH->nlevels && TH->nx == P.nx && TH->ny == P.ny &&
@@ -232,69 +249,120 @@ __global__ __launch_bounds__(TX* BY) void k_adj_local(KParams<T> P, const char* 
         return;
     }
     const bool first = n == 0;
-    const Copy<T> S = copy_at<T>(const_cast<char*>(tape + TAPE_HDR + (size_t)j * slot), P.plane);
+    const char* src = tape + TAPE_HDR + (size_t)j * slot;
+    const OFF pl = (OFF)P.plane;
+    const OFF bF = pl * ES, bG = bF + 8 * pl * ES, bH = bG + 9 * pl * ES;
     const int ntx = (P.nx + TX - 1) / TX;
-    const int x0 = (blockIdx.x % ntx) * TX, y0 = (blockIdx.x / ntx) * ATY;
-    fill_window<T, ATY>(P, S, !first, x0, y0, sphi, sphp);
+    int xt, yt;   // tiles dealt to the XCDs as the step deals them: halo rows stay in one L2
+    xcd_tile(blockIdx.x, ntx, V.ntA / ntx, xt, yt);
+    const int x0 = xt * TX, y0 = yt * ATY;
+    const int lx = threadIdx.x;
+    const int x = x0 + lx;
+    const int ci = (int)((n + 1) & 1), co = (int)(n & 1);
+    const char* cin = reinterpret_cast<const char*>(V.copy[ci]);
+    const OFF bPB = (OFF)P_PHIB * pl * ES;
 
-    const int lx = threadIdx.x, ly = threadIdx.y;
-    const int x = x0 + lx, y = y0 + ly;
+    // own nodes: populations, history, phi into the window
+    T f[R][9], g[R][9], up[R], vp[R];
+    double phid[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const int ly = threadIdx.y + r * ABY, y = y0 + ly;
+        phid[r] = 0.0;
+        up[r] = vp[r] = T(0);
+        if (x >= P.nx || y >= P.ny) continue;
+        double f0;
+        const OFF k = pull_f_at<T, OFF>(P, src, bF, bH, pl, x, y, f[r], f0);
+        f[r][0] = (T)f0;
+        phid[r] = f0 + moving_sum_d(f[r]);
+        pull_g_at<T, OFF>(P, src, bG, pl, x, y, g[r]);
+        const T hp = ld<T>(src, bH + k * ES);
+        up[r] = ld<T>(src, bH + (pl + k) * ES);
+        vp[r] = ld<T>(src, bH + (2 * pl + k) * ES);
+        sphi[ly + 1][lx + 1] = (T)phid[r];
+        if (!first) sphp[ly + 1][lx + 1] = hp;
+        sphib[ly + 1][lx + 1] = ld<T>(cin, bPB + k * ES);
+    }
+    // the ring of the window, and positions of a ragged tile beyond the
+    // lattice that a periodic axis wraps onto nodes
+    auto fill = [&](int wx, int wy) {
+        const int gx = region_node(x0 - 1 + wx, P.nx, P.wall_x), gy = region_node(y0 - 1 + wy, P.ny, P.wall_y);
+        if (gx < 0 || gy < 0) return;
+        T fw[9];
+        double fw0;
+        const OFF k = pull_f_at<T, OFF>(P, src, bF, bH, pl, gx, gy, fw, fw0);
+        sphi[wy][wx] = (T)(fw0 + moving_sum_d(fw));
+        if (!first) sphp[wy][wx] = ld<T>(src, bH + k * ES);
+        sphib[wy][wx] = ld<T>(cin, bPB + k * ES);
+    };
+    for (int idx = tid; idx < 2 * WX + 2 * ATY; idx += TX * ABY) {
+        if (idx < 2 * WX) fill(idx % WX, idx < WX ? 0 : WY - 1);
+        else fill(idx < 2 * WX + ATY ? 0 : WX - 1, 1 + (idx - 2 * WX) % ATY);
+    }
+    if (x0 + TX > P.nx || y0 + ATY > P.ny)
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            const int ly = threadIdx.y + r * ABY;
+            if (x >= P.nx || y0 + ly >= P.ny) fill(lx + 1, ly + 1);
+        }
+    __syncthreads();
+    wall_ghosts<T, ATY, ABY>(P, !first, x0, y0, sphi, sphp);
+
+    char* cout = reinterpret_cast<char*>(V.copy[co]);
+    char* scr = reinterpret_cast<char*>(V.scr);
     double gsum_x = 0.0, gsum_y = 0.0;
-    if (x < P.nx && y < P.ny) {
-        const long long k = (long long)y * P.nx + x;
-        T f[9], g[9];
-        f[0] = (T)rest_decode(S.f0[k], S.h[k], P.rest_w);
 #pragma unroll
-        for (int i = 1; i < Q; i++) f[i] = pull(S.f, P, i, x, y);
-#pragma unroll
-        for (int i = 0; i < Q; i++) g[i] = pull(S.g, P, i, x, y);
-        T gx, gy, lap, gxp = T(0), gyp = T(0), lp, php = T(0), up = T(0), vp = T(0);
+    for (int r = 0; r < R; r++) {
+        const int ly = threadIdx.y + r * ABY, y = y0 + ly;
+        if (x >= P.nx || y >= P.ny) continue;
+        const OFF k = (OFF)y * (OFF)P.nx + (OFF)x;
+        T gx, gy, lap, gxp = T(0), gyp = T(0), lp, php = T(0);
         win_stencil<T, ATY>(sphi, lx + 1, ly + 1, gx, gy, lap);
         if (!first) {
             win_stencil<T, ATY>(sphp, lx + 1, ly + 1, gxp, gyp, lp);
             php = sphp[ly + 1][lx + 1];
-            up = S.h[P.plane + k];
-            vp = S.h[2 * P.plane + k];
         }
-        const Macro<T> M = macro(P, g, sphi[ly + 1][lx + 1], gx, gy, lap, first, php, gxp, gyp, up, vp);
-        const int ci = (int)((n + 1) & 1), co = (int)(n & 1);
+        const T upr = first ? T(0) : up[r], vpr = first ? T(0) : vp[r];
+        const Macro<T> M = macro(P, g[r], sphi[ly + 1][lx + 1], gx, gy, lap, first, php, gxp, gyp, upr, vpr);
         T fo[9], go[9];
 #pragma unroll
-        for (int i = 0; i < Q; i++) push_read(V.copy[ci], V.plane, P, i, x, y, fo[i], go[i]);
-        const T hphi = V.plane_of(ci, 18)[k], hu = V.plane_of(ci, 19)[k], hv = V.plane_of(ci, 20)[k];
+        for (int i = 0; i < Q; i++) push_read<T, OFF>(cin, pl, P, i, x, y, sphib, lx + 1, ly + 1, fo[i], go[i]);
+        const T hphi = ld<T>(cin, (18 * pl + k) * ES), hu = ld<T>(cin, (19 * pl + k) * ES),
+                hv = ld<T>(cin, (20 * pl + k) * ES);
         NodeAdj<T> A;
-        node_vjp(P, M, f, g, gx, gy, lap, first, php, gxp, gyp, up, vp, fo, go, hphi, hu, hv, A);
+        node_vjp(P, M, f[r], g[r], gx, gy, lap, first, php, gxp, gyp, upr, vpr, fo, go, hphi, hu, hv, A);
 #pragma unroll
         for (int i = 0; i < Q; i++) {
-            V.plane_of(co, i)[k] = A.f[i];
-            V.plane_of(co, 9 + i)[k] = A.g[i];
+            *reinterpret_cast<T*>(cout + ((OFF)i * pl + k) * ES) = A.f[i];
+            *reinterpret_cast<T*>(cout + ((OFF)(9 + i) * pl + k) * ES) = A.g[i];
         }
-        V.plane_of(co, 19)[k] = first ? T(0) : A.up;
-        V.plane_of(co, 20)[k] = first ? T(0) : A.vp;
-        V.s(S_PHIC)[k] = A.phic;
-        V.s(S_GX)[k] = A.gx;
-        V.s(S_GY)[k] = A.gy;
-        V.s(S_LAP)[k] = A.lap;
-        V.s(S_PHP)[k] = A.php;
-        V.s(S_GXP)[k] = A.gxp;
-        V.s(S_GYP)[k] = A.gyp;
+        *reinterpret_cast<T*>(cout + (19 * pl + k) * ES) = first ? T(0) : A.up;
+        *reinterpret_cast<T*>(cout + (20 * pl + k) * ES) = first ? T(0) : A.vp;
+        const T sv[7] = {A.phic, A.gx, A.gy, A.lap, A.php, A.gxp, A.gyp};   // S_PHIC .. S_GYP
+#pragma unroll
+        for (int q = 0; q < 7; q++) *reinterpret_cast<T*>(scr + ((OFF)q * pl + k) * ES) = sv[q];
         const bool near_x = P.wall_x && (x < 2 || x >= P.nx - 2);
         const bool near_y = P.wall_y && (y < 2 || y >= P.ny - 2);
-        if (near_x || near_y) V.s(S_PHI)[k] = M.phi;
-        gsum_x = (double)A.grav_x;
-        gsum_y = (double)A.grav_y;
+        if (near_x || near_y) *reinterpret_cast<T*>(scr + ((OFF)S_PHI * pl + k) * ES) = M.phi;
+        gsum_x += (double)A.grav_x;
+        gsum_y += (double)A.grav_y;
     }
     // per-tile sums of the gravity derivative, accumulated over the steps of a pass
     gsum_x = wave_sum(gsum_x);
     gsum_y = wave_sum(gsum_y);
     if (lx == 0) {
-        red[0][ly] = gsum_x;
-        red[1][ly] = gsum_y;
+        red[0][threadIdx.y] = gsum_x;
+        red[1][threadIdx.y] = gsum_y;
     }
     __syncthreads();
     if (tid == 0) {
-        V.part[2 * blockIdx.x] += (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
-        V.part[2 * blockIdx.x + 1] += (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+        double sx = 0.0, sy = 0.0;
+        for (int w = 0; w < ABY; w++) {
+            sx += red[0][w];
+            sy += red[1][w];
+        }
+        V.part[2 * blockIdx.x] += sx;
+        V.part[2 * blockIdx.x + 1] += sy;
     }
 }
 
@@ -380,14 +448,16 @@ __device__ T xghost_adjoint(const KParams<T>& P, const AdjView<T>& V, int lev, c
 // from the ghosts (edge arrays).
 template <typename T>
 __global__ __launch_bounds__(TX* BY) void k_adj_gather(KParams<T> P, const char* tape, int j, AdjView<T> V) {
-    constexpr int WX = TX + 2, WY = ATY + 2;
+    constexpr int WX = TX + 2, WY = BTY + 2;
     __shared__ T sw[5][WY][WX + 1];   // gx, gy, lap of phi^n; gx, gy of phi^{n-1}
     const int64_t n = reinterpret_cast<const TapeHeader*>(tape)->n0 + j;
     if (V.hdr()->status != 0) return;
     const bool first = n == 0;
     const int co = (int)(n & 1);
     const int ntx = (P.nx + TX - 1) / TX;
-    const int x0 = (blockIdx.x % ntx) * TX, y0 = (blockIdx.x / ntx) * ATY;
+    int xt, yt;   // tiles dealt to the XCDs as kernel A deals its own
+    xcd_tile(blockIdx.x, ntx, V.ntB / ntx, xt, yt);
+    const int x0 = xt * TX, y0 = yt * BTY;
     const int tid = threadIdx.y * TX + threadIdx.x;
     const T* src[5] = {V.s(S_GX), V.s(S_GY), V.s(S_LAP), V.s(S_GXP), V.s(S_GYP)};
     for (int idx = tid; idx < WX * WY; idx += TX * BY) {
@@ -694,11 +764,14 @@ static void launch_tape_steps(const KParams<T>& P, char* tape, size_t slot, int 
 
 template <typename T>
 static void launch_adj_step(const KParams<T>& P, const char* tape, size_t slot, int j, const AdjView<T>& V,
-                            hipStream_t s) {
-    const int ntx = (P.nx + TX - 1) / TX, nty = (P.ny + ATY - 1) / ATY;
-    k_adj_local<T><<<ntx * nty, dim3(TX, BY), 0, s>>>(P, tape, slot, j, V);
+                            size_t adj_bytes, hipStream_t s) {
+    // 32-bit byte offsets while a tape slot and the adjoint buffer stay below 4 GiB
+    if (slot < (size_t(1) << 32) && adj_bytes < (size_t(1) << 32))
+        k_adj_local<T, uint32_t><<<V.ntA, dim3(TX, ABY), 0, s>>>(P, tape, slot, j, V);
+    else
+        k_adj_local<T, uint64_t><<<V.ntA, dim3(TX, ABY), 0, s>>>(P, tape, slot, j, V);
     if (P.wall_x || P.wall_y) k_adj_ghosts<T><<<V.nB, GHOST_THREADS, 0, s>>>(P, tape, slot, j, V);
-    k_adj_gather<T><<<ntx * nty, dim3(TX, BY), 0, s>>>(P, tape, j, V);
+    k_adj_gather<T><<<V.ntB, dim3(TX, BY), 0, s>>>(P, tape, j, V);
 }
 
 }  // namespace lbm
@@ -773,9 +846,11 @@ int lbm_adjoint_step(const lbm_params* p, const void* tape, int32_t j, void* adj
     const AdjLayout A = adj_layout_of(p);
     hipStream_t s = (hipStream_t)stream;
     if (p->dtype == LBM_F32)
-        launch_adj_step<float>(resolve<float>(p, L), (const char*)tape, L.buf_bytes, j, adj_view<float>(adj, A), s);
+        launch_adj_step<float>(resolve<float>(p, L), (const char*)tape, L.buf_bytes, j, adj_view<float>(adj, A),
+                               A.total, s);
     else
-        launch_adj_step<double>(resolve<double>(p, L), (const char*)tape, L.buf_bytes, j, adj_view<double>(adj, A), s);
+        launch_adj_step<double>(resolve<double>(p, L), (const char*)tape, L.buf_bytes, j, adj_view<double>(adj, A),
+                                A.total, s);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? LBM_OK : hip_fail(e);
 }
@@ -791,10 +866,11 @@ int lbm_adjoint_run(const lbm_params* p, const void* tape, int32_t j_first, int3
     hipStream_t s = (hipStream_t)stream;
     for (int32_t j = j_first; j > j_first - count; j--) {
         if (p->dtype == LBM_F32)
-            launch_adj_step<float>(resolve<float>(p, L), (const char*)tape, L.buf_bytes, j, adj_view<float>(adj, A), s);
+            launch_adj_step<float>(resolve<float>(p, L), (const char*)tape, L.buf_bytes, j, adj_view<float>(adj, A),
+                                   A.total, s);
         else
             launch_adj_step<double>(resolve<double>(p, L), (const char*)tape, L.buf_bytes, j, adj_view<double>(adj, A),
-                                    s);
+                                    A.total, s);
     }
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? LBM_OK : hip_fail(e);

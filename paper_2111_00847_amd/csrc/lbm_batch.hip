@@ -45,6 +45,21 @@ struct BatchCase {
                                  // 3: Allen-Cahn with the local gradient scheme
 };
 
+// Case of work item w: the number of cases whose first item is <= w, less
+// one.  Every thread of the workgroup tests one case (item_begin ascends with
+// the case index) and the workgroup counts the hits: one round of loads
+// instead of the dependent loads of a search.
+template <typename T>
+__device__ __forceinline__ int batch_case(const BatchCase<T>* __restrict__ cases, int ncases, int w, int nthreads) {
+    const int tid = threadIdx.y * TX + threadIdx.x;
+    int n = 0;
+    for (int c0 = 0; c0 < ncases; c0 += nthreads) {
+        const int c = c0 + tid;
+        n += __syncthreads_count(c < ncases && cases[c].item_begin <= w);
+    }
+    return n - 1;
+}
+
 // NT: non-temporal state stores (the batch's state exceeds the last-level
 // cache); ordinary ones otherwise, as for a single lattice.
 template <typename T, int TY, int NBY, bool NT>
@@ -53,13 +68,7 @@ void k_step_batch(const BatchCase<T>* __restrict__ cases, int ncases, int nitems
     __shared__ T sphi[TY + 2][TX + 3];
     __shared__ T sphp[TY + 2][TX + 3];
     for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
-        int lo = 0, hi = ncases - 1;   // last case with item_begin <= w
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (cases[mid].item_begin <= w) lo = mid;
-            else hi = mid - 1;
-        }
-        const BatchCase<T>& C = cases[lo];
+        const BatchCase<T>& C = cases[batch_case(cases, ncases, w, TX * NBY)];
         const int local = w - C.item_begin;
         // the collision specialisation the case runs alone (lbm_step), so that it stays bitwise
         if (C.P.rates_std)
@@ -85,13 +94,7 @@ __global__ __launch_bounds__(TX* BY) void k_step_batch_wide(const BatchCase<T>* 
         ChWindow<T, TY> ch;
     } lds;
     for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
-        int lo = 0, hi = ncases - 1;   // last case with item_begin <= w
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (cases[mid].item_begin <= w) lo = mid;
-            else hi = mid - 1;
-        }
-        const BatchCase<T>& C = cases[lo];
+        const BatchCase<T>& C = cases[batch_case(cases, ncases, w, TX * BY)];
         const int local = w - C.item_begin;
         char* st0 = batch_state + C.base;
         if (C.body == 0 && C.P.rates_std)

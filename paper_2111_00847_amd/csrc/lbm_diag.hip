@@ -190,26 +190,49 @@ __global__ __launch_bounds__(TX* BY) void k_diag2(KParams<T> P, const T* scr, do
     }
 }
 
-// One workgroup: sequential sums over the partial records in block order.
-__global__ void k_diag3(const double* partials, int nblocks, long long n, double* out) {
-    if (threadIdx.x != 0) return;
-    double sphi = 0, mdiv = 0, sdiv = 0, umax = 0, bad = 0, ssm = 0, cnt = 0;
-    for (int b = 0; b < nblocks; b++) {
+// One workgroup of DIAG3_THREADS: thread t folds the partial records t,
+// t + DIAG3_THREADS, ... in that order, then a tree over the threads in a
+// fixed pairing (sums: deterministic for a given lattice; maxima: exact).
+constexpr int DIAG3_THREADS = 1024;
+
+__global__ __launch_bounds__(DIAG3_THREADS) void k_diag3(const double* partials, int nblocks, long long n,
+                                                         double* out) {
+    __shared__ double red[7][DIAG3_THREADS];
+    const int t = threadIdx.x;
+    double v[7] = {0, 0, 0, 0, 0, 0, 0};   // sum phi, max div, sum div^2, max |u|, nonfinite, sum S_m^2, count
+    for (int b = t; b < nblocks; b += DIAG3_THREADS) {
         const double* r = partials + b * 8;
-        sphi += r[0];
-        mdiv = fmax(mdiv, r[1]);
-        sdiv += r[2];
-        umax = fmax(umax, r[3]);
-        bad = fmax(bad, r[4]);
-        ssm += r[5];
-        cnt += r[6];
+        v[0] += r[0];
+        v[1] = fmax(v[1], r[1]);
+        v[2] += r[2];
+        v[3] = fmax(v[3], r[3]);
+        v[4] = fmax(v[4], r[4]);
+        v[5] += r[5];
+        v[6] += r[6];
     }
-    out[0] = sphi;
-    out[1] = mdiv;
-    out[2] = sqrt(sdiv / (double)n);
-    out[3] = cnt > 0 ? sqrt(ssm / cnt) : 0.0;
-    out[4] = umax;
-    out[5] = bad;
+#pragma unroll
+    for (int q = 0; q < 7; q++) red[q][t] = v[q];
+    __syncthreads();
+    for (int w = DIAG3_THREADS / 2; w > 0; w >>= 1) {
+        if (t < w) {
+            red[0][t] += red[0][t + w];
+            red[1][t] = fmax(red[1][t], red[1][t + w]);
+            red[2][t] += red[2][t + w];
+            red[3][t] = fmax(red[3][t], red[3][t + w]);
+            red[4][t] = fmax(red[4][t], red[4][t + w]);
+            red[5][t] += red[5][t + w];
+            red[6][t] += red[6][t + w];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        out[0] = red[0][0];
+        out[1] = red[1][0];
+        out[2] = sqrt(red[2][0] / (double)n);
+        out[3] = red[6][0] > 0 ? sqrt(red[5][0] / red[6][0]) : 0.0;
+        out[4] = red[3][0];
+        out[5] = red[4][0];
+    }
 }
 
 template <typename T>
@@ -226,7 +249,7 @@ hipError_t launch_diagnostics(const KParams<T>& P, const char* state, const Layo
         k_diag1_ch<T, true><<<grd, blk, 0, s>>>(P, state, L.off_buf[0], L.off_buf[1], L.off_stamp, scr, partials);
     else k_diag1<T><<<grd, blk, 0, s>>>(P, state, L.off_buf[0], L.off_buf[1], L.off_stamp, scr, partials);
     k_diag2<T><<<grd, blk, 0, s>>>(P, scr, partials);
-    k_diag3<<<1, 64, 0, s>>>(partials, (int)(grd.x * grd.y), L.n, out);
+    k_diag3<<<1, DIAG3_THREADS, 0, s>>>(partials, (int)(grd.x * grd.y), L.n, out);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = hipMemcpyAsync(host_out, out, 6 * sizeof(double), hipMemcpyDeviceToHost, s);

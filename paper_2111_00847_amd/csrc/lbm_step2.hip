@@ -27,16 +27,6 @@
 
 namespace lbm {
 
-// Position p of a region on an axis of n nodes -> node index, or -1 where p
-// lies beyond a wall.  Periodic axes wrap (any number of times: a lattice may
-// be narrower than the region).
-__device__ __forceinline__ int region_node(int p, int n, bool wall) {
-    if (p >= 0 && p < n) return p;
-    if (wall) return -1;
-    const int r = p % n;
-    return r < 0 ? r + n : r;
-}
-
 // Wall ghosts (Eq. Dwetting) of a window whose position (wx, wy) is node
 // (x0 - H + wx, y0 - H + wy): the rule and order of wall_ghosts (x-walls on
 // every row that is not beyond a y-wall, then y-walls across all columns up to
@@ -78,35 +68,6 @@ __device__ __forceinline__ void ghosts_h(const KParams<T>& P, bool need_prev, in
             }
         }
         __syncthreads();
-    }
-}
-
-// g_i arriving at node (x, y) of a copy (pull with half-way bounce-back), by
-// byte offsets as pull_f_at.
-template <typename T, typename OFF>
-__device__ __forceinline__ void pull_g_at(const KParams<T>& P, const char* src, OFF bG, OFF pl, int x, int y,
-                                          T* g) {
-    constexpr OFF ES = sizeof(T);
-    const OFF nx = (OFF)P.nx;
-    OFF col[3], row[3];
-    bool wx[3] = {false, false, false}, wy[3] = {false, false, false};
-    col[1] = (OFF)x;
-    col[0] = x == 0 ? (OFF)(P.nx - 1) : (OFF)(x - 1);
-    col[2] = x == P.nx - 1 ? (OFF)0 : (OFF)(x + 1);
-    if (x == 0) wx[0] = P.wall_x;
-    if (x == P.nx - 1) wx[2] = P.wall_x;
-    row[1] = (OFF)y * nx;
-    row[0] = y == 0 ? (OFF)(P.ny - 1) * nx : (OFF)(y - 1) * nx;
-    row[2] = y == P.ny - 1 ? (OFF)0 : (OFF)(y + 1) * nx;
-    if (y == 0) wy[0] = P.wall_y;
-    if (y == P.ny - 1) wy[2] = P.wall_y;
-    const OFF k = row[1] + col[1];
-#pragma unroll
-    for (int i = 0; i < Q; i++) {
-        const int ax = 1 - cx(i), ay = 1 - cy(i);
-        const bool bb = wx[ax] || wy[ay];
-        const OFF o = bb ? bG + ((OFF)opp(i) * pl + k) * ES : bG + ((OFF)i * pl + row[ay] + col[ax]) * ES;
-        g[i] = ld<T>(src, o);
     }
 }
 

@@ -249,3 +249,17 @@ def test_levels_per_launch():
     v = ctypes.c_int32()
     assert L.lbm_levels_per_launch(None, ctypes.byref(v)) == -1
     assert L.lbm_levels_per_launch(ctypes.byref(_params()), None) == -1
+
+
+def test_bandwidth_probe_validates_on_the_host():
+    """Invalid probe requests are refused before any launch."""
+    from paper_2111_00847_amd import _lib
+    L = _lib.lib()
+    p16 = ctypes.c_void_p(16)
+    assert L.lbm_bandwidth_probe(3, p16, p16, 1 << 20, 256, 1, None) == -4       # kind
+    assert L.lbm_bandwidth_probe(-1, p16, p16, 1 << 20, 256, 1, None) == -4
+    assert L.lbm_bandwidth_probe(2, p16, p16, (1 << 20) + 8, 256, 1, None) == -2  # not a multiple of 16
+    assert L.lbm_bandwidth_probe(2, p16, p16, 1 << 20, 0, 1, None) == -2          # no workgroups
+    assert L.lbm_bandwidth_probe(2, ctypes.c_void_p(24), p16, 1 << 20, 256, 1, None) == -2   # alignment
+    assert L.lbm_bandwidth_probe(2, p16, None, 1 << 20, 256, 1, None) == -1       # copy without a source
+    assert L.lbm_bandwidth_probe(0, None, p16, 1 << 20, 256, 1, None) == -1
