@@ -10,10 +10,10 @@ benchmark times for their size; total phi is conserved to 1e-12 (FP64) and
 
 FP64: max|dphi| and max|du| / Umax within 1e-10 at every stored level up to
 FP64_HORIZON (measured on MI355X: the droplet spreading over its whole 10000
-steps, 1.1e-14; the Rayleigh-Taylor run through 18000 steps, 9.9e-11, then
-1.0e-9 at 20000 as the instability's roll-ups amplify the rounding-order
-differences; the dam break through 100 steps, 5.1e-12, then 8.4e-10 at 150 and
-3e-3 by 500 -- the collapse pushes the bulk water off phi_A, where the
+steps, 1.1e-14; the Rayleigh-Taylor run through 18000 steps, 5.9e-11, then
+6.1e-10 at 20000 as the instability's roll-ups amplify the rounding-order
+differences; the dam break through 100 steps, 5.2e-12, then 7.6e-10 at 150 and
+5e-3 by 2000 -- the collapse pushes the bulk water off phi_A, where the
 direction of n is set by rounding, test_oracle_conditioning.py), and within
 FP64_BOUND beyond.
 
