@@ -60,8 +60,8 @@ static int validate_ac(const lbm_params* p) {
 
 constexpr size_t ADJ_HDR = 256;
 constexpr size_t TAPE_HDR = 256;
-constexpr int ATY = 8;    // tiles of kernel A: 64 x 8, one node per thread of 64 x ABY
-constexpr int ABY = 8;
+constexpr int ATY = 16;   // tiles of kernel A: 64 x 16, one node per thread of 64 x ABY
+constexpr int ABY = 16;
 constexpr int BTY = BY;   // tiles of kernel B: 64 x 4, one node per thread
 
 struct TapeHeader {
@@ -272,10 +272,9 @@ __global__ __launch_bounds__(TX* ABY) void k_adj_local(KParams<T> P, const char*
         up[r] = vp[r] = T(0);
         if (x >= P.nx || y >= P.ny) continue;
         double f0;
-        const OFF k = pull_f_at<T, OFF>(P, src, bF, bH, pl, x, y, f[r], f0);
+        const OFF k = pull_fg_at<T, OFF>(P, src, bF, bG, bH, pl, x, y, f[r], f0, g[r]);
         f[r][0] = (T)f0;
         phid[r] = f0 + moving_sum_d(f[r]);
-        pull_g_at<T, OFF>(P, src, bG, pl, x, y, g[r]);
         const T hp = ld<T>(src, bH + k * ES);
         up[r] = ld<T>(src, bH + (pl + k) * ES);
         vp[r] = ld<T>(src, bH + (2 * pl + k) * ES);

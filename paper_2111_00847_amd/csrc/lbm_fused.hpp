@@ -103,11 +103,12 @@ __device__ __forceinline__ OFF pull_f_at(const KParams<T>& P, const char* src, O
     return k;
 }
 
-// g_i arriving at node (x, y) of a copy (pull with half-way bounce-back), by
-// byte offsets as pull_f_at.
+// f (with the rest population decoded in FP64, as pull_f_at) and g arriving
+// at node (x, y) of a copy, the nine source offsets computed once for both.
+// Returns the node's element index.
 template <typename T, typename OFF>
-__device__ __forceinline__ void pull_g_at(const KParams<T>& P, const char* src, OFF bG, OFF pl, int x, int y,
-                                          T* g) {
+__device__ __forceinline__ OFF pull_fg_at(const KParams<T>& P, const char* src, OFF bF, OFF bG, OFF bH, OFF pl,
+                                          int x, int y, T* f, double& f0, T* g) {
     constexpr OFF ES = sizeof(T);
     const OFF nx = (OFF)P.nx;
     OFF col[3], row[3];
@@ -123,13 +124,19 @@ __device__ __forceinline__ void pull_g_at(const KParams<T>& P, const char* src, 
     if (y == 0) wy[0] = P.wall_y;
     if (y == P.ny - 1) wy[2] = P.wall_y;
     const OFF k = row[1] + col[1];
+    f0 = rest_decode(ld<T>(src, k * ES), ld<T>(src, bH + k * ES), P.rest_w);
+    g[0] = ld<T>(src, bG + k * ES);
 #pragma unroll
-    for (int i = 0; i < Q; i++) {
+    for (int i = 1; i < Q; i++) {
         const int ax = 1 - cx(i), ay = 1 - cy(i);
         const bool bb = wx[ax] || wy[ay];
-        const OFF o = bb ? bG + ((OFF)opp(i) * pl + k) * ES : bG + ((OFF)i * pl + row[ay] + col[ax]) * ES;
-        g[i] = ld<T>(src, o);
+        // element offset of the source within a plane, and the plane: i, or opp(i) of the node itself
+        const OFF e = bb ? k : row[ay] + col[ax];
+        const OFF pf = bb ? (OFF)(opp(i) - 1) : (OFF)(i - 1), pg = pf + 1;
+        f[i] = ld<T>(src, bF + (pf * pl + e) * ES);
+        g[i] = ld<T>(src, bG + (pg * pl + e) * ES);
     }
+    return k;
 }
 
 // Position p of a region on an axis of n nodes -> node index, or -1 where p

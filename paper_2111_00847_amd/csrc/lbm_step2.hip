@@ -130,8 +130,7 @@ __global__ __launch_bounds__(TX* NBY) void k_step2(KParams<T> P, char* state, si
         hp[s] = hu[s] = hv[s] = T(0);
         f0d[s] = 0.0;
         if (ok[s]) {
-            const uint32_t k = pull_f_at<T, uint32_t>(P, src, bF, bH, pl, nxi, nyi, f[s], f0d[s]);
-            pull_g_at<T, uint32_t>(P, src, bG, pl, nxi, nyi, g[s]);
+            const uint32_t k = pull_fg_at<T, uint32_t>(P, src, bF, bG, bH, pl, nxi, nyi, f[s], f0d[s], g[s]);
             hp[s] = ld<T>(src, bH + k * ES);
             hu[s] = ld<T>(src, bH + (pl + k) * ES);
             hv[s] = ld<T>(src, bH + (2 * pl + k) * ES);
@@ -217,16 +216,24 @@ __global__ __launch_bounds__(TX* NBY) void k_step2(KParams<T> P, char* state, si
     __syncthreads();
 
     // ---- B: phi of level n + 1 on the tile and its one-node ring, from A's f
+    // Wall sides of position (x, y) that a population pulled there would come
+    // from beyond (x-, x+, y-, y+; on a wall axis a position is its node).
+    struct Beyond {
+        bool xl, xh, yl, yh;
+        __device__ bool of(int i) const {
+            return (cx(i) > 0 ? xl : (cx(i) < 0 ? xh : false)) || (cy(i) > 0 ? yl : (cy(i) < 0 ? yh : false));
+        }
+    };
+    auto beyond = [&](int x, int y) -> Beyond {
+        return Beyond{P.wall_x && x == 0, P.wall_x && x == P.nx - 1, P.wall_y && y == 0, P.wall_y && y == P.ny - 1};
+    };
     // f_i arriving at region position (ax, ay) of node (x, y): from position
     // (ax, ay) - c_i, or its own opp(i) where (x, y) - c_i lies beyond a wall.
     auto pull_a = [&](int ax, int ay, int x, int y, T* fo) -> double {
         const int c = ay * AW + ax;
+        const Beyond w = beyond(x, y);
 #pragma unroll
-        for (int i = 1; i < Q; i++) {
-            const int sx = x - cx(i), sy = y - cy(i);
-            const bool bb = (P.wall_x && (sx < 0 || sx >= P.nx)) || (P.wall_y && (sy < 0 || sy >= P.ny));
-            fo[i] = bb ? L.fa[opp(i)][c] : L.fa[i][c - cy(i) * AW - cx(i)];
-        }
+        for (int i = 1; i < Q; i++) fo[i] = w.of(i) ? L.fa[opp(i)][c] : L.fa[i][c - cy(i) * AW - cx(i)];
         const double f0 = rest_decode(L.fa[0][c], L.pa[ay + 1][ax + 1], P.rest_w);
         fo[0] = (T)f0;
         return f0 + moving_sum_d(fo);
@@ -276,13 +283,10 @@ __global__ __launch_bounds__(TX* NBY) void k_step2(KParams<T> P, char* state, si
         const int ly = threadIdx.y + r * NBY, y = y0 + ly;
         if (x >= P.nx || y >= P.ny) continue;
         const int c1 = (ly + 1) * GW + (lx + 1);
+        const Beyond w = beyond(x, y);
         T gb[9];
 #pragma unroll
-        for (int i = 0; i < Q; i++) {
-            const int sx = x - cx(i), sy = y - cy(i);
-            const bool bb = (P.wall_x && (sx < 0 || sx >= P.nx)) || (P.wall_y && (sy < 0 || sy >= P.ny));
-            gb[i] = bb ? L.ga[opp(i)][c1] : L.ga[i][c1 - cy(i) * GW - cx(i)];
-        }
+        for (int i = 0; i < Q; i++) gb[i] = w.of(i) ? L.ga[opp(i)][c1] : L.ga[i][c1 - cy(i) * GW - cx(i)];
         T gx, gy, lap, gxp, gyp, lp;
         win_stencil_at(L.pb, lx + 1, ly + 1, gx, gy, lap);
         win_stencil_at(L.pa, lx + 3, ly + 3, gxp, gyp, lp);
