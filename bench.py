@@ -13,7 +13,7 @@ of the median replay.  The 46 MB state of this lattice stays in the 256 MB
 last-level cache from step to step, where lbm_step advances two levels per
 launch (the two-level kernel: bit for bit two one-level launches); the
 `one_level` entry times the same K steps as K one-level launches.  The
-HBM-bound point is `large_grid`.
+point streamed from HBM is `large_grid`.
 
 The JSON line also carries:
   roofline     -- the step kernel against the HBM peak: algorithmic bytes per
@@ -27,10 +27,11 @@ The JSON line also carries:
                   device copy of the same bytes (half read, half written),
                   which stays in the 256 MB cache as the step's 46 MB state
                   does, and `frac_of_copy` the step's rate against it;
-  large_grid   -- the same kernel at 4096 x 4096 (state 2.9 GB, far beyond the
-                  256 MB Infinity Cache), where HBM is the real bound, next to
-                  the bandwidth of torch's own device copy; large_grid_fp64 the
-                  FP64 kernel there;
+  large_grid   -- the same kernels at 4096 x 4096 (state 2.9 GB, far beyond the
+                  256 MB Infinity Cache), where a one-level launch is bound by
+                  HBM and the two-level launch crosses HBM once per two levels,
+                  next to the bandwidth of torch's own device copy and of the
+                  streaming probe; large_grid_fp64 the FP64 kernels there;
   batched      -- 64 droplet-spreading cases of uneven sizes (Sec. 4.3 set-up,
                   FP32): one autotuned persistent launch per step replayed from a
                   captured graph, against the same cases advanced one after
@@ -200,7 +201,7 @@ def measure_main(args, torch, W, Sim):
                      "kernel": kernel, "levels_per_launch": levels, "alg_bytes_per_launch": alg,
                      "avg_launch_ms": round(ms_launch, 5),
                      "state": "46 MB, resident in the 256 MB last-level cache between steps: the launch is "
-                              "bound by latency and VALU issue there, not by HBM; the HBM-bound point is "
+                              "bound by latency and VALU issue there, not by HBM; the point streamed from HBM is "
                               "large_grid (4096 x 4096)"},
         "one_level": {"kernel": "k_step<float>", "value": round(nodes * args.steps / (ms1 * 1e-3) / 1e6, 2),
                       "unit": "MLUPS", "avg_launch_ms": round(ms1 / args.steps, 5),
@@ -210,21 +211,37 @@ def measure_main(args, torch, W, Sim):
 
 def measure_large(args, torch, W, Sim, dtype="f32"):
     """The same kernel on a 4096 x 4096 lattice (state 2.9 GB in FP32, 5.6 GB in
-    FP64: far beyond the 256 MB cache), where HBM is the bound."""
+    FP64: far beyond the 256 MB cache), where a one-level launch is bound by HBM.
+    lbm_step advances two levels per launch there too, crossing HBM once per
+    two levels: `achieved_GBs` counts the algorithmic 168 B (FP32) per lattice
+    update, `hbm_GBs` the bytes one launch must move (the state read once and
+    written once, whatever the levels it advances) over its duration; `one_level`
+    times the same steps as one-level launches."""
+    from paper_2111_00847_amd import api
     caseL, phiL = W.rti(nx=4096, ny=4096, dtype=dtype)
     simL = Sim(caseL, "cuda:0").init(phiL, None, "hydrostatic")
     simL.step(10)
     steps = args.large_steps if dtype == "f32" else max(args.large_steps // 2, 1)
+    levels = api.lbm_levels_per_launch(api.make_params(caseL))
     msL = _median(time_graph(simL, steps, 3, torch))
+    ms1 = _median(time_graph(simL, steps, 3, torch, one_level=True))
+    assert simL.diagnostics()["nonfinite"] == 0, "non-finite state after the timed large-lattice steps"
     msLl = msL / steps
-    algL = ALG_BYTES[dtype] * caseL.nodes
-    achL = algL / (msLl * 1e-3) / 1e9
+    alg = ALG_BYTES[dtype] * caseL.nodes
+    achL = alg / (msLl * 1e-3) / 1e9
+    ach1 = alg / (ms1 / steps * 1e-3) / 1e9
     del simL
     torch.cuda.empty_cache()
+    t = "float" if dtype == "f32" else "double"
     return {"workload": "rayleigh_taylor_4096x4096", "dtype": dtype, "steps": steps,
-            "value": round(caseL.nodes * steps / (msL * 1e-3) / 1e6, 1),
-            "unit": "MLUPS", "achieved_GBs": round(achL, 1),
-            "frac": round(achL / HBM_PEAK_GBS, 4), "avg_launch_ms": round(msLl, 4)}
+            "value": round(caseL.nodes * steps / (msL * 1e-3) / 1e6, 1), "unit": "MLUPS",
+            "kernel": f"k_step2<{t}> (two levels per launch)" if levels == 2 else f"k_step<{t}>",
+            "levels_per_launch": levels, "achieved_GBs": round(achL, 1),
+            "frac": round(achL / HBM_PEAK_GBS, 4), "avg_level_ms": round(msLl, 4),
+            "hbm_GBs": round(achL / levels, 1), "hbm_frac": round(achL / levels / HBM_PEAK_GBS, 4),
+            "one_level": {"kernel": f"k_step<{t}>", "value": round(caseL.nodes * steps / (ms1 * 1e-3) / 1e6, 1),
+                          "achieved_GBs": round(ach1, 1), "frac": round(ach1 / HBM_PEAK_GBS, 4),
+                          "avg_launch_ms": round(ms1 / steps, 4)}}
 
 
 def measure_ch(args, torch, W, Sim, n=4096):

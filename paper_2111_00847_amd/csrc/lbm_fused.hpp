@@ -145,6 +145,8 @@ __device__ __forceinline__ OFF pull_fg_at(const KParams<T>& P, const char* src, 
 __device__ __forceinline__ int region_node(int p, int n, bool wall) {
     if (p >= 0 && p < n) return p;
     if (wall) return -1;
+    p = p < 0 ? p + n : p - n;   // one wrap: every lattice at least a few nodes wide
+    if (p >= 0 && p < n) return p;
     const int r = p % n;
     return r < 0 ? r + n : r;
 }

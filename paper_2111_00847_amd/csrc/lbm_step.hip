@@ -373,21 +373,23 @@ static void launch_tile(const KParams<T>& P, char* state, const Layout& L, hipSt
     }
 }
 
-// Two levels per launch for the plain Allen-Cahn step on states the
-// last-level cache holds, once the lattice has at least one 64 x 8 tile per
-// CU (measured on MI355X, FP32, per level: 256 x 1024 7.8 us against 9.0 us
-// one-level, 1024 x 512 15.6 against 16.1; below, where every CU runs at most
-// one short tile, the longer chain of the two-level tile costs more than the
-// launch it saves: 256 x 128 5.1 against 4.8, 64 x 8 4.9 against 4.7).  The
-// environment variable LBM_TWO_LEVEL, read at every call, overrides the size
-// rule: "0" never, "1" on every eligible state whatever its size.  The
-// compile-time LBM_TWO_LEVEL=0 removes the path.
+// Two levels per launch for the plain Allen-Cahn step (lbm_step2.hip) on
+// lattices of at least one 64 x 8 tile per CU whose copy fits 32-bit offsets.
+// Measured on MI355X, FP32, per level: 256 x 1024 (cache-resident) 7.2 us
+// against 9.0 one-level, 1024 x 512 14.4 against 16.1, 4096 x 4096 (streamed
+// from HBM, which the two-level launch crosses once per two levels) 378 against
+// 521; FP64 4096 x 4096 974 against 985.  Below the size rule, where every CU
+// runs at most one short tile, the longer chain of the two-level tile costs
+// more than the launch it saves (256 x 128: 5.1 against 4.8 us, 64 x 8: 4.9
+// against 4.7).  The environment variable LBM_TWO_LEVEL, read at every call,
+// overrides the size rule: "0" never, "1" on every eligible state whatever its
+// size.  The compile-time LBM_TWO_LEVEL=0 removes the path.
 #ifndef LBM_TWO_LEVEL
 #define LBM_TWO_LEVEL 1
 #endif
 
 bool two_level_path(const Layout& L, int nx, int ny, int pf, int model, int grad) {
-    if (!LBM_TWO_LEVEL || pf != 0 || model == 2 || grad != 0 || !resident_state(L)) return false;
+    if (!LBM_TWO_LEVEL || pf != 0 || model == 2 || grad != 0 || L.buf_bytes >= (size_t(1) << 32)) return false;
     const char* e = getenv("LBM_TWO_LEVEL");
     if (e && e[0] == '0' && e[1] == 0) return false;
     if (e && e[0] == '1' && e[1] == 0) return true;

@@ -1,10 +1,12 @@
 // lbm_step2.hip -- two time levels of the Allen-Cahn step (stencil gradients)
-// per launch, for states that the last-level cache holds.
+// per launch.
 //
-// There a one-level launch is bound by its own latency (the load, window,
-// collide, store chain of every tile, and the launch itself) more than by
-// bytes.  A two-level launch pays that chain once for two levels: a tile of
-// 64 x TY nodes advances from level n to n + 2 by
+// On states that the last-level cache holds, a one-level launch is bound by
+// its own latency (the load, window, collide, store chain of every tile, and
+// the launch itself) more than by bytes; on larger states it is bound by HBM,
+// which it crosses once per level.  A two-level launch pays the chain once and
+// crosses HBM once for two levels: a tile of 64 x TY nodes advances from level
+// n to n + 2 by
 //   A. computing level n + 1 (the step of level n) on the tile and a two-node
 //      ring around it: the populations of that region are pulled from the
 //      state, phi of level n on a three-node ring is summed into an LDS
@@ -17,8 +19,10 @@
 // what a one-level step would load back from the copy written by A (the FP32
 // rest population included: it is kept in the stored encoding), so two levels
 // of this launch equal two one-level launches bit for bit.  The ring costs
-// recomputation (the region of A is (64 + 4)(TY + 4) nodes) and L2 reads, not
-// HBM traffic: a launch reads the state once and writes it once for two levels.
+// recomputation (the region of A is (64 + 4)(TY + 4) nodes) and L2 reads of
+// the neighbouring tiles' rows, not HBM traffic beyond those rows: a launch
+// reads the state once and writes it once for two levels.  Stores bypass the
+// caches (non-temporal) on states larger than the last-level cache.
 //
 // A launch writes level n + 2 into the other copy (the level stamps carry the
 // copy, lbm_common.hpp).
@@ -86,7 +90,7 @@ struct Step2Lds {
 
 // Two levels of the tile (xt, yt).  NBY thread rows of 64; every thread owns
 // TY / NBY nodes of the tile in B and up to S positions of A's region.
-template <typename T, int TY, int NBY, bool STD>
+template <typename T, int TY, int NBY, bool STD, bool NTS>
 __global__ __launch_bounds__(TX* NBY) void k_step2(KParams<T> P, char* state, size_t off0, size_t off1,
                                                    size_t off_stamp, int ntx, int nty) {
     using Lds = Step2Lds<T, TY>;
@@ -295,28 +299,35 @@ __global__ __launch_bounds__(TX* NBY) void k_step2(KParams<T> P, char* state, si
         const double f0n = collide_f<T, false, STD>(P, M, fb[r], phb[r]);
         collide_g<T, STD>(P, M, gb);
         const uint32_t k = (uint32_t)y * (uint32_t)P.nx + (uint32_t)x;
-        st<T, uint32_t, false>(dst, k * ES, rest_encode<T>(f0n, M.phi, P.rest_w));
+        st<T, uint32_t, NTS>(dst, k * ES, rest_encode<T>(f0n, M.phi, P.rest_w));
 #pragma unroll
-        for (int i = 1; i < Q; i++) st<T, uint32_t, false>(dst, bF + ((uint32_t)(i - 1) * pl + k) * ES, fb[r][i]);
+        for (int i = 1; i < Q; i++) st<T, uint32_t, NTS>(dst, bF + ((uint32_t)(i - 1) * pl + k) * ES, fb[r][i]);
 #pragma unroll
-        for (int i = 0; i < Q; i++) st<T, uint32_t, false>(dst, bG + ((uint32_t)i * pl + k) * ES, gb[i]);
-        st<T, uint32_t, false>(dst, bH + k * ES, M.phi);
-        st<T, uint32_t, false>(dst, bH + (pl + k) * ES, M.u);
-        st<T, uint32_t, false>(dst, bH + (2 * pl + k) * ES, M.v);
+        for (int i = 0; i < Q; i++) st<T, uint32_t, NTS>(dst, bG + ((uint32_t)i * pl + k) * ES, gb[i]);
+        st<T, uint32_t, NTS>(dst, bH + k * ES, M.phi);
+        st<T, uint32_t, NTS>(dst, bH + (pl + k) * ES, M.u);
+        st<T, uint32_t, NTS>(dst, bH + (2 * pl + k) * ES, M.v);
     }
     // every wave read stamp[0] before the barriers above
     if (tid < TY && y0 + tid < P.ny) stamp[tid] = stamp_of(lev + 2, 1 - cur);
 }
 
+template <typename T, int TY, int NBY, bool STD>
+static void launch_step2_std(const KParams<T>& P, char* state, const Layout& L, hipStream_t s) {
+    const int ntx = (P.nx + TX - 1) / TX, nty = (P.ny + TY - 1) / TY;
+    // the one-level step's store policy: ordinary stores while both copies fit the cache
+    if (cached_state(L))
+        k_step2<T, TY, NBY, STD, false><<<ntx * nty, dim3(TX, NBY), 0, s>>>(P, state, L.off_buf[0], L.off_buf[1],
+                                                                            L.off_stamp, ntx, nty);
+    else
+        k_step2<T, TY, NBY, STD, true><<<ntx * nty, dim3(TX, NBY), 0, s>>>(P, state, L.off_buf[0], L.off_buf[1],
+                                                                           L.off_stamp, ntx, nty);
+}
+
 template <typename T, int TY, int NBY>
 static void launch_step2_ty(const KParams<T>& P, char* state, const Layout& L, hipStream_t s) {
-    const int ntx = (P.nx + TX - 1) / TX, nty = (P.ny + TY - 1) / TY;
-    if (P.rates_std)
-        k_step2<T, TY, NBY, true><<<ntx * nty, dim3(TX, NBY), 0, s>>>(P, state, L.off_buf[0], L.off_buf[1],
-                                                                      L.off_stamp, ntx, nty);
-    else
-        k_step2<T, TY, NBY, false><<<ntx * nty, dim3(TX, NBY), 0, s>>>(P, state, L.off_buf[0], L.off_buf[1],
-                                                                       L.off_stamp, ntx, nty);
+    if (P.rates_std) launch_step2_std<T, TY, NBY, true>(P, state, L, s);
+    else launch_step2_std<T, TY, NBY, false>(P, state, L, s);
 }
 
 // Tile rows of the two-level launch.  8-row tiles (68 KB of LDS in FP32, 136 KB

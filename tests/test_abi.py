@@ -209,9 +209,9 @@ def test_noalloc_batch_step_validates_on_the_host():
 
 def test_levels_per_launch():
     """Two levels per launch exactly for the plain Allen-Cahn step (stencil
-    gradients, present or original model) on a state whose two copies fit the
-    256 MB last-level cache, of at least 256 tiles of 64 x 8 nodes (any size
-    with LBM_TWO_LEVEL=1, none with LBM_TWO_LEVEL=0); one otherwise."""
+    gradients, present or original model) on a lattice whose state copy fits
+    32-bit byte offsets (below 4 GiB), of at least 256 tiles of 64 x 8 nodes
+    (any size with LBM_TWO_LEVEL=1, none with LBM_TWO_LEVEL=0); one otherwise."""
     from paper_2111_00847_amd import _lib
     L = ctypes.CDLL(_lib.LIB_PATH)
 
@@ -224,12 +224,14 @@ def test_levels_per_launch():
     assert levels(nx=256, ny=512, dtype="f32") == 2       # 4 x 64 tiles
     assert levels(nx=256, ny=504, dtype="f32") == 1       # 4 x 63 tiles
     assert levels(nx=64, ny=64, dtype="f32") == 1
+    assert levels(nx=4096, ny=4096, dtype="f32") == 2     # streamed from HBM
     os.environ["LBM_TWO_LEVEL"] = "0"
     try:
         assert levels(nx=256, ny=1024, dtype="f32") == 1
+        assert levels(nx=4096, ny=4096, dtype="f32") == 1
         os.environ["LBM_TWO_LEVEL"] = "1"
         assert levels(nx=64, ny=64, dtype="f32") == 2
-        assert levels(nx=2048, ny=1024, dtype="f32") == 1   # still only on cache-resident states
+        assert levels(nx=51200, ny=1024, dtype="f32") == 1  # a copy of 4 GiB and more
     finally:
         os.environ["LBM_TWO_LEVEL"] = "1"
 
@@ -242,9 +244,9 @@ def test_levels_per_launch():
     assert levels(nx=256, ny=1024, model="corrected", **f32) == 1
     assert levels(nx=256, ny=1024, grad_scheme="local", **f32) == 1
     assert levels(nx=256, ny=1024, phase_eq="cahn_hilliard", phiA=1.0, phiB=-1.0, **f32) == 1
-    assert levels(nx=1024, ny=1024, **f32) == 2            # 2 x 88 MB
-    assert levels(nx=2048, ny=1024, **f32) == 1            # 2 x 176 MB: streamed from HBM
-    assert levels(nx=1024, ny=1024, dtype="f64") == 1
+    assert levels(nx=2048, ny=1024, **f32) == 2            # 2 x 176 MB: streamed from HBM
+    assert levels(nx=4096, ny=4096, dtype="f64") == 2      # 2 x 2.8 GB
+    assert levels(nx=8192, ny=4096, dtype="f64") == 1      # 2 x 5.6 GB
     os.environ.pop("LBM_TWO_LEVEL", None)
     v = ctypes.c_int32()
     assert L.lbm_levels_per_launch(None, ctypes.byref(v)) == -1

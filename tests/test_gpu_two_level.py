@@ -1,15 +1,15 @@
 """Two levels per launch against two one-level launches.
 
-On a state that the last-level cache holds, the plain Allen-Cahn step (stencil
-gradients, present or original model) advances two levels per launch; an odd
-level count ends on a one-level launch.  Advancing one state n levels by one
+The plain Allen-Cahn step (stencil gradients, present or original model)
+advances two levels per launch; an odd level count ends on a one-level launch.  Advancing one state n levels by one
 lbm_step call and a copy of it one level per call therefore runs the two kernels
 on the same input.  The two must agree bit for bit on every population and
 history value (the two-level launch computes its first level with the
 one-level step's device functions and hands the second exactly what the copy
 would hold), from level 0 (no history yet) and from an odd level, in FP32 and
 FP64, on periodic and walled lattices (wetting walls at four contact angles),
-ragged tiles, and lattices narrower than the launch's region.
+ragged tiles, lattices narrower than the launch's region, and states larger
+than the last-level cache (streamed, with non-temporal stores).
 """
 import math
 import os
@@ -49,6 +49,9 @@ def _cases():
             out[f"random_{nx}x{ny}{'_walls_' + walls if walls else ''}_{dtype}"] = _random(nx, ny, dtype, **kw)
     # 16-row tiles of the two-level launch (3 x 80 of them), ragged in x and y
     out["random_190x1270_walls_xy_f32"] = _random(190, 1270, "f32", wall_x=True, wall_y=True)
+    # states streamed from HBM (two copies above the 320 MB cache bound: non-temporal stores), ragged tiles
+    out["random_2050x1030_walls_y_f32"] = _random(2050, 1030, "f32", wall_y=True)
+    out["random_1030x1030_walls_x_f64"] = _random(1030, 1030, "f64", wall_x=True)
     case, phi0, u0, p0 = _random(96, 40, "f32", wall_y=True)
     out["random_96x40_walls_y_original_f32"] = (case.replace(model="original"), phi0, u0, p0)
     case, phi0, u0, p0 = _random(96, 40, "f64", wall_x=True)
