@@ -33,9 +33,12 @@ The JSON line also carries:
                   next to the bandwidth of torch's own device copy and of the
                   streaming probe; large_grid_fp64 the FP64 kernels there;
   batched      -- 64 droplet-spreading cases of uneven sizes (Sec. 4.3 set-up,
-                  FP32): one autotuned persistent launch per step replayed from a
-                  captured graph, against the same cases advanced one after
-                  another with the plain step (graph-captured, and eager);
+                  FP32): one launch per two levels over all cases (the
+                  two-level batch kernel; the autotuned one-level launch for an
+                  odd tail) replayed from a captured graph, against the same
+                  cases advanced one after another with the plain step
+                  (graph-captured, and eager); `batched_frac` counts the
+                  algorithmic 168 B per update;
   square_droplet -- total-phi drift and max |div u| of the 64 x 64 square
                   droplet after 2000 FP64 steps;
   cahn_hilliard -- the Cahn-Hilliard variant's step kernel on a 4096 x 4096
@@ -62,7 +65,8 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 ALG_BYTES = {"f32": 168, "f64": 336}   # per lattice update: f, g read+write, (phi, u, v) history read+write
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "k_step2_rti_256x1024_traffic.json")
 # everything the headline's two-level kernel is compiled from (with the build flags)
-KERNEL_SOURCES = ["paper_2111_00847_amd/csrc/lbm_step2.hip", "paper_2111_00847_amd/csrc/lbm_fused.hpp",
+KERNEL_SOURCES = ["paper_2111_00847_amd/csrc/lbm_step2.hip", "paper_2111_00847_amd/csrc/lbm_step2.hpp",
+                  "paper_2111_00847_amd/csrc/lbm_fused.hpp",
                   "paper_2111_00847_amd/csrc/lbm_tile.hpp", "paper_2111_00847_amd/csrc/lbm_device.hpp",
                   "paper_2111_00847_amd/csrc/lbm_common.hpp", "paper_2111_00847_amd/build.py"]
 
@@ -363,6 +367,7 @@ def measure_batched(args, torch, W, Sim, BatchSim):
     B.step(64)
     ms_b = _timed(s, torch, lambda: B.step(K))
     tun = B.tuning()
+    levels = B.levels_per_launch()
     nonfinite = sum(B.case(c).diagnostics()["nonfinite"] for c in range(len(cases)))
     assert nonfinite == 0, "non-finite batched state"
     del B
@@ -380,7 +385,7 @@ def measure_batched(args, torch, W, Sim, BatchSim):
             "sequential_eager_MLUPS": mlups(ms_e), "speedup_vs_sequential_graph": round(ms_g / ms_b, 3),
             "speedup_vs_sequential_eager": round(ms_e / ms_b, 3),
             "batched_frac": round(ALG_BYTES["f32"] * nodes * K / (ms_b * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-            "tuning": tun}
+            "levels_per_launch": levels, "tuning": tun}
 
 
 def measure_adjoint(args, torch, W, Sim):

@@ -261,7 +261,12 @@ int lbm_adjoint_import(const lbm_params *p, void *adj, const void *fbar, const v
  * batch kernels address a case with 32-bit offsets).  Batches holding Cahn-Hilliard,
  * corrected Allen-Cahn or local-gradient cases run 64 x 4-thread tiles of 4
  * or 8 rows; those cases equal the lone runs to rounding (the tile height may
- * differ), the plain Allen-Cahn cases bitwise.  The plan is
+ * differ), the plain Allen-Cahn cases bitwise.  A batch whose every case runs
+ * the plain Allen-Cahn step (stencil gradients, present or original model)
+ * advances two levels per launch as lbm_step does (64 x 8 tiles; an odd step
+ * count ends on a one-level launch) when it has at least 256 such tiles, or
+ * whatever its size with LBM_TWO_LEVEL=1 in the environment when the plan is
+ * made (never with LBM_TWO_LEVEL=0).  The plan is
  * library-owned (a small device table of the cases and, once lbm_batch_step
  * runs on a non-NULL stream with nsteps >= 32 that the caller is not
  * capturing, a captured hipGraph of 32 steps for that state and stream). */
@@ -287,6 +292,8 @@ int lbm_batch_step(lbm_batch *batch, void *state, int64_t nsteps, void *stream);
  * per launch, work items per step (any pointer may be NULL). */
 int lbm_batch_tuning(const lbm_batch *batch, int32_t *tile_rows, int32_t *thread_rows, int32_t *grid,
                      int32_t *items);
+/* Levels one launch of the plan advances (1 or 2; host *levels). */
+int lbm_batch_levels_per_launch(const lbm_batch *batch, int32_t *levels);
 int lbm_batch_destroy(lbm_batch *batch);
 
 /* ---- a batch step that allocates nothing ----------------------------------
@@ -296,7 +303,8 @@ int lbm_batch_destroy(lbm_batch *batch);
  * lbm_batch_case_offset give for the same cases, initialised by
  * lbm_batch_init or by lbm_init of every case at its offset) exactly as
  * lbm_batch_step does with an untuned plan of the same cases (8-row tiles,
- * one workgroup per work item), without a plan and without allocating: the
+ * one workgroup per work item, two levels per launch under the same rule,
+ * LBM_TWO_LEVEL read at every call), without a plan and without allocating: the
  * case table (at most LBM_NOALLOC_MAX_CASES cases, about 140 KB) lives in a
  * fixed device array of the library that every GPU it runs on holds until
  * the process ends; the call writes it with small kernels on `stream` before

@@ -78,6 +78,7 @@ _SIGS = {
     "lbm_batch_init": [vp, vp, P(vp), P(vp), vp],
     "lbm_batch_step": [vp, vp, ctypes.c_int64, vp],
     "lbm_batch_tuning": [vp, P(ctypes.c_int32), P(ctypes.c_int32), P(ctypes.c_int32), P(ctypes.c_int32)],
+    "lbm_batch_levels_per_launch": [vp, P(ctypes.c_int32)],
     "lbm_batch_destroy": [vp],
     "lbm_batch_step_noalloc": [P(LbmParams), ctypes.c_int32, vp, ctypes.c_int64, vp],
     "lbm_bandwidth_probe": [ctypes.c_int32, vp, vp, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32, vp],

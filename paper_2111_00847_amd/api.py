@@ -291,5 +291,11 @@ def lbm_batch_tuning(batch):
     return dict(tile_rows=ty.value, thread_rows=by.value, grid=g.value, items=items.value)
 
 
+def lbm_batch_levels_per_launch(batch):
+    v = ctypes.c_int32()
+    call("lbm_batch_levels_per_launch", batch, ctypes.byref(v))
+    return v.value
+
+
 def lbm_batch_destroy(batch):
     call("lbm_batch_destroy", batch)

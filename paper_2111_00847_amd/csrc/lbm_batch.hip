@@ -13,9 +13,13 @@
 // Batches that hold Cahn-Hilliard or corrected Allen-Cahn cases (the
 // two-node-window body of lbm_ch_step.hpp) or local-gradient cases
 // (lbm_local_step.hpp) run a second kernel whose LDS holds any of the windows;
-// each item runs its case's body.
+// each item runs its case's body.  Batches whose every case runs the plain
+// Allen-Cahn step (stencil gradients, present or original model) advance two
+// levels per launch, as a single lattice does (lbm_step2.hpp; bitwise two
+// one-level steps), with an odd step count ending on a one-level launch.
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <vector>
@@ -25,6 +29,7 @@
 #include "lbm_fused.hpp"
 #include "lbm_kernels.hpp"
 #include "lbm_local_step.hpp"
+#include "lbm_step2.hpp"
 
 namespace lbm {
 
@@ -61,13 +66,16 @@ __device__ __forceinline__ int batch_case(const BatchCase<T>* __restrict__ cases
 }
 
 // NT: non-temporal state stores (the batch's state exceeds the last-level
-// cache); ordinary ones otherwise, as for a single lattice.
-template <typename T, int TY, int NBY, bool NT>
+// cache); ordinary ones otherwise, as for a single lattice.  LOOP: a
+// persistent grid (items b, b + G, ...); without it one item per workgroup,
+// whose body needs fewer registers (60 against 92 VGPRs for 64 x 4 tiles in
+// FP32: 8 waves per SIMD against 5).
+template <typename T, int TY, int NBY, bool NT, bool LOOP = true>
 __global__ __launch_bounds__(TX* NBY) __attribute__((amdgpu_waves_per_eu(StepWaves<T, TY, NBY>::value)))
 void k_step_batch(const BatchCase<T>* __restrict__ cases, int ncases, int nitems, char* batch_state) {
     __shared__ T sphi[TY + 2][TX + 3];
     __shared__ T sphp[TY + 2][TX + 3];
-    for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
+    auto item = [&](int w) {
         const BatchCase<T>& C = cases[batch_case(cases, ncases, w, TX * NBY)];
         const int local = w - C.item_begin;
         // the collision specialisation the case runs alone (lbm_step), so that it stays bitwise
@@ -77,8 +85,35 @@ void k_step_batch(const BatchCase<T>* __restrict__ cases, int ncases, int nitems
         else
             step_tile<T, TY, 0, uint32_t, NBY, false, NT>(C.P, batch_state + C.base, C.off0, C.off1, C.off_stamp,
                                                       local % C.ntx, local / C.ntx, nullptr, nullptr, nullptr, sphi, sphp);
-        __syncthreads();   // the next item reuses the LDS window
+    };
+    if constexpr (LOOP) {
+        for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
+            item(w);
+            __syncthreads();   // the next item reuses the LDS window
+        }
+    } else if ((int)blockIdx.x < nitems) {   // uniform over the workgroup
+        item(blockIdx.x);
     }
+}
+
+// Two levels per launch: work item blockIdx.x, one 64 x 8 tile of one case, per
+// workgroup of 64 x 8 threads (items of a case table for 8-row tiles).  One
+// item per workgroup: a loop over items (a persistent grid) doubles the
+// registers of the body (169 against 86 VGPRs in FP32).
+template <typename T, bool NTS>
+__global__ __launch_bounds__(TX * 8) void k_step2_batch(const BatchCase<T>* __restrict__ cases, int ncases,
+                                                       int nitems, char* batch_state) {
+    __shared__ Step2Lds<T, 8> L;
+    const int w = blockIdx.x;
+    if (w >= nitems) return;   // uniform over the workgroup
+    const BatchCase<T>& C = cases[batch_case(cases, ncases, w, TX * 8)];
+    const int local = w - C.item_begin;
+    if (C.P.rates_std)
+        step2_tile<T, 8, 8, true, NTS>(C.P, batch_state + C.base, C.off0, C.off1, C.off_stamp, local % C.ntx,
+                                       local / C.ntx, L);
+    else
+        step2_tile<T, 8, 8, false, NTS>(C.P, batch_state + C.base, C.off0, C.off1, C.off_stamp, local % C.ntx,
+                                        local / C.ntx, L);
 }
 
 // Batches with two-node-window or local-gradient cases: 64 x 4 threads, the
@@ -145,7 +180,12 @@ struct lbm_batch {
     int nitems = 0;
     void* d_cases = nullptr;
     int cus = 256;
-    // graph of `graph_steps` launches for (graph_state, graph_stream)
+    // two levels per launch (every case runs the plain Allen-Cahn step), on a
+    // case table of 8-row tiles
+    bool two_level = false;
+    void* d_cases2 = nullptr;
+    int nitems2 = 0;
+    // graph of `graph_steps` levels for (graph_state, graph_stream)
     hipGraphExec_t graph = nullptr;
     void* graph_state = nullptr;
     hipStream_t graph_stream = nullptr;
@@ -196,6 +236,16 @@ hipError_t upload_cases(lbm_batch* B, int ty) {
     return hipMemcpy(B->d_cases, h.data(), sizeof(BatchCase<T>) * B->ncases, hipMemcpyHostToDevice);
 }
 
+// The case table of the two-level launch (8-row tiles).
+template <typename T>
+hipError_t upload_cases2(lbm_batch* B) {
+    std::vector<BatchCase<T>> h(B->ncases);
+    B->nitems2 = fill_cases<T>(B->params.data(), B->layouts.data(), B->base.data(), B->ncases, 8, h.data());
+    hipError_t e = hipMalloc(&B->d_cases2, sizeof(BatchCase<T>) * B->ncases);
+    if (e != hipSuccess) return e;
+    return hipMemcpy(B->d_cases2, h.data(), sizeof(BatchCase<T>) * B->ncases, hipMemcpyHostToDevice);
+}
+
 // One launch of the batch kernels over `nitems` work items of a device case
 // table (grid 0: one workgroup per item).
 struct BatchShape {
@@ -206,12 +256,15 @@ struct BatchShape {
 
 template <typename T, int TY, int NBY>
 void batch_launch(const BatchShape& S, const void* d_cases, char* state, hipStream_t s) {
-    const int g = S.grid > 0 ? S.grid : S.nitems;
     const BatchCase<T>* cases = reinterpret_cast<const BatchCase<T>*>(d_cases);
-    if (S.total <= (size_t)LBM_NT_MIN_BYTES)
-        k_step_batch<T, TY, NBY, false><<<g, dim3(TX, NBY), 0, s>>>(cases, S.ncases, S.nitems, state);
-    else
-        k_step_batch<T, TY, NBY, true><<<g, dim3(TX, NBY), 0, s>>>(cases, S.ncases, S.nitems, state);
+    const bool nt = S.total > (size_t)LBM_NT_MIN_BYTES;
+    if (S.grid > 0 && S.grid < S.nitems) {
+        if (nt) k_step_batch<T, TY, NBY, true><<<S.grid, dim3(TX, NBY), 0, s>>>(cases, S.ncases, S.nitems, state);
+        else k_step_batch<T, TY, NBY, false><<<S.grid, dim3(TX, NBY), 0, s>>>(cases, S.ncases, S.nitems, state);
+    } else {
+        if (nt) k_step_batch<T, TY, NBY, true, false><<<S.nitems, dim3(TX, NBY), 0, s>>>(cases, S.ncases, S.nitems, state);
+        else k_step_batch<T, TY, NBY, false, false><<<S.nitems, dim3(TX, NBY), 0, s>>>(cases, S.ncases, S.nitems, state);
+    }
 }
 
 template <typename T, int TY>
@@ -248,6 +301,27 @@ void launch_batch_once(lbm_batch* B, char* state, hipStream_t s) {
     launch_batch_shape<T>(S, B->d_cases, state, s);
 }
 
+// One two-level launch over `nitems` items of a case table for 8-row tiles.
+template <typename T>
+void launch_batch2(int nitems, int ncases, const void* d_cases, size_t total, char* state, hipStream_t s) {
+    const BatchCase<T>* cases = reinterpret_cast<const BatchCase<T>*>(d_cases);
+    if (total <= (size_t)LBM_NT_MIN_BYTES)
+        k_step2_batch<T, false><<<nitems, dim3(TX, 8), 0, s>>>(cases, ncases, nitems, state);
+    else
+        k_step2_batch<T, true><<<nitems, dim3(TX, 8), 0, s>>>(cases, ncases, nitems, state);
+}
+
+// `n` levels of the batch: two-level launches, and a one-level launch for an odd n.
+template <typename T>
+void launch_batch_levels(lbm_batch* B, char* state, int64_t n, hipStream_t s) {
+    if (B->two_level) {
+        for (int64_t t = 0; t + 2 <= n; t += 2) launch_batch2<T>(B->nitems2, B->ncases, B->d_cases2, B->total, state, s);
+        if (n & 1) launch_batch_once<T>(B, state, s);
+    } else {
+        for (int64_t t = 0; t < n; t++) launch_batch_once<T>(B, state, s);
+    }
+}
+
 void drop_graph(lbm_batch* B) {
     if (B->graph) (void)hipGraphExecDestroy(B->graph);
     B->graph = nullptr;
@@ -272,7 +346,7 @@ int batch_step_t(lbm_batch* B, char* state, int64_t nsteps, hipStream_t s) {
             hipGraph_t g;
             e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
             if (e != hipSuccess) return hip_fail(e);
-            for (int k = 0; k < K; k++) launch_batch_once<T>(B, state, s);
+            launch_batch_levels<T>(B, state, K, s);
             e = hipStreamEndCapture(s, &g);
             if (e != hipSuccess) return hip_fail(e);
             e = hipGraphInstantiate(&B->graph, g, nullptr, nullptr, 0);
@@ -288,7 +362,7 @@ int batch_step_t(lbm_batch* B, char* state, int64_t nsteps, hipStream_t s) {
         }
         nsteps %= K;
     }
-    for (int64_t t = 0; t < nsteps; t++) launch_batch_once<T>(B, state, s);
+    launch_batch_levels<T>(B, state, nsteps, s);
     e = hipGetLastError();
     return e == hipSuccess ? LBM_OK : hip_fail(e);
 }
@@ -385,6 +459,27 @@ bool wide_batch(const lbm_params* cases, int ncases) {
     return w;
 }
 
+// Two levels per launch: every case runs the plain Allen-Cahn step (stencil
+// gradients, present or original model) and the batch has at least 256 tiles
+// of 64 x 8 nodes, the size rule of a single lattice (lbm_step.hip).  The
+// environment variable LBM_TWO_LEVEL, read when a plan is made (and at every
+// call of the allocation-free step), overrides the size rule: "0" never, "1"
+// whatever the size.
+bool two_level_batch(const lbm_params* cases, int ncases) {
+    long long tiles8 = 0;
+    for (int c = 0; c < ncases; c++) {
+        const lbm_params& q = cases[c];
+        if (q.phase_eq != LBM_ALLEN_CAHN || q.model == LBM_MODEL_CORRECTED || q.grad_scheme != LBM_GRAD_STENCIL)
+            return false;
+        int ntx, nty;
+        tiles8 += tiles_for(q, 8, &ntx, &nty);
+    }
+    const char* e = getenv("LBM_TWO_LEVEL");
+    if (e && e[0] == '0' && e[1] == 0) return false;
+    if (e && e[0] == '1' && e[1] == 0) return true;
+    return tiles8 >= 256;
+}
+
 // ---- the batch step that allocates nothing (lbm_batch_step_noalloc) ----
 // Its case table lives in `scratch`, a fixed array of the library in every
 // GPU's memory.  In host code `scratch` only names the symbol: the kernels get
@@ -441,7 +536,8 @@ int batch_step_noalloc_t(const lbm_params* cases, int ncases, char* state, int64
     hipError_t e = scratch_address(&dtab);
     if (e != hipSuccess) return hip_fail(e);
     BatchCase<T>* table = reinterpret_cast<BatchCase<T>*>(dtab);
-    // the untuned plan's shape: 8-row tiles, 64 x 4 threads, one workgroup per item
+    // the untuned plan's shape: 8-row tiles, 64 x 4 threads, one workgroup per
+    // item; the same table serves the two-level launch (8-row tiles too)
     const int ty = 8;
     CaseChunk<T> chunk;
     int nitems = 0;
@@ -456,7 +552,10 @@ int batch_step_noalloc_t(const lbm_params* cases, int ncases, char* state, int64
         k_put_cases<T><<<1, 64, 0, s>>>(chunk, table);
     }
     const BatchShape S{ty, 4, 0, nitems, ncases, wide_batch(cases, ncases), total};
-    for (int64_t t = 0; t < nsteps; t++) launch_batch_shape<T>(S, table, state, s);
+    int64_t t = 0;
+    if (two_level_batch(cases, ncases))
+        for (; t + 2 <= nsteps; t += 2) launch_batch2<T>(nitems, ncases, table, total, state, s);
+    for (; t < nsteps; t++) launch_batch_shape<T>(S, table, state, s);
     e = hipGetLastError();
     return e == hipSuccess ? LBM_OK : hip_fail(e);
 }
@@ -485,6 +584,8 @@ int lbm_batch_create(const lbm_params* cases, int32_t ncases, int32_t autotune, 
     B->ty = 8;
     B->grid = 0;
     hipError_t e = B->dtype == LBM_F32 ? upload_cases<float>(B, B->ty) : upload_cases<double>(B, B->ty);
+    B->two_level = two_level_batch(cases, ncases);
+    if (e == hipSuccess && B->two_level) e = B->dtype == LBM_F32 ? upload_cases2<float>(B) : upload_cases2<double>(B);
     if (e != hipSuccess) {
         lbm_batch_destroy(B);
         return hip_fail(e);
@@ -552,10 +653,17 @@ int lbm_batch_tuning(const lbm_batch* B, int32_t* tile_rows, int32_t* thread_row
     return LBM_OK;
 }
 
+int lbm_batch_levels_per_launch(const lbm_batch* B, int32_t* levels) {
+    if (!B || !levels) return LBM_E_NULL;
+    *levels = B->two_level ? 2 : 1;
+    return LBM_OK;
+}
+
 int lbm_batch_destroy(lbm_batch* B) {
     if (!B) return LBM_E_NULL;
     drop_graph(B);
     if (B->d_cases) (void)hipFree(B->d_cases);
+    if (B->d_cases2) (void)hipFree(B->d_cases2);
     delete B;
     return LBM_OK;
 }

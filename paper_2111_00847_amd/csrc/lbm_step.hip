@@ -25,8 +25,14 @@
 
 namespace lbm {
 
-// Steps start their loads on the copy of the host's parity guess `hint` while
-// the level stamp is read (step_core); LBM_PARITY_HINT=0 reads the stamp first.
+// Steps on states that the last-level cache holds (NT false) start their loads
+// on the copy of the host's parity guess `hint` while the level stamp is read
+// (step_core); LBM_PARITY_HINT=0 reads the stamp first there too.  States
+// streamed from HBM always read the stamp first: a wrong guess would cost a
+// whole extra copy of HBM reads (the guess is wrong after every replay of a
+// captured graph of an odd number of launches, 1.5x the step time measured on
+// 4096 x 4096 FP32), while the stamp read costs a tile little next to its
+// stream of loads.
 #ifndef LBM_PARITY_HINT
 #define LBM_PARITY_HINT 1
 #endif
@@ -44,7 +50,7 @@ void k_step(KParams<T> P, char* state, size_t off0, size_t off1, size_t off_stam
         xt = blockIdx.x % ntx;
         yt = blockIdx.x / ntx;
     }
-    step_tile<T, TY, MODE, OFF, NBY, STD, NT, LATE_G, MODE == 0 && LBM_PARITY_HINT>(
+    step_tile<T, TY, MODE, OFF, NBY, STD, NT, LATE_G, MODE == 0 && LBM_PARITY_HINT && !NT>(
         P, state, off0, off1, off_stamp, xt, yt, out_phi, out_u, out_p, sphi, sphp, hint);
 }
 

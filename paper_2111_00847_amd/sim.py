@@ -150,6 +150,9 @@ class BatchSim:
     def tuning(self):
         return api.lbm_batch_tuning(self.handle)
 
+    def levels_per_launch(self):
+        return api.lbm_batch_levels_per_launch(self.handle)
+
     def case(self, c):
         """Sim view of case c (its state lives inside the batch state)."""
         off = api.lbm_batch_case_offset(self.handle, c)

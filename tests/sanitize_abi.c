@@ -154,6 +154,7 @@ int main(void) {
     EXPECT(lbm_batch_state_size(NULL, &n), LBM_E_NULL);
     EXPECT(lbm_batch_step(NULL, NULL, 1, NULL), LBM_E_NULL);
     EXPECT(lbm_batch_destroy(NULL), LBM_E_NULL);
+    EXPECT(lbm_batch_levels_per_launch(NULL, &lv), LBM_E_NULL);
     lbm_params* many = (lbm_params*)malloc(sizeof(lbm_params) * 257);
     for (int c = 0; c < 257; c++) many[c] = p;
     EXPECT(lbm_batch_step_noalloc(many, 257, fake, 1, NULL), LBM_E_SIZE);

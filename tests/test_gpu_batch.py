@@ -61,6 +61,54 @@ def test_batch_bitwise_equals_single(dtype, mode):
     assert d["nonfinite"] == 0
 
 
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("mode", ["eager_default_stream", "graph_side_stream", "autotuned_graph"])
+def test_batch_two_level_bitwise_equals_single(dtype, mode):
+    """Plain Allen-Cahn batches advance two levels per launch (forced here on a
+    batch below the size rule); 75 steps end on a one-level launch.  Every case
+    equals its lone run bit for bit, and a batch with a Cahn-Hilliard case
+    keeps one level per launch."""
+    import os
+    Sim, BatchSim = _mods()
+    cases = _mixed_cases(dtype)
+    p0s = ["hydrostatic"] * len(cases)
+    stream = None if mode == "eager_default_stream" else torch.cuda.Stream()
+    os.environ["LBM_TWO_LEVEL"] = "1"
+    try:
+        B = BatchSim([c for c, _ in cases], autotune=(mode == "autotuned_graph"), stream=stream)
+        ch, php = W.to_cahn_hilliard(*W.static_droplet(n=40, R=10.0, dtype=dtype))
+        mixed = BatchSim([cases[0][0], ch], stream=stream)
+    finally:
+        os.environ.pop("LBM_TWO_LEVEL", None)
+    assert B.levels_per_launch() == 2
+    assert mixed.levels_per_launch() == 1
+    del mixed
+    B.init([p for _, p in cases], p0s)
+    steps = 75                         # two graph replays of 32 plus 11 eager levels
+    B.step(steps)
+    for c, ((case, phi0), p0) in enumerate(zip(cases, p0s)):
+        alone = Sim(case).init(phi0, None, p0).step(steps)
+        torch.cuda.synchronize()
+        _assert_same_state(B.case(c), alone, f"case {c} {case.name}")
+    assert B.case(2).diagnostics()["nonfinite"] == 0
+
+
+def test_batch_spreading_64_two_level_by_size_rule():
+    """The 64-case spreading batch (3.3 M nodes) takes two levels per launch by
+    the size rule, and stays bitwise equal to lone runs of a few of its cases."""
+    Sim, BatchSim = _mods()
+    cases = W.spreading_batch()
+    B = BatchSim([c for c, _ in cases], stream=torch.cuda.Stream()).init([p for _, p in cases])
+    assert B.levels_per_launch() == 2
+    steps = 41
+    B.step(steps)
+    for c in (0, 17, 63):
+        case, phi0 = cases[c]
+        alone = Sim(case).init(phi0).step(steps)
+        torch.cuda.synchronize()
+        _assert_same_state(B.case(c), alone, f"spreading case {c}")
+
+
 def test_batch_fp64_against_oracle():
     Sim, BatchSim = _mods()
     cases = _mixed_cases("f64")[:3]

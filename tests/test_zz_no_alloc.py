@@ -60,6 +60,26 @@ def test_noalloc_batch_step_equals_planned_step(dtype):
         torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_noalloc_two_level_batch_step_equals_planned_step(dtype):
+    """Plain Allen-Cahn batches with two levels per launch forced on (both
+    paths read LBM_TWO_LEVEL): odd step counts end on a one-level launch."""
+    import os
+    os.environ["LBM_TWO_LEVEL"] = "1"
+    try:
+        for small, steps in ((False, 23), (True, 17)):
+            cases = _mixed_cases(dtype, small)[:4 if not small else 2]
+            print(f"noalloc two-level batch {dtype}: {len(cases)} cases, {steps} steps", flush=True)
+            B, other = _run_both(cases, steps)
+            assert B.levels_per_launch() == 2
+            assert torch.equal(B.state, other), "no-alloc two-level batch step differs from the planned batch step"
+            assert B.case(0).diagnostics()["nonfinite"] == 0
+            del B, other
+            torch.cuda.empty_cache()
+    finally:
+        os.environ.pop("LBM_TWO_LEVEL", None)
+
+
 def test_noalloc_rejects_oversized_batches():
     from paper_2111_00847_amd import api
     from paper_2111_00847_amd._lib import LbmError
