@@ -3,8 +3,9 @@
 //
 // Tape.  A segment of the forward trajectory, levels n0 .. n0 + L - 1, each
 // one state copy (the same bytes as a ping-pong copy), recorded by running the
-// ordinary step body from slot j into slot j + 1, so that its levels are
-// bitwise those of the plain path.
+// step bodies of lbm_step from slot j into slot j + 1 (the two-level body from
+// slot j into slots j + 1 and j + 2 where lbm_step takes two levels per
+// launch), so that its levels are bitwise those of the plain path.
 //
 // Adjoint.  The adjoint of level n holds dL/df^n and dL/dg^n of the
 // post-streaming populations and dL/d(phi, u, v) of the history stored at
@@ -38,6 +39,8 @@
 #include "../../include/lbm.h"
 #include "lbm_adjoint.hpp"
 #include "lbm_fused.hpp"
+#include "lbm_kernels.hpp"
+#include "lbm_step2.hpp"
 
 namespace lbm {
 
@@ -190,6 +193,21 @@ void k_tape_step(KParams<T> P, char* tape, size_t slot, int j, int ntx, int nty)
     int xt, yt;
     xcd_tile(blockIdx.x, ntx, nty, xt, yt);
     step_core<T, TY, 0, OFF, NBY, STD, NT>(P, src, src + slot, n, xt, yt, nullptr, nullptr, nullptr, sphi, sphp);
+}
+
+// Two tape levels per launch (lbm_step2.hpp): slot j to slot j + 1 (the
+// intermediate level, stored non-temporally: the adjoint reads it back later)
+// and slot j + 2, on the lattices where lbm_step takes two levels per launch;
+// bitwise the levels of two k_tape_step launches.
+template <typename T, int TY, int NBY, bool STD, bool NTS>
+__global__ __launch_bounds__(TX* NBY) void k_tape_step2(KParams<T> P, char* tape, size_t slot, int j, int ntx,
+                                                         int nty) {
+    __shared__ Step2Lds<T, TY> L;
+    const int64_t n = reinterpret_cast<const TapeHeader*>(tape)->n0 + j;
+    char* src = tape + TAPE_HDR + (size_t)j * slot;
+    int xt, yt;
+    xcd_tile(blockIdx.x, ntx, nty, xt, yt);
+    step2_mid<T, TY, NBY, STD, NTS>(P, src, src + slot, src + 2 * slot, n, xt, yt, L);
 }
 
 // ---------------------------------------------------------------- adjoint step, kernel A
@@ -449,10 +467,10 @@ template <typename T>
 __global__ __launch_bounds__(TX* BY) void k_adj_gather(KParams<T> P, const char* tape, int j, AdjView<T> V) {
     constexpr int WX = TX + 2, WY = BTY + 2;
     __shared__ T sw[5][WY][WX + 1];   // gx, gy, lap of phi^n; gx, gy of phi^{n-1}
+    // the header and status are read with the staging loads (all of valid
+    // memory); the status gates the stores
     const int64_t n = reinterpret_cast<const TapeHeader*>(tape)->n0 + j;
-    if (V.hdr()->status != 0) return;
-    const bool first = n == 0;
-    const int co = (int)(n & 1);
+    const int32_t status = V.hdr()->status;
     const int ntx = (P.nx + TX - 1) / TX;
     int xt, yt;   // tiles dealt to the XCDs as kernel A deals its own
     xcd_tile(blockIdx.x, ntx, V.ntB / ntx, xt, yt);
@@ -473,13 +491,12 @@ __global__ __launch_bounds__(TX* BY) void k_adj_gather(KParams<T> P, const char*
         }
         const long long k = (long long)gy * P.nx + gx;
 #pragma unroll
-        for (int q = 0; q < 3; q++) sw[q][wy][wx] = none ? T(0) : src[q][k];
-        if (!first) {
-#pragma unroll
-            for (int q = 3; q < 5; q++) sw[q][wy][wx] = none ? T(0) : src[q][k];
-        }
+        for (int q = 0; q < 5; q++) sw[q][wy][wx] = none ? T(0) : src[q][k];
     }
     __syncthreads();
+    if (status != 0) return;
+    const bool first = n == 0;
+    const int co = (int)(n & 1);
     if (blockIdx.x == 0 && tid == 0) V.hdr()->level = n;
     const int lx = threadIdx.x, ly = threadIdx.y;
     const int x = x0 + lx, y = y0 + ly;
@@ -545,44 +562,54 @@ template <typename T>
 __global__ __launch_bounds__(GHOST_THREADS) void k_adj_ghosts(KParams<T> P, const char* tape, size_t slot, int j,
                                                              AdjView<T> V) {
     __shared__ double red[4][GHOST_THREADS / 64];
+    // A chain of a few dependent loads per item bounds this kernel: the
+    // header, the status and the workgroup's parameter slots are read together
+    // with the items' first loads (every item of both levels reads valid
+    // memory), and the status gates the stores instead of the loads.
     const int64_t n = reinterpret_cast<const TapeHeader*>(tape)->n0 + j;
-    if (V.hdr()->status != 0) return;
-    const bool first = n == 0;
+    const int32_t status = V.hdr()->status;
+    double* pth = V.part + 2 * V.ntA + 4 * blockIdx.x;
+    double pold[4] = {0.0, 0.0, 0.0, 0.0};
+    if (threadIdx.x == 0)
+        for (int q = 0; q < 4; q++) pold[q] = pth[q];
     const Copy<T> S = copy_at<T>(const_cast<char*>(tape + TAPE_HDR + (size_t)j * slot), P.plane);
     const long long per = ghost_items(P.nx, P.ny, P.wall_x, P.wall_y);
     const long long ny2 = P.wall_y ? 2LL * P.nx : 0LL;
     double th[4] = {0.0, 0.0, 0.0, 0.0};
-    for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < (first ? 1 : 2) * per;
+    for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < 2 * per;
          idx += (long long)gridDim.x * blockDim.x) {
         const int lev = (int)(idx / per);
         const long long it = idx - lev * per;
         const T* phi = lev ? S.h : V.s(S_PHI);
+        int wall, at;
+        T d1, d2, dth, q, cth = T(0), qc = T(0);
         if (it < ny2) {   // y-wall ghost (x, -1) or (x, ny)
             const int sy = (int)(it / P.nx), x = (int)(it - (long long)sy * P.nx);
             const int y1 = sy ? P.ny - 1 : 0, y2 = sy ? P.ny - 2 : 1;
-            const T q = ext_adjoint(P, V, lev, x, sy ? P.ny : -1);
-            T d1, d2, dth;
+            q = ext_adjoint(P, V, lev, x, sy ? P.ny : -1);
             wet_ghost_grad(P, 2 + sy, phi_at(P, phi, x, y1), phi_at(P, phi, x, y2), d1, d2, dth);
-            V.e(lev, 2 + sy, 0)[x] = d1 * q;
-            V.e(lev, 2 + sy, 1)[x] = d2 * q;
-            th[2 + sy] += (double)(dth * q);
             if (P.wall_x && (x == 0 || x == P.nx - 1)) {   // the corner ghost beside it
                 const int side = x == 0 ? 0 : 1;
-                const T qc = ext_adjoint(P, V, lev, side ? P.nx : -1, sy ? P.ny : -1);
-                T c1, c2, cth;
+                qc = ext_adjoint(P, V, lev, side ? P.nx : -1, sy ? P.ny : -1);
+                T c1, c2;
                 wet_ghost_grad(P, 2 + sy, xghost(P, phi, side, y1), xghost(P, phi, side, y2), c1, c2, cth);
-                th[2 + sy] += (double)(cth * qc);
             }
+            wall = 2 + sy;
+            at = x;
         } else {          // x-wall ghost (-1, y) or (nx, y)
             const long long i2 = it - ny2;
             const int sx = (int)(i2 / P.ny), y = (int)(i2 - (long long)sx * P.ny);
             const int x1 = sx ? P.nx - 1 : 0, x2 = sx ? P.nx - 2 : 1;
-            const T q = xghost_adjoint(P, V, lev, phi, sx, y);
-            T d1, d2, dth;
+            q = xghost_adjoint(P, V, lev, phi, sx, y);
             wet_ghost_grad(P, sx, phi_at(P, phi, x1, y), phi_at(P, phi, x2, y), d1, d2, dth);
-            V.e(lev, sx, 0)[y] = d1 * q;
-            V.e(lev, sx, 1)[y] = d2 * q;
-            th[sx] += (double)(dth * q);
+            wall = sx;
+            at = y;
+        }
+        if (status == 0 && (lev == 0 || n > 0)) {   // the previous level only when n > 0
+            V.e(lev, wall, 0)[at] = d1 * q;
+            V.e(lev, wall, 1)[at] = d2 * q;
+            th[wall] += (double)(dth * q);
+            if (wall >= 2) th[wall] += (double)(cth * qc);
         }
     }
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -591,10 +618,12 @@ __global__ __launch_bounds__(GHOST_THREADS) void k_adj_ghosts(KParams<T> P, cons
         if (lane == 0) red[q][wv] = v;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double* pth = V.part + 2 * V.ntA + 4 * blockIdx.x;
-        for (int q = 0; q < 4; q++) pth[q] += (red[q][0] + red[q][1]) + (red[q][2] + red[q][3]);
-    }
+    if (threadIdx.x == 0 && status == 0)
+        for (int q = 0; q < 4; q++) {
+            double t = red[q][0];
+            for (int w = 1; w < GHOST_THREADS / 64; w++) t += red[q][w];
+            pth[q] = pold[q] + t;
+        }
 }
 
 // ---------------------------------------------------------------- seed, init, parameters
@@ -744,12 +773,43 @@ static void tape_step_launch(const KParams<T>& P, char* tape, size_t slot, int j
     }
 }
 
-// The same launch shapes as lbm_step (step_shape).
+template <typename T, int TY, int NBY>
+static void tape_step2_launch(const KParams<T>& P, char* tape, size_t slot, int j, hipStream_t s) {
+    const int ntx = (P.nx + TX - 1) / TX, nty = (P.ny + TY - 1) / TY;
+    const dim3 blk(TX, NBY);
+    // slot j + 2 with ordinary stores while it and the next fit the last-level cache (the next launch reads it)
+    if (2 * slot <= (size_t)LBM_NT_MIN_BYTES) {
+        if (P.rates_std) k_tape_step2<T, TY, NBY, true, false><<<ntx * nty, blk, 0, s>>>(P, tape, slot, j, ntx, nty);
+        else k_tape_step2<T, TY, NBY, false, false><<<ntx * nty, blk, 0, s>>>(P, tape, slot, j, ntx, nty);
+    } else {
+        if (P.rates_std) k_tape_step2<T, TY, NBY, true, true><<<ntx * nty, blk, 0, s>>>(P, tape, slot, j, ntx, nty);
+        else k_tape_step2<T, TY, NBY, false, true><<<ntx * nty, blk, 0, s>>>(P, tape, slot, j, ntx, nty);
+    }
+}
+
+// The tile rows of the two-level launch of lbm_step (lbm_step2.hip).
 template <typename T>
-static void launch_tape_steps(const KParams<T>& P, char* tape, size_t slot, int nlevels, int ty, int by,
+static void tape_step2(const KParams<T>& P, char* tape, size_t slot, int j, hipStream_t s) {
+    const long long ntx = (P.nx + TX - 1) / TX;
+    const long long t8 = ntx * ((P.ny + 7) / 8), t16 = ntx * ((P.ny + 15) / 16);
+    if constexpr (sizeof(T) == 4) {
+        if (t16 <= 256 && t8 > 256) tape_step2_launch<T, 16, 16>(P, tape, slot, j, s);
+        else tape_step2_launch<T, 8, 8>(P, tape, slot, j, s);
+    } else {
+        tape_step2_launch<T, 8, 8>(P, tape, slot, j, s);
+    }
+}
+
+// The launches of lbm_step: two levels per launch where it takes two (`two`),
+// then one-level launches of its shapes (step_shape).
+template <typename T>
+static void launch_tape_steps(const KParams<T>& P, char* tape, size_t slot, int nlevels, bool two, int ty, int by,
                               hipStream_t s) {
     constexpr int T16 = sizeof(T) == 8 ? 8 : 16;
-    for (int j = 0; j + 1 < nlevels; j++) {
+    int j0 = 0;
+    if (two)
+        for (; j0 + 2 < nlevels; j0 += 2) tape_step2<T>(P, tape, slot, j0, s);
+    for (int j = j0; j + 1 < nlevels; j++) {
         if (ty == 4) tape_step_launch<T, 4, 4>(P, tape, slot, j, s);
         else if (ty == 8 || sizeof(T) == 8) {
             if (by == 8) tape_step_launch<T, 8, 8>(P, tape, slot, j, s);
@@ -801,10 +861,11 @@ int lbm_tape_record(const lbm_params* p, const void* state, void* tape, int32_t 
                                                                        p->nx, p->ny, p->dtype);
     int ty, by;
     step_shape(p, &ty, &by);
+    const bool two = two_level_path(L, p->nx, p->ny, p->phase_eq, p->model, p->grad_scheme);
     if (p->dtype == LBM_F32)
-        launch_tape_steps<float>(resolve<float>(p, L), (char*)tape, L.buf_bytes, nlevels, ty, by, s);
+        launch_tape_steps<float>(resolve<float>(p, L), (char*)tape, L.buf_bytes, nlevels, two, ty, by, s);
     else
-        launch_tape_steps<double>(resolve<double>(p, L), (char*)tape, L.buf_bytes, nlevels, ty, by, s);
+        launch_tape_steps<double>(resolve<double>(p, L), (char*)tape, L.buf_bytes, nlevels, two, ty, by, s);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? LBM_OK : hip_fail(e);
 }

@@ -65,14 +65,21 @@ struct Step2Lds {
     T ua[TY * TX], va[TY * TX];   // velocity of level n on the tile (B's history)
 };
 
-// Two levels of the tile (xt, yt) of the lattice whose state copies lie at
-// off0 and off1, with the LDS `L` of the workgroup.  NBY thread rows of 64;
+// Two levels of the tile (xt, yt), with the LDS `L` of the workgroup.
+// STAMPED: on a ping-pong state (copies at `state` + off0 and + off1), the
+// level stamp of the tile's first row selects the source copy, the tile's rows
+// move to level n + 2 in the other copy and their stamps follow.  Otherwise
+// level lev in the copy at `src` goes to level lev + 2 in the copy at `dst`,
+// and MID also stores the tile's level lev + 1 (what a one-level step would
+// write) into the copy at `mid`, non-temporally.  NBY thread rows of 64;
 // every thread owns TY / NBY nodes of the tile in B and up to S positions of
-// A's region.  NTS: non-temporal stores.  Ends with the tile's stamps
-// written; a caller that reuses `L` for another tile synchronises first.
-template <typename T, int TY, int NBY, bool STD, bool NTS>
-__device__ __forceinline__ void step2_tile(const KParams<T>& P, char* state, size_t off0, size_t off1,
-                                           size_t off_stamp, int xt, int yt, Step2Lds<T, TY>& L) {
+// A's region.  NTS: non-temporal stores into the destination copy.  A caller
+// that reuses `L` for another tile synchronises first.  P is taken by value:
+// by reference the compiler spent 1.3% more VALU instructions on the body.
+template <typename T, int TY, int NBY, bool STD, bool NTS, bool STAMPED, bool MID = false>
+__device__ __forceinline__ void step2_body(const KParams<T> P, char* state, size_t off0, size_t off1,
+                                           size_t off_stamp, const char* src_in, char* mid, char* dst_in,
+                                           int64_t lev_in, int xt, int yt, Step2Lds<T, TY>& L) {
     using Lds = Step2Lds<T, TY>;
     constexpr int AW = Lds::AW, AH = Lds::AH, NA = AW * AH;
     constexpr int WW = Lds::WW, WH = Lds::WH, GW = Lds::GW, GH = Lds::GH;
@@ -87,12 +94,12 @@ __device__ __forceinline__ void step2_tile(const KParams<T>& P, char* state, siz
 
     const int x0 = xt * TX, y0 = yt * TY;
     const int tid = threadIdx.y * TX + threadIdx.x;
-    int64_t* stamp = reinterpret_cast<int64_t*>(state + off_stamp) + (size_t)xt * P.ny + y0;
-    const int64_t sv = stamp[0];
-    const int64_t lev = stamp_level(sv);
+    int64_t* stamp = STAMPED ? reinterpret_cast<int64_t*>(state + off_stamp) + (size_t)xt * P.ny + y0 : nullptr;
+    const int64_t sv = STAMPED ? stamp[0] : 0;
+    const int64_t lev = STAMPED ? stamp_level(sv) : lev_in;
     const int cur = stamp_copy(sv);
-    const char* src = state + (cur ? off1 : off0);
-    char* dst = state + (cur ? off0 : off1);
+    const char* src = STAMPED ? state + (cur ? off1 : off0) : src_in;
+    char* dst = STAMPED ? state + (cur ? off0 : off1) : dst_in;
     const bool first = lev == 0;
     const uint32_t pl = (uint32_t)P.plane;
     const uint32_t bF = pl * ES, bG = bF + 8 * pl * ES, bH = bG + 9 * pl * ES;
@@ -180,7 +187,8 @@ __device__ __forceinline__ void step2_tile(const KParams<T>& P, char* state, siz
         }
         const Macro<T> M = macro(P, g[s], L.pa[ay + 1][ax + 1], gx, gy, lap, first, php, gxp, gyp, up, vp);
         const double f0n = collide_f<T, false, STD>(P, M, f[s], phid[s]);
-        L.fa[0][idx] = rest_encode<T>(f0n, M.phi, P.rest_w);
+        const T f0e = rest_encode<T>(f0n, M.phi, P.rest_w);
+        L.fa[0][idx] = f0e;
 #pragma unroll
         for (int i = 1; i < Q; i++) L.fa[i][idx] = f[s][i];
         if (ax >= 1 && ax < AW - 1 && ay >= 1 && ay < AH - 1) {
@@ -191,6 +199,18 @@ __device__ __forceinline__ void step2_tile(const KParams<T>& P, char* state, siz
             if (ax >= 2 && ax < AW - 2 && ay >= 2 && ay < AH - 2) {
                 L.ua[(ay - 2) * TX + (ax - 2)] = M.u;
                 L.va[(ay - 2) * TX + (ax - 2)] = M.v;
+                const int x = x0 + ax - 2, y = y0 + ay - 2;
+                if (MID && x < P.nx && y < P.ny) {   // a node of the tile (not a wrapped position)
+                    const uint32_t k = (uint32_t)y * (uint32_t)P.nx + (uint32_t)x;
+                    st<T, uint32_t, true>(mid, k * ES, f0e);
+#pragma unroll
+                    for (int i = 1; i < Q; i++) st<T, uint32_t, true>(mid, bF + ((uint32_t)(i - 1) * pl + k) * ES, f[s][i]);
+#pragma unroll
+                    for (int i = 0; i < Q; i++) st<T, uint32_t, true>(mid, bG + ((uint32_t)i * pl + k) * ES, g[s][i]);
+                    st<T, uint32_t, true>(mid, bH + k * ES, M.phi);
+                    st<T, uint32_t, true>(mid, bH + (pl + k) * ES, M.u);
+                    st<T, uint32_t, true>(mid, bH + (2 * pl + k) * ES, M.v);
+                }
             }
         }
     }
@@ -286,7 +306,23 @@ __device__ __forceinline__ void step2_tile(const KParams<T>& P, char* state, siz
         st<T, uint32_t, NTS>(dst, bH + (2 * pl + k) * ES, M.v);
     }
     // every wave read stamp[0] before the barriers above
-    if (tid < TY && y0 + tid < P.ny) stamp[tid] = stamp_of(lev + 2, 1 - cur);
+    if (STAMPED && tid < TY && y0 + tid < P.ny) stamp[tid] = stamp_of(lev + 2, 1 - cur);
+}
+
+// Two levels of the tile (xt, yt) of a ping-pong state (copies at off0 and
+// off1, level stamps at off_stamp).
+template <typename T, int TY, int NBY, bool STD, bool NTS>
+__device__ __forceinline__ void step2_tile(const KParams<T>& P, char* state, size_t off0, size_t off1,
+                                           size_t off_stamp, int xt, int yt, Step2Lds<T, TY>& L) {
+    step2_body<T, TY, NBY, STD, NTS, true>(P, state, off0, off1, off_stamp, nullptr, nullptr, nullptr, 0, xt, yt, L);
+}
+
+// Level lev in the copy at `src` to level lev + 2 in the copy at `dst`, the
+// intermediate level into the copy at `mid` (tapes).
+template <typename T, int TY, int NBY, bool STD, bool NTS>
+__device__ __forceinline__ void step2_mid(const KParams<T>& P, const char* src, char* mid, char* dst, int64_t lev,
+                                          int xt, int yt, Step2Lds<T, TY>& L) {
+    step2_body<T, TY, NBY, STD, NTS, false, true>(P, nullptr, 0, 0, 0, src, mid, dst, lev, xt, yt, L);
 }
 
 }  // namespace lbm

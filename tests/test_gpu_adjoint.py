@@ -143,6 +143,37 @@ def test_trajectory_gradient_equals_reference(kind):
     _close(theta.grad.numpy(), dth_ref, 1e-9, f"{kind} dL/dtheta")
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("kind", ["walls_xy_inverse_nu", "dam_break_32x16"])
+def test_two_level_tape_equals_one_level_tape(kind, dtype):
+    """Tapes recorded two levels per launch (LBM_TWO_LEVEL=1: the two-level body
+    stores its intermediate level too) hold the forward levels bitwise, so the
+    gradients equal those from one-level tapes (LBM_TWO_LEVEL=0) bit for bit;
+    segments of 7 levels end on a one-level launch."""
+    import os
+    from paper_2111_00847_amd.autograd import trajectory_phi
+    case, phi0, target = _traj_case(kind)
+    case = case.replace(dtype=dtype)
+    nsteps, chk = 25, 7
+    out = {}
+    for mode in ("1", "0"):
+        os.environ["LBM_TWO_LEVEL"] = mode
+        try:
+            phi0_t = torch.tensor(phi0, dtype=torch.float64 if dtype == "f64" else torch.float32, device="cuda",
+                                  requires_grad=True)
+            grav = torch.tensor(list(case.gravity), dtype=torch.float64, requires_grad=True)
+            theta = torch.tensor(list(case.theta), dtype=torch.float64, requires_grad=True)
+            phiN = trajectory_phi(phi0_t, grav, theta, case, nsteps, None, chk)
+            L = ((phiN - torch.tensor(target, dtype=phiN.dtype, device="cuda")) ** 2).sum()
+            L.backward()
+            torch.cuda.synchronize()
+            out[mode] = (phi0_t.grad.cpu().numpy(), grav.grad.numpy(), theta.grad.numpy())
+        finally:
+            os.environ.pop("LBM_TWO_LEVEL", None)
+    for a, b, what in zip(out["1"], out["0"], ("dL/dphi0", "dL/dgravity", "dL/dtheta")):
+        assert np.array_equal(a, b), (kind, dtype, what, float(np.abs(a - b).max()))
+
+
 # ---------------------------------------------------------------- cfg: differentiable dam break, 64 x 32 copy
 def _dam_small(dtype="f64"):
     """64 x 32 copy of the dam break; the target is phi of a run with seeded
