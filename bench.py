@@ -456,6 +456,8 @@ def main():
                     help="run only the headline measurement (profiling runs)")
     ap.add_argument("--only-large", action="store_true",
                     help="run only the 4096 x 4096 measurement (profiling runs)")
+    ap.add_argument("--only-local", action="store_true",
+                    help="run only the local-gradient measurement (profiling runs)")
     ap.add_argument("--only-adjoint", action="store_true",
                     help="run only the adjoint measurement (profiling runs)")
     ap.add_argument("--only-batched", action="store_true",
@@ -497,6 +499,9 @@ def main():
         return
     if args.only_ceiling:
         print(json.dumps({"stream_ceiling": measure_ceiling(torch)}), flush=True)
+        return
+    if args.only_local:
+        print(json.dumps({"local_gradient": measure_local(args, torch, W, Sim)}), flush=True)
         return
     if args.only_adjoint:
         print(json.dumps({"adjoint": measure_adjoint(args, torch, W, Sim)}), flush=True)
