@@ -230,6 +230,46 @@ def test_dam_break_64x32_gradients_equal_finite_differences(nsteps):
         assert abs(fd - ad) <= 1e-4 * abs(ad), (what, fd, ad)
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("geom", ["periodic", "walls_xy", "walls_y"])
+def test_adjoint_run_equals_single_steps(geom, dtype):
+    """Two lbm_adjoint_run calls in a row over one tape equal that many
+    lbm_adjoint_step calls bit for bit: adjoint populations, history adjoint,
+    parameter sums and dL/dphi0 (ragged tiles, 37 x 23)."""
+    api, Sim = _api()
+    case = _case(geom).replace(dtype=dtype)
+    phi0, u0, p0 = W.random_state_fields(case, seed=11)
+    s = Sim(case).init(phi0, u0, p0)
+    nl = 9
+    tape = api.new_tape(s.p, nl)
+    api.lbm_tape_record(s.p, s.state, tape, nl)
+    s.step(nl - 1)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    rng = np.random.default_rng(3)
+    dL = torch.tensor(rng.standard_normal((case.ny, case.nx)), dtype=tdt, device="cuda")
+    out = []
+    for mode in ("run", "steps"):
+        adj = api.new_adjoint(s.p)
+        api.lbm_adjoint_phi(s.p, s.state, adj, dL)
+        if mode == "run":                                  # the adjoint of level 8 down to level 0
+            api.lbm_adjoint_run(s.p, tape, nl - 2, 5, adj)     # slots 7 .. 3
+            api.lbm_adjoint_run(s.p, tape, nl - 7, nl - 6, adj)  # slots 2 .. 0
+        else:
+            for j in range(nl - 2, -1, -1):
+                api.lbm_adjoint_step(s.p, tape, j, adj)
+        fb = torch.empty((9, case.ny, case.nx), dtype=tdt, device="cuda")
+        gb = torch.empty_like(fb)
+        hb = torch.empty((3, case.ny, case.nx), dtype=tdt, device="cuda")
+        api.lbm_adjoint_export(s.p, adj, fb, gb, hb)
+        d0 = torch.empty((case.ny, case.nx), dtype=tdt, device="cuda")
+        api.lbm_adjoint_init(s.p, adj, d0)
+        prm, lev = api.lbm_adjoint_params(s.p, adj)
+        assert lev == 0
+        out.append([t.cpu().numpy() for t in (fb, gb, hb, d0)] + [np.array(prm)])
+    for a, b, what in zip(out[0], out[1], ("fbar", "gbar", "hbar", "dL/dphi0", "params")):
+        assert np.array_equal(a, b), (geom, dtype, what, float(np.abs(a - b).max()))
+
+
 def test_level_mismatch_is_reported():
     """An adjoint step whose tape level is not one below the adjoint's level is
     skipped on the device and reported by lbm_adjoint_params."""
