@@ -13,8 +13,9 @@ hipError_t launch_step(const KParams<T>& P, char* state, const Layout& L, int64_
 // two levels of the plain Allen-Cahn step in one launch (lbm_step2.hip)
 template <typename T>
 void launch_step2(const KParams<T>& P, char* state, const Layout& L, hipStream_t s);
-// the plain Allen-Cahn step on a lattice of at least one tile per CU whose copy
-// fits 32-bit offsets: two levels per launch
+// the Allen-Cahn step (either gradient scheme, not the corrected model) on a
+// lattice of at least one tile per CU whose copy fits 32-bit offsets: two
+// levels per launch
 bool two_level_path(const Layout& L, int nx, int ny, int pf, int model, int grad);
 template <typename T>
 hipError_t launch_moments(const KParams<T>& P, const char* state, const Layout& L, T* phi, T* u, T* p,

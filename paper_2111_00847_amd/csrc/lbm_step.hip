@@ -379,7 +379,8 @@ static void launch_tile(const KParams<T>& P, char* state, const Layout& L, hipSt
     }
 }
 
-// Two levels per launch for the plain Allen-Cahn step (lbm_step2.hip) on
+// Two levels per launch for the Allen-Cahn step with either gradient scheme
+// (stencils or Eq. local; present or original model; lbm_step2.hip) on
 // lattices of at least one 64 x 8 tile per CU whose copy fits 32-bit offsets.
 // Measured on MI355X, FP32, per level: 256 x 1024 (cache-resident) 7.2 us
 // against 9.0 one-level, 1024 x 512 14.4 against 16.1, 4096 x 4096 (streamed
@@ -395,7 +396,7 @@ static void launch_tile(const KParams<T>& P, char* state, const Layout& L, hipSt
 #endif
 
 bool two_level_path(const Layout& L, int nx, int ny, int pf, int model, int grad) {
-    if (!LBM_TWO_LEVEL || pf != 0 || model == 2 || grad != 0 || L.buf_bytes >= (size_t(1) << 32)) return false;
+    if (!LBM_TWO_LEVEL || pf != 0 || model == 2 || L.buf_bytes >= (size_t(1) << 32)) return false;
     const char* e = getenv("LBM_TWO_LEVEL");
     if (e && e[0] == '0' && e[1] == 0) return false;
     if (e && e[0] == '1' && e[1] == 0) return true;

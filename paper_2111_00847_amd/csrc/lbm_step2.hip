@@ -41,6 +41,28 @@ __global__ __launch_bounds__(TX* NBY) void k_step2(KParams<T> P, char* state, si
     step2_tile<T, TY, NBY, STD, NTS>(P, state, off0, off1, off_stamp, xt, yt, L);
 }
 
+// The same for the local gradient scheme (Eq. local; the general collision,
+// as the one-level kernel runs it).
+template <typename T, int TY, int NBY, bool NTS>
+__global__ __launch_bounds__(TX* NBY) void k_step2_local(KParams<T> P, char* state, size_t off0, size_t off1,
+                                                         size_t off_stamp, int ntx, int nty) {
+    __shared__ Step2LdsLocal<T, TY> L;
+    int xt, yt;
+    xcd_tile(blockIdx.x, ntx, nty, xt, yt);
+    step2_local_tile<T, TY, NBY, NTS>(P, state, off0, off1, off_stamp, xt, yt, L);
+}
+
+template <typename T, int TY, int NBY>
+static void launch_step2_local(const KParams<T>& P, char* state, const Layout& L, hipStream_t s) {
+    const int ntx = (P.nx + TX - 1) / TX, nty = (P.ny + TY - 1) / TY;
+    if (cached_state(L))
+        k_step2_local<T, TY, NBY, false><<<ntx * nty, dim3(TX, NBY), 0, s>>>(P, state, L.off_buf[0], L.off_buf[1],
+                                                                             L.off_stamp, ntx, nty);
+    else
+        k_step2_local<T, TY, NBY, true><<<ntx * nty, dim3(TX, NBY), 0, s>>>(P, state, L.off_buf[0], L.off_buf[1],
+                                                                            L.off_stamp, ntx, nty);
+}
+
 template <typename T, int TY, int NBY, bool STD>
 static void launch_step2_std(const KParams<T>& P, char* state, const Layout& L, hipStream_t s) {
     const int ntx = (P.nx + TX - 1) / TX, nty = (P.ny + TY - 1) / TY;
@@ -55,7 +77,8 @@ static void launch_step2_std(const KParams<T>& P, char* state, const Layout& L, 
 
 template <typename T, int TY, int NBY>
 static void launch_step2_ty(const KParams<T>& P, char* state, const Layout& L, hipStream_t s) {
-    if (P.rates_std) launch_step2_std<T, TY, NBY, true>(P, state, L, s);
+    if (P.grad == 1) launch_step2_local<T, TY, NBY>(P, state, L, s);
+    else if (P.rates_std) launch_step2_std<T, TY, NBY, true>(P, state, L, s);
     else launch_step2_std<T, TY, NBY, false>(P, state, L, s);
 }
 

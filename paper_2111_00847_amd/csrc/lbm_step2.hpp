@@ -65,6 +65,12 @@ struct Step2Lds {
     T ua[TY * TX], va[TY * TX];   // velocity of level n on the tile (B's history)
 };
 
+// The local gradient scheme (Eq. local) also hands B m^phiC of level n.
+template <typename T, int TY>
+struct Step2LdsLocal : Step2Lds<T, TY> {
+    T mxa[TY * TX], mya[TY * TX];
+};
+
 // Two levels of the tile (xt, yt), with the LDS `L` of the workgroup.
 // STAMPED: on a ping-pong state (copies at `state` + off0 and + off1), the
 // level stamp of the tile's first row selects the source copy, the tile's rows
@@ -76,11 +82,18 @@ struct Step2Lds {
 // A's region.  NTS: non-temporal stores into the destination copy.  A caller
 // that reuses `L` for another tile synchronises first.  P is taken by value:
 // by reference the compiler spent 1.3% more VALU instructions on the body.
-template <typename T, int TY, int NBY, bool STD, bool NTS, bool STAMPED, bool MID = false>
+// LOCAL: the Allen-Cahn step with the local gradient scheme (Eq. local; the
+// one-level body of lbm_local_step.hpp): grad phi of levels >= 1 from each
+// node's own f and g, a history of five planes (phi, u, v and m^phiC of the
+// previous level), no window of the previous phi, and the general collision
+// (STD false), as the one-level kernel runs it.
+template <typename T, int TY, int NBY, bool STD, bool NTS, bool STAMPED, bool MID = false, bool LOCAL = false,
+          typename LdsT = Step2Lds<T, TY>>
 __device__ __forceinline__ void step2_body(const KParams<T> P, char* state, size_t off0, size_t off1,
                                            size_t off_stamp, const char* src_in, char* mid, char* dst_in,
-                                           int64_t lev_in, int xt, int yt, Step2Lds<T, TY>& L) {
+                                           int64_t lev_in, int xt, int yt, LdsT& L) {
     using Lds = Step2Lds<T, TY>;
+    static_assert(!(LOCAL && (MID || STD)), "the local scheme: no tape, general collision");
     constexpr int AW = Lds::AW, AH = Lds::AH, NA = AW * AH;
     constexpr int WW = Lds::WW, WH = Lds::WH, GW = Lds::GW, GH = Lds::GH;
     constexpr int NT = TX * NBY;
@@ -105,7 +118,7 @@ __device__ __forceinline__ void step2_body(const KParams<T> P, char* state, size
     const uint32_t bF = pl * ES, bG = bF + 8 * pl * ES, bH = bG + 9 * pl * ES;
 
     // ---- A: loads of the region (f, g, history) and of the window ring (f, history phi)
-    T f[S][9], g[S][9], hp[S], hu[S], hv[S];
+    T f[S][9], g[S][9], hp[S], hu[S], hv[S], hmx[S], hmy[S];
     double f0d[S];
     bool ok[S];
 #pragma unroll
@@ -115,13 +128,17 @@ __device__ __forceinline__ void step2_body(const KParams<T> P, char* state, size
         const int nxi = region_node(x0 - 2 + ax, P.nx, P.wall_x);
         const int nyi = region_node(y0 - 2 + ay, P.ny, P.wall_y);
         ok[s] = idx < NA && nxi >= 0 && nyi >= 0;
-        hp[s] = hu[s] = hv[s] = T(0);
+        hp[s] = hu[s] = hv[s] = hmx[s] = hmy[s] = T(0);
         f0d[s] = 0.0;
         if (ok[s]) {
             const uint32_t k = pull_fg_at<T, uint32_t>(P, src, bF, bG, bH, pl, nxi, nyi, f[s], f0d[s], g[s]);
             hp[s] = ld<T>(src, bH + k * ES);
             hu[s] = ld<T>(src, bH + (pl + k) * ES);
             hv[s] = ld<T>(src, bH + (2 * pl + k) * ES);
+            if constexpr (LOCAL) {
+                hmx[s] = ld<T>(src, bH + (3 * pl + k) * ES);
+                hmy[s] = ld<T>(src, bH + (4 * pl + k) * ES);
+            }
         }
     }
     // ring of the windows: top row, bottom row, left column, right column
@@ -148,7 +165,7 @@ __device__ __forceinline__ void step2_body(const KParams<T> P, char* state, size
         rok = nxi >= 0 && nyi >= 0;
         if (rok) {
             const uint32_t k = pull_f_at<T, uint32_t>(P, src, bF, bH, pl, nxi, nyi, fr, fr0);
-            rh = ld<T>(src, bH + k * ES);
+            if constexpr (!LOCAL) rh = ld<T>(src, bH + k * ES);
         }
     }
     double phid[S];
@@ -161,15 +178,15 @@ __device__ __forceinline__ void step2_body(const KParams<T> P, char* state, size
             f[s][0] = (T)f0d[s];
             phid[s] = f0d[s] + moving_sum_d(f[s]);
             L.pa[ay + 1][ax + 1] = (T)phid[s];
-            L.pp[ay + 1][ax + 1] = hp[s];
+            if constexpr (!LOCAL) L.pp[ay + 1][ax + 1] = hp[s];
         }
     }
     if (rok) {
         L.pa[rwy][rwx] = (T)(fr0 + moving_sum_d(fr));
-        L.pp[rwy][rwx] = rh;
+        if constexpr (!LOCAL) L.pp[rwy][rwx] = rh;
     }
     __syncthreads();
-    ghosts_h<T, WW, WH, 3, NT, WW + 1>(P, !first, x0, y0, L.pa, L.pp);
+    ghosts_h<T, WW, WH, 3, NT, WW + 1>(P, !first && !LOCAL, x0, y0, L.pa, L.pp);
 
     // ---- A: the step of level n on the region
 #pragma unroll
@@ -179,13 +196,30 @@ __device__ __forceinline__ void step2_body(const KParams<T> P, char* state, size
         const int ay = idx / AW, ax = idx - ay * AW;
         T gx, gy, lap, gxp = T(0), gyp = T(0), lp, php = T(0), up = T(0), vp = T(0);
         win_stencil_at(L.pa, ax + 1, ay + 1, gx, gy, lap);
-        if (!first) {
-            win_stencil_at(L.pp, ax + 1, ay + 1, gxp, gyp, lp);
-            php = L.pp[ay + 1][ax + 1];
-            up = hu[s];
-            vp = hv[s];
-        }
-        const Macro<T> M = macro(P, g[s], L.pa[ay + 1][ax + 1], gx, gy, lap, first, php, gxp, gyp, up, vp);
+        const Macro<T> M = [&]() -> Macro<T> {
+            if constexpr (LOCAL) {
+                const T phi = L.pa[ay + 1][ax + 1];
+                T mpx = T(0), mpy = T(0);
+                if (!first) {
+                    php = hp[s];
+                    up = hu[s];
+                    vp = hv[s];
+                    mpx = hmx[s];
+                    mpy = hmy[s];
+                    local_grad(P, f[s], g[s], phi, lap, php * up, php * vp, gx, gy);
+                }
+                return macro<T, false, true>(P, g[s], phi, gx, gy, lap, first, php, T(0), T(0), up, vp, T(0), T(0),
+                                             mpx, mpy);
+            } else {
+                if (!first) {
+                    win_stencil_at(L.pp, ax + 1, ay + 1, gxp, gyp, lp);
+                    php = L.pp[ay + 1][ax + 1];
+                    up = hu[s];
+                    vp = hv[s];
+                }
+                return macro(P, g[s], L.pa[ay + 1][ax + 1], gx, gy, lap, first, php, gxp, gyp, up, vp);
+            }
+        }();
         const double f0n = collide_f<T, false, STD>(P, M, f[s], phid[s]);
         const T f0e = rest_encode<T>(f0n, M.phi, P.rest_w);
         L.fa[0][idx] = f0e;
@@ -199,6 +233,10 @@ __device__ __forceinline__ void step2_body(const KParams<T> P, char* state, size
             if (ax >= 2 && ax < AW - 2 && ay >= 2 && ay < AH - 2) {
                 L.ua[(ay - 2) * TX + (ax - 2)] = M.u;
                 L.va[(ay - 2) * TX + (ax - 2)] = M.v;
+                if constexpr (LOCAL) {
+                    L.mxa[(ay - 2) * TX + (ax - 2)] = M.mx;
+                    L.mya[(ay - 2) * TX + (ax - 2)] = M.my;
+                }
                 const int x = x0 + ax - 2, y = y0 + ay - 2;
                 if (MID && x < P.nx && y < P.ny) {   // a node of the tile (not a wrapped position)
                     const uint32_t k = (uint32_t)y * (uint32_t)P.nx + (uint32_t)x;
@@ -290,9 +328,19 @@ __device__ __forceinline__ void step2_body(const KParams<T> P, char* state, size
         for (int i = 0; i < Q; i++) gb[i] = w.of(i) ? L.ga[opp(i)][c1] : L.ga[i][c1 - cy(i) * GW - cx(i)];
         T gx, gy, lap, gxp, gyp, lp;
         win_stencil_at(L.pb, lx + 1, ly + 1, gx, gy, lap);
-        win_stencil_at(L.pa, lx + 3, ly + 3, gxp, gyp, lp);
-        const Macro<T> M = macro(P, gb, L.pb[ly + 1][lx + 1], gx, gy, lap, false, L.pa[ly + 3][lx + 3], gxp, gyp,
-                                 L.ua[ly * TX + lx], L.va[ly * TX + lx]);
+        const Macro<T> M = [&]() -> Macro<T> {
+            if constexpr (LOCAL) {
+                const T phi = L.pb[ly + 1][lx + 1], php = L.pa[ly + 3][lx + 3];
+                const T up = L.ua[ly * TX + lx], vp = L.va[ly * TX + lx];
+                local_grad(P, fb[r], gb, phi, lap, php * up, php * vp, gx, gy);
+                return macro<T, false, true>(P, gb, phi, gx, gy, lap, false, php, T(0), T(0), up, vp, T(0), T(0),
+                                             L.mxa[ly * TX + lx], L.mya[ly * TX + lx]);
+            } else {
+                win_stencil_at(L.pa, lx + 3, ly + 3, gxp, gyp, lp);
+                return macro(P, gb, L.pb[ly + 1][lx + 1], gx, gy, lap, false, L.pa[ly + 3][lx + 3], gxp, gyp,
+                             L.ua[ly * TX + lx], L.va[ly * TX + lx]);
+            }
+        }();
         const double f0n = collide_f<T, false, STD>(P, M, fb[r], phb[r]);
         collide_g<T, STD>(P, M, gb);
         const uint32_t k = (uint32_t)y * (uint32_t)P.nx + (uint32_t)x;
@@ -304,6 +352,10 @@ __device__ __forceinline__ void step2_body(const KParams<T> P, char* state, size
         st<T, uint32_t, NTS>(dst, bH + k * ES, M.phi);
         st<T, uint32_t, NTS>(dst, bH + (pl + k) * ES, M.u);
         st<T, uint32_t, NTS>(dst, bH + (2 * pl + k) * ES, M.v);
+        if constexpr (LOCAL) {
+            st<T, uint32_t, NTS>(dst, bH + (3 * pl + k) * ES, M.mx);
+            st<T, uint32_t, NTS>(dst, bH + (4 * pl + k) * ES, M.my);
+        }
     }
     // every wave read stamp[0] before the barriers above
     if (STAMPED && tid < TY && y0 + tid < P.ny) stamp[tid] = stamp_of(lev + 2, 1 - cur);
@@ -315,6 +367,14 @@ template <typename T, int TY, int NBY, bool STD, bool NTS>
 __device__ __forceinline__ void step2_tile(const KParams<T>& P, char* state, size_t off0, size_t off1,
                                            size_t off_stamp, int xt, int yt, Step2Lds<T, TY>& L) {
     step2_body<T, TY, NBY, STD, NTS, true>(P, state, off0, off1, off_stamp, nullptr, nullptr, nullptr, 0, xt, yt, L);
+}
+
+// The same with the local gradient scheme (Eq. local).
+template <typename T, int TY, int NBY, bool NTS>
+__device__ __forceinline__ void step2_local_tile(const KParams<T>& P, char* state, size_t off0, size_t off1,
+                                                 size_t off_stamp, int xt, int yt, Step2LdsLocal<T, TY>& L) {
+    step2_body<T, TY, NBY, false, NTS, true, false, true>(P, state, off0, off1, off_stamp, nullptr, nullptr, nullptr,
+                                                          0, xt, yt, L);
 }
 
 // Level lev in the copy at `src` to level lev + 2 in the copy at `dst`, the

@@ -208,7 +208,7 @@ def test_noalloc_batch_step_validates_on_the_host():
 
 
 def test_levels_per_launch():
-    """Two levels per launch exactly for the plain Allen-Cahn step (stencil
+    """Two levels per launch exactly for the Allen-Cahn step (stencil or local
     gradients, present or original model) on a lattice whose state copy fits
     32-bit byte offsets (below 4 GiB), of at least 256 tiles of 64 x 8 nodes
     (any size with LBM_TWO_LEVEL=1, none with LBM_TWO_LEVEL=0); one otherwise."""
@@ -242,7 +242,7 @@ def test_levels_per_launch():
     assert levels(nx=2, ny=2, wall_x=True, wall_y=True, **f32) == 2
     assert levels(nx=256, ny=1024, model="original", **f32) == 2
     assert levels(nx=256, ny=1024, model="corrected", **f32) == 1
-    assert levels(nx=256, ny=1024, grad_scheme="local", **f32) == 1
+    assert levels(nx=256, ny=1024, grad_scheme="local", **f32) == 2
     assert levels(nx=256, ny=1024, phase_eq="cahn_hilliard", phiA=1.0, phiB=-1.0, **f32) == 1
     assert levels(nx=2048, ny=1024, **f32) == 2            # 2 x 176 MB: streamed from HBM
     assert levels(nx=4096, ny=4096, dtype="f64") == 2      # 2 x 2.8 GB

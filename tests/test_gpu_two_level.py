@@ -1,6 +1,6 @@
 """Two levels per launch against two one-level launches.
 
-The plain Allen-Cahn step (stencil gradients, present or original model)
+The Allen-Cahn step (stencil or local gradients, present or original model)
 advances two levels per launch; an odd level count ends on a one-level launch.  Advancing one state n levels by one
 lbm_step call and a copy of it one level per call therefore runs the two kernels
 on the same input.  The two must agree bit for bit on every population and
@@ -52,6 +52,16 @@ def _cases():
     # states streamed from HBM (two copies above the 320 MB cache bound: non-temporal stores), ragged tiles
     out["random_2050x1030_walls_y_f32"] = _random(2050, 1030, "f32", wall_y=True)
     out["random_1030x1030_walls_x_f64"] = _random(1030, 1030, "f64", wall_x=True)
+    # the local gradient scheme (Eq. local; five history planes, general collision)
+    for nx, ny, kw, dtype in ((70, 9, {}, "f32"), (70, 9, dict(wall_x=True, wall_y=True), "f64"),
+                              (2, 2, dict(wall_x=True, wall_y=True), "f32"), (66, 130, dict(wall_y=True), "f64"),
+                              (190, 1270, dict(wall_x=True, wall_y=True), "f32"), (2050, 1030, dict(wall_y=True), "f32")):
+        case, phi0, u0, p0 = _random(nx, ny, dtype, **kw)
+        walls = "".join(a for a, k in (("x", "wall_x"), ("y", "wall_y")) if kw.get(k))
+        out[f"local_{nx}x{ny}{'_walls_' + walls if walls else ''}_{dtype}"] = (case.replace(grad_scheme="local"), phi0,
+                                                                              u0, p0)
+    case, phi0, u0, p0 = _random(96, 40, "f32", wall_y=True)
+    out["local_96x40_walls_y_original_f32"] = (case.replace(model="original", grad_scheme="local"), phi0, u0, p0)
     case, phi0, u0, p0 = _random(96, 40, "f32", wall_y=True)
     out["random_96x40_walls_y_original_f32"] = (case.replace(model="original"), phi0, u0, p0)
     case, phi0, u0, p0 = _random(96, 40, "f64", wall_x=True)
