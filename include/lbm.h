@@ -151,9 +151,9 @@ int lbm_hydrostatic_pressure(const lbm_params *p, const void *phi0, void *p0, vo
 
 /* Advance nsteps >= 0 time steps (Sec. 3): moments, closure, both MRT
  * collisions and streaming with bounce-back, fused in one kernel per step --
- * or per two steps, for the Allen-Cahn step with stencil gradients (present
- * and original models) on a state whose two copies fit the 256 MB last-level
- * cache and whose lattice has at least 256 tiles of 64 x 8 nodes
+ * or per two steps, for the Allen-Cahn step with stencil or local gradients
+ * (present and original models) on a lattice of at least 256 tiles of 64 x 8
+ * nodes whose state copy is below 4 GiB, cache-resident or streamed from HBM
  * (lbm_levels_per_launch; the environment variable LBM_TWO_LEVEL = "0" or "1"
  * turns the size rule off or on for every such state): a run of n steps is
  * then n / 2 two-level launches and, for odd n, one one-level launch, with
