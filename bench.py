@@ -154,8 +154,14 @@ def cpu_baseline(budget_s=15.0, budget_1t_s=6.0):
     oracle.set_threads(1)
     mlups1, steps1, dt1 = run(budget_1t_s)
     oracle.set_threads(cores)
+    cpu = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            cpu = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), cpu)
+    except OSError:
+        pass
     return {"value": round(mlups, 3), "unit": "MLUPS", "cores": cores, "kind": "oracle",
-            "single_thread_value": round(mlups1, 3),
+            "single_thread_value": round(mlups1, 3), "cpu_model": cpu, "host_cpus": os.cpu_count(),
             "sample": f"FP64 oracle, rti 256x1024: {steps} steps on {cores} threads ({dt:.1f} s), "
                       f"{steps1} steps on 1 thread ({dt1:.1f} s), each after 2 untimed"}
 
