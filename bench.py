@@ -31,7 +31,9 @@ The JSON line also carries:
                   256 MB Infinity Cache), where a one-level launch is bound by
                   HBM and the two-level launch crosses HBM once per two levels,
                   next to the bandwidth of torch's own device copy and of the
-                  streaming probe; large_grid_fp64 the FP64 kernels there;
+                  streaming probe; large_grid_fp64 the FP64 kernels there,
+                  large_grid_2048x8192 the FP32 kernels on a lattice of the
+                  same nodes, four times taller than wide;
   batched      -- 64 droplet-spreading cases of uneven sizes (Sec. 4.3 set-up,
                   FP32): one launch per two levels over all cases (the
                   two-level batch kernel; the autotuned one-level launch for an
@@ -220,16 +222,17 @@ def measure_main(args, torch, W, Sim):
     }
 
 
-def measure_large(args, torch, W, Sim, dtype="f32"):
-    """The same kernel on a 4096 x 4096 lattice (state 2.9 GB in FP32, 5.6 GB in
-    FP64: far beyond the 256 MB cache), where a one-level launch is bound by HBM.
+def measure_large(args, torch, W, Sim, dtype="f32", nx=4096, ny=4096):
+    """The same kernel on a large lattice, nx x ny (4096 x 4096: state 2.9 GB in
+    FP32, 5.6 GB in FP64, far beyond the 256 MB cache), where a one-level launch
+    is bound by HBM.
     lbm_step advances two levels per launch there too, crossing HBM once per
     two levels: `achieved_GBs` counts the algorithmic 168 B (FP32) per lattice
     update, `hbm_GBs` the bytes one launch must move (the state read once and
     written once, whatever the levels it advances) over its duration; `one_level`
     times the same steps as one-level launches."""
     from paper_2111_00847_amd import api
-    caseL, phiL = W.rti(nx=4096, ny=4096, dtype=dtype)
+    caseL, phiL = W.rti(nx=nx, ny=ny, dtype=dtype)
     simL = Sim(caseL, "cuda:0").init(phiL, None, "hydrostatic")
     simL.step(10)
     steps = args.large_steps if dtype == "f32" else max(args.large_steps // 2, 1)
@@ -244,7 +247,7 @@ def measure_large(args, torch, W, Sim, dtype="f32"):
     del simL
     torch.cuda.empty_cache()
     t = "float" if dtype == "f32" else "double"
-    return {"workload": "rayleigh_taylor_4096x4096", "dtype": dtype, "steps": steps,
+    return {"workload": f"rayleigh_taylor_{nx}x{ny}", "dtype": dtype, "steps": steps,
             "value": round(caseL.nodes * steps / (msL * 1e-3) / 1e6, 1), "unit": "MLUPS",
             "kernel": f"k_step2<{t}> (two levels per launch)" if levels == 2 else f"k_step<{t}>",
             "levels_per_launch": levels, "achieved_GBs": round(achL, 1),
@@ -540,6 +543,7 @@ def main():
         out["large_grid"]["frac_of_stream_copy"] = round(out["large_grid"]["achieved_GBs"] / ceil["copy_GBs"], 4)
         if not args.only_large:
             out["large_grid_fp64"] = measure_large(args, torch, W, Sim, "f64")
+            out["large_grid_2048x8192"] = measure_large(args, torch, W, Sim, "f32", nx=2048, ny=8192)
     if not args.only_large:
         out["square_droplet"] = measure_square_droplet(torch, W, Sim)
     if not args.no_ch and not args.only_large:
