@@ -274,7 +274,9 @@ typedef struct lbm_batch lbm_batch;
 
 /* Plan a batch of `ncases` lattices (cases: host array of ncases lbm_params).
  * autotune != 0: the first lbm_batch_init times the candidate tile shapes and
- * persistent grid sizes on the batch itself and keeps the fastest. */
+ * grid sizes of the one-level batch launch (one workgroup per tile, or fewer
+ * workgroups striding over the tiles) on the batch itself and keeps the
+ * fastest. */
 int lbm_batch_create(const lbm_params *cases, int32_t ncases, int32_t autotune, lbm_batch **out);
 /* Bytes of the caller-allocated batch state (every case's state back to back). */
 int lbm_batch_state_size(const lbm_batch *batch, size_t *nbytes /* host */);

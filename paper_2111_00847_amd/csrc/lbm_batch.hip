@@ -1,15 +1,16 @@
 // lbm_batch.hip -- many independent lattices of uneven sizes advanced by one
-// persistent launch per time step.
+// launch per time step (or per two).
 //
 // The batch state is one caller buffer holding every case's own state
 // (same layout as a single lattice, 256-byte aligned, back to back).  A work
 // item is one 64 x TY tile of one case; items are numbered case by case and
-// a persistent grid of G workgroups takes items b, b + G, b + 2G, ...  Each
-// item runs exactly the single-lattice tile body (lbm_fused.hpp) with its
-// case's parameters and level stamps, so a case advanced in a batch is
-// bitwise identical to the same case advanced alone.  The tile height and G
-// are picked per batch by timing the candidates on the batch itself (the
-// autotuner), and K steps are captured once into a hipGraph and replayed.
+// a grid of one workgroup per item, or a grid of G workgroups that stride
+// over the items (b, b + G, b + 2G, ...), takes them.  Each item runs exactly
+// the single-lattice tile body (lbm_fused.hpp) with its case's parameters and
+// level stamps, so a case advanced in a batch is bitwise identical to the
+// same case advanced alone.  The tile height and G are picked per batch by
+// timing the candidates on the batch itself (the autotuner), and K steps are
+// captured once into a hipGraph and replayed.
 // Batches that hold Cahn-Hilliard or corrected Allen-Cahn cases (the
 // two-node-window body of lbm_ch_step.hpp) or local-gradient cases
 // (lbm_local_step.hpp) run a second kernel whose LDS holds any of the windows;
