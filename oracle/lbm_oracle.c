@@ -34,9 +34,11 @@
  * (tanh derivative); the wall rules that the paper leaves open -- the mirror
  * of mu_phi at walls (Cahn-Hilliard) and the mirror of D with reversed normal
  * component (corrected AC model) -- by the no-flux property they stand for
- * (sum of F_a's coefficient over a walled lattice is zero).  Parity unpinned,
- * checked only against the GPU path: the values of the diagnostics S_m^rms,
- * D_u^rms.
+ * (sum of F_a's coefficient over a walled lattice is zero); the diagnostics
+ * (Sec. 4.1) by the expansion Eq. strainRate comes from (its trace on a
+ * compressive wave) and by S_m = rho div u at equal densities and its
+ * second-order fall for a carried, relaxing interface
+ * (tests/test_oracle_diagnostics.py).
  */
 #include "lbm_oracle.h"
 
