@@ -61,14 +61,16 @@ __device__ __forceinline__ void ch_fill(const KParams<T>& P, const Copy<T>& S, b
 
 // per_node(M, f, g, phid, x, y, k): called for every node of the tile with its
 // Macro (Cahn-Hilliard closure), pulled populations f, g and FP64 phi.
-// Thread (lx, ly) owns nodes (x0 + lx, y0 + ly + BY r), r < TY / BY: their f, g
-// and history are pulled first and kept in registers to the collision; the
-// two-node ring of the phi window is pulled afterwards by all threads.
-template <typename T, int TY, bool ACC = false, typename F>
+// Thread (lx, ly) of 64 x NBY owns nodes (x0 + lx, y0 + ly + NBY r), r < TY /
+// NBY: their f, g and history are pulled first and kept in registers to the
+// collision; the two-node ring of the phi window is pulled afterwards by all
+// threads.
+template <typename T, int TY, bool ACC = false, int NBY = BY, typename F>
 __device__ __forceinline__ void ch_tile(const KParams<T>& P, const Copy<T>& S, int64_t step, int x0, int y0,
                                         ChWindow<T, TY>& W, F&& per_node) {
     using Win = ChWindow<T, TY>;
-    constexpr int R = TY / BY;
+    static_assert(TY % NBY == 0, "whole thread rows");
+    constexpr int R = TY / NBY;
     constexpr int NRING = 4 * Win::PX + 4 * TY;   // two rows above and below, two columns left and right
     const bool first = step == 0;
     const int tid = threadIdx.y * TX + threadIdx.x;
@@ -78,7 +80,7 @@ __device__ __forceinline__ void ch_tile(const KParams<T>& P, const Copy<T>& S, i
     double phid[R];
 #pragma unroll
     for (int r = 0; r < R; r++) {
-        const int ly = threadIdx.y + r * BY;
+        const int ly = threadIdx.y + r * NBY;
         const int x = x0 + lx, y = y0 + ly;
         if (x < P.nx && y < P.ny) {
             const long long k = (long long)y * P.nx + x;
@@ -95,7 +97,7 @@ __device__ __forceinline__ void ch_tile(const KParams<T>& P, const Copy<T>& S, i
             ch_fill<T, TY>(P, S, first, x0, y0, lx + 2, ly + 2, W);   // ragged tile: serves as ring
         }
     }
-    for (int idx = tid; idx < NRING; idx += TX * BY) {
+    for (int idx = tid; idx < NRING; idx += TX * NBY) {
         int wx, wy;
         if (idx < 4 * Win::PX) {
             const int band = idx / Win::PX;
@@ -112,7 +114,7 @@ __device__ __forceinline__ void ch_tile(const KParams<T>& P, const Copy<T>& S, i
     // 2. first ghost layer of phi: x-walls on rows that hold nodes, then y-walls across all columns
     if (P.wall_x) {
         const int wr = P.nx - x0 + 2;   // window column of x = nx
-        for (int wy = tid; wy < Win::PY; wy += TX * BY) {
+        for (int wy = tid; wy < Win::PY; wy += TX * NBY) {
             const int gy = y0 - 2 + wy;
             if (gy > P.ny + 1 || (P.wall_y && (gy < 0 || gy >= P.ny))) continue;
             if (x0 == 0) {
@@ -128,7 +130,7 @@ __device__ __forceinline__ void ch_tile(const KParams<T>& P, const Copy<T>& S, i
     }
     if (P.wall_y) {
         const int wt = P.ny - y0 + 2;   // window row of y = ny
-        for (int wx = tid; wx < Win::PX; wx += TX * BY) {
+        for (int wx = tid; wx < Win::PX; wx += TX * NBY) {
             const int gx = x0 - 2 + wx;
             if (P.wall_x ? (gx < -1 || gx > P.nx) : gx > P.nx + 1) continue;
             if (y0 == 0) {
@@ -143,7 +145,7 @@ __device__ __forceinline__ void ch_tile(const KParams<T>& P, const Copy<T>& S, i
         __syncthreads();
     }
     // 3. mu (ACC: D) on the one-node window (nodes only)
-    for (int idx = tid; idx < Win::MX * Win::MY; idx += TX * BY) {
+    for (int idx = tid; idx < Win::MX * Win::MY; idx += TX * NBY) {
         const int wy = idx / Win::MX, wx = idx - wy * Win::MX;
         int gx = x0 - 1 + wx, gy = y0 - 1 + wy;
         if (!ch_node(P, gx, gy, P.nx, P.ny)) continue;
@@ -170,7 +172,7 @@ __device__ __forceinline__ void ch_tile(const KParams<T>& P, const Copy<T>& S, i
     const bool second = ACC || !first;  // mup holds D_y (ACC) or the previous mu
     if (P.wall_x) {
         const int wr = P.nx - x0 + 1;   // mu-window column of x = nx
-        for (int wy = tid; wy < Win::MY; wy += TX * BY) {
+        for (int wy = tid; wy < Win::MY; wy += TX * NBY) {
             const int gy = y0 - 1 + wy;
             if (gy > P.ny || (P.wall_y && (gy < 0 || gy >= P.ny))) continue;
             if (x0 == 0) {
@@ -186,7 +188,7 @@ __device__ __forceinline__ void ch_tile(const KParams<T>& P, const Copy<T>& S, i
     }
     if (P.wall_y) {
         const int wt = P.ny - y0 + 1;
-        for (int wx = tid; wx < Win::MX; wx += TX * BY) {
+        for (int wx = tid; wx < Win::MX; wx += TX * NBY) {
             const int gx = x0 - 1 + wx;
             if (gx > P.nx) continue;
             if (y0 == 0) {
@@ -203,7 +205,7 @@ __device__ __forceinline__ void ch_tile(const KParams<T>& P, const Copy<T>& S, i
     // 5. the nodes of the tile
 #pragma unroll
     for (int r = 0; r < R; r++) {
-        const int ly = threadIdx.y + r * BY;
+        const int ly = threadIdx.y + r * NBY;
         const int x = x0 + lx, y = y0 + ly;
         if (x >= P.nx || y >= P.ny) continue;
         const long long k = (long long)y * P.nx + x;

@@ -13,7 +13,7 @@ namespace lbm {
 // MODE 0: one time step, the tile's rows move to the next level; MODE 1:
 // phi, u, p of the current level into out_*.  W: the tile's LDS windows.
 // STD: the paper's default rates compiled in (P.rates_std).
-template <typename T, int TY, int MODE, bool ACC, bool STD = false, bool NT = true>
+template <typename T, int TY, int MODE, bool ACC, bool STD = false, bool NT = true, int NBY = BY>
 __device__ __forceinline__ void ch_step_tile(const KParams<T>& P, char* state, size_t off0, size_t off1,
                                              size_t off_stamp, int xt, int yt, T* out_phi, T* out_u, T* out_p,
                                              ChWindow<T, TY>& W) {
@@ -23,7 +23,7 @@ __device__ __forceinline__ void ch_step_tile(const KParams<T>& P, char* state, s
     const int cur = stamp_copy(sv);
     const Copy<T> S = copy_at<T>(state + (cur ? off1 : off0), P.plane);
     const Copy<T> D = copy_at<T>(state + (cur ? off0 : off1), P.plane);
-    ch_tile<T, TY, ACC>(P, S, step, x0, y0, W, [&](const Macro<T>& M, T* f, T* g, double phid, int, int, long long k) {
+    ch_tile<T, TY, ACC, NBY>(P, S, step, x0, y0, W, [&](const Macro<T>& M, T* f, T* g, double phid, int, int, long long k) {
         if (MODE == 1) {
             if (out_phi) out_phi[k] = M.phi;
             if (out_u) {

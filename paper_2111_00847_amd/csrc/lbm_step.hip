@@ -56,22 +56,23 @@ void k_step(KParams<T> P, char* state, size_t off0, size_t off1, size_t off_stam
 
 // The Cahn-Hilliard variant and the corrected comparison model with the
 // Allen-Cahn phase field (ACC), both on the two-node phi window of lbm_ch.hpp:
-// one 64 x TY tile per workgroup of 64 x 4 threads, tiles dealt to the XCDs as
-// for the Allen-Cahn step, the same state layout, level stamps and store
-// policy.  MODE 0: one time step; MODE 1: phi, u, p of the current level.
-// Tile rows (measured on MI355X, square droplet): 8 when that still gives >= 1024
-// tiles (+9% over 4 rows at 4096^2 FP32, +3% at 1024^2, equal in FP64), else 4
-// (+57% over 8 rows at 200^2, where the step is latency-bound); 16 rows lose
-// 4-10% (FP32) and spill to one wave per SIMD in FP64.  LBM_CH_TY forces 4, 8
-// or 16.
+// one 64 x TY tile per workgroup, one node per thread (64 x TY threads; 64 x 8
+// for 16 rows), tiles dealt to the XCDs as for the Allen-Cahn step, the same
+// state layout, level stamps and store policy.  MODE 0: one time step; MODE 1:
+// phi, u, p of the current level.  Tile shape (measured on MI355X, FP32 square
+// droplet, us per step): 8 rows on 64 x 8 threads 574 / 39.5 / 9.4 at 4096^2 /
+// 1024^2 / 200^2, against 589 / 42.0 / 11.7 for the shapes used before (8 rows
+// on 64 x 4 threads with two nodes per thread, 4 rows on 64 x 4 below 1024
+// tiles); 16 rows on 64 x 8 threads 575 / 38.2 / 18.4; 16 rows on 64 x 16 656 /
+// 43.2 / 14.0.  LBM_CH_TY forces 4, 8 or 16 rows.
 #ifndef LBM_CH_TY
 #define LBM_CH_TY 0
 #endif
 
-template <typename T, int TY, int MODE, bool ACC, bool STD, bool NT = true>
-__global__ __launch_bounds__(TX* BY) void k_step_ch(KParams<T> P, char* state, size_t off0, size_t off1,
-                                                   size_t off_stamp, int ntx, int nty, T* out_phi, T* out_u,
-                                                   T* out_p) {
+template <typename T, int TY, int MODE, bool ACC, bool STD, bool NT = true, int NBY = BY>
+__global__ __launch_bounds__(TX* NBY) void k_step_ch(KParams<T> P, char* state, size_t off0, size_t off1,
+                                                    size_t off_stamp, int ntx, int nty, T* out_phi, T* out_u,
+                                                    T* out_p) {
     __shared__ ChWindow<T, TY> W;
     int xt, yt;
     if (LBM_XCD_REMAP) {
@@ -80,29 +81,28 @@ __global__ __launch_bounds__(TX* BY) void k_step_ch(KParams<T> P, char* state, s
         xt = blockIdx.x % ntx;
         yt = blockIdx.x / ntx;
     }
-    ch_step_tile<T, TY, MODE, ACC, STD, NT>(P, state, off0, off1, off_stamp, xt, yt, out_phi, out_u, out_p, W);
+    ch_step_tile<T, TY, MODE, ACC, STD, NT, NBY>(P, state, off0, off1, off_stamp, xt, yt, out_phi, out_u, out_p, W);
 }
 
-static int ch_rows(int nx, int ny) {
+static int ch_rows() {
     if (LBM_CH_TY == 4 || LBM_CH_TY == 8 || LBM_CH_TY == 16) return LBM_CH_TY;
-    const long long ntx = (nx + TX - 1) / TX;
-    return ntx * ((ny + 7) / 8) >= 1024 ? 8 : 4;
+    return 8;
 }
 
 template <typename T, int MODE, bool ACC, bool STD, bool NT = true>
 static void launch_ch_acc_std(const KParams<T>& P, char* state, const Layout& L, hipStream_t s, T* phi, T* u, T* p) {
-    const int ty = ch_rows(P.nx, P.ny);
+    const int ty = ch_rows();
     const int ntx = (P.nx + TX - 1) / TX, nty = (P.ny + ty - 1) / ty;
-    const dim3 grd(ntx * nty), blk(TX, BY);
+    const dim3 grd(ntx * nty);
     if (ty == 16)
-        k_step_ch<T, 16, MODE, ACC, STD, NT><<<grd, blk, 0, s>>>(P, state, L.off_buf[0], L.off_buf[1], L.off_stamp,
-                                                                 ntx, nty, phi, u, p);
+        k_step_ch<T, 16, MODE, ACC, STD, NT, 8><<<grd, dim3(TX, 8), 0, s>>>(P, state, L.off_buf[0], L.off_buf[1],
+                                                                           L.off_stamp, ntx, nty, phi, u, p);
     else if (ty == 8)
-        k_step_ch<T, 8, MODE, ACC, STD, NT><<<grd, blk, 0, s>>>(P, state, L.off_buf[0], L.off_buf[1], L.off_stamp,
-                                                                ntx, nty, phi, u, p);
+        k_step_ch<T, 8, MODE, ACC, STD, NT, 8><<<grd, dim3(TX, 8), 0, s>>>(P, state, L.off_buf[0], L.off_buf[1],
+                                                                          L.off_stamp, ntx, nty, phi, u, p);
     else
-        k_step_ch<T, 4, MODE, ACC, STD, NT><<<grd, blk, 0, s>>>(P, state, L.off_buf[0], L.off_buf[1], L.off_stamp,
-                                                                ntx, nty, phi, u, p);
+        k_step_ch<T, 4, MODE, ACC, STD, NT, 4><<<grd, dim3(TX, 4), 0, s>>>(P, state, L.off_buf[0], L.off_buf[1],
+                                                                          L.off_stamp, ntx, nty, phi, u, p);
 }
 
 // the standard rates compiled in for steps (moments do not collide); steps on
