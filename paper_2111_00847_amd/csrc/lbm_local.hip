@@ -2,7 +2,7 @@
 // Eq. local (levels >= 1; level 0 and lap phi by the stencils of Eqs. central1
 // and central2).  The history of a copy then holds phi, u, v and m^phiC of the
 // previous level (5 planes), since m^phiC of that level came from its own
-// local gradient.  One 64 x 8 tile per workgroup of 64 x 4 threads, the phi
+// local gradient.  One 64 x 8 tile per workgroup of 64 x 8 threads, the phi
 // window with a one-node ring in LDS (for lap phi), tiles dealt to the XCDs as
 // for the stencil step, the same store policy (non-temporal for states beyond
 // the last-level cache).
@@ -11,10 +11,18 @@
 
 namespace lbm {
 
+// Thread rows: one node per thread (measured on MI355X, FP32 RTI, us per
+// step against 64 x 4 threads of two nodes each: 256 x 256 7.65 against 10.0,
+// 4096 x 4096 582 against 599, 1024 x 512 20.9 against 20.1 -- a lattice the
+// two-level launch takes).  LBM_LOC_NBY=4 restores two nodes per thread.
 constexpr int LOC_TY = 8;
+#ifndef LBM_LOC_NBY
+#define LBM_LOC_NBY 8
+#endif
+constexpr int LOC_NBY = LBM_LOC_NBY;
 
 template <typename T, int MODE, bool NT = true>
-__global__ __launch_bounds__(TX* BY) void k_step_local(KParams<T> P, char* state, size_t off0, size_t off1,
+__global__ __launch_bounds__(TX* LOC_NBY) void k_step_local(KParams<T> P, char* state, size_t off0, size_t off1,
                                                       size_t off_stamp, int ntx, int nty, T* out_phi, T* out_u,
                                                       T* out_p) {
     __shared__ T sphi[LOC_TY + 2][TX + 3];
@@ -25,17 +33,18 @@ __global__ __launch_bounds__(TX* BY) void k_step_local(KParams<T> P, char* state
         xt = blockIdx.x % ntx;
         yt = blockIdx.x / ntx;
     }
-    local_step_tile<T, LOC_TY, MODE, NT>(P, state, off0, off1, off_stamp, xt, yt, out_phi, out_u, out_p, sphi);
+    local_step_tile<T, LOC_TY, MODE, NT, LOC_NBY>(P, state, off0, off1, off_stamp, xt, yt, out_phi, out_u, out_p,
+                                              sphi);
 }
 
 template <typename T, int MODE>
 void launch_local(const KParams<T>& P, char* state, const Layout& L, hipStream_t s, T* phi, T* u, T* p) {
     const int ntx = (P.nx + TX - 1) / TX, nty = (P.ny + LOC_TY - 1) / LOC_TY;
     if (MODE == 0 && cached_state(L))
-        k_step_local<T, MODE, false><<<ntx * nty, dim3(TX, BY), 0, s>>>(P, state, L.off_buf[0], L.off_buf[1],
+        k_step_local<T, MODE, false><<<ntx * nty, dim3(TX, LOC_NBY), 0, s>>>(P, state, L.off_buf[0], L.off_buf[1],
                                                                          L.off_stamp, ntx, nty, phi, u, p);
     else
-        k_step_local<T, MODE><<<ntx * nty, dim3(TX, BY), 0, s>>>(P, state, L.off_buf[0], L.off_buf[1], L.off_stamp,
+        k_step_local<T, MODE><<<ntx * nty, dim3(TX, LOC_NBY), 0, s>>>(P, state, L.off_buf[0], L.off_buf[1], L.off_stamp,
                                                                   ntx, nty, phi, u, p);
 }
 

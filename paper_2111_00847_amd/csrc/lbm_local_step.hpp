@@ -12,11 +12,12 @@ namespace lbm {
 
 // MODE 0: one time step, the tile's rows move to the next level; MODE 1:
 // phi, u, p of the current level into out_*.  sphi: the tile's phi window.
-template <typename T, int TY, int MODE, bool NT = true>
+template <typename T, int TY, int MODE, bool NT = true, int NBY = BY>
 __device__ __forceinline__ void local_step_tile(const KParams<T>& P, char* state, size_t off0, size_t off1,
                                                 size_t off_stamp, int xt, int yt, T* out_phi, T* out_u, T* out_p,
                                                 T (*sphi)[TX + 3]) {
-    constexpr int R = TY / BY;
+    static_assert(TY % NBY == 0, "whole thread rows");
+    constexpr int R = TY / NBY;
     const int x0 = xt * TX, y0 = yt * TY;
     int64_t* stamp = reinterpret_cast<int64_t*>(state + off_stamp) + (size_t)xt * P.ny + y0;
     const int64_t sv = stamp[0], step = stamp_level(sv);
@@ -48,7 +49,7 @@ __device__ __forceinline__ void local_step_tile(const KParams<T>& P, char* state
     double phid[R];
 #pragma unroll
     for (int r = 0; r < R; r++) {
-        const int ly = threadIdx.y + r * BY;
+        const int ly = threadIdx.y + r * NBY;
         const int x = x0 + lx, y = y0 + ly;
         if (x < P.nx && y < P.ny) {
             const long long k = (long long)y * P.nx + x;
@@ -64,15 +65,15 @@ __device__ __forceinline__ void local_step_tile(const KParams<T>& P, char* state
         }
     }
     constexpr int WX = TX + 2;
-    for (int idx = tid; idx < 2 * WX + 2 * TY; idx += TX * BY) {
+    for (int idx = tid; idx < 2 * WX + 2 * TY; idx += TX * NBY) {
         if (idx < 2 * WX) fill(idx % WX, idx < WX ? 0 : TY + 1);
         else fill(idx < 2 * WX + TY ? 0 : WX - 1, 1 + (idx - 2 * WX) % TY);
     }
     __syncthreads();
-    wall_ghosts<T, TY>(P, false, x0, y0, sphi, sphi);
+    wall_ghosts<T, TY, NBY>(P, false, x0, y0, sphi, sphi);
 #pragma unroll
     for (int r = 0; r < R; r++) {
-        const int ly = threadIdx.y + r * BY;
+        const int ly = threadIdx.y + r * NBY;
         const int x = x0 + lx, y = y0 + ly;
         if (x >= P.nx || y >= P.ny) continue;
         const long long k = (long long)y * P.nx + x;
