@@ -259,8 +259,8 @@ int lbm_adjoint_import(const lbm_params *p, void *adj, const void *fbar, const v
  * (the per-step update above applied to every case).  All cases share one
  * dtype; any option; each case's state copy below 4 GiB (else LBM_E_SIZE: the
  * batch kernels address a case with 32-bit offsets).  Batches holding Cahn-Hilliard,
- * corrected Allen-Cahn or local-gradient cases run 64 x 4-thread tiles of 4
- * or 8 rows; those cases equal the lone runs to rounding (the tile height may
+ * corrected Allen-Cahn or local-gradient cases run tiles of 4 or 8 rows, one
+ * node per thread; those cases equal the lone runs to rounding (the tile height may
  * differ), the plain Allen-Cahn cases bitwise.  A batch whose every case runs
  * the plain Allen-Cahn step (stencil gradients, present or original model)
  * advances two levels per launch as lbm_step does (64 x 8 tiles; an odd step

@@ -117,11 +117,13 @@ __global__ __launch_bounds__(TX * 8) void k_step2_batch(const BatchCase<T>* __re
                                         local / C.ntx, L);
 }
 
-// Batches with two-node-window or local-gradient cases: 64 x 4 threads, the
-// LDS holds any of the windows, each item runs its case's body.
-template <typename T, int TY, bool NT>
-__global__ __launch_bounds__(TX* BY) void k_step_batch_wide(const BatchCase<T>* __restrict__ cases, int ncases,
+// Batches with two-node-window or local-gradient cases: 64 x TY threads (one
+// node per thread), the LDS holds any of the windows, each item runs its
+// case's body; LOOP as for k_step_batch.
+template <typename T, int TY, bool NT, bool LOOP = true>
+__global__ __launch_bounds__(TX* TY) void k_step_batch_wide(const BatchCase<T>* __restrict__ cases, int ncases,
                                                             int nitems, char* batch_state) {
+    constexpr int NBY = TY;
     __shared__ union {
         struct {
             T sphi[TY + 2][TX + 3];
@@ -129,32 +131,40 @@ __global__ __launch_bounds__(TX* BY) void k_step_batch_wide(const BatchCase<T>* 
         } ac;
         ChWindow<T, TY> ch;
     } lds;
-    for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
-        const BatchCase<T>& C = cases[batch_case(cases, ncases, w, TX * BY)];
+    auto item = [&](int w) {
+        const BatchCase<T>& C = cases[batch_case(cases, ncases, w, TX * NBY)];
         const int local = w - C.item_begin;
+        const int xt = local % C.ntx, yt = local / C.ntx;
         char* st0 = batch_state + C.base;
         if (C.body == 0 && C.P.rates_std)
-            step_tile<T, TY, 0, uint32_t, BY, true, NT>(C.P, st0, C.off0, C.off1, C.off_stamp, local % C.ntx,
-                                                    local / C.ntx, nullptr, nullptr, nullptr, lds.ac.sphi, lds.ac.sphp);
+            step_tile<T, TY, 0, uint32_t, NBY, true, NT>(C.P, st0, C.off0, C.off1, C.off_stamp, xt, yt, nullptr,
+                                                         nullptr, nullptr, lds.ac.sphi, lds.ac.sphp);
         else if (C.body == 0)
-            step_tile<T, TY, 0, uint32_t, BY, false, NT>(C.P, st0, C.off0, C.off1, C.off_stamp, local % C.ntx,
-                                                     local / C.ntx, nullptr, nullptr, nullptr, lds.ac.sphi, lds.ac.sphp);
+            step_tile<T, TY, 0, uint32_t, NBY, false, NT>(C.P, st0, C.off0, C.off1, C.off_stamp, xt, yt, nullptr,
+                                                          nullptr, nullptr, lds.ac.sphi, lds.ac.sphp);
         else if (C.body == 1 && C.P.rates_std)
-            ch_step_tile<T, TY, 0, false, true, NT>(C.P, st0, C.off0, C.off1, C.off_stamp, local % C.ntx, local / C.ntx,
-                                                nullptr, nullptr, nullptr, lds.ch);
+            ch_step_tile<T, TY, 0, false, true, NT, NBY>(C.P, st0, C.off0, C.off1, C.off_stamp, xt, yt, nullptr,
+                                                         nullptr, nullptr, lds.ch);
         else if (C.body == 1)
-            ch_step_tile<T, TY, 0, false, false, NT>(C.P, st0, C.off0, C.off1, C.off_stamp, local % C.ntx, local / C.ntx,
-                                                 nullptr, nullptr, nullptr, lds.ch);
+            ch_step_tile<T, TY, 0, false, false, NT, NBY>(C.P, st0, C.off0, C.off1, C.off_stamp, xt, yt, nullptr,
+                                                          nullptr, nullptr, lds.ch);
         else if (C.body == 3)
-            local_step_tile<T, TY, 0, NT>(C.P, st0, C.off0, C.off1, C.off_stamp, local % C.ntx, local / C.ntx, nullptr,
-                                      nullptr, nullptr, lds.ac.sphi);
+            local_step_tile<T, TY, 0, NT, NBY>(C.P, st0, C.off0, C.off1, C.off_stamp, xt, yt, nullptr, nullptr,
+                                               nullptr, lds.ac.sphi);
         else if (C.P.rates_std)
-            ch_step_tile<T, TY, 0, true, true, NT>(C.P, st0, C.off0, C.off1, C.off_stamp, local % C.ntx, local / C.ntx,
-                                               nullptr, nullptr, nullptr, lds.ch);
+            ch_step_tile<T, TY, 0, true, true, NT, NBY>(C.P, st0, C.off0, C.off1, C.off_stamp, xt, yt, nullptr,
+                                                        nullptr, nullptr, lds.ch);
         else
-            ch_step_tile<T, TY, 0, true, false, NT>(C.P, st0, C.off0, C.off1, C.off_stamp, local % C.ntx, local / C.ntx,
-                                                nullptr, nullptr, nullptr, lds.ch);
-        __syncthreads();   // the next item reuses the LDS
+            ch_step_tile<T, TY, 0, true, false, NT, NBY>(C.P, st0, C.off0, C.off1, C.off_stamp, xt, yt, nullptr,
+                                                         nullptr, nullptr, lds.ch);
+    };
+    if constexpr (LOOP) {
+        for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
+            item(w);
+            __syncthreads();   // the next item reuses the LDS
+        }
+    } else if ((int)blockIdx.x < nitems) {   // uniform over the workgroup
+        item(blockIdx.x);
     }
 }
 
@@ -174,7 +184,7 @@ struct lbm_batch {
     size_t total = 0;
     int autotune = 0;
     bool tuned = false;
-    bool wide = false;    // some case runs the two-node-window or local body (64 x 4 threads only)
+    bool wide = false;    // some case runs the two-node-window or local body (one node per thread)
     int ty = 8;
     int by = 4;           // thread rows per workgroup
     int grid = 0;
@@ -270,12 +280,16 @@ void batch_launch(const BatchShape& S, const void* d_cases, char* state, hipStre
 
 template <typename T, int TY>
 void batch_launch_wide(const BatchShape& S, const void* d_cases, char* state, hipStream_t s) {
-    const int g = S.grid > 0 ? S.grid : S.nitems;
     const BatchCase<T>* cases = reinterpret_cast<const BatchCase<T>*>(d_cases);
-    if (S.total <= (size_t)LBM_NT_MIN_BYTES)
-        k_step_batch_wide<T, TY, false><<<g, dim3(TX, BY), 0, s>>>(cases, S.ncases, S.nitems, state);
-    else
-        k_step_batch_wide<T, TY, true><<<g, dim3(TX, BY), 0, s>>>(cases, S.ncases, S.nitems, state);
+    const bool nt = S.total > (size_t)LBM_NT_MIN_BYTES;
+    const dim3 blk(TX, TY);
+    if (S.grid > 0 && S.grid < S.nitems) {
+        if (nt) k_step_batch_wide<T, TY, true><<<S.grid, blk, 0, s>>>(cases, S.ncases, S.nitems, state);
+        else k_step_batch_wide<T, TY, false><<<S.grid, blk, 0, s>>>(cases, S.ncases, S.nitems, state);
+    } else {
+        if (nt) k_step_batch_wide<T, TY, true, false><<<S.nitems, blk, 0, s>>>(cases, S.ncases, S.nitems, state);
+        else k_step_batch_wide<T, TY, false, false><<<S.nitems, blk, 0, s>>>(cases, S.ncases, S.nitems, state);
+    }
 }
 
 template <typename T>
@@ -389,7 +403,7 @@ int autotune_t(lbm_batch* B, char* state, const void* const* phi0, const void* c
     for (const auto& sh : shapes) {
         const int ty = sh[0];
         if (ty == 16 && sizeof(T) == 8) continue;
-        if (B->wide && (sh[1] != 4 || ty > 8)) continue;   // the wide bodies: 64 x 4 threads
+        if (B->wide && (sh[1] != ty || ty > 8)) continue;   // the wide bodies: one node per thread
         B->ty = ty;
         B->by = sh[1];
         hipError_t e = upload_cases<T>(B, ty);
@@ -537,8 +551,8 @@ int batch_step_noalloc_t(const lbm_params* cases, int ncases, char* state, int64
     hipError_t e = scratch_address(&dtab);
     if (e != hipSuccess) return hip_fail(e);
     BatchCase<T>* table = reinterpret_cast<BatchCase<T>*>(dtab);
-    // the untuned plan's shape: 8-row tiles, 64 x 4 threads, one workgroup per
-    // item; the same table serves the two-level launch (8-row tiles too)
+    // the untuned plan's shape: 8-row tiles, 64 x 4 threads (64 x 8 for the wide bodies), one
+    // workgroup per item; the same table serves the two-level launch (8-row tiles too)
     const int ty = 8;
     CaseChunk<T> chunk;
     int nitems = 0;
@@ -552,7 +566,8 @@ int batch_step_noalloc_t(const lbm_params* cases, int ncases, char* state, int64
         chunk.count = cnt;
         k_put_cases<T><<<1, 64, 0, s>>>(chunk, table);
     }
-    const BatchShape S{ty, 4, 0, nitems, ncases, wide_batch(cases, ncases), total};
+    const bool wide = wide_batch(cases, ncases);
+    const BatchShape S{ty, wide ? ty : 4, 0, nitems, ncases, wide, total};
     int64_t t = 0;
     if (two_level_batch(cases, ncases))
         for (; t + 2 <= nsteps; t += 2) launch_batch2<T>(nitems, ncases, table, total, state, s);
@@ -581,8 +596,10 @@ int lbm_batch_create(const lbm_params* cases, int32_t ncases, int32_t autotune, 
     int dev = 0;
     if (hipGetDevice(&dev) == hipSuccess)
         (void)hipDeviceGetAttribute(&B->cus, hipDeviceAttributeMultiprocessorCount, dev);
-    // default (untuned) choice: 8-row tiles on 256-thread workgroups, one workgroup per item
+    // default (untuned) choice: 8-row tiles, one workgroup per item (64 x 4 threads; the
+    // wide bodies: 64 x 8, one node per thread)
     B->ty = 8;
+    B->by = B->wide ? 8 : 4;
     B->grid = 0;
     hipError_t e = B->dtype == LBM_F32 ? upload_cases<float>(B, B->ty) : upload_cases<double>(B, B->ty);
     B->two_level = two_level_batch(cases, ncases);
