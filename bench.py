@@ -49,9 +49,13 @@ The JSON line also carries:
                   local) on the 4096 x 4096 RTI lattice (FP32), two levels per
                   launch (and one-level launches beside it);
   adjoint      -- the differentiable dam break (Sec. 4.5 set-up, 1024 x 512,
-                  FP32, 4000 steps, checkpoints every 200): time of the
-                  backward pass (tape recompute + adjoint steps) over the time
-                  of the plain forward without snapshots;
+                  FP32, 4000 steps): time of the backward pass over the time
+                  of the plain forward.  With the full tape (every level kept:
+                  176 GB, used when it fits in 3/4 of the free device memory)
+                  the forward records the tape and the backward runs only the
+                  adjoint steps; `checkpointed` times the same gradients with
+                  checkpoints every 200 levels (tape recompute + adjoint steps
+                  in backward);
   cpu_baseline -- the FP64 oracle timed on the host on a bounded sample.
 """
 import argparse
@@ -428,25 +432,43 @@ def measure_adjoint(args, torch, W, Sim):
     theta = torch.tensor([math.pi / 2] * 4, dtype=torch.float64, requires_grad=True)
     box = {}
 
-    def fwd():
-        box["phi"] = LBMFunction.apply(phi0_t, grav, theta, case, N, None, chk)
-
-    def run():
+    def run(c):
         for t in (phi0_t, grav, theta):
             t.grad = None
-        ms_f = _timed(stream, torch, fwd)
+        ms_f = _timed(stream, torch, lambda: box.__setitem__("phi", LBMFunction.apply(phi0_t, grav, theta, case, N,
+                                                                                       None, c)))
         box["L"] = ((box["phi"] - target) ** 2).sum()
         ms_b = _timed(stream, torch, lambda: box["L"].backward())
-        return ms_f, ms_b
+        grads = (float(grav.grad[1]), float(theta.grad.sum()))
+        ok = bool(torch.isfinite(phi0_t.grad).all()) and all(math.isfinite(v) for v in grads)
+        assert ok, "non-finite gradient"
+        return ms_f, ms_b, grads
 
-    run()   # untimed: afterwards the snapshots, tape and adjoint buffers come from torch's cache
-    ms_fwd_ckpt, ms_bwd = run()
-    ok = bool(torch.isfinite(phi0_t.grad).all()) and math.isfinite(float(grav.grad[1]))
-    assert ok, "non-finite gradient"
-    out = {"workload": "dam_break_1024x512_fp32", "steps": N, "checkpoint_every": chk,
-           "forward_ms": round(ms_fwd, 2), "forward_with_snapshots_ms": round(ms_fwd_ckpt, 2),
+    # the full tape (every level kept, no recomputation) when it fits in 3/4 of
+    # the free device memory, else checkpoints only
+    from paper_2111_00847_amd import api
+    tape_bytes = api.lbm_tape_size(api.make_params(case), N + 1)
+    full = tape_bytes <= 0.75 * torch.cuda.mem_get_info()[0]
+    modes = ([0] if full else []) + [chk]
+    res = {}
+    for c in modes:
+        run(c)   # untimed: afterwards the snapshots, tape and adjoint buffers come from torch's cache
+        res[c] = run(c)
+        box.clear()
+        torch.cuda.empty_cache()
+    if full:
+        assert res[0][2] == res[chk][2], "full-tape and checkpointed gradients differ"
+    ms_fwd_m, ms_bwd, grads = res[modes[0]]
+    out = {"workload": "dam_break_1024x512_fp32", "steps": N,
+           "mode": "full tape" if full else f"checkpoints every {chk}",
+           "tape_GB": round(tape_bytes / 1e9, 1) if full else None,
+           "forward_ms": round(ms_fwd, 2), "forward_recording_ms": round(ms_fwd_m, 2),
            "backward_ms": round(ms_bwd, 2), "backward_over_forward": round(ms_bwd / ms_fwd, 3),
-           "dL_dg": -float(grav.grad[1]), "dL_dtheta": float(theta.grad.sum())}
+           "dL_dg": -grads[0], "dL_dtheta": grads[1]}
+    if full:
+        ck = res[chk]
+        out["checkpointed"] = {"checkpoint_every": chk, "forward_with_snapshots_ms": round(ck[0], 2),
+                               "backward_ms": round(ck[1], 2), "backward_over_forward": round(ck[1] / ms_fwd, 3)}
     del box, phi0_t
     torch.cuda.empty_cache()
     return out

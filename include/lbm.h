@@ -226,6 +226,13 @@ int lbm_tape_size(const lbm_params *p, int32_t nlevels, size_t *nbytes /* host *
  * nlevels - 1 ordinary steps run from tape slot to tape slot (bitwise the
  * levels lbm_step would produce). */
 int lbm_tape_record(const lbm_params *p, const void *state, void *tape, int32_t nlevels, void *stream);
+/* Make tape slot j the current level of `state` (level = the tape's first
+ * level + j; the state's other copy is left as it is): with a tape recorded
+ * for every level of a trajectory, the forward pass ends here instead of
+ * stepping again.  Reads the tape's header back to the host (synchronises the
+ * stream): LBM_E_SIZE when the tape holds no slot j, LBM_E_PARAM when it was
+ * recorded for another lattice or dtype. */
+int lbm_tape_restore(const lbm_params *p, const void *tape, int32_t j, void *state, void *stream);
 /* Bytes of an adjoint buffer. */
 int lbm_adjoint_size(const lbm_params *p, size_t *nbytes /* host */);
 /* Start a backward pass at the level N of `state`: dL/df_i^N = dL/dphi^N for

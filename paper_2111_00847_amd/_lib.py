@@ -64,6 +64,7 @@ _SIGS = {
     "lbm_import_state": [P(LbmParams), vp, vp, vp, vp, ctypes.c_int64, vp],
     "lbm_tape_size": [P(LbmParams), ctypes.c_int32, P(ctypes.c_size_t)],
     "lbm_tape_record": [P(LbmParams), vp, vp, ctypes.c_int32, vp],
+    "lbm_tape_restore": [P(LbmParams), vp, ctypes.c_int32, vp, vp],
     "lbm_adjoint_size": [P(LbmParams), P(ctypes.c_size_t)],
     "lbm_adjoint_phi": [P(LbmParams), vp, vp, vp, vp],
     "lbm_adjoint_step": [P(LbmParams), vp, ctypes.c_int32, vp, vp],

@@ -179,6 +179,10 @@ def lbm_tape_record(p, state, tape, nlevels, stream=None):
     call("lbm_tape_record", ctypes.byref(p), _state_ptr(state), _state_ptr(tape), int(nlevels), _stream(stream))
 
 
+def lbm_tape_restore(p, tape, j, state, stream=None):
+    call("lbm_tape_restore", ctypes.byref(p), _state_ptr(tape), int(j), _state_ptr(state), _stream(stream))
+
+
 def lbm_adjoint_size(p) -> int:
     n = ctypes.c_size_t()
     call("lbm_adjoint_size", ctypes.byref(p), ctypes.byref(n))

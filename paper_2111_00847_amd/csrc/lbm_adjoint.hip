@@ -183,6 +183,20 @@ __global__ void k_tape_copy(const char* state, size_t off0, size_t off1, size_t 
     }
 }
 
+// Tape slot j as the current level of a state: copy 0, and every level stamp
+// set to `sv` (that level in copy 0).
+__global__ void k_tape_restore(const char* tape, size_t slot, int j, size_t bytes, char* state, size_t off0,
+                               size_t off_stamp, size_t nstamp, int64_t sv) {
+    const uint4* src = reinterpret_cast<const uint4*>(tape + TAPE_HDR + (size_t)j * slot);
+    uint4* dst = reinterpret_cast<uint4*>(state + off0);
+    int64_t* stamps = reinterpret_cast<int64_t*>(state + off_stamp);
+    const size_t nv = bytes / sizeof(uint4);
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nv; i += (size_t)gridDim.x * blockDim.x) {
+        dst[i] = src[i];
+        if (i < nstamp) stamps[i] = sv;
+    }
+}
+
 template <typename T, int TY, typename OFF, int NBY, bool STD, bool NT = true>
 __global__ __launch_bounds__(TX* NBY) __attribute__((amdgpu_waves_per_eu(StepWaves<T, TY, NBY>::value)))
 void k_tape_step(KParams<T> P, char* tape, size_t slot, int j, int ntx, int nty) {
@@ -867,6 +881,28 @@ int lbm_tape_record(const lbm_params* p, const void* state, void* tape, int32_t 
     else
         launch_tape_steps<double>(resolve<double>(p, L), (char*)tape, L.buf_bytes, nlevels, two, ty, by, s);
     hipError_t e = hipGetLastError();
+    return e == hipSuccess ? LBM_OK : hip_fail(e);
+}
+
+int lbm_tape_restore(const lbm_params* p, const void* tape, int32_t j, void* state, void* stream) {
+    int rc = validate_ac(p);
+    if (rc) return rc;
+    if (!state || !tape) return LBM_E_NULL;
+    if ((uintptr_t)tape % 256) return LBM_E_SIZE;
+    const Layout L = layout_of(p);
+    hipStream_t s = (hipStream_t)stream;
+    TapeHeader h;
+    hipError_t e = hipMemcpyAsync(&h, tape, sizeof(h), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e);
+    if (h.nx != p->nx || h.ny != p->ny || h.dtype != p->dtype) return LBM_E_PARAM;
+    if (j < 0 || j >= h.nlevels) return LBM_E_SIZE;
+    // nstamp (one per 64-node band of a row) is below the slot's 16-byte words
+    k_tape_restore<<<grid1d((long long)(L.buf_bytes / 16)), 256, 0, s>>>((const char*)tape, L.buf_bytes, j,
+                                                                         L.buf_bytes, (char*)state, L.off_buf[0],
+                                                                         L.off_stamp, L.nstamp,
+                                                                         stamp_of(h.n0 + j, 0));
+    e = hipGetLastError();
     return e == hipSuccess ? LBM_OK : hip_fail(e);
 }
 

@@ -126,6 +126,8 @@ int main(void) {
     EXPECT(lbm_tape_size(&p, 0, &n), LBM_E_SIZE);
     EXPECT(lbm_tape_size(&p, 2, NULL), LBM_E_NULL);
     EXPECT(lbm_tape_record(&p, fake, fake, 0, NULL), LBM_E_SIZE);
+    EXPECT(lbm_tape_restore(&p, fake, 0, NULL, NULL), LBM_E_NULL);
+    EXPECT(lbm_tape_restore(&p, (void*)(uintptr_t)((1 << 20) + 8), 0, fake, NULL), LBM_E_SIZE);
     EXPECT(lbm_adjoint_step(&p, fake, -1, fake, NULL), LBM_E_SIZE);
     EXPECT(lbm_adjoint_run(&p, fake, 0, 2, fake, NULL), LBM_E_SIZE);
     EXPECT(lbm_adjoint_phi(&p, NULL, fake, fake, NULL), LBM_E_NULL);
@@ -136,6 +138,7 @@ int main(void) {
     EXPECT(lbm_adjoint_export(&p, NULL, NULL, NULL, NULL, NULL), LBM_E_NULL);
     q = p; q.phase_eq = LBM_CAHN_HILLIARD; q.phi_B = -1.0;
     EXPECT(lbm_tape_record(&q, fake, fake, 1, NULL), LBM_E_UNSUPPORTED);
+    EXPECT(lbm_tape_restore(&q, fake, 0, fake, NULL), LBM_E_UNSUPPORTED);
     EXPECT(lbm_adjoint_run(&q, fake, 0, 1, fake, NULL), LBM_E_UNSUPPORTED);
 
     /* batches: host checks (a valid plan needs a device table, so none is made) */

@@ -141,6 +141,7 @@ def test_cahn_hilliard_rejected_by_reverse_mode():
     assert L.lbm_state_size(ctypes.byref(p), ctypes.byref(n)) == 0
     assert L.lbm_tape_record(ctypes.byref(p), ctypes.c_void_p(256), ctypes.c_void_p(256), 1, None) == -8
     assert L.lbm_adjoint_run(ctypes.byref(p), ctypes.c_void_p(256), 0, 1, ctypes.c_void_p(256), None) == -8
+    assert L.lbm_tape_restore(ctypes.byref(p), ctypes.c_void_p(256), 0, ctypes.c_void_p(256), None) == -8
 
 
 def test_corrected_model_options():

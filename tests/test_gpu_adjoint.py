@@ -174,6 +174,65 @@ def test_two_level_tape_equals_one_level_tape(kind, dtype):
         assert np.array_equal(a, b), (kind, dtype, what, float(np.abs(a - b).max()))
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("kind", ["walls_xy_inverse_nu", "dam_break_32x16"])
+def test_full_tape_equals_checkpointed(kind, dtype):
+    """chk = 0 records every forward level on one tape and ends the forward on
+    its last slot: phi^N and the gradients equal those of checkpoints every 7
+    levels (segments recomputed in backward) bit for bit; 25 levels, so the
+    two-level tape launches end on a one-level one."""
+    from paper_2111_00847_amd.autograd import trajectory_phi
+    case, phi0, target = _traj_case(kind)
+    case = case.replace(dtype=dtype)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    nsteps = 25
+    out = {}
+    for chk in (0, 7):
+        phi0_t = torch.tensor(phi0, dtype=tdt, device="cuda", requires_grad=True)
+        grav = torch.tensor(list(case.gravity), dtype=torch.float64, requires_grad=True)
+        theta = torch.tensor(list(case.theta), dtype=torch.float64, requires_grad=True)
+        phiN = trajectory_phi(phi0_t, grav, theta, case, nsteps, None, chk)
+        L = ((phiN - torch.tensor(target, dtype=tdt, device="cuda")) ** 2).sum()
+        L.backward()
+        torch.cuda.synchronize()
+        out[chk] = (phiN.detach().cpu().numpy(), phi0_t.grad.cpu().numpy(), grav.grad.numpy(), theta.grad.numpy())
+    for a, b, what in zip(out[0], out[7], ("phi^N", "dL/dphi0", "dL/dgravity", "dL/dtheta")):
+        assert np.array_equal(a, b), (kind, dtype, what, float(np.abs(a - b).max()))
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_tape_restore_resumes_the_trajectory(dtype):
+    """lbm_tape_restore makes a tape slot the current level of a state: slot 3
+    of a tape recorded from level 2 is level 5 exactly (populations, history,
+    step), and the restored state steps on as the original does, bit for bit.
+    A slot the tape does not hold is LBM_E_SIZE, a tape of another lattice
+    LBM_E_PARAM (both from the host, before any copy)."""
+    from paper_2111_00847_amd._lib import LbmError
+    api, Sim = _api()
+    case = _case("walls_xy").replace(dtype=dtype)
+    phi0, u0, p0 = W.random_state_fields(case, seed=21)
+    ref = Sim(case).init(phi0, u0, p0).step(2)
+    tape = api.new_tape(ref.p, 4)
+    api.lbm_tape_record(ref.p, ref.state, tape, 4)        # levels 2 .. 5
+    ref.step(3)
+    other = Sim(case).init(phi0)
+    api.lbm_tape_restore(other.p, tape, 3, other.state)
+    for k in range(2):
+        a, b = other.export_state(), ref.export_state()
+        assert a["step"] == b["step"] == 5 + 3 * k
+        for key in ("f", "g", "hist"):
+            assert torch.equal(a[key], b[key]), (dtype, k, key)
+        other.step(3)
+        ref.step(3)
+    with pytest.raises(LbmError) as e:
+        api.lbm_tape_restore(other.p, tape, 4, other.state)
+    assert e.value.code == -2
+    taller = Sim(case.replace(ny=case.ny + 1)).init(np.vstack([phi0, phi0[-1:]]))
+    with pytest.raises(LbmError) as e:
+        api.lbm_tape_restore(taller.p, tape, 0, taller.state)
+    assert e.value.code == -4
+
+
 # ---------------------------------------------------------------- cfg: differentiable dam break, 64 x 32 copy
 def _dam_small(dtype="f64"):
     """64 x 32 copy of the dam break; the target is phi of a run with seeded
