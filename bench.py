@@ -50,7 +50,7 @@ The JSON line also carries:
                   launch (and one-level launches beside it);
   adjoint      -- the differentiable dam break (Sec. 4.5 set-up, 1024 x 512,
                   FP32, 4000 steps): time of the backward pass over the time
-                  of the plain forward.  With the full tape (every level kept:
+                  of the plain forward (medians of three passes each).  With the full tape (every level kept:
                   176 GB, used when it fits in 3/4 of the free device memory)
                   the forward records the tape and the backward runs only the
                   adjoint steps; `checkpointed` times the same gradients with
@@ -424,8 +424,11 @@ def measure_adjoint(args, torch, W, Sim):
     target = tgt.moments()[0]
     del tgt
     stream = torch.cuda.current_stream()
-    plain = Sim(case).init(phi0)
-    ms_fwd = _timed(stream, torch, lambda: plain.step(N))
+    plain, fw = Sim(case), []
+    for _ in range(3):   # the median of three forward passes from phi0
+        plain.init(phi0)
+        fw.append(_timed(stream, torch, lambda: plain.step(N)))
+    ms_fwd = _median(fw)
     del plain
     phi0_t = torch.tensor(phi0, dtype=torch.float32, device="cuda", requires_grad=True)
     grav = torch.tensor([0.0, -1e-6], dtype=torch.float64, requires_grad=True)
@@ -453,7 +456,9 @@ def measure_adjoint(args, torch, W, Sim):
     res = {}
     for c in modes:
         run(c)   # untimed: afterwards the snapshots, tape and adjoint buffers come from torch's cache
-        res[c] = run(c)
+        rs = [run(c) for _ in range(3)]   # medians of three passes
+        res[c] = (_median([r[0] for r in rs]), _median([r[1] for r in rs]), rs[-1][2])
+        assert all(r[2] == rs[0][2] for r in rs), "gradients differ from pass to pass"
         box.clear()
         torch.cuda.empty_cache()
     if full:
