@@ -20,6 +20,7 @@
 // one-level steps), with an odd step count ending on a one-level launch.
 #include <hip/hip_runtime.h>
 
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
@@ -601,6 +602,22 @@ int lbm_batch_create(const lbm_params* cases, int32_t ncases, int32_t autotune, 
     B->ty = 8;
     B->by = B->wide ? 8 : 4;
     B->grid = 0;
+    // LBM_BATCH_SHAPE="ty,by,grid" fixes the one-level shape (no autotuning):
+    // one of the tuner's candidates, grid 0 for one workgroup per item
+    if (const char* env = getenv("LBM_BATCH_SHAPE")) {
+        int ty = 0, by = 0, grid = -1;
+        const bool ok = sscanf(env, "%d,%d,%d", &ty, &by, &grid) == 3 && grid >= 0 &&
+                        ((ty == 4 && by == 4) || ((ty == 8 || ty == 16) && (by == 4 || by == 8))) &&
+                        !(ty == 16 && B->dtype == LBM_F64) && !(B->wide && (by != ty || ty > 8));
+        if (!ok) {
+            delete B;
+            return LBM_E_PARAM;
+        }
+        B->ty = ty;
+        B->by = by;
+        B->grid = grid;
+        B->tuned = true;
+    }
     hipError_t e = B->dtype == LBM_F32 ? upload_cases<float>(B, B->ty) : upload_cases<double>(B, B->ty);
     B->two_level = two_level_batch(cases, ncases);
     if (e == hipSuccess && B->two_level) e = B->dtype == LBM_F32 ? upload_cases2<float>(B) : upload_cases2<double>(B);

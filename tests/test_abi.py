@@ -266,3 +266,27 @@ def test_bandwidth_probe_validates_on_the_host():
     assert L.lbm_bandwidth_probe(2, ctypes.c_void_p(24), p16, 1 << 20, 256, 1, None) == -2   # alignment
     assert L.lbm_bandwidth_probe(2, p16, None, 1 << 20, 256, 1, None) == -1       # copy without a source
     assert L.lbm_bandwidth_probe(0, None, p16, 1 << 20, 256, 1, None) == -1
+
+
+def test_forced_batch_shape_is_validated_on_the_host(monkeypatch):
+    """LBM_BATCH_SHAPE must name one of the tuner's shapes that the batch can
+    run (16-row tiles in FP32 only; one node per thread for Cahn-Hilliard,
+    corrected and local-gradient cases) and a grid >= 0: anything else makes
+    lbm_batch_create return LBM_E_PARAM before any HIP call."""
+    from paper_2111_00847_amd._lib import LbmParams, lib
+    L = lib()
+    f32, f64 = _params(dtype="f32"), _params(dtype="f64")
+    ch = _params(dtype="f32", phase_eq="cahn_hilliard", phiB=-1.0)
+    bad = [("16,8,0", f64), ("3,3,0", f32), ("8,4", f32), ("8,4,-1", f32), ("8,16,0", f32), ("x", f32),
+           ("8,4,0", ch), ("16,16,0", ch)]
+    for val, p in bad:
+        monkeypatch.setenv("LBM_BATCH_SHAPE", val)
+        h = ctypes.c_void_p()
+        assert L.lbm_batch_create((LbmParams * 1)(p), 1, 1, ctypes.byref(h)) == -4, val
+    for val, p in [("16,8,0", f32), ("4,4,7", f64), ("8,8,0", ch)]:
+        monkeypatch.setenv("LBM_BATCH_SHAPE", val)
+        h = ctypes.c_void_p()
+        rc = L.lbm_batch_create((LbmParams * 1)(p), 1, 1, ctypes.byref(h))
+        assert rc in (0, -6), val   # accepted (the device table needs a GPU: LBM_E_HIP without one)
+        if rc == 0:
+            assert L.lbm_batch_destroy(h) == 0

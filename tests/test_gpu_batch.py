@@ -251,3 +251,63 @@ def test_wide_batch_bitwise_equals_single(dtype, mode):
             err = float(np.abs(ta - tb).max())
             print(f"{what} {key}: max|diff| {err:.2e}", flush=True)
             assert err <= 16 * eps * max(1.0, float(np.abs(tb).max())), (what, key, err)
+
+
+SHAPES = [(4, 4), (8, 4), (8, 8), (16, 4), (16, 8)]
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("wide", [False, True])
+def test_every_batch_shape_equals_single(dtype, wide):
+    """Every tile shape of the one-level batch launch (forced with
+    LBM_BATCH_SHAPE, one workgroup per tile and a strided grid of 7
+    workgroups) against the cases advanced alone: plain Allen-Cahn cases
+    bitwise, the wide bodies' cases to a few units of rounding (as in the
+    wide-batch test above).  Two-level launches are off (LBM_TWO_LEVEL=0) so
+    that every level runs the forced shape."""
+    import os
+    from paper_2111_00847_amd._lib import LbmError
+    Sim, BatchSim = _mods()
+    cases = _wide_cases(dtype) if wide else _mixed_cases(dtype)
+    p0s = ["hydrostatic"] * len(cases)
+    steps = 13
+    alone = [Sim(c).init(phi0, None, p0).step(steps) for (c, phi0), p0 in zip(cases, p0s)]
+    torch.cuda.synchronize()
+    eps = np.finfo(np.float64 if dtype == "f64" else np.float32).eps
+    ran = 0
+    for ty, by in SHAPES:
+        for grid in (0, 7):
+            runnable = not (ty == 16 and dtype == "f64") and not (wide and (by != ty or ty > 8))
+            os.environ["LBM_BATCH_SHAPE"] = f"{ty},{by},{grid}"
+            os.environ["LBM_TWO_LEVEL"] = "0"
+            try:
+                if not runnable:
+                    with pytest.raises(LbmError) as e:
+                        BatchSim([c for c, _ in cases])
+                    assert e.value.code == -4
+                    continue
+                B = BatchSim([c for c, _ in cases], autotune=True)   # the forced shape wins
+            finally:
+                os.environ.pop("LBM_BATCH_SHAPE", None)
+                os.environ.pop("LBM_TWO_LEVEL", None)
+            t = B.tuning()
+            assert (t["tile_rows"], t["thread_rows"]) == (ty, by), t
+            assert t["grid"] == (grid if grid else t["items"]), t
+            B.init([p for _, p in cases], p0s)
+            B.step(steps)
+            torch.cuda.synchronize()
+            ran += 1
+            for c, (case, _) in enumerate(cases):
+                what = f"shape {ty},{by},{grid} case {c} {case.name}"
+                exact = case.phase_eq == "allen_cahn" and case.model != "corrected" and case.grad_scheme == "stencil"
+                if exact:
+                    _assert_same_state(B.case(c), alone[c], what)
+                    continue
+                sa, sb = B.case(c).export_state(), alone[c].export_state()
+                assert sa["step"] == sb["step"], what
+                for key in ("f", "g", "hist"):
+                    ta, tb = sa[key].cpu().numpy(), sb[key].cpu().numpy()
+                    err = float(np.abs(ta - tb).max())
+                    assert err <= 16 * eps * max(1.0, float(np.abs(tb).max())), (what, key, err)
+            del B
+    assert ran == (4 if wide else (6 if dtype == "f64" else 10))
