@@ -49,13 +49,13 @@ The JSON line also carries:
                   local) on the 4096 x 4096 RTI lattice (FP32), two levels per
                   launch (and one-level launches beside it);
   adjoint      -- the differentiable dam break (Sec. 4.5 set-up, 1024 x 512,
-                  FP32, 4000 steps): time of the backward pass over the time
-                  of the plain forward (medians of three passes each).  With the full tape (every level kept:
-                  176 GB, used when it fits in 3/4 of the free device memory)
-                  the forward records the tape and the backward runs only the
-                  adjoint steps; `checkpointed` times the same gradients with
-                  checkpoints every 200 levels (tape recompute + adjoint steps
-                  in backward);
+                  FP32, 4000 steps, checkpoints every 200): time of the
+                  backward pass (tape recompute + adjoint steps) over the time
+                  of the plain forward (medians of three passes each);
+                  `full_tape` times the same gradients with every level kept
+                  on one tape (176 GB, when it fits in 3/4 of the free device
+                  memory): the forward records the tape and the backward runs
+                  only the adjoint steps;
   cpu_baseline -- the FP64 oracle timed on the host on a bounded sample.
 """
 import argparse
@@ -463,17 +463,15 @@ def measure_adjoint(args, torch, W, Sim):
         torch.cuda.empty_cache()
     if full:
         assert res[0][2] == res[chk][2], "full-tape and checkpointed gradients differ"
-    ms_fwd_m, ms_bwd, grads = res[modes[0]]
-    out = {"workload": "dam_break_1024x512_fp32", "steps": N,
-           "mode": "full tape" if full else f"checkpoints every {chk}",
-           "tape_GB": round(tape_bytes / 1e9, 1) if full else None,
-           "forward_ms": round(ms_fwd, 2), "forward_recording_ms": round(ms_fwd_m, 2),
-           "backward_ms": round(ms_bwd, 2), "backward_over_forward": round(ms_bwd / ms_fwd, 3),
-           "dL_dg": -grads[0], "dL_dtheta": grads[1]}
+    ck = res[chk]
+    out = {"workload": "dam_break_1024x512_fp32", "steps": N, "checkpoint_every": chk,
+           "forward_ms": round(ms_fwd, 2), "forward_with_snapshots_ms": round(ck[0], 2),
+           "backward_ms": round(ck[1], 2), "backward_over_forward": round(ck[1] / ms_fwd, 3),
+           "dL_dg": -ck[2][0], "dL_dtheta": ck[2][1], "full_tape": None}
     if full:
-        ck = res[chk]
-        out["checkpointed"] = {"checkpoint_every": chk, "forward_with_snapshots_ms": round(ck[0], 2),
-                               "backward_ms": round(ck[1], 2), "backward_over_forward": round(ck[1] / ms_fwd, 3)}
+        ft = res[0]
+        out["full_tape"] = {"tape_GB": round(tape_bytes / 1e9, 1), "forward_recording_ms": round(ft[0], 2),
+                            "backward_ms": round(ft[1], 2), "backward_over_forward": round(ft[1] / ms_fwd, 3)}
     del box, phi0_t
     torch.cuda.empty_cache()
     return out
