@@ -144,20 +144,20 @@ __global__ __launch_bounds__(TX* TY) void k_step_batch_wide(const BatchCase<T>* 
             step_tile<T, TY, 0, uint32_t, NBY, false, NT>(C.P, st0, C.off0, C.off1, C.off_stamp, xt, yt, nullptr,
                                                           nullptr, nullptr, lds.ac.sphi, lds.ac.sphp);
         else if (C.body == 1 && C.P.rates_std)
-            ch_step_tile<T, TY, 0, false, true, NT, NBY>(C.P, st0, C.off0, C.off1, C.off_stamp, xt, yt, nullptr,
-                                                         nullptr, nullptr, lds.ch);
+            ch_step_tile<T, TY, 0, false, true, NT, NBY, uint32_t>(C.P, st0, C.off0, C.off1, C.off_stamp, xt, yt,
+                                                                   nullptr, nullptr, nullptr, lds.ch);
         else if (C.body == 1)
-            ch_step_tile<T, TY, 0, false, false, NT, NBY>(C.P, st0, C.off0, C.off1, C.off_stamp, xt, yt, nullptr,
-                                                          nullptr, nullptr, lds.ch);
+            ch_step_tile<T, TY, 0, false, false, NT, NBY, uint32_t>(C.P, st0, C.off0, C.off1, C.off_stamp, xt, yt,
+                                                                    nullptr, nullptr, nullptr, lds.ch);
         else if (C.body == 3)
-            local_step_tile<T, TY, 0, NT, NBY>(C.P, st0, C.off0, C.off1, C.off_stamp, xt, yt, nullptr, nullptr,
-                                               nullptr, lds.ac.sphi);
+            local_step_tile<T, TY, 0, NT, NBY, uint32_t>(C.P, st0, C.off0, C.off1, C.off_stamp, xt, yt, nullptr,
+                                                         nullptr, nullptr, lds.ac.sphi);
         else if (C.P.rates_std)
-            ch_step_tile<T, TY, 0, true, true, NT, NBY>(C.P, st0, C.off0, C.off1, C.off_stamp, xt, yt, nullptr,
-                                                        nullptr, nullptr, lds.ch);
+            ch_step_tile<T, TY, 0, true, true, NT, NBY, uint32_t>(C.P, st0, C.off0, C.off1, C.off_stamp, xt, yt,
+                                                                  nullptr, nullptr, nullptr, lds.ch);
         else
-            ch_step_tile<T, TY, 0, true, false, NT, NBY>(C.P, st0, C.off0, C.off1, C.off_stamp, xt, yt, nullptr,
-                                                         nullptr, nullptr, lds.ch);
+            ch_step_tile<T, TY, 0, true, false, NT, NBY, uint32_t>(C.P, st0, C.off0, C.off1, C.off_stamp, xt, yt,
+                                                                   nullptr, nullptr, nullptr, lds.ch);
     };
     if constexpr (LOOP) {
         for (int w = blockIdx.x; w < nitems; w += gridDim.x) {

@@ -16,7 +16,7 @@
 // a wall mirrors D of the first fluid node with its normal component reversed.
 #pragma once
 
-#include "lbm_tile.hpp"
+#include "lbm_fused.hpp"
 
 namespace lbm {
 
@@ -48,24 +48,30 @@ __device__ __forceinline__ bool ch_node(const KParams<T>& P, int& gx, int& gy, i
 
 // phi (and the previous phi) of window position (wx, wy), filled from the
 // lattice by the ghost-free rule of ch_node; positions beyond a wall are left
-// for the wall-ghost passes.
-template <typename T, int TY>
-__device__ __forceinline__ void ch_fill(const KParams<T>& P, const Copy<T>& S, bool first, int x0, int y0, int wx,
-                                        int wy, ChWindow<T, TY>& W) {
+// for the wall-ghost passes.  The copy is addressed by byte offsets of type
+// OFF from its base `src` (bF, bH: offsets of plane f_1 and of the history).
+template <typename T, int TY, typename OFF>
+__device__ __forceinline__ void ch_fill(const KParams<T>& P, const char* src, OFF bF, OFF bH, OFF pl, bool first,
+                                        int x0, int y0, int wx, int wy, ChWindow<T, TY>& W) {
     int gx = x0 - 2 + wx, gy = y0 - 2 + wy;
     if (!ch_node(P, gx, gy, P.nx + 1, P.ny + 1)) return;
     T fw[9];
-    W.phi[wy][wx] = (T)node_phi(P, S, gx, gy, fw);
-    if (!first) W.php[wy][wx] = S.h[(long long)gy * P.nx + gx];
+    double f0;
+    const OFF k = pull_f_at<T, OFF>(P, src, bF, bH, pl, gx, gy, fw, f0);
+    W.phi[wy][wx] = (T)(f0 + moving_sum_d(fw));
+    if (!first) W.php[wy][wx] = ld<T>(src, bH + k * (OFF)sizeof(T));
 }
 
 // per_node(M, f, g, phid, x, y, k): called for every node of the tile with its
-// Macro (Cahn-Hilliard closure), pulled populations f, g and FP64 phi.
+// Macro (Cahn-Hilliard closure), pulled populations f, g and FP64 phi.  The
+// copy S is read through byte offsets of type OFF from its base (32-bit ones
+// while the copy is below 4 GiB: a uniform base and one offset register per
+// load, as the Allen-Cahn step reads its copy).
 // Thread (lx, ly) of 64 x NBY owns nodes (x0 + lx, y0 + ly + NBY r), r < TY /
 // NBY: their f, g and history are pulled first and kept in registers to the
 // collision; the two-node ring of the phi window is pulled afterwards by all
 // threads.
-template <typename T, int TY, bool ACC = false, int NBY = BY, typename F>
+template <typename T, int TY, bool ACC = false, int NBY = BY, typename OFF = uint64_t, typename F>
 __device__ __forceinline__ void ch_tile(const KParams<T>& P, const Copy<T>& S, int64_t step, int x0, int y0,
                                         ChWindow<T, TY>& W, F&& per_node) {
     using Win = ChWindow<T, TY>;
@@ -75,6 +81,10 @@ __device__ __forceinline__ void ch_tile(const KParams<T>& P, const Copy<T>& S, i
     const bool first = step == 0;
     const int tid = threadIdx.y * TX + threadIdx.x;
     const int lx = threadIdx.x;
+    const char* src = reinterpret_cast<const char*>(S.f0);
+    constexpr OFF ES = sizeof(T);
+    const OFF pl = (OFF)P.plane;
+    const OFF bF = pl * ES, bG = 9 * pl * ES, bH = 18 * pl * ES;
     // 1. own nodes (kept), then the ring of the two-node phi window
     T f[R][9], g[R][9], up[R], vp[R];
     double phid[R];
@@ -83,18 +93,18 @@ __device__ __forceinline__ void ch_tile(const KParams<T>& P, const Copy<T>& S, i
         const int ly = threadIdx.y + r * NBY;
         const int x = x0 + lx, y = y0 + ly;
         if (x < P.nx && y < P.ny) {
-            const long long k = (long long)y * P.nx + x;
-            phid[r] = node_phi(P, S, x, y, f[r]);
-#pragma unroll
-            for (int i = 0; i < Q; i++) g[r][i] = pull(S.g, P, i, x, y);
+            double f0d;
+            const OFF k = pull_fg_at<T, OFF>(P, src, bF, bG, bH, pl, x, y, f[r], f0d, g[r]);
+            f[r][0] = (T)f0d;
+            phid[r] = f0d + moving_sum_d(f[r]);
             W.phi[ly + 2][lx + 2] = (T)phid[r];
             if (!first) {
-                W.php[ly + 2][lx + 2] = S.h[k];
-                up[r] = S.h[P.plane + k];
-                vp[r] = S.h[2 * P.plane + k];
+                W.php[ly + 2][lx + 2] = ld<T>(src, bH + k * ES);
+                up[r] = ld<T>(src, bH + (pl + k) * ES);
+                vp[r] = ld<T>(src, bH + (2 * pl + k) * ES);
             }
         } else {
-            ch_fill<T, TY>(P, S, first, x0, y0, lx + 2, ly + 2, W);   // ragged tile: serves as ring
+            ch_fill<T, TY, OFF>(P, src, bF, bH, pl, first, x0, y0, lx + 2, ly + 2, W);   // ragged tile: serves as ring
         }
     }
     for (int idx = tid; idx < NRING; idx += TX * NBY) {
@@ -108,7 +118,7 @@ __device__ __forceinline__ void ch_tile(const KParams<T>& P, const Copy<T>& S, i
             wy = 2 + (j >> 2);
             wx = c < 2 ? c : TX + c;
         }
-        ch_fill<T, TY>(P, S, first, x0, y0, wx, wy, W);
+        ch_fill<T, TY, OFF>(P, src, bF, bH, pl, first, x0, y0, wx, wy, W);
     }
     __syncthreads();
     // 2. first ghost layer of phi: x-walls on rows that hold nodes, then y-walls across all columns

@@ -12,8 +12,10 @@ namespace lbm {
 
 // MODE 0: one time step, the tile's rows move to the next level; MODE 1:
 // phi, u, p of the current level into out_*.  W: the tile's LDS windows.
-// STD: the paper's default rates compiled in (P.rates_std).
-template <typename T, int TY, int MODE, bool ACC, bool STD = false, bool NT = true, int NBY = BY>
+// STD: the paper's default rates compiled in (P.rates_std).  OFF: byte
+// offsets within a copy (uint32_t while the copy is below 4 GiB).
+template <typename T, int TY, int MODE, bool ACC, bool STD = false, bool NT = true, int NBY = BY,
+          typename OFF = uint64_t>
 __device__ __forceinline__ void ch_step_tile(const KParams<T>& P, char* state, size_t off0, size_t off1,
                                              size_t off_stamp, int xt, int yt, T* out_phi, T* out_u, T* out_p,
                                              ChWindow<T, TY>& W) {
@@ -23,7 +25,9 @@ __device__ __forceinline__ void ch_step_tile(const KParams<T>& P, char* state, s
     const int cur = stamp_copy(sv);
     const Copy<T> S = copy_at<T>(state + (cur ? off1 : off0), P.plane);
     const Copy<T> D = copy_at<T>(state + (cur ? off0 : off1), P.plane);
-    ch_tile<T, TY, ACC, NBY>(P, S, step, x0, y0, W, [&](const Macro<T>& M, T* f, T* g, double phid, int, int, long long k) {
+    char* dst = reinterpret_cast<char*>(D.f0);
+    ch_tile<T, TY, ACC, NBY, OFF>(P, S, step, x0, y0, W, [&](const Macro<T>& M, T* f, T* g, double phid, int, int,
+                                                           long long k) {
         if (MODE == 1) {
             if (out_phi) out_phi[k] = M.phi;
             if (out_u) {
@@ -35,13 +39,16 @@ __device__ __forceinline__ void ch_step_tile(const KParams<T>& P, char* state, s
         }
         const double f0n = collide_f<T, !ACC, STD>(P, M, f, phid);
         collide_g<T, STD>(P, M, g);
-        const long long pl = P.plane;
-        st<T, long long, NT>(reinterpret_cast<char*>(D.f0), (long long)sizeof(T) * k, rest_encode<T>(f0n, M.phi, P.rest_w));
-        for (int i = 1; i < Q; i++) st<T, long long, NT>(reinterpret_cast<char*>(D.f), (long long)sizeof(T) * (i * pl + k), f[i]);
-        for (int i = 0; i < Q; i++) st<T, long long, NT>(reinterpret_cast<char*>(D.g), (long long)sizeof(T) * (i * pl + k), g[i]);
-        st<T, long long, NT>(reinterpret_cast<char*>(D.h), (long long)sizeof(T) * k, M.phi);
-        st<T, long long, NT>(reinterpret_cast<char*>(D.h), (long long)sizeof(T) * (pl + k), M.u);
-        st<T, long long, NT>(reinterpret_cast<char*>(D.h), (long long)sizeof(T) * (2 * pl + k), M.v);
+        constexpr OFF ES = sizeof(T);
+        const OFF pl = (OFF)P.plane, kk = (OFF)k;
+        st<T, OFF, NT>(dst, kk * ES, rest_encode<T>(f0n, M.phi, P.rest_w));
+#pragma unroll
+        for (int i = 1; i < Q; i++) st<T, OFF, NT>(dst, ((OFF)i * pl + kk) * ES, f[i]);
+#pragma unroll
+        for (int i = 0; i < Q; i++) st<T, OFF, NT>(dst, ((OFF)(9 + i) * pl + kk) * ES, g[i]);
+        st<T, OFF, NT>(dst, (18 * pl + kk) * ES, M.phi);
+        st<T, OFF, NT>(dst, (19 * pl + kk) * ES, M.u);
+        st<T, OFF, NT>(dst, (20 * pl + kk) * ES, M.v);
     });
     // every wave read stamp[0] before the barriers of the tile body
     const int tid = threadIdx.y * TX + threadIdx.x;

@@ -12,7 +12,8 @@ namespace lbm {
 
 // MODE 0: one time step, the tile's rows move to the next level; MODE 1:
 // phi, u, p of the current level into out_*.  sphi: the tile's phi window.
-template <typename T, int TY, int MODE, bool NT = true, int NBY = BY>
+// OFF: byte offsets within a copy (uint32_t while the copy is below 4 GiB).
+template <typename T, int TY, int MODE, bool NT = true, int NBY = BY, typename OFF = uint64_t>
 __device__ __forceinline__ void local_step_tile(const KParams<T>& P, char* state, size_t off0, size_t off1,
                                                 size_t off_stamp, int xt, int yt, T* out_phi, T* out_u, T* out_p,
                                                 T (*sphi)[TX + 3]) {
@@ -23,9 +24,11 @@ __device__ __forceinline__ void local_step_tile(const KParams<T>& P, char* state
     const int64_t sv = stamp[0], step = stamp_level(sv);
     const bool first = step == 0;
     const int cur = stamp_copy(sv);
-    const Copy<T> S = copy_at<T>(state + (cur ? off1 : off0), P.plane);
-    const Copy<T> D = copy_at<T>(state + (cur ? off0 : off1), P.plane);
-    const long long pl = P.plane;
+    const char* src = state + (cur ? off1 : off0);
+    char* dst = state + (cur ? off0 : off1);
+    constexpr OFF ES = sizeof(T);
+    const OFF pl = (OFF)P.plane;
+    const OFF bF = pl * ES, bG = 9 * pl * ES, bH = 18 * pl * ES;
     const int tid = threadIdx.y * TX + threadIdx.x;
     const int lx = threadIdx.x;
     // phi of window position (wx, wy) = node (x0 - 1 + wx, y0 - 1 + wy): periodic
@@ -42,7 +45,9 @@ __device__ __forceinline__ void local_step_tile(const KParams<T>& P, char* state
             gy = gy < 0 ? gy + P.ny : gy - P.ny;
         }
         T fw[9];
-        sphi[wy][wx] = (T)node_phi(P, S, gx, gy, fw);
+        double f0;
+        pull_f_at<T, OFF>(P, src, bF, bH, pl, gx, gy, fw, f0);
+        sphi[wy][wx] = (T)(f0 + moving_sum_d(fw));
     };
     // 1. own nodes first (f, g and the history kept in registers), then the ring
     T f[R][9], g[R][9], hv[R][5];
@@ -52,13 +57,13 @@ __device__ __forceinline__ void local_step_tile(const KParams<T>& P, char* state
         const int ly = threadIdx.y + r * NBY;
         const int x = x0 + lx, y = y0 + ly;
         if (x < P.nx && y < P.ny) {
-            const long long k = (long long)y * P.nx + x;
-            phid[r] = node_phi(P, S, x, y, f[r]);
-#pragma unroll
-            for (int i = 0; i < Q; i++) g[r][i] = pull(S.g, P, i, x, y);
+            double f0d;
+            const OFF k = pull_fg_at<T, OFF>(P, src, bF, bG, bH, pl, x, y, f[r], f0d, g[r]);
+            f[r][0] = (T)f0d;
+            phid[r] = f0d + moving_sum_d(f[r]);
             if (!first)
 #pragma unroll
-                for (int j = 0; j < 5; j++) hv[r][j] = S.h[j * pl + k];
+                for (int j = 0; j < 5; j++) hv[r][j] = ld<T>(src, bH + ((OFF)j * pl + k) * ES);
             sphi[ly + 1][lx + 1] = (T)phid[r];
         } else {
             fill(lx + 1, ly + 1);   // ragged tile: the position serves as ring
@@ -102,11 +107,15 @@ __device__ __forceinline__ void local_step_tile(const KParams<T>& P, char* state
         }
         const double f0n = collide_f(P, M, f[r], phid[r]);
         collide_g(P, M, g[r]);
-        st<T, long long, NT>(reinterpret_cast<char*>(D.f0), (long long)sizeof(T) * k, rest_encode<T>(f0n, M.phi, P.rest_w));
-        for (int i = 1; i < Q; i++) st<T, long long, NT>(reinterpret_cast<char*>(D.f), (long long)sizeof(T) * (i * pl + k), f[r][i]);
-        for (int i = 0; i < Q; i++) st<T, long long, NT>(reinterpret_cast<char*>(D.g), (long long)sizeof(T) * (i * pl + k), g[r][i]);
+        const OFF kk = (OFF)k;
+        st<T, OFF, NT>(dst, kk * ES, rest_encode<T>(f0n, M.phi, P.rest_w));
+#pragma unroll
+        for (int i = 1; i < Q; i++) st<T, OFF, NT>(dst, ((OFF)i * pl + kk) * ES, f[r][i]);
+#pragma unroll
+        for (int i = 0; i < Q; i++) st<T, OFF, NT>(dst, ((OFF)(9 + i) * pl + kk) * ES, g[r][i]);
         const T hout[5] = {M.phi, M.u, M.v, M.mx, M.my};
-        for (int j = 0; j < 5; j++) st<T, long long, NT>(reinterpret_cast<char*>(D.h), (long long)sizeof(T) * (j * pl + k), hout[j]);
+#pragma unroll
+        for (int j = 0; j < 5; j++) st<T, OFF, NT>(dst, ((OFF)(18 + j) * pl + kk) * ES, hout[j]);
     }
     // every wave read stamp[0] before the window barrier
     if (MODE == 0 && tid < TY && y0 + tid < P.ny) stamp[tid] = stamp_of(step + 1, 1 - cur);
