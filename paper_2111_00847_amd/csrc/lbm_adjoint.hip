@@ -415,7 +415,19 @@ __device__ __forceinline__ T wlap(int ex, int ey) {
 
 // Sum of what the fluid nodes around position (X, Y) of the extended lattice
 // took from it through their stencils (lev 0: current phi; 1: previous phi).
-template <typename T>
+// Element k of a plane through a byte offset of type OFF (uint32_t while the
+// adjoint buffer and a tape slot stay below 4 GiB: a uniform base and one
+// offset register per load).
+template <typename T, typename OFF>
+__device__ __forceinline__ T at(const T* plane, OFF k) {
+    return ld<T, OFF>(reinterpret_cast<const char*>(plane), k * (OFF)sizeof(T));
+}
+template <typename T, typename OFF>
+__device__ __forceinline__ void put(T* plane, OFF k, T v) {
+    st<T, OFF, false>(reinterpret_cast<char*>(plane), k * (OFF)sizeof(T), v);
+}
+
+template <typename T, typename OFF>
 __device__ T ext_adjoint(const KParams<T>& P, const AdjView<T>& V, int lev, int X, int Y) {
     const T* sgx = V.s(lev ? S_GXP : S_GX);
     const T* sgy = V.s(lev ? S_GYP : S_GY);
@@ -432,38 +444,39 @@ __device__ T ext_adjoint(const KParams<T>& P, const AdjView<T>& V, int lev, int 
                 if (P.wall_y) continue;
                 ys = ys < 0 ? ys + P.ny : ys - P.ny;
             }
-            const long long k = (long long)ys * P.nx + xs;
-            acc += wgx<T>(-dx, -dy) * sgx[k] + wgy<T>(-dx, -dy) * sgy[k];
-            if (!lev) acc += wlap<T>(-dx, -dy) * slp[k];
+            const OFF k = (OFF)ys * (OFF)P.nx + (OFF)xs;
+            acc += wgx<T>(-dx, -dy) * at<T, OFF>(sgx, k) + wgy<T>(-dx, -dy) * at<T, OFF>(sgy, k);
+            if (!lev) acc += wlap<T>(-dx, -dy) * at<T, OFF>(slp, k);
         }
     return acc;
 }
 
-template <typename T>
+template <typename T, typename OFF>
 __device__ __forceinline__ T phi_at(const KParams<T>& P, const T* phi, int x, int y) {
-    return phi[(long long)y * P.nx + x];
+    return at<T, OFF>(phi, (OFF)y * (OFF)P.nx + (OFF)x);
 }
 
 // phi on an x-wall ghost column (forward value, for the corner derivatives).
-template <typename T>
+template <typename T, typename OFF>
 __device__ __forceinline__ T xghost(const KParams<T>& P, const T* phi, int side, int y) {
-    return side == 0 ? wet_ghost(P, 0, phi_at(P, phi, 0, y), phi_at(P, phi, 1, y))
-                     : wet_ghost(P, 1, phi_at(P, phi, P.nx - 1, y), phi_at(P, phi, P.nx - 2, y));
+    return side == 0 ? wet_ghost(P, 0, phi_at<T, OFF>(P, phi, 0, y), phi_at<T, OFF>(P, phi, 1, y))
+                     : wet_ghost(P, 1, phi_at<T, OFF>(P, phi, P.nx - 1, y), phi_at<T, OFF>(P, phi, P.nx - 2, y));
 }
 
 // Adjoint of the x-wall ghost (side 0: x = -1, side 1: x = nx) in row y,
 // including what the corner ghosts built on it took from it.
-template <typename T>
+template <typename T, typename OFF>
 __device__ T xghost_adjoint(const KParams<T>& P, const AdjView<T>& V, int lev, const T* phi, int side, int y) {
     const int X = side ? P.nx : -1;
-    T q = ext_adjoint(P, V, lev, X, y);
+    T q = ext_adjoint<T, OFF>(P, V, lev, X, y);
     if (P.wall_y) {
         for (int sy = 0; sy < 2; sy++) {
             const int y1 = sy ? P.ny - 1 : 0, y2 = sy ? P.ny - 2 : 1;
             if (y != y1 && y != y2) continue;
-            const T qc = ext_adjoint(P, V, lev, X, sy ? P.ny : -1);
+            const T qc = ext_adjoint<T, OFF>(P, V, lev, X, sy ? P.ny : -1);
             T c1, c2, cth;
-            wet_ghost_grad(P, 2 + sy, xghost(P, phi, side, y1), xghost(P, phi, side, y2), c1, c2, cth);
+            wet_ghost_grad(P, 2 + sy, xghost<T, OFF>(P, phi, side, y1), xghost<T, OFF>(P, phi, side, y2), c1, c2,
+                           cth);
             if (y == y1) q += c1 * qc;
             if (y == y2) q += c2 * qc;
         }
@@ -477,7 +490,7 @@ __device__ T xghost_adjoint(const KParams<T>& P, const AdjView<T>& V, int lev, c
 // hold no node and contribute nothing); every node gathers the nine
 // transposed stencil terms, and wall nodes add what kernel G routed to them
 // from the ghosts (edge arrays).
-template <typename T>
+template <typename T, typename OFF>
 __global__ __launch_bounds__(TX* BY) void k_adj_gather(KParams<T> P, const char* tape, int j, AdjView<T> V) {
     constexpr int WX = TX + 2, WY = BTY + 2;
     __shared__ T sw[5][WY][WX + 1];   // gx, gy, lap of phi^n; gx, gy of phi^{n-1}
@@ -503,9 +516,9 @@ __global__ __launch_bounds__(TX* BY) void k_adj_gather(KParams<T> P, const char*
             if (P.wall_y) none = true;
             else gy = gy < 0 ? gy + P.ny : gy - P.ny;
         }
-        const long long k = (long long)gy * P.nx + gx;
+        const OFF k = (OFF)gy * (OFF)P.nx + (OFF)gx;
 #pragma unroll
-        for (int q = 0; q < 5; q++) sw[q][wy][wx] = none ? T(0) : src[q][k];
+        for (int q = 0; q < 5; q++) sw[q][wy][wx] = none ? T(0) : at<T, OFF>(src[q], k);
     }
     __syncthreads();
     if (status != 0) return;
@@ -515,26 +528,26 @@ __global__ __launch_bounds__(TX* BY) void k_adj_gather(KParams<T> P, const char*
     const int lx = threadIdx.x, ly = threadIdx.y;
     const int x = x0 + lx, y = y0 + ly;
     if (x >= P.nx || y >= P.ny) return;
-    const long long k = (long long)y * P.nx + x;
+    const OFF k = (OFF)y * (OFF)P.nx + (OFF)x;
     // what the wall ghosts built from this node received (kernel G)
     auto edges = [&](int lev) -> T {
         T a = T(0);
         if (P.wall_x) {
-            if (x == 0) a += V.e(lev, 0, 0)[y];
-            if (x == 1) a += V.e(lev, 0, 1)[y];
-            if (x == P.nx - 1) a += V.e(lev, 1, 0)[y];
-            if (x == P.nx - 2) a += V.e(lev, 1, 1)[y];
+            if (x == 0) a += at<T, OFF>(V.e(lev, 0, 0), (OFF)y);
+            if (x == 1) a += at<T, OFF>(V.e(lev, 0, 1), (OFF)y);
+            if (x == P.nx - 1) a += at<T, OFF>(V.e(lev, 1, 0), (OFF)y);
+            if (x == P.nx - 2) a += at<T, OFF>(V.e(lev, 1, 1), (OFF)y);
         }
         if (P.wall_y) {
-            if (y == 0) a += V.e(lev, 2, 0)[x];
-            if (y == 1) a += V.e(lev, 2, 1)[x];
-            if (y == P.ny - 1) a += V.e(lev, 3, 0)[x];
-            if (y == P.ny - 2) a += V.e(lev, 3, 1)[x];
+            if (y == 0) a += at<T, OFF>(V.e(lev, 2, 0), (OFF)x);
+            if (y == 1) a += at<T, OFF>(V.e(lev, 2, 1), (OFF)x);
+            if (y == P.ny - 1) a += at<T, OFF>(V.e(lev, 3, 0), (OFF)x);
+            if (y == P.ny - 2) a += at<T, OFF>(V.e(lev, 3, 1), (OFF)x);
         }
         return a;
     };
     // node (x - dx, y - dy) holds (x, y) at window offset (dx, dy)
-    T acc = V.s(S_PHIC)[k] + edges(0), accp = T(0);
+    T acc = at<T, OFF>(V.s(S_PHIC), k) + edges(0), accp = T(0);
 #pragma unroll
     for (int dy = -1; dy <= 1; dy++)
 #pragma unroll
@@ -542,9 +555,9 @@ __global__ __launch_bounds__(TX* BY) void k_adj_gather(KParams<T> P, const char*
             const int wy = ly + 1 - dy, wx = lx + 1 - dx;
             acc += wgx<T>(dx, dy) * sw[0][wy][wx] + wgy<T>(dx, dy) * sw[1][wy][wx] + wlap<T>(dx, dy) * sw[2][wy][wx];
         }
-    V.plane_of(co, P_PHIB)[k] = acc;
+    put<T, OFF>(V.plane_of(co, P_PHIB), k, acc);
     if (!first) {
-        accp = V.s(S_PHP)[k] + edges(1);
+        accp = at<T, OFF>(V.s(S_PHP), k) + edges(1);
 #pragma unroll
         for (int dy = -1; dy <= 1; dy++)
 #pragma unroll
@@ -553,7 +566,7 @@ __global__ __launch_bounds__(TX* BY) void k_adj_gather(KParams<T> P, const char*
                 accp += wgx<T>(dx, dy) * sw[3][wy][wx] + wgy<T>(dx, dy) * sw[4][wy][wx];
             }
     }
-    V.plane_of(co, 18)[k] = accp;
+    put<T, OFF>(V.plane_of(co, 18), k, accp);
 }
 
 // ---------------------------------------------------------------- adjoint step, kernel G
@@ -566,13 +579,16 @@ __host__ __device__ inline long long ghost_items(int nx, int ny, bool wall_x, bo
     return (wall_y ? 2LL * nx : 0LL) + (wall_x ? 2LL * ny : 0LL);
 }
 
+// Workgroups of kernel G: the first half takes the items of the current phi,
+// the second half those of the previous phi (so that every pointer a
+// workgroup reads through is uniform).
 static int ghost_blocks(const lbm_params* p) {
-    const long long items = 2 * ghost_items(p->nx, p->ny, p->bc_x == LBM_WALLS, p->bc_y == LBM_WALLS);
-    const long long b = (items + GHOST_THREADS - 1) / GHOST_THREADS;
-    return (int)(b < 1 ? 1 : (b > 1024 ? 1024 : b));
+    const long long per = ghost_items(p->nx, p->ny, p->bc_x == LBM_WALLS, p->bc_y == LBM_WALLS);
+    const long long b = (per + GHOST_THREADS - 1) / GHOST_THREADS;
+    return 2 * (int)(b < 1 ? 1 : (b > 512 ? 512 : b));
 }
 
-template <typename T>
+template <typename T, typename OFF>
 __global__ __launch_bounds__(GHOST_THREADS) void k_adj_ghosts(KParams<T> P, const char* tape, size_t slot, int j,
                                                              AdjView<T> V) {
     __shared__ double red[4][GHOST_THREADS / 64];
@@ -590,38 +606,40 @@ __global__ __launch_bounds__(GHOST_THREADS) void k_adj_ghosts(KParams<T> P, cons
     const long long per = ghost_items(P.nx, P.ny, P.wall_x, P.wall_y);
     const long long ny2 = P.wall_y ? 2LL * P.nx : 0LL;
     double th[4] = {0.0, 0.0, 0.0, 0.0};
-    for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < 2 * per;
-         idx += (long long)gridDim.x * blockDim.x) {
-        const int lev = (int)(idx / per);
-        const long long it = idx - lev * per;
-        const T* phi = lev ? S.h : V.s(S_PHI);
-        int wall, at;
+    const int half = (int)gridDim.x / 2;
+    const int lev = (int)blockIdx.x >= half ? 1 : 0;   // uniform over the workgroup
+    const T* phi = lev ? S.h : V.s(S_PHI);
+    for (long long it = (blockIdx.x - lev * half) * (long long)blockDim.x + threadIdx.x; it < per;
+         it += (long long)half * blockDim.x) {
+        // item -> (wall, position) by comparisons: it < 2 nx + 2 ny
+        int wall, pos;
         T d1, d2, dth, q, cth = T(0), qc = T(0);
         if (it < ny2) {   // y-wall ghost (x, -1) or (x, ny)
-            const int sy = (int)(it / P.nx), x = (int)(it - (long long)sy * P.nx);
+            const int sy = it >= P.nx ? 1 : 0, x = (int)(it - (sy ? P.nx : 0));
             const int y1 = sy ? P.ny - 1 : 0, y2 = sy ? P.ny - 2 : 1;
-            q = ext_adjoint(P, V, lev, x, sy ? P.ny : -1);
-            wet_ghost_grad(P, 2 + sy, phi_at(P, phi, x, y1), phi_at(P, phi, x, y2), d1, d2, dth);
+            q = ext_adjoint<T, OFF>(P, V, lev, x, sy ? P.ny : -1);
+            wet_ghost_grad(P, 2 + sy, phi_at<T, OFF>(P, phi, x, y1), phi_at<T, OFF>(P, phi, x, y2), d1, d2, dth);
             if (P.wall_x && (x == 0 || x == P.nx - 1)) {   // the corner ghost beside it
                 const int side = x == 0 ? 0 : 1;
-                qc = ext_adjoint(P, V, lev, side ? P.nx : -1, sy ? P.ny : -1);
+                qc = ext_adjoint<T, OFF>(P, V, lev, side ? P.nx : -1, sy ? P.ny : -1);
                 T c1, c2;
-                wet_ghost_grad(P, 2 + sy, xghost(P, phi, side, y1), xghost(P, phi, side, y2), c1, c2, cth);
+                wet_ghost_grad(P, 2 + sy, xghost<T, OFF>(P, phi, side, y1), xghost<T, OFF>(P, phi, side, y2), c1, c2,
+                               cth);
             }
             wall = 2 + sy;
-            at = x;
+            pos = x;
         } else {          // x-wall ghost (-1, y) or (nx, y)
             const long long i2 = it - ny2;
-            const int sx = (int)(i2 / P.ny), y = (int)(i2 - (long long)sx * P.ny);
+            const int sx = i2 >= P.ny ? 1 : 0, y = (int)(i2 - (sx ? P.ny : 0));
             const int x1 = sx ? P.nx - 1 : 0, x2 = sx ? P.nx - 2 : 1;
-            q = xghost_adjoint(P, V, lev, phi, sx, y);
-            wet_ghost_grad(P, sx, phi_at(P, phi, x1, y), phi_at(P, phi, x2, y), d1, d2, dth);
+            q = xghost_adjoint<T, OFF>(P, V, lev, phi, sx, y);
+            wet_ghost_grad(P, sx, phi_at<T, OFF>(P, phi, x1, y), phi_at<T, OFF>(P, phi, x2, y), d1, d2, dth);
             wall = sx;
-            at = y;
+            pos = y;
         }
         if (status == 0 && (lev == 0 || n > 0)) {   // the previous level only when n > 0
-            V.e(lev, wall, 0)[at] = d1 * q;
-            V.e(lev, wall, 1)[at] = d2 * q;
+            put<T, OFF>(V.e(lev, wall, 0), (OFF)pos, d1 * q);
+            put<T, OFF>(V.e(lev, wall, 1), (OFF)pos, d2 * q);
             th[wall] += (double)(dth * q);
             if (wall >= 2) th[wall] += (double)(cth * qc);
         }
@@ -839,12 +857,15 @@ template <typename T>
 static void launch_adj_step(const KParams<T>& P, const char* tape, size_t slot, int j, const AdjView<T>& V,
                             size_t adj_bytes, hipStream_t s) {
     // 32-bit byte offsets while a tape slot and the adjoint buffer stay below 4 GiB
-    if (slot < (size_t(1) << 32) && adj_bytes < (size_t(1) << 32))
+    if (slot < (size_t(1) << 32) && adj_bytes < (size_t(1) << 32)) {
         k_adj_local<T, uint32_t><<<V.ntA, dim3(TX, ABY), 0, s>>>(P, tape, slot, j, V);
-    else
+        if (P.wall_x || P.wall_y) k_adj_ghosts<T, uint32_t><<<V.nB, GHOST_THREADS, 0, s>>>(P, tape, slot, j, V);
+        k_adj_gather<T, uint32_t><<<V.ntB, dim3(TX, BY), 0, s>>>(P, tape, j, V);
+    } else {
         k_adj_local<T, uint64_t><<<V.ntA, dim3(TX, ABY), 0, s>>>(P, tape, slot, j, V);
-    if (P.wall_x || P.wall_y) k_adj_ghosts<T><<<V.nB, GHOST_THREADS, 0, s>>>(P, tape, slot, j, V);
-    k_adj_gather<T><<<V.ntB, dim3(TX, BY), 0, s>>>(P, tape, j, V);
+        if (P.wall_x || P.wall_y) k_adj_ghosts<T, uint64_t><<<V.nB, GHOST_THREADS, 0, s>>>(P, tape, slot, j, V);
+        k_adj_gather<T, uint64_t><<<V.ntB, dim3(TX, BY), 0, s>>>(P, tape, j, V);
+    }
 }
 
 }  // namespace lbm
