@@ -283,11 +283,12 @@ typedef struct lbm_batch lbm_batch;
  * autotune != 0: the first lbm_batch_init times the candidate tile shapes and
  * grid sizes of the one-level batch launch (one workgroup per tile, or fewer
  * workgroups striding over the tiles) on the batch itself and keeps the
- * fastest.  LBM_BATCH_SHAPE="ty,by,grid" in the environment fixes that shape
- * instead (tile rows ty and thread rows by: 4,4 8,4 8,8 16,4 16,8, 16-row
- * tiles in FP32 only, by = ty when the batch holds Cahn-Hilliard, corrected or
- * local-gradient cases; grid workgroups, 0 for one per tile) and skips the
- * timing; another value makes this call return LBM_E_PARAM. */
+ * fastest.  LBM_BATCH_SHAPE="ty,by,grid" in the environment fixes the shape
+ * of the one-level launch instead and skips the timing: tile rows ty and
+ * thread rows by (4,4 8,4 8,8 16,4 16,8; 16-row tiles in FP32 only; by = ty
+ * when the batch holds Cahn-Hilliard, corrected or local-gradient cases) and
+ * grid workgroups (0: one per tile); another value makes this call return
+ * LBM_E_PARAM. */
 int lbm_batch_create(const lbm_params *cases, int32_t ncases, int32_t autotune, lbm_batch **out);
 /* Bytes of the caller-allocated batch state (every case's state back to back). */
 int lbm_batch_state_size(const lbm_batch *batch, size_t *nbytes /* host */);
