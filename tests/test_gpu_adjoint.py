@@ -200,6 +200,31 @@ def test_full_tape_equals_checkpointed(kind, dtype):
         assert np.array_equal(a, b), (kind, dtype, what, float(np.abs(a - b).max()))
 
 
+@pytest.mark.parametrize("nsteps", [0, 1, 2])
+def test_full_tape_short_trajectories(nsteps):
+    """Zero, one and two levels with the full tape (tapes of 1, 2, 3 slots)
+    against checkpoints every level: phi^N and gradients bit for bit; at zero
+    levels phi^N is phi0 and dL/dphi0 = 2 (phi0 - target) to rounding."""
+    from paper_2111_00847_amd.autograd import trajectory_phi
+    case, phi0, target = _traj_case("dam_break_32x16")
+    out = {}
+    for chk in (0, 1):
+        phi0_t = torch.tensor(phi0, dtype=torch.float64, device="cuda", requires_grad=True)
+        grav = torch.tensor(list(case.gravity), dtype=torch.float64, requires_grad=True)
+        theta = torch.tensor(list(case.theta), dtype=torch.float64, requires_grad=True)
+        phiN = trajectory_phi(phi0_t, grav, theta, case, nsteps, None, chk)
+        L = ((phiN - torch.tensor(target, device="cuda")) ** 2).sum()
+        L.backward()
+        torch.cuda.synchronize()
+        out[chk] = (phiN.detach().cpu().numpy(), phi0_t.grad.cpu().numpy(), grav.grad.numpy(), theta.grad.numpy())
+    for a, b, what in zip(out[0], out[1], ("phi^N", "dL/dphi0", "dL/dgravity", "dL/dtheta")):
+        assert np.array_equal(a, b), (nsteps, what, float(np.abs(a - b).max()))
+    if nsteps == 0:
+        assert np.abs(out[0][0] - phi0).max() <= 1e-14
+        assert np.abs(out[0][1] - 2.0 * (phi0 - target)).max() <= 1e-13
+        assert not out[0][2].any() and not out[0][3].any()
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_tape_restore_resumes_the_trajectory(dtype):
     """lbm_tape_restore makes a tape slot the current level of a state: slot 3
