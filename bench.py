@@ -497,6 +497,8 @@ def main():
                     help="run only the Cahn-Hilliard measurement (profiling runs)")
     ap.add_argument("--only-main", action="store_true",
                     help="run only the headline measurement (profiling runs)")
+    ap.add_argument("--large-dtype", choices=["f32", "f64"], default="f32",
+                    help="with --only-large: the dtype of the 4096 x 4096 measurement (profiling runs)")
     ap.add_argument("--only-large", action="store_true",
                     help="run only the 4096 x 4096 measurement (profiling runs)")
     ap.add_argument("--only-local", action="store_true",
@@ -558,7 +560,9 @@ def main():
         copy_gbs = measure_copy(torch, mib=max(1, round(half / (1 << 20))), reps=200)
         out["roofline"]["copy_GBs"] = copy_gbs
         out["roofline"]["frac_of_copy"] = round(out["roofline"]["achieved"] / copy_gbs, 4)
-    if not args.no_large:
+    if not args.no_large and args.only_large and args.large_dtype == "f64":
+        out["large_grid_fp64"] = measure_large(args, torch, W, Sim, "f64")
+    elif not args.no_large:
         out["large_grid"] = measure_large(args, torch, W, Sim)
         copy_gbs = measure_copy(torch)
         out["large_grid"]["torch_copy_GBs"] = copy_gbs
