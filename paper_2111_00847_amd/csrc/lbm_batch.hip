@@ -101,14 +101,17 @@ void k_step_batch(const BatchCase<T>* __restrict__ cases, int ncases, int nitems
 // Two levels per launch: work item blockIdx.x, one 64 x 8 tile of one case, per
 // workgroup of 64 x 8 threads (items of a case table for 8-row tiles).  One
 // item per workgroup: a loop over items (a persistent grid) doubles the
-// registers of the body (169 against 86 VGPRs in FP32).
-template <typename T, bool NTS>
+// registers of the body (169 against 86 VGPRs in FP32).  PER_ITEM: the table
+// holds one entry per item (its case's), so that the workgroup reads its case
+// directly instead of counting item_begin over the cases first (one round
+// trip and a barrier fewer before the tile's loads).
+template <typename T, bool NTS, bool PER_ITEM = false>
 __global__ __launch_bounds__(TX * 8) void k_step2_batch(const BatchCase<T>* __restrict__ cases, int ncases,
                                                        int nitems, char* batch_state) {
     __shared__ Step2Lds<T, 8> L;
     const int w = blockIdx.x;
     if (w >= nitems) return;   // uniform over the workgroup
-    const BatchCase<T>& C = cases[batch_case(cases, ncases, w, TX * 8)];
+    const BatchCase<T>& C = cases[PER_ITEM ? w : batch_case(cases, ncases, w, TX * 8)];
     const int local = w - C.item_begin;
     if (C.P.rates_std)
         step2_tile<T, 8, 8, true, NTS>(C.P, batch_state + C.base, C.off0, C.off1, C.off_stamp, local % C.ntx,
@@ -253,9 +256,15 @@ template <typename T>
 hipError_t upload_cases2(lbm_batch* B) {
     std::vector<BatchCase<T>> h(B->ncases);
     B->nitems2 = fill_cases<T>(B->params.data(), B->layouts.data(), B->base.data(), B->ncases, 8, h.data());
-    hipError_t e = hipMalloc(&B->d_cases2, sizeof(BatchCase<T>) * B->ncases);
+    // one entry per item: entry w is the case of item w (k_step2_batch, PER_ITEM)
+    std::vector<BatchCase<T>> items((size_t)B->nitems2);
+    for (int c = 0; c < B->ncases; c++) {
+        const int end = c + 1 < B->ncases ? h[c + 1].item_begin : B->nitems2;
+        for (int w = h[c].item_begin; w < end; w++) items[(size_t)w] = h[c];
+    }
+    hipError_t e = hipMalloc(&B->d_cases2, sizeof(BatchCase<T>) * items.size());
     if (e != hipSuccess) return e;
-    return hipMemcpy(B->d_cases2, h.data(), sizeof(BatchCase<T>) * B->ncases, hipMemcpyHostToDevice);
+    return hipMemcpy(B->d_cases2, items.data(), sizeof(BatchCase<T>) * items.size(), hipMemcpyHostToDevice);
 }
 
 // One launch of the batch kernels over `nitems` work items of a device case
@@ -317,21 +326,28 @@ void launch_batch_once(lbm_batch* B, char* state, hipStream_t s) {
     launch_batch_shape<T>(S, B->d_cases, state, s);
 }
 
-// One two-level launch over `nitems` items of a case table for 8-row tiles.
+// One two-level launch over `nitems` items of a case table for 8-row tiles
+// (per_item: one entry per item, as upload_cases2 writes it; else one per case).
 template <typename T>
-void launch_batch2(int nitems, int ncases, const void* d_cases, size_t total, char* state, hipStream_t s) {
+void launch_batch2(int nitems, int ncases, const void* d_cases, size_t total, char* state, hipStream_t s,
+                   bool per_item) {
     const BatchCase<T>* cases = reinterpret_cast<const BatchCase<T>*>(d_cases);
-    if (total <= (size_t)LBM_NT_MIN_BYTES)
-        k_step2_batch<T, false><<<nitems, dim3(TX, 8), 0, s>>>(cases, ncases, nitems, state);
-    else
-        k_step2_batch<T, true><<<nitems, dim3(TX, 8), 0, s>>>(cases, ncases, nitems, state);
+    const bool nts = total > (size_t)LBM_NT_MIN_BYTES;
+    if (per_item) {
+        if (nts) k_step2_batch<T, true, true><<<nitems, dim3(TX, 8), 0, s>>>(cases, ncases, nitems, state);
+        else k_step2_batch<T, false, true><<<nitems, dim3(TX, 8), 0, s>>>(cases, ncases, nitems, state);
+    } else {
+        if (nts) k_step2_batch<T, true><<<nitems, dim3(TX, 8), 0, s>>>(cases, ncases, nitems, state);
+        else k_step2_batch<T, false><<<nitems, dim3(TX, 8), 0, s>>>(cases, ncases, nitems, state);
+    }
 }
 
 // `n` levels of the batch: two-level launches, and a one-level launch for an odd n.
 template <typename T>
 void launch_batch_levels(lbm_batch* B, char* state, int64_t n, hipStream_t s) {
     if (B->two_level) {
-        for (int64_t t = 0; t + 2 <= n; t += 2) launch_batch2<T>(B->nitems2, B->ncases, B->d_cases2, B->total, state, s);
+        for (int64_t t = 0; t + 2 <= n; t += 2)
+            launch_batch2<T>(B->nitems2, B->ncases, B->d_cases2, B->total, state, s, true);
         if (n & 1) launch_batch_once<T>(B, state, s);
     } else {
         for (int64_t t = 0; t < n; t++) launch_batch_once<T>(B, state, s);
@@ -571,7 +587,7 @@ int batch_step_noalloc_t(const lbm_params* cases, int ncases, char* state, int64
     const BatchShape S{ty, wide ? ty : 4, 0, nitems, ncases, wide, total};
     int64_t t = 0;
     if (two_level_batch(cases, ncases))
-        for (; t + 2 <= nsteps; t += 2) launch_batch2<T>(nitems, ncases, table, total, state, s);
+        for (; t + 2 <= nsteps; t += 2) launch_batch2<T>(nitems, ncases, table, total, state, s, false);
     for (; t < nsteps; t++) launch_batch_shape<T>(S, table, state, s);
     e = hipGetLastError();
     return e == hipSuccess ? LBM_OK : hip_fail(e);
