@@ -209,6 +209,9 @@ int lbm_import_state(const lbm_params *p, void *state, const void *f, const void
  *   for each segment, newest first: lbm_tape_record from the segment's first
  *   level, then lbm_adjoint_step(tape, j) for j = L-1 .. 0 (or one lbm_adjoint_run)
  *   lbm_adjoint_init -> dL/dphi0; lbm_adjoint_params -> dL/dgravity, dL/dtheta.
+ * Or, with memory for every level, one segment recorded by the forward pass
+ * itself (levels 0 .. N, ending on lbm_tape_restore of slot N) and no
+ * recomputation in the backward pass.
  * Level mismatches (a step whose tape level is not one below the adjoint's),
  * a slot j the tape does not hold and a tape recorded for another lattice or
  * dtype are detected on the device from the tape's header before any slot is
